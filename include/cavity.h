@@ -1,0 +1,172 @@
+/*
+ * cavity.h - C ABI of the MI355X (gfx950) solver for time-harmonic electromagnetic
+ * scattering from an open rectangular cavity in a perfectly conducting ground plane
+ * (Chen, Jiang, Lai, Li, "A fast algorithm for the electromagnetic scattering from a
+ * large rectangular cavity in three dimensions", arXiv 2008.01966).
+ *
+ * Problem statement (Section 2 of the paper): cavity [0,a] x [0,b] x [-c,0] below the
+ * ground plane, aperture [0,a] x [0,b] at z = 0, walls and ground perfectly conducting,
+ * non-magnetic medium with relative permittivity eps_r(z) piecewise constant in layers,
+ * vacuum above the ground plane with wavenumber k, time convention e^{-i omega t}
+ * (Im eps_r >= 0 is lossy).  Lengths are in any unit consistent with k (the paper's
+ * examples use the wavelength, k = 2 pi).
+ *
+ * Method (Sections 3-6): the field components are expanded in the sine/cosine series
+ * (E123F) with M = Nx-1, N = Ny-1 modes per axis; each mode's z-column is discretised by
+ * second-order differences on Nz uniform intervals (h = c/Nz) and eliminated down to the
+ * aperture (the LU relation r_JJ E_J + E_{J+1} = 0 and its layered form (uTT1)); the
+ * transparent boundary condition (ENU1) couples the aperture modes through three
+ * single-layer operators whose singular integrals are applied by FFT convolution with
+ * the spectrum of the truncated kernel (Section 5); the reduced aperture system (EJ1) /
+ * (uT1) is solved by preconditioned GMRES; the interior is recovered by
+ * back-substitution (EInter) and the backscatter RCS is evaluated from the aperture
+ * field (Section 7).
+ *
+ * Conventions shared by every entry point
+ *  - Complex numbers are interleaved double pairs (cavity_c128).
+ *  - "device" pointers are HIP device memory owned by the caller; they are written
+ *    asynchronously on the plan's stream and valid after that stream is synchronised.
+ *  - "host" pointers are ordinary host memory; calls taking host outputs synchronise
+ *    the plan's stream before returning.
+ *  - Every function returns a status (0 = CAVITY_OK).  On failure nothing is written to
+ *    the outputs except where stated, and cavity_last_error() returns a message for the
+ *    calling thread.
+ *  - A plan is not thread-safe; distinct plans may be used from distinct threads/streams.
+ *  - Field output layout E_out[3][Nz+1][Ny+1][Nx+1] (component, z-node, y-node, x-node;
+ *    x fastest) on the nodes x = i1 a/Nx, y = i2 b/Ny, z = -c + j h.  At an interface
+ *    node the normal component E3 is reported on the upper side.
+ *  - Aperture vector layout (paper's Appendix A order): E1 on N1 = {0..M} x {1..N},
+ *    then E2 on N2 = {1..M} x {0..N}, then E3 on N3 = {1..M} x {1..N}, each m-major;
+ *    n_ap = (M+1)N + M(N+1) + MN entries.
+ */
+#ifndef CAVITY_H
+#define CAVITY_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  CAVITY_OK = 0,
+  CAVITY_EINVAL = 1,     /* invalid argument (sizes, angles, NULL pointers, layer sums) */
+  CAVITY_ENOMEM = 2,     /* plan footprint exceeds the HBM budget or allocation failed */
+  CAVITY_ERESONANT = 3,  /* a z-elimination pivot vanished: discrete closed-cavity resonance */
+  CAVITY_ENOCONV = 4,    /* GMRES did not reach the tolerance within max_iter */
+  CAVITY_EDEVICE = 5,    /* HIP runtime error (detail in cavity_last_error) */
+  CAVITY_ENOTIMPL = 6    /* option not implemented */
+};
+
+enum { CAVITY_FP64 = 0, CAVITY_MIXED = 1 };
+enum { CAVITY_TM = 0 /* theta-hat polarisation */, CAVITY_TE = 1 /* phi-hat */ };
+
+typedef struct cavity_plan_s* cavity_plan; /* opaque; owns all of its device memory */
+
+typedef struct {
+  double re, im;
+} cavity_c128;
+
+/* Layer stack, bottom to top (Section 4 and its closing remark for more layers).
+ * layer_nz[i] >= 1 intervals of layer i with sum equal to Nz; eps_r[i] its relative
+ * permittivity.  Interfaces sit on the z-grid nodes. */
+typedef struct {
+  int n_layers;
+  const int* layer_nz;        /* host, n_layers entries */
+  const cavity_c128* eps_r;   /* host, n_layers entries */
+} cavity_eps;
+
+/* Solver options; cavity_opts_default() fills the defaults listed here. */
+typedef struct {
+  int precision;        /* CAVITY_FP64 (default); CAVITY_MIXED returns CAVITY_ENOTIMPL */
+  int tbc_oversample;   /* s >= 1: TBC quadrature grid has s*Nx x s*Ny intervals (default 1) */
+  double tol;           /* relative residual of the aperture system (default 1e-12) */
+  int max_iter;         /* total GMRES iterations per right-hand side (default 400) */
+  int restart;          /* GMRES restart length, 1..200 (default 60) */
+  size_t hbm_budget;    /* bytes the plan may allocate; 0 = 90 % of free device memory */
+  void* stream;         /* hipStream_t for all work of the plan; NULL = default stream */
+} cavity_opts;
+
+/* Plan description and the statistics of its last solve. */
+typedef struct {
+  int M, N, Nz;
+  int P1, P2;                  /* FFT box of the TBC convolution */
+  long long n_ap;              /* aperture unknowns */
+  long long unknowns;          /* n_ap * Nz: unknowns per right-hand side */
+  size_t device_bytes;         /* device memory held by the plan */
+  double min_pivot;            /* smallest |pivot| met in the z-elimination */
+  int last_iterations;         /* GMRES iterations of the last solve */
+  double last_rel_residual;    /* true relative residual of the last solve */
+  double ms_spectrum, ms_elimination, ms_preconditioner; /* plan phases (device time) */
+  double ms_rhs, ms_krylov, ms_synthesis;                /* last solve phases */
+} cavity_info;
+
+int cavity_opts_default(cavity_opts* opts);
+
+/* Build a plan: validates arguments, derives sizes, allocates device memory, computes
+ * the truncated-kernel spectrum (Section 5), runs the per-mode z-elimination (Sections
+ * 3-4) and the block preconditioner.  a, b, c, k > 0; Nx, Ny >= 2 with 2*s*Nx and 2*s*Ny
+ * products of 2, 3 and 5; Nz >= 1; eps may be NULL (vacuum).  opts may be NULL.
+ * Errors: CAVITY_EINVAL, CAVITY_ENOMEM, CAVITY_ERESONANT, CAVITY_EDEVICE. */
+int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
+                       const cavity_eps* eps, double k, const cavity_opts* opts,
+                       cavity_plan* out);
+
+/* Solve for one plane wave (Section 7): direction angles theta in [0, pi/2], phi any,
+ * pol CAVITY_TM or CAVITY_TE.  Writes the field on all nodes to E_out (device, caller
+ * owned, 3*(Nz+1)*(Ny+1)*(Nx+1) entries) unless E_out is NULL; keeps the aperture
+ * solution in the plan as right-hand side 0 for cavity_rcs / cavity_aperture.
+ * Errors: CAVITY_EINVAL, CAVITY_ENOCONV (E_out still written with the last iterate),
+ * CAVITY_EDEVICE. */
+int cavity_solve(cavity_plan plan, double theta, double phi, int pol, cavity_c128* E_out);
+
+/* Solve nrhs plane waves (host arrays theta, phi, pol) one after another on the plan's
+ * stream.  E_out (device) holds nrhs consecutive fields or is NULL; aperture_out
+ * (device) holds nrhs consecutive aperture vectors of n_ap entries or is NULL.  The plan
+ * keeps every aperture solution (indices 0..nrhs-1) for cavity_rcs. */
+int cavity_solve_batch(cavity_plan plan, int nrhs, const double* theta, const double* phi,
+                       const int* pol, cavity_c128* E_out, cavity_c128* aperture_out);
+
+/* Radar cross section (units of length squared) of stored solution rhs_index at n_obs
+ * observation directions (host arrays); sigma (host) receives {sigma_theta, sigma_phi}
+ * per direction.  Backscatter: observation direction equal to the incidence angles.
+ * Errors: CAVITY_EINVAL (no such solution), CAVITY_EDEVICE. */
+int cavity_rcs(cavity_plan plan, int rhs_index, int n_obs, const double* theta_o,
+               const double* phi_o, double* sigma);
+
+/* Copy stored aperture solution rhs_index to host memory (n_ap entries, paper order). */
+int cavity_aperture(cavity_plan plan, int rhs_index, cavity_c128* out_host);
+
+int cavity_plan_info(cavity_plan plan, cavity_info* out);
+void cavity_plan_destroy(cavity_plan plan);
+const char* cavity_status_string(int status);
+const char* cavity_last_error(void);
+
+/* ---- Inspection of individual steps (host in, host out; for parity testing) ------
+ * Mode-grid arrays are (M+1) x (N+1), m-major; entries outside a component's mode set
+ * are zero. */
+
+/* Schur data of the elimination: rho_d, T (tau_1 = mu_m T, tau_2 = nu_n T), rho_n. */
+int cavity_debug_columns(cavity_plan plan, cavity_c128* rho_d, cavity_c128* T,
+                         cavity_c128* rho_n);
+/* Profiles at nodes 0..Nz: pi_d, theta_d (zero when homogeneous), pi_n; each
+ * (Nz+1) x (M+1) x (N+1). */
+int cavity_debug_profiles(cavity_plan plan, cavity_c128* pi_d, cavity_c128* theta_d,
+                          cavity_c128* pi_n);
+/* Kernel spectrum K^ on the P1 x P2 FFT lattice (FFT index order, unscaled). */
+int cavity_debug_spectrum(cavity_plan plan, cavity_c128* khat);
+/* Single-layer operator family f (0 = cos-sin, 1 = sin-cos, 2 = cos-cos) applied to a
+ * coefficient grid. */
+int cavity_debug_tbc(cavity_plan plan, int family, const cavity_c128* in, cavity_c128* out);
+/* Reduced aperture operator (no preconditioner) on a padded 3 x (M+1) x (N+1) vector. */
+int cavity_debug_operator(cavity_plan plan, const cavity_c128* in, cavity_c128* out);
+/* Right-hand side grids g1, g2 of one incidence. */
+int cavity_debug_rhs(cavity_plan plan, double theta, double phi, int pol, cavity_c128* g1,
+                     cavity_c128* g2);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CAVITY_H */

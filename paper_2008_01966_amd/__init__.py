@@ -1,0 +1,268 @@
+"""Python binding of libcavity.so, the MI355X cavity-scattering solver.
+
+Argument marshalling only: every step of the solver runs in the library's HIP kernels.
+PyTorch provides device memory for the field output and the current stream.  The
+library must have been built in-tree (``paper_2008_01966_amd.build``); importing the
+binding without it raises immediately - there is no CPU fallback.
+
+Entry points mirror the C ABI in include/cavity.h: plan creation, solve, batched
+solve, radar cross section, aperture coefficients, plan info, and the inspection
+calls used by the parity tests.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcavity.so")
+
+TM, TE = 0, 1
+STATUS = {0: "ok", 1: "EINVAL", 2: "ENOMEM", 3: "ERESONANT", 4: "ENOCONV", 5: "EDEVICE",
+          6: "ENOTIMPL"}
+
+
+class CavityError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class C128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class EpsStack(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int), ("layer_nz", ctypes.POINTER(ctypes.c_int)),
+                ("eps_r", ctypes.POINTER(C128))]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("tbc_oversample", ctypes.c_int),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
+                ("hbm_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("N", ctypes.c_int), ("Nz", ctypes.c_int),
+                ("P1", ctypes.c_int), ("P2", ctypes.c_int), ("n_ap", ctypes.c_longlong),
+                ("unknowns", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t),
+                ("min_pivot", ctypes.c_double), ("last_iterations", ctypes.c_int),
+                ("last_rel_residual", ctypes.c_double), ("ms_spectrum", ctypes.c_double),
+                ("ms_elimination", ctypes.c_double), ("ms_preconditioner", ctypes.c_double),
+                ("ms_rhs", ctypes.c_double), ("ms_krylov", ctypes.c_double),
+                ("ms_synthesis", ctypes.c_double)]
+
+
+EXPORTS = [
+    "cavity_opts_default", "cavity_plan_create", "cavity_solve", "cavity_solve_batch",
+    "cavity_rcs", "cavity_aperture", "cavity_plan_info", "cavity_plan_destroy",
+    "cavity_status_string", "cavity_last_error", "cavity_debug_columns",
+    "cavity_debug_profiles", "cavity_debug_spectrum", "cavity_debug_tbc",
+    "cavity_debug_operator", "cavity_debug_rhs",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libcavity.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_2008_01966_amd.build`")
+    # PyTorch ships its own HIP runtime.  Loading torch first makes the library bind to that
+    # same runtime (identical soname), so the process holds one HIP runtime, not two.
+    _torch()
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp, d, i = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+    lib.cavity_opts_default.argtypes = [P(Opts)]
+    lib.cavity_plan_create.argtypes = [d, d, d, i, i, i, P(EpsStack), d, P(Opts), P(vp)]
+    lib.cavity_solve.argtypes = [vp, d, d, i, vp]
+    lib.cavity_solve_batch.argtypes = [vp, i, P(d), P(d), P(i), vp, vp]
+    lib.cavity_rcs.argtypes = [vp, i, i, P(d), P(d), P(d)]
+    lib.cavity_aperture.argtypes = [vp, i, P(C128)]
+    lib.cavity_plan_info.argtypes = [vp, P(Info)]
+    lib.cavity_plan_destroy.argtypes = [vp]
+    lib.cavity_plan_destroy.restype = None
+    lib.cavity_status_string.argtypes = [i]
+    lib.cavity_status_string.restype = ctypes.c_char_p
+    lib.cavity_last_error.argtypes = []
+    lib.cavity_last_error.restype = ctypes.c_char_p
+    lib.cavity_debug_columns.argtypes = [vp, P(C128), P(C128), P(C128)]
+    lib.cavity_debug_profiles.argtypes = [vp, P(C128), P(C128), P(C128)]
+    lib.cavity_debug_spectrum.argtypes = [vp, P(C128)]
+    lib.cavity_debug_tbc.argtypes = [vp, i, P(C128), P(C128)]
+    lib.cavity_debug_operator.argtypes = [vp, P(C128), P(C128)]
+    lib.cavity_debug_rhs.argtypes = [vp, d, d, i, P(C128), P(C128)]
+    for name in EXPORTS:
+        if name not in ("cavity_plan_destroy", "cavity_status_string", "cavity_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = load_library().cavity_last_error().decode(errors="replace")
+        raise CavityError(status, msg)
+
+
+def _cbuf(arr: np.ndarray):
+    assert arr.dtype == np.complex128 and arr.flags.c_contiguous
+    return arr.ctypes.data_as(ctypes.POINTER(C128))
+
+
+def _torch():
+    import torch  # device memory and streams only
+    return torch
+
+
+class Plan:
+    """One cavity geometry, grid and layer stack, with its resident device data."""
+
+    def __init__(self, a: float, b: float, c: float, nx: int, ny: int, nz: int,
+                 layer_nz: Optional[Sequence[int]] = None,
+                 layer_eps: Optional[Sequence[complex]] = None, k: float = 2 * np.pi, *,
+                 tol: float = 1e-12, restart: int = 60, max_iter: int = 400,
+                 oversample: int = 1, hbm_budget: int = 0, stream: Optional[int] = None):
+        lib = load_library()
+        self._lib = lib
+        self.a, self.b, self.c = float(a), float(b), float(c)
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        opts = Opts()
+        _check(lib.cavity_opts_default(ctypes.byref(opts)))
+        opts.tol, opts.restart, opts.max_iter = float(tol), int(restart), int(max_iter)
+        opts.tbc_oversample = int(oversample)
+        opts.hbm_budget = int(hbm_budget)
+        if stream is None:
+            torch = _torch()
+            stream = torch.cuda.current_stream().cuda_stream
+        opts.stream = ctypes.c_void_p(int(stream))
+        self._stream = stream
+        eps_p = None
+        if layer_nz is not None:
+            nzs = (ctypes.c_int * len(layer_nz))(*[int(v) for v in layer_nz])
+            epsv = (C128 * len(layer_eps))(*[C128(complex(e).real, complex(e).imag)
+                                              for e in layer_eps])
+            self._keep = (nzs, epsv)
+            eps_p = ctypes.pointer(EpsStack(len(layer_nz), nzs, epsv))
+        handle = ctypes.c_void_p()
+        _check(lib.cavity_plan_create(self.a, self.b, self.c, self.nx, self.ny, self.nz, eps_p,
+                                      float(k), ctypes.byref(opts), ctypes.byref(handle)))
+        self._h = handle
+        self.info_ = self.info()
+
+    @classmethod
+    def from_cavity(cls, cav, **kw) -> "Plan":
+        kw.setdefault("oversample", cav.tbc_oversample)
+        return cls(cav.a, cav.b, cav.c, cav.nx, cav.ny, cav.nz, cav.layer_nz, cav.layer_eps,
+                   cav.k, **kw)
+
+    # -- lifecycle -------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.cavity_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> Info:
+        out = Info()
+        _check(self._lib.cavity_plan_info(self._h, ctypes.byref(out)))
+        return out
+
+    @property
+    def grid_shape(self):
+        inf = self.info_
+        return (inf.M + 1, inf.N + 1)
+
+    @property
+    def field_shape(self):
+        return (3, self.nz + 1, self.ny + 1, self.nx + 1)
+
+    # -- solves ------------------------------------------------------------------------
+    def empty_field(self, count: int = 1):
+        torch = _torch()
+        shape = self.field_shape if count == 1 else (count,) + self.field_shape
+        return torch.empty(shape, dtype=torch.complex128, device="cuda")
+
+    def solve(self, theta: float, phi: float, pol: int, out=None, field: bool = True):
+        """Solve one incidence; returns the device field tensor (or None if field=False)."""
+        if field and out is None:
+            out = self.empty_field()
+        ptr = ctypes.c_void_p(out.data_ptr()) if field else None
+        _check(self._lib.cavity_solve(self._h, float(theta), float(phi), int(pol), ptr))
+        return out if field else None
+
+    def solve_batch(self, thetas, phis, pols, out=None, field: bool = True, aperture=None):
+        n = len(thetas)
+        th = (ctypes.c_double * n)(*map(float, thetas))
+        ph = (ctypes.c_double * n)(*map(float, phis))
+        po = (ctypes.c_int * n)(*map(int, pols))
+        if field and out is None:
+            out = self.empty_field(n)
+        eptr = ctypes.c_void_p(out.data_ptr()) if field else None
+        aptr = ctypes.c_void_p(aperture.data_ptr()) if aperture is not None else None
+        _check(self._lib.cavity_solve_batch(self._h, n, th, ph, po, eptr, aptr))
+        return out if field else None
+
+    def rcs(self, index: int, theta_o, phi_o) -> np.ndarray:
+        th = np.ascontiguousarray(np.atleast_1d(theta_o), dtype=np.float64)
+        ph = np.ascontiguousarray(np.atleast_1d(phi_o), dtype=np.float64)
+        sig = np.zeros((th.size, 2))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(self._lib.cavity_rcs(self._h, int(index), th.size, th.ctypes.data_as(dp),
+                                    ph.ctypes.data_as(dp), sig.ctypes.data_as(dp)))
+        return sig
+
+    def aperture(self, index: int = 0) -> np.ndarray:
+        out = np.zeros(self.info_.n_ap, dtype=np.complex128)
+        _check(self._lib.cavity_aperture(self._h, int(index), _cbuf(out)))
+        return out
+
+    # -- inspection of individual steps ------------------------------------------------
+    def debug_columns(self):
+        shp = self.grid_shape
+        rd, T, rn = (np.zeros(shp, np.complex128) for _ in range(3))
+        _check(self._lib.cavity_debug_columns(self._h, _cbuf(rd), _cbuf(T), _cbuf(rn)))
+        return rd, T, rn
+
+    def debug_profiles(self):
+        shp = (self.nz + 1,) + self.grid_shape
+        pd, td, pn = (np.zeros(shp, np.complex128) for _ in range(3))
+        _check(self._lib.cavity_debug_profiles(self._h, _cbuf(pd), _cbuf(td), _cbuf(pn)))
+        return pd, td, pn
+
+    def debug_spectrum(self):
+        out = np.zeros((self.info_.P1, self.info_.P2), np.complex128)
+        _check(self._lib.cavity_debug_spectrum(self._h, _cbuf(out)))
+        return out
+
+    def debug_tbc(self, family: int, coef: np.ndarray) -> np.ndarray:
+        inp = np.ascontiguousarray(coef, dtype=np.complex128).reshape(self.grid_shape)
+        out = np.zeros(self.grid_shape, np.complex128)
+        _check(self._lib.cavity_debug_tbc(self._h, int(family), _cbuf(inp), _cbuf(out)))
+        return out
+
+    def debug_operator(self, e1, e2, e3):
+        inp = np.ascontiguousarray(np.stack([e1, e2, e3]), dtype=np.complex128)
+        out = np.zeros_like(inp)
+        _check(self._lib.cavity_debug_operator(self._h, _cbuf(inp), _cbuf(out)))
+        return out[0], out[1], out[2]
+
+    def debug_rhs(self, theta: float, phi: float, pol: int):
+        g1 = np.zeros(self.grid_shape, np.complex128)
+        g2 = np.zeros(self.grid_shape, np.complex128)
+        _check(self._lib.cavity_debug_rhs(self._h, float(theta), float(phi), int(pol), _cbuf(g1),
+                                          _cbuf(g2)))
+        return g1, g2

@@ -1,0 +1,94 @@
+// Host-visible launchers of the cavity kernels and the parameter blocks they take.
+// Every launcher enqueues work on the given stream and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace cav {
+
+// Sizes and scalars of one plan, passed by value to the kernels.
+struct Geo {
+  int M, N, Nz, NM;     // modes per axis, z-intervals, (M+1)(N+1)
+  int nq1, nq2;         // TBC quadrature intervals per axis (s*Nx, s*Ny)
+  int P1, P2;           // FFT box of the TBC convolution
+  int nx, ny;           // output grid intervals (Nx, Ny)
+  double a, b, h, k;
+  double hq1, hq2;
+};
+
+// An FFT length with its device twiddle table.
+struct Fft {
+  FftPlan p;
+  const zd* tw;
+};
+
+// The transforms one plan needs.
+struct Trig {
+  Fft ext1, ext2;   // length 2*nq1, 2*nq2: sine/cosine transforms on the TBC grid
+  Fft box1, box2;   // length P1, P2: the zero-padded convolution
+  Fft out1, out2;   // length 2*Nx, 2*Ny: sine/cosine transforms on the output grid
+};
+
+// Layer description on the z-grid for the elimination kernel.
+struct Layers {
+  const int* node_code;   // per node j = 0..Nz: >= 0 interior of that layer, -(s+1) interface s
+  const zd* kappa2;       // per layer: k^2 eps_r
+  const zd* ratio;        // per interface: eps_upper / eps_lower
+  int layered;            // 1 when there is at least one interface
+};
+
+// Plane-wave data of one right-hand side, set up on the host (Section 7 incidence).
+struct Wave {
+  double alpha1, alpha2, beta;
+  double p1, p2, p3;
+};
+
+// ---- plan-time kernels ------------------------------------------------------------
+hipError_t launch_spectrum(const Geo& g, double R, double scale, zd* khat, hipStream_t st);
+hipError_t launch_elimination(const Geo& g, const Layers& ly, zd* rho_d, zd* T, zd* rho_n,
+                              zd* pi_d, zd* theta_d, zd* pi_n, double* pivmin,
+                              hipStream_t st);
+hipError_t launch_basis_power(const Geo& g, const Trig& t, double* pw1, double* pw2,
+                              hipStream_t st);
+hipError_t launch_diag_contract(const Geo& g, const zd* khat, const double* pw1,
+                                const double* pw2, zd* tmp, zd* diag, hipStream_t st);
+hipError_t launch_precond_build(const Geo& g, const zd* rho_d, const zd* T, const zd* rho_n,
+                                const zd* diag, zd* pinv, hipStream_t st);
+
+// ---- solve-time kernels -----------------------------------------------------------
+hipError_t launch_rhs(const Geo& g, const Wave& w, zd* b, hipStream_t st);
+// y = A (P^{-1} v) when precond != 0, else y = A v.  X, Y: 3 x (M+1) x P2 workspaces,
+// S: 3 x NM workspace.
+hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const zd* rho_d,
+                           const zd* T, const zd* rho_n, const zd* pinv, int precond,
+                           const zd* v, zd* X, zd* Y, zd* S, zd* y, hipStream_t st);
+// One single-layer family on a coefficient grid (inspection path).
+hipError_t launch_single_family(const Geo& g, const Trig& t, const zd* khat, int family,
+                                const zd* in, zd* X, zd* Y, zd* out, hipStream_t st);
+
+// Krylov building blocks on vectors of length n.
+hipError_t launch_dots(const zd* V, long long ldv, int nv, const zd* w, long long n,
+                       zd* partial, int nblk, zd* h, hipStream_t st);
+hipError_t launch_update(const zd* V, long long ldv, int nv, const zd* h, zd* w, long long n,
+                         hipStream_t st);
+hipError_t launch_norm2(const zd* w, long long n, double* partial, int nblk, double* out,
+                        hipStream_t st);
+hipError_t launch_scale_copy(const zd* w, const double* nrm2, zd* v, long long n,
+                             hipStream_t st);
+hipError_t launch_sub(const zd* b, const zd* w, zd* r, long long n, hipStream_t st);
+hipError_t launch_combine(const Geo& g, const zd* V, long long ldv, int nv, const zd* y,
+                          const zd* pinv, zd* x, hipStream_t st);
+
+// Back-substitution and synthesis of E_out for levels [j0, j1).
+hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const zd* theta_d,
+                            const zd* pi_n, const zd* xap, int j0, int j1, zd* tbuf,
+                            zd* eout, hipStream_t st);
+// Aperture transforms E^1(u), E^2(u): per-block partial sums (2 complex per block).
+hipError_t launch_rcs_partial(const Geo& g, const zd* xap, double u1, double u2, zd* partial,
+                              int nblk, hipStream_t st);
+hipError_t launch_pack(const Geo& g, const zd* xpad, zd* xcompact, hipStream_t st);
+hipError_t launch_unpack(const Geo& g, const zd* xcompact, zd* xpad, hipStream_t st);
+
+}  // namespace cav

@@ -1,0 +1,365 @@
+// Plan-time kernels: truncated-kernel spectrum (Section 5.2), per-mode z-elimination
+// (Sections 3-4), and the per-mode block preconditioner of the aperture system.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace cav {
+
+// ---------------------------------------------------------------------------------
+// Spectrum.  G^_R(rho) = 1/2 int_0^R J0(rho r) e^{ikr} dr is evaluated through
+// J0(x) = (1/pi) int_0^pi e^{i x cos t} dt as (1/(2 pi)) int_0^pi E_R(k + rho cos t) dt,
+// E_R(w) = (e^{iwR} - 1)/(iw) = R e^{i wR/2} sinc(wR/2).  The t-integrand is analytic and
+// even-periodic, so the midpoint rule with n_t > rho R / 2 nodes converges geometrically.
+// One thread per lattice point of the first quadrant (|j1|, |j2|); K^ depends on |xi|
+// only and is scattered to the mirror points.
+// ---------------------------------------------------------------------------------
+__device__ inline zd exp_integral(double w, double len) {
+  const double th = 0.5 * w * len;
+  double s, c;
+  sincos(th, &s, &c);
+  double sinc;
+  if (fabs(th) < 1e-4) {
+    const double t2 = th * th;
+    sinc = 1.0 - t2 * (1.0 / 6.0) + t2 * t2 * (1.0 / 120.0);
+  } else {
+    sinc = s / th;
+  }
+  return mk(len * c * sinc, len * s * sinc);
+}
+
+__global__ void k_spectrum(Geo g, double R, double scale, zd* __restrict__ khat) {
+  const int u1 = blockIdx.y * blockDim.y + threadIdx.y;
+  const int u2 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u1 > g.P1 / 2 || u2 > g.P2 / 2) return;
+  const double L1 = g.P1 * g.hq1, L2 = g.P2 * g.hq2;
+  const double x1 = 2.0 * M_PI * u1 / L1, x2 = 2.0 * M_PI * u2 / L2;
+  const double rho = sqrt(x1 * x1 + x2 * x2);
+  const int nt = (int)ceil(0.5 * (rho + g.k) * R) + 48;
+  double sr = 0.0, si = 0.0;
+  for (int i = 0; i < nt; ++i) {
+    const double ct = cospi((i + 0.5) / nt);
+    const zd e = exp_integral(g.k + rho * ct, R);
+    sr += e.re;
+    si += e.im;
+  }
+  const zd val = mk(scale * sr / (2.0 * nt), scale * si / (2.0 * nt));
+  const int i1a = u1, i1b = (g.P1 - u1) % g.P1;
+  const int i2a = u2, i2b = (g.P2 - u2) % g.P2;
+  khat[(long long)i1a * g.P2 + i2a] = val;
+  khat[(long long)i1a * g.P2 + i2b] = val;
+  khat[(long long)i1b * g.P2 + i2a] = val;
+  khat[(long long)i1b * g.P2 + i2b] = val;
+}
+
+hipError_t launch_spectrum(const Geo& g, double R, double scale, zd* khat, hipStream_t st) {
+  dim3 blk(64, 4);
+  dim3 grd((g.P2 / 2 + 1 + blk.x - 1) / blk.x, (g.P1 / 2 + 1 + blk.y - 1) / blk.y);
+  hipLaunchKernelGGL(k_spectrum, grd, blk, 0, st, g, R, scale, khat);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Elimination.  One thread per mode (m, n); profiles laid out [node][mode] so that a
+// wavefront touches 64 consecutive modes (coalesced).
+//
+// E3 (Neumann bottom, E3_0 = E3_1): relation V(j-1) = alpha_j V(j) within a layer;
+//   interior node: alpha_{j+1} = -1 / (alpha_j - 2 + h^2 lambda_layer)
+//   interface node (derivative continuity with eps_up E3^+ = eps_lo E3^-):
+//                  alpha_{j+1} = 1 / (1 + (1 - alpha_j) eps_up / eps_lo)
+// E1/E2 (Dirichlet bottom): E_{j-1} = alpha_j E_j + b_j E3_top (times mu_m or nu_n);
+//   interior: pivot alpha_j - 2 + h^2 lambda, no source;
+//   interface: pivot alpha_j - 2, source h (1 - eps_up/eps_lo) Pi3_s (tangential-curl
+//   continuity with one-sided differences).
+// rho = alpha_Nz, T = b_Nz; profiles by back-substitution from the aperture (value 1).
+// The up-sweep stores alpha_j in the profile slot j; the down-sweep overwrites it.
+// ---------------------------------------------------------------------------------
+__global__ void k_elimination(Geo g, Layers ly, zd* __restrict__ rho_d, zd* __restrict__ Tout,
+                              zd* __restrict__ rho_n, zd* __restrict__ pi_d,
+                              zd* __restrict__ theta_d, zd* __restrict__ pi_n,
+                              double* __restrict__ pivmin) {
+  const int mn = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mn >= g.NM) return;
+  const int m = mn / (g.N + 1), n = mn % (g.N + 1);
+  const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
+  const double mn2 = mu * mu + nu * nu;
+  const double h2 = g.h * g.h;
+  const long long NM = g.NM;
+  const int Nz = g.Nz;
+  const bool has3 = (m >= 1 && n >= 1);
+  double pmin = 1e300;
+
+  // ---- E3 column ----
+  if (has3) {
+    zd al = mk(1.0, 0.0);
+    pi_n[1 * NM + mn] = al;
+    for (int j = 1; j < Nz; ++j) {
+      const int code = ly.node_code[j];
+      zd piv;
+      if (code >= 0) {
+        const zd k2 = ly.kappa2[code];
+        piv = mk(al.re - 2.0 + h2 * (k2.re - mn2), al.im + h2 * k2.im);
+        al = cdiv(mk(-1.0, 0.0), piv);
+      } else {
+        const zd r = ly.ratio[-code - 1];
+        const zd one_m = mk(1.0 - al.re, -al.im);
+        piv = mk(1.0, 0.0) + one_m * r;
+        al = cdiv(mk(1.0, 0.0), piv);
+      }
+      pmin = fmin(pmin, sqrt(cabs2(piv)));
+      pi_n[(long long)(j + 1) * NM + mn] = al;
+    }
+    rho_n[mn] = al;
+    zd cur = mk(1.0, 0.0);
+    for (int j = Nz; j >= 1; --j) {
+      zd aj = pi_n[(long long)j * NM + mn];
+      pi_n[(long long)j * NM + mn] = cur;
+      const int code = ly.node_code[j];
+      if (code < 0) aj = aj * ly.ratio[-code - 1];
+      cur = aj * cur;
+    }
+    pi_n[mn] = cur;
+  } else {
+    for (int j = 0; j <= Nz; ++j) pi_n[(long long)j * NM + mn] = mk(0.0, 0.0);
+    rho_n[mn] = mk(0.0, 0.0);
+  }
+
+  // ---- E1/E2 column ----
+  zd al = mk(0.0, 0.0), bb = mk(0.0, 0.0);
+  pi_d[1 * NM + mn] = al;
+  if (ly.layered) theta_d[1 * NM + mn] = bb;
+  for (int j = 1; j < Nz; ++j) {
+    const int code = ly.node_code[j];
+    zd piv, f = mk(0.0, 0.0);
+    if (code >= 0) {
+      const zd k2 = ly.kappa2[code];
+      piv = mk(al.re - 2.0 + h2 * (k2.re - mn2), al.im + h2 * k2.im);
+    } else {
+      piv = mk(al.re - 2.0, al.im);
+      if (has3) {
+        const zd r = ly.ratio[-code - 1];
+        const zd p3 = pi_n[(long long)j * NM + mn];
+        f = g.h * (mk(1.0 - r.re, -r.im) * p3);
+      }
+    }
+    if (mn != 0) pmin = fmin(pmin, sqrt(cabs2(piv)));
+    const zd inv = cdiv(mk(1.0, 0.0), piv);
+    al = mk(-inv.re, -inv.im);
+    bb = (f - bb) * inv;
+    pi_d[(long long)(j + 1) * NM + mn] = al;
+    if (ly.layered) theta_d[(long long)(j + 1) * NM + mn] = bb;
+  }
+  rho_d[mn] = al;
+  Tout[mn] = has3 ? bb : mk(0.0, 0.0);
+  zd cp = mk(1.0, 0.0), ct = mk(0.0, 0.0);
+  for (int j = Nz; j >= 1; --j) {
+    const zd aj = pi_d[(long long)j * NM + mn];
+    pi_d[(long long)j * NM + mn] = cp;
+    zd bj = mk(0.0, 0.0);
+    if (ly.layered) {
+      bj = theta_d[(long long)j * NM + mn];
+      theta_d[(long long)j * NM + mn] = has3 ? ct : mk(0.0, 0.0);
+    }
+    ct = aj * ct + bj;
+    cp = aj * cp;
+  }
+  pi_d[mn] = cp;
+  if (ly.layered) theta_d[mn] = mk(0.0, 0.0);
+  pivmin[mn] = pmin;
+}
+
+hipError_t launch_elimination(const Geo& g, const Layers& ly, zd* rho_d, zd* T, zd* rho_n,
+                              zd* pi_d, zd* theta_d, zd* pi_n, double* pivmin,
+                              hipStream_t st) {
+  const int blk = 128;
+  hipLaunchKernelGGL(k_elimination, dim3((g.NM + blk - 1) / blk), dim3(blk), 0, st, g, ly,
+                     rho_d, T, rho_n, pi_d, theta_d, pi_n, pivmin);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Exact diagonal of the discrete single-layer operators (used by the preconditioner).
+// S_aa = sum_j K^s[j] |A1_m(j1)|^2 |A2_n(j2)|^2 with A_m(j) = sum_i w_i psi_m(x_i)
+// e^{-2 pi i j i / P} (the padded DFT of the trapezoid-weighted mode), K^s the scaled
+// spectrum.  Kinds: 0 = cos, 1 = sin.  pw1[kind][m][j1]; pw2[kind][j2][n] (transposed).
+// ---------------------------------------------------------------------------------
+__global__ void k_basis_power(Geo g, Fft box1, Fft box2, double* __restrict__ pw1,
+                              double* __restrict__ pw2) {
+  CAV_DYN_SMEM(smem_raw);
+  zd* buf = reinterpret_cast<zd*>(smem_raw);
+  const int axis = blockIdx.y >> 1, kind = blockIdx.y & 1;
+  const int m = blockIdx.x;
+  const int nmodes = axis == 0 ? g.M + 1 : g.N + 1;
+  if (m >= nmodes) return;
+  const Fft& F = axis == 0 ? box1 : box2;
+  const int P = F.p.n;
+  const int nq = axis == 0 ? g.nq1 : g.nq2;
+  const double hq = axis == 0 ? g.hq1 : g.hq2;
+  zd* a = buf;
+  zd* b = buf + P;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    zd v = mk(0.0, 0.0);
+    if (i <= nq) {
+      const long long t = ((long long)m * i) % (2LL * nq);
+      const double arg = (double)t / nq;
+      const double psi = kind == 0 ? cospi(arg) : sinpi(arg);
+      const double w = (i == 0 || i == nq) ? 0.5 * hq : hq;
+      v = mk(w * psi, 0.0);
+    }
+    a[i] = v;
+  }
+  __syncthreads();
+  zd* r = fft_lds<double, false>(a, b, F.p, F.tw, threadIdx.x, blockDim.x);
+  for (int j = threadIdx.x; j < P; j += blockDim.x) {
+    const double p = cabs2(r[j]);
+    if (axis == 0)
+      pw1[((long long)kind * (g.M + 1) + m) * P + j] = p;
+    else
+      pw2[((long long)kind * P + j) * (g.N + 1) + m] = p;
+  }
+}
+
+hipError_t launch_basis_power(const Geo& g, const Trig& t, double* pw1, double* pw2,
+                              hipStream_t st) {
+  const int rows = (g.M > g.N ? g.M : g.N) + 1;
+  const int pmax = g.P1 > g.P2 ? g.P1 : g.P2;
+  hipLaunchKernelGGL(k_basis_power, dim3(rows, 4), dim3(256), 2 * pmax * sizeof(zd), st, g,
+                     t.box1, t.box2, pw1, pw2);
+  return hipGetLastError();
+}
+
+// tmp[kind2][j1][n] = sum_j2 khat[j1][j2] pw2[kind2][j2][n]
+__global__ void k_contract_a(Geo g, const zd* __restrict__ khat, const double* __restrict__ pw2,
+                             zd* __restrict__ tmp) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j1 = blockIdx.y;
+  const int kind = blockIdx.z;
+  if (n > g.N) return;
+  double sr = 0.0, si = 0.0;
+  const zd* krow = khat + (long long)j1 * g.P2;
+  const double* col = pw2 + (long long)kind * g.P2 * (g.N + 1) + n;
+  for (int j2 = 0; j2 < g.P2; ++j2) {
+    const double p = col[(long long)j2 * (g.N + 1)];
+    const zd kv = krow[j2];
+    sr += kv.re * p;
+    si += kv.im * p;
+  }
+  tmp[((long long)kind * g.P1 + j1) * (g.N + 1) + n] = mk(sr, si);
+}
+
+// diag[f][m][n] = sum_j1 pw1[k1(f)][m][j1] tmp[k2(f)][j1][n]
+__global__ void k_contract_b(Geo g, const double* __restrict__ pw1, const zd* __restrict__ tmp,
+                             zd* __restrict__ diag) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  const int f = blockIdx.z;
+  if (n > g.N) return;
+  const int k1 = (f == 1) ? 1 : 0;   // cs: cos, sc: sin, cc: cos along x1
+  const int k2 = (f == 0) ? 1 : 0;   // cs: sin, sc: cos, cc: cos along x2
+  const double* row = pw1 + ((long long)k1 * (g.M + 1) + m) * g.P1;
+  const zd* col = tmp + (long long)k2 * g.P1 * (g.N + 1) + n;
+  double sr = 0.0, si = 0.0;
+  for (int j1 = 0; j1 < g.P1; ++j1) {
+    const double p = row[j1];
+    const zd t = col[(long long)j1 * (g.N + 1)];
+    sr += p * t.re;
+    si += p * t.im;
+  }
+  diag[(long long)f * g.NM + (long long)m * (g.N + 1) + n] = mk(sr, si);
+}
+
+hipError_t launch_diag_contract(const Geo& g, const zd* khat, const double* pw1,
+                                const double* pw2, zd* tmp, zd* diag, hipStream_t st) {
+  const int blk = 64;
+  const int gx = (g.N + 1 + blk - 1) / blk;
+  hipLaunchKernelGGL(k_contract_a, dim3(gx, g.P1, 2), dim3(blk), 0, st, g, khat, pw2, tmp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_contract_b, dim3(gx, g.M + 1, 3), dim3(blk), 0, st, g, pw1, tmp, diag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Block preconditioner: per mode the 3x3 block of the reduced aperture operator with
+// each S^f replaced by its diagonal; components outside their mode set get identity
+// rows/columns.  Stored inverted, pinv[e][mn], e = 3*row + col.
+// ---------------------------------------------------------------------------------
+__global__ void k_precond_build(Geo g, const zd* __restrict__ rho_d, const zd* __restrict__ T,
+                                const zd* __restrict__ rho_n, const zd* __restrict__ diag,
+                                zd* __restrict__ pinv) {
+  const int mn = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mn >= g.NM) return;
+  const int m = mn / (g.N + 1), n = mn % (g.N + 1);
+  const double mu = M_PI * m / g.a, nu = M_PI * n / g.b, h = g.h, k2 = g.k * g.k;
+  const double hq = h / ((m == 0 ? 0.5 : 0.25) * g.a * g.b);
+  const double hc = h / ((n == 0 ? 0.5 : 0.25) * g.a * g.b);
+  const zd dcs = diag[mn], dsc = diag[g.NM + mn], dcc = diag[2LL * g.NM + mn];
+  const zd rd = rho_d[mn], rn = rho_n[mn], t = T[mn];
+  const zd one = mk(1.0, 0.0);
+  zd A[3][3];
+  A[0][0] = (rd - one) + hq * ((2.0 * k2) * dcs - (2.0 * nu * nu) * dcc);
+  A[0][1] = (hq * 2.0 * nu * mu) * dcc;
+  A[0][2] = mu * (t + mk(h, 0.0));
+  A[1][0] = (hc * 2.0 * mu * nu) * dcc;
+  A[1][1] = (rd - one) + hc * ((2.0 * k2) * dsc - (2.0 * mu * mu) * dcc);
+  A[1][2] = nu * (t + mk(h, 0.0));
+  A[2][0] = mk(mu * h, 0.0);
+  A[2][1] = mk(nu * h, 0.0);
+  A[2][2] = rn - one;
+  const bool valid[3] = {n >= 1, m >= 1, m >= 1 && n >= 1};
+  for (int c = 0; c < 3; ++c) {
+    if (!valid[c]) {
+      for (int e = 0; e < 3; ++e) {
+        A[c][e] = mk(0.0, 0.0);
+        A[e][c] = mk(0.0, 0.0);
+      }
+      A[c][c] = one;
+    }
+  }
+  // Gauss-Jordan with partial pivoting on [A | I]
+  zd B[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) B[r][c] = (r == c) ? one : mk(0.0, 0.0);
+  for (int col = 0; col < 3; ++col) {
+    int piv = col;
+    double best = cabs2(A[col][col]);
+    for (int r = col + 1; r < 3; ++r) {
+      const double v = cabs2(A[r][col]);
+      if (v > best) {
+        best = v;
+        piv = r;
+      }
+    }
+    if (piv != col) {
+      for (int c = 0; c < 3; ++c) {
+        zd tmp = A[col][c]; A[col][c] = A[piv][c]; A[piv][c] = tmp;
+        tmp = B[col][c]; B[col][c] = B[piv][c]; B[piv][c] = tmp;
+      }
+    }
+    const zd inv = cdiv(one, A[col][col]);
+    for (int c = 0; c < 3; ++c) {
+      A[col][c] = A[col][c] * inv;
+      B[col][c] = B[col][c] * inv;
+    }
+    for (int r = 0; r < 3; ++r) {
+      if (r == col) continue;
+      const zd f = A[r][col];
+      for (int c = 0; c < 3; ++c) {
+        A[r][c] = A[r][c] - f * A[col][c];
+        B[r][c] = B[r][c] - f * B[col][c];
+      }
+    }
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) pinv[(long long)(3 * r + c) * g.NM + mn] = B[r][c];
+}
+
+hipError_t launch_precond_build(const Geo& g, const zd* rho_d, const zd* T, const zd* rho_n,
+                                const zd* diag, zd* pinv, hipStream_t st) {
+  const int blk = 128;
+  hipLaunchKernelGGL(k_precond_build, dim3((g.NM + blk - 1) / blk), dim3(blk), 0, st, g, rho_d,
+                     T, rho_n, diag, pinv);
+  return hipGetLastError();
+}
+
+}  // namespace cav

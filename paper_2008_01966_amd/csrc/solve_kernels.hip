@@ -1,0 +1,648 @@
+// Solve-time kernels: right-hand side (Section 3 (nosig), Appendix A), the matrix-free
+// reduced aperture operator with its three single-layer families applied by FFT
+// convolution (Sections 3, 5), Krylov building blocks, back-substitution and field
+// synthesis (EInter), and the aperture transforms behind the RCS (Section 7).
+//
+// Mode grids are (M+1) x (N+1), m-major (mn = m (N+1) + n).  A padded aperture vector is
+// three such grids [E1 | E2 | E3]; entries outside N1, N2, N3 stay zero.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace cav {
+
+__device__ inline zd exp_int(double w, double len) {
+  const double th = 0.5 * w * len;
+  double s, c;
+  sincos(th, &s, &c);
+  double sinc;
+  if (fabs(th) < 1e-4) {
+    const double t2 = th * th;
+    sinc = 1.0 - t2 * (1.0 / 6.0) + t2 * t2 * (1.0 / 120.0);
+  } else {
+    sinc = s / th;
+  }
+  return mk(len * c * sinc, len * s * sinc);
+}
+// int_0^len cos(f x) e^{i alpha x} dx and int_0^len sin(f x) e^{i alpha x} dx
+__device__ inline zd cos_proj(double alpha, double f, double len) {
+  return 0.5 * (exp_int(alpha + f, len) + exp_int(alpha - f, len));
+}
+__device__ inline zd sin_proj(double alpha, double f, double len) {
+  const zd d = exp_int(alpha + f, len) - exp_int(alpha - f, len);
+  return mk(0.5 * d.im, -0.5 * d.re);  // d / (2i)
+}
+
+// ---------------------------------------------------------------------------------
+// Right-hand side: g1 = (h/q) 2i (alpha1 p3 + beta p1) C_m(alpha1) S_n(alpha2) on N1,
+//                  g2 = (h/c) 2i (alpha2 p3 + beta p2) S_m(alpha1) C_n(alpha2) on N2.
+// ---------------------------------------------------------------------------------
+__global__ void k_rhs(Geo g, Wave wv, zd* __restrict__ b) {
+  const int mn = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mn >= g.NM) return;
+  const int m = mn / (g.N + 1), n = mn % (g.N + 1);
+  const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
+  zd g1 = mk(0.0, 0.0), g2 = mk(0.0, 0.0);
+  if (n >= 1) {
+    const double q = (m == 0 ? 0.5 : 0.25) * g.a * g.b;
+    const double amp = 2.0 * (wv.alpha1 * wv.p3 + wv.beta * wv.p1) * g.h / q;
+    const zd pr = cos_proj(wv.alpha1, mu, g.a) * sin_proj(wv.alpha2, nu, g.b);
+    g1 = mk(-amp * pr.im, amp * pr.re);  // i * amp * pr
+  }
+  if (m >= 1) {
+    const double c = (n == 0 ? 0.5 : 0.25) * g.a * g.b;
+    const double amp = 2.0 * (wv.alpha2 * wv.p3 + wv.beta * wv.p2) * g.h / c;
+    const zd pr = sin_proj(wv.alpha1, mu, g.a) * cos_proj(wv.alpha2, nu, g.b);
+    g2 = mk(-amp * pr.im, amp * pr.re);
+  }
+  b[mn] = g1;
+  b[g.NM + mn] = g2;
+  b[2LL * g.NM + mn] = mk(0.0, 0.0);
+}
+
+hipError_t launch_rhs(const Geo& g, const Wave& w, zd* b, hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL(k_rhs, dim3((g.NM + blk - 1) / blk), dim3(blk), 0, st, g, w, b);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// TBC single-layer families f: 0 = cos-sin (acts on E1), 1 = sin-cos (E2), 2 = cos-cos
+// (sigma = nu E1 - mu E2, the cos-cos coefficients of div_Gamma(z x E)).
+//   (S^f c)_mn = hq1 hq2 ANA1 ANA2 [ IFFT( FFT( w1 w2 SYN1 SYN2 c ) K^s ) ]
+// on the (s Nx + 1) x (s Ny + 1) trapezoid grid, zero-padded to P1 x P2.
+// Three passes: rows forward (SYN along y, FFT along y), columns (SYN, FFT, multiply,
+// inverse FFT, ANA along x), rows backward (inverse FFT along y, ANA along y).
+// ---------------------------------------------------------------------------------
+__device__ inline bool fam_xcos(int f) { return f != 1; }
+__device__ inline bool fam_ycos(int f) { return f != 0; }
+
+// Pass 1.  fam_fixed >= 0: `v` is the coefficient grid of that family (inspection path);
+// otherwise `v` is a padded aperture vector, optionally preconditioned first.
+__global__ void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2, const zd* __restrict__ pinv,
+                               int precond, int fam_fixed, const zd* __restrict__ v,
+                               zd* __restrict__ X) {
+  CAV_DYN_SMEM(smem_raw);
+  __shared__ zd c0s;
+  const int m = blockIdx.x;
+  const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
+  const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
+  const int L = g.nq2, P = g.P2;
+  zd* a = reinterpret_cast<zd*>(smem_raw);
+  zd* b = a + P;
+  const bool ycos = fam_ycos(f);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double mu = M_PI * m / g.a;
+  for (int i = tid; i < 2 * L; i += nt) a[i] = mk(0.0, 0.0);
+  __syncthreads();
+  for (int n = tid; n <= g.N; n += nt) {
+    const long long mn = (long long)m * (g.N + 1) + n;
+    zd c;
+    if (fam_fixed >= 0) {
+      c = v[mn];
+    } else {
+      zd z[3] = {v[mn], v[g.NM + mn], v[2LL * g.NM + mn]};
+      if (precond) {
+        zd y[3];
+        for (int r = 0; r < 3; ++r)
+          y[r] = pinv[(3 * r) * (long long)g.NM + mn] * z[0] +
+                 pinv[(3 * r + 1) * (long long)g.NM + mn] * z[1] +
+                 pinv[(3 * r + 2) * (long long)g.NM + mn] * z[2];
+        z[0] = y[0]; z[1] = y[1]; z[2] = y[2];
+      }
+      const double nu = M_PI * n / g.b;
+      c = f == 0 ? z[0] : (f == 1 ? z[1] : (nu * z[0] - mu * z[1]));
+    }
+    store_extension(a, L, ycos, n, c);
+    if (n == 0) c0s = c;
+  }
+  __syncthreads();
+  zd* r = fft_lds<double, false>(a, b, ext2.p, ext2.tw, tid, nt);
+  zd* o = (r == a) ? b : a;
+  for (int i = tid; i < P; i += nt) {
+    zd val = mk(0.0, 0.0);
+    if (i <= L) {
+      const zd F = r[i];
+      const zd s = ycos ? 0.5 * (F + c0s) : 0.5 * mul_i(F);
+      const double w = (i == 0 || i == L) ? 0.5 * g.hq2 : g.hq2;
+      val = w * s;
+    }
+    o[i] = val;
+  }
+  __syncthreads();
+  zd* r2 = fft_lds<double, false>(o, r, box2.p, box2.tw, tid, nt);
+  zd* dst = X + ((long long)slot * (g.M + 1) + m) * g.P2;
+  for (int k = tid; k < P; k += nt) dst[k] = r2[k];
+}
+
+// Pass 2: TK adjacent columns k2 per block, blockDim.x / TK threads per column.
+__global__ void k_tbc_cols(Geo g, Fft ext1, Fft box1, const zd* __restrict__ khat, int fam_fixed,
+                           int TK, const zd* __restrict__ X, zd* __restrict__ Y) {
+  CAV_DYN_SMEM(smem_raw);
+  __shared__ zd c0s[16];
+  const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
+  const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
+  const int tpc = blockDim.x / TK;
+  const int sub = threadIdx.x / tpc, lt = threadIdx.x % tpc;
+  const int k2 = blockIdx.x * TK + sub;
+  const bool valid = k2 < g.P2;
+  const int L = g.nq1, P = g.P1;
+  zd* a = reinterpret_cast<zd*>(smem_raw) + (long long)sub * 2 * P;
+  zd* b = a + P;
+  const bool xcos = fam_xcos(f);
+  const zd* src = X + (long long)slot * (g.M + 1) * g.P2;
+  for (int i = lt; i < 2 * L; i += tpc) a[i] = mk(0.0, 0.0);
+  __syncthreads();
+  for (int m = lt; m <= g.M; m += tpc) {
+    const zd x = valid ? src[(long long)m * g.P2 + k2] : mk(0.0, 0.0);
+    store_extension(a, L, xcos, m, x);
+    if (m == 0) c0s[sub] = x;
+  }
+  __syncthreads();
+  zd* r = fft_lds<double, false>(a, b, ext1.p, ext1.tw, lt, tpc);
+  zd* o = (r == a) ? b : a;
+  const zd c0 = c0s[sub];
+  for (int i = lt; i < P; i += tpc) {
+    zd val = mk(0.0, 0.0);
+    if (i <= L) {
+      const zd F = r[i];
+      const zd s = xcos ? 0.5 * (F + c0) : 0.5 * mul_i(F);
+      const double w = (i == 0 || i == L) ? 0.5 * g.hq1 : g.hq1;
+      val = w * s;
+    }
+    o[i] = val;
+  }
+  __syncthreads();
+  zd* r2 = fft_lds<double, false>(o, r, box1.p, box1.tw, lt, tpc);
+  for (int k1 = lt; k1 < P; k1 += tpc)
+    r2[k1] = valid ? r2[k1] * khat[(long long)k1 * g.P2 + k2] : mk(0.0, 0.0);
+  __syncthreads();
+  zd* o2 = (r2 == a) ? b : a;
+  zd* r3 = fft_lds<double, true>(r2, o2, box1.p, box1.tw, lt, tpc);
+  zd* o3 = (r3 == a) ? b : a;
+  for (int i = lt; i <= L; i += tpc) store_extension(o3, L, xcos, i, r3[i]);
+  __syncthreads();
+  zd* r4 = fft_lds<double, false>(o3, r3, ext1.p, ext1.tw, lt, tpc);
+  if (valid) {
+    zd* dst = Y + (long long)slot * (g.M + 1) * g.P2;
+    for (int m = lt; m <= g.M; m += tpc) {
+      const zd F = r4[m];
+      const zd s = xcos ? 0.5 * F : 0.5 * mul_i(F);
+      dst[(long long)m * g.P2 + k2] = g.hq1 * s;
+    }
+  }
+}
+
+// Pass 3: rows backward; writes S[slot][mn].
+__global__ void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed, const zd* __restrict__ Y,
+                               zd* __restrict__ S) {
+  CAV_DYN_SMEM(smem_raw);
+  const int m = blockIdx.x;
+  const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
+  const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
+  const int L = g.nq2, P = g.P2;
+  zd* a = reinterpret_cast<zd*>(smem_raw);
+  zd* b = a + P;
+  const bool ycos = fam_ycos(f);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const zd* src = Y + ((long long)slot * (g.M + 1) + m) * g.P2;
+  for (int k = tid; k < P; k += nt) a[k] = src[k];
+  __syncthreads();
+  zd* r = fft_lds<double, true>(a, b, box2.p, box2.tw, tid, nt);
+  zd* o = (r == a) ? b : a;
+  for (int i = tid; i <= L; i += nt) store_extension(o, L, ycos, i, r[i]);
+  __syncthreads();
+  zd* r2 = fft_lds<double, false>(o, r, ext2.p, ext2.tw, tid, nt);
+  zd* dst = S + (long long)slot * g.NM + (long long)m * (g.N + 1);
+  for (int n = tid; n <= g.N; n += nt) {
+    const zd F = r2[n];
+    const zd s = ycos ? 0.5 * F : 0.5 * mul_i(F);
+    dst[n] = g.hq2 * s;
+  }
+}
+
+// Pass 4: the local (mode-diagonal) terms of the three aperture rows plus the TBC terms.
+//  r1 = (rho_d - 1) z1 + mu (T + h) z3 + (h/q) (2k^2 S^cs z1 - 2 nu S^cc sigma)   on N1
+//  r2 = (rho_d - 1) z2 + nu (T + h) z3 + (h/c) (2k^2 S^sc z2 + 2 mu S^cc sigma)   on N2
+//  r3 = (rho_n - 1) z3 + mu h z1 + nu h z2                                        on N3
+__global__ void k_operator_epilogue(Geo g, const zd* __restrict__ rho_d, const zd* __restrict__ T,
+                                    const zd* __restrict__ rho_n, const zd* __restrict__ pinv,
+                                    int precond, const zd* __restrict__ v,
+                                    const zd* __restrict__ S, zd* __restrict__ y) {
+  const int mn = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mn >= g.NM) return;
+  const int m = mn / (g.N + 1), n = mn % (g.N + 1);
+  const double mu = M_PI * m / g.a, nu = M_PI * n / g.b, h = g.h, k2 = g.k * g.k;
+  zd z[3] = {v[mn], v[g.NM + mn], v[2LL * g.NM + mn]};
+  if (precond) {
+    zd t[3];
+    for (int r = 0; r < 3; ++r)
+      t[r] = pinv[(3 * r) * (long long)g.NM + mn] * z[0] +
+             pinv[(3 * r + 1) * (long long)g.NM + mn] * z[1] +
+             pinv[(3 * r + 2) * (long long)g.NM + mn] * z[2];
+    z[0] = t[0]; z[1] = t[1]; z[2] = t[2];
+  }
+  const zd scs = S[mn], ssc = S[g.NM + mn], scc = S[2LL * g.NM + mn];
+  const zd rd = rho_d[mn] - mk(1.0, 0.0), rn = rho_n[mn] - mk(1.0, 0.0);
+  const zd th = T[mn] + mk(h, 0.0);
+  const double hq = h / ((m == 0 ? 0.5 : 0.25) * g.a * g.b);
+  const double hc = h / ((n == 0 ? 0.5 : 0.25) * g.a * g.b);
+  zd r1 = mk(0.0, 0.0), r2 = mk(0.0, 0.0), r3 = mk(0.0, 0.0);
+  if (n >= 1) r1 = rd * z[0] + mu * (th * z[2]) + hq * ((2.0 * k2) * scs - (2.0 * nu) * scc);
+  if (m >= 1) r2 = rd * z[1] + nu * (th * z[2]) + hc * ((2.0 * k2) * ssc + (2.0 * mu) * scc);
+  if (m >= 1 && n >= 1) r3 = rn * z[2] + (mu * h) * z[0] + (nu * h) * z[1];
+  y[mn] = r1;
+  y[g.NM + mn] = r2;
+  y[2LL * g.NM + mn] = r3;
+}
+
+static int cols_per_block(int P) {
+  int tk = 8;
+  while (tk > 1 && (size_t)tk * 2 * P * sizeof(zd) > 80 * 1024) tk >>= 1;
+  return tk;
+}
+
+static hipError_t launch_tbc_passes(const Geo& g, const Trig& t, const zd* khat, const zd* pinv,
+                                    int precond, int fam_fixed, const zd* v, zd* X, zd* Y,
+                                    zd* S, hipStream_t st) {
+  const int nf = fam_fixed >= 0 ? 1 : 3;
+  hipLaunchKernelGGL(k_tbc_rows_fwd, dim3(g.M + 1, nf), dim3(256), 2 * g.P2 * sizeof(zd), st, g,
+                     t.ext2, t.box2, pinv, precond, fam_fixed, v, X);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int tk = cols_per_block(g.P1);
+  hipLaunchKernelGGL(k_tbc_cols, dim3((g.P2 + tk - 1) / tk, nf), dim3(256),
+                     (size_t)tk * 2 * g.P1 * sizeof(zd), st, g, t.ext1, t.box1, khat, fam_fixed,
+                     tk, X, Y);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tbc_rows_bwd, dim3(g.M + 1, nf), dim3(256), 2 * g.P2 * sizeof(zd), st, g,
+                     t.ext2, t.box2, fam_fixed, Y, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const zd* rho_d,
+                           const zd* T, const zd* rho_n, const zd* pinv, int precond,
+                           const zd* v, zd* X, zd* Y, zd* S, zd* y, hipStream_t st) {
+  hipError_t e = launch_tbc_passes(g, t, khat, pinv, precond, -1, v, X, Y, S, st);
+  if (e != hipSuccess) return e;
+  const int blk = 256;
+  hipLaunchKernelGGL(k_operator_epilogue, dim3((g.NM + blk - 1) / blk), dim3(blk), 0, st, g,
+                     rho_d, T, rho_n, pinv, precond, v, S, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_single_family(const Geo& g, const Trig& t, const zd* khat, int family,
+                                const zd* in, zd* X, zd* Y, zd* out, hipStream_t st) {
+  return launch_tbc_passes(g, t, khat, nullptr, 0, family, in, X, Y, out, st);
+}
+
+// ---------------------------------------------------------------------------------
+// Krylov building blocks (deterministic two-stage reductions).
+// ---------------------------------------------------------------------------------
+constexpr int kDotGroup = 8;
+
+__global__ void k_dots(const zd* __restrict__ V, long long ldv, int nv, const zd* __restrict__ w,
+                       long long n, zd* __restrict__ partial) {
+  __shared__ zd red[kDotGroup][256];
+  const int grp = blockIdx.y;
+  zd acc[kDotGroup];
+  for (int t = 0; t < kDotGroup; ++t) acc[t] = mk(0.0, 0.0);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const zd wi = w[i];
+    for (int t = 0; t < kDotGroup; ++t) {
+      const int vi = grp * kDotGroup + t;
+      if (vi < nv) acc[t] = acc[t] + conj(V[vi * ldv + i]) * wi;
+    }
+  }
+  for (int t = 0; t < kDotGroup; ++t) red[t][threadIdx.x] = acc[t];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int t = 0; t < kDotGroup; ++t)
+        red[t][threadIdx.x] = red[t][threadIdx.x] + red[t][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < kDotGroup) {
+    const int vi = grp * kDotGroup + threadIdx.x;
+    if (vi < nv) partial[(long long)vi * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
+  }
+}
+
+__global__ void k_reduce_cols(const zd* __restrict__ partial, int nblk, zd* __restrict__ out) {
+  __shared__ zd red[256];
+  const int vi = blockIdx.x;
+  zd acc = mk(0.0, 0.0);
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc = acc + partial[(long long)vi * nblk + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[vi] = red[0];
+}
+
+hipError_t launch_dots(const zd* V, long long ldv, int nv, const zd* w, long long n,
+                       zd* partial, int nblk, zd* h, hipStream_t st) {
+  const int ng = (nv + kDotGroup - 1) / kDotGroup;
+  hipLaunchKernelGGL(k_dots, dim3(nblk, ng), dim3(256), 0, st, V, ldv, nv, w, n, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_cols, dim3(nv), dim3(256), 0, st, partial, nblk, h);
+  return hipGetLastError();
+}
+
+__global__ void k_update(const zd* __restrict__ V, long long ldv, int nv, const zd* __restrict__ h,
+                         zd* __restrict__ w, long long n) {
+  __shared__ zd hs[256];
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[i];
+  __syncthreads();
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    zd acc = w[i];
+    for (int vi = 0; vi < nv; ++vi) acc = acc - hs[vi] * V[vi * ldv + i];
+    w[i] = acc;
+  }
+}
+
+hipError_t launch_update(const zd* V, long long ldv, int nv, const zd* h, zd* w, long long n,
+                         hipStream_t st) {
+  int nblk = (int)((n + 255) / 256);
+  if (nblk > 2048) nblk = 2048;
+  hipLaunchKernelGGL(k_update, dim3(nblk), dim3(256), 0, st, V, ldv, nv, h, w, n);
+  return hipGetLastError();
+}
+
+__global__ void k_norm2(const zd* __restrict__ w, long long n, double* __restrict__ partial) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    acc += cabs2(w[i]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_reduce_d(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+hipError_t launch_norm2(const zd* w, long long n, double* partial, int nblk, double* out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_norm2, dim3(nblk), dim3(256), 0, st, w, n, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_d, dim3(1), dim3(256), 0, st, partial, nblk, out);
+  return hipGetLastError();
+}
+
+// v = w / sqrt(nrm2[0]); v may alias w (element-wise, same index).
+__global__ void k_scale_copy(const zd* w, const double* __restrict__ nrm2, zd* v, long long n) {
+  const double s2 = nrm2[0];
+  const double sc = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    v[i] = sc * w[i];
+}
+
+hipError_t launch_scale_copy(const zd* w, const double* nrm2, zd* v, long long n,
+                             hipStream_t st) {
+  int nblk = (int)((n + 255) / 256);
+  if (nblk > 4096) nblk = 4096;
+  hipLaunchKernelGGL(k_scale_copy, dim3(nblk), dim3(256), 0, st, w, nrm2, v, n);
+  return hipGetLastError();
+}
+
+__global__ void k_sub(const zd* __restrict__ b, const zd* __restrict__ w, zd* __restrict__ r,
+                      long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    r[i] = b[i] - w[i];
+}
+
+hipError_t launch_sub(const zd* b, const zd* w, zd* r, long long n, hipStream_t st) {
+  int nblk = (int)((n + 255) / 256);
+  if (nblk > 4096) nblk = 4096;
+  hipLaunchKernelGGL(k_sub, dim3(nblk), dim3(256), 0, st, b, w, r, n);
+  return hipGetLastError();
+}
+
+// x += P^{-1} (sum_i y_i V_i)
+__global__ void k_combine(Geo g, const zd* __restrict__ V, long long ldv, int nv,
+                          const zd* __restrict__ y, const zd* __restrict__ pinv,
+                          zd* __restrict__ x) {
+  __shared__ zd ys[256];
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) ys[i] = y[i];
+  __syncthreads();
+  const int mn = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mn >= g.NM) return;
+  zd u[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+  for (int vi = 0; vi < nv; ++vi) {
+    const zd* col = V + vi * ldv;
+    for (int c = 0; c < 3; ++c) u[c] = u[c] + ys[vi] * col[(long long)c * g.NM + mn];
+  }
+  for (int r = 0; r < 3; ++r) {
+    const zd z = pinv[(3 * r) * (long long)g.NM + mn] * u[0] +
+                 pinv[(3 * r + 1) * (long long)g.NM + mn] * u[1] +
+                 pinv[(3 * r + 2) * (long long)g.NM + mn] * u[2];
+    x[(long long)r * g.NM + mn] = x[(long long)r * g.NM + mn] + z;
+  }
+}
+
+hipError_t launch_combine(const Geo& g, const zd* V, long long ldv, int nv, const zd* y,
+                          const zd* pinv, zd* x, hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL(k_combine, dim3((g.NM + blk - 1) / blk), dim3(blk), 0, st, g, V, ldv, nv, y,
+                     pinv, x);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Back-substitution and synthesis (EInter): at level j the mode values are
+//   E1 = Pi_j a1 + mu_m Theta_j a3,  E2 = Pi_j a2 + nu_n Theta_j a3,  E3 = Pi3_j a3,
+// then the 2D sine/cosine series is summed on the output nodes: rows along y, then
+// columns along x with TK adjacent columns per block.
+// tbuf[l][jj][m][i2], jj = j - j0.
+// ---------------------------------------------------------------------------------
+__global__ void k_synth_rows(Geo g, Fft out2, const zd* __restrict__ pi_d,
+                             const zd* __restrict__ theta_d, const zd* __restrict__ pi_n,
+                             const zd* __restrict__ xap, int j0, int jn, zd* __restrict__ tbuf) {
+  CAV_DYN_SMEM(smem_raw);
+  __shared__ zd c0s;
+  const int m = blockIdx.x, jj = blockIdx.y, l = blockIdx.z;
+  const int j = j0 + jj;
+  const int L = g.ny;
+  zd* a = reinterpret_cast<zd*>(smem_raw);
+  zd* b = a + 2 * L;
+  const bool ycos = (l == 1);  // E1: sin, E2: cos, E3: sin along y
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double mu = M_PI * m / g.a;
+  for (int i = tid; i < 2 * L; i += nt) a[i] = mk(0.0, 0.0);
+  __syncthreads();
+  const long long NM = g.NM;
+  for (int n = tid; n <= g.N; n += nt) {
+    const long long mn = (long long)m * (g.N + 1) + n;
+    zd c;
+    if (l < 2) {
+      c = pi_d[(long long)j * NM + mn] * xap[l * NM + mn];
+      if (theta_d) {
+        const double fac = l == 0 ? mu : M_PI * n / g.b;
+        c = c + fac * (theta_d[(long long)j * NM + mn] * xap[2 * NM + mn]);
+      }
+    } else {
+      c = pi_n[(long long)j * NM + mn] * xap[2 * NM + mn];
+    }
+    store_extension(a, L, ycos, n, c);
+    if (n == 0) c0s = c;
+  }
+  __syncthreads();
+  zd* r = fft_lds<double, false>(a, b, out2.p, out2.tw, tid, nt);
+  zd* dst = tbuf + (((long long)l * jn + jj) * (g.M + 1) + m) * (g.ny + 1);
+  for (int i = tid; i <= L; i += nt) {
+    const zd F = r[i];
+    dst[i] = ycos ? 0.5 * (F + c0s) : 0.5 * mul_i(F);
+  }
+}
+
+__global__ void k_synth_cols(Geo g, Fft out1, int TK, int j0, int jn, const zd* __restrict__ tbuf,
+                             zd* __restrict__ eout) {
+  CAV_DYN_SMEM(smem_raw);
+  __shared__ zd c0s[16];
+  const int jj = blockIdx.y, l = blockIdx.z;
+  const int j = j0 + jj;
+  const int tpc = blockDim.x / TK;
+  const int sub = threadIdx.x / tpc, lt = threadIdx.x % tpc;
+  const int i2 = blockIdx.x * TK + sub;
+  const bool valid = i2 <= g.ny;
+  const int L = g.nx;
+  zd* a = reinterpret_cast<zd*>(smem_raw) + (long long)sub * 4 * L;
+  zd* b = a + 2 * L;
+  const bool xcos = (l == 0);  // E1: cos, E2: sin, E3: sin along x
+  const zd* src = tbuf + ((long long)l * jn + jj) * (g.M + 1) * (g.ny + 1);
+  for (int i = lt; i < 2 * L; i += tpc) a[i] = mk(0.0, 0.0);
+  __syncthreads();
+  for (int m = lt; m <= g.M; m += tpc) {
+    const zd x = valid ? src[(long long)m * (g.ny + 1) + i2] : mk(0.0, 0.0);
+    store_extension(a, L, xcos, m, x);
+    if (m == 0) c0s[sub] = x;
+  }
+  __syncthreads();
+  zd* r = fft_lds<double, false>(a, b, out1.p, out1.tw, lt, tpc);
+  if (valid) {
+    const zd c0 = c0s[sub];
+    zd* dst = eout + (((long long)l * (g.Nz + 1) + j) * (g.ny + 1) + i2) * (g.nx + 1);
+    for (int i = lt; i <= L; i += tpc) {
+      const zd F = r[i];
+      dst[i] = xcos ? 0.5 * (F + c0) : 0.5 * mul_i(F);
+    }
+  }
+}
+
+hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const zd* theta_d,
+                            const zd* pi_n, const zd* xap, int j0, int j1, zd* tbuf, zd* eout,
+                            hipStream_t st) {
+  const int jn = j1 - j0;
+  hipLaunchKernelGGL(k_synth_rows, dim3(g.M + 1, jn, 3), dim3(256), 4 * g.ny * sizeof(zd), st, g,
+                     t.out2, pi_d, theta_d, pi_n, xap, j0, jn, tbuf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int tk = 8;
+  while (tk > 1 && (size_t)tk * 4 * g.nx * sizeof(zd) > 64 * 1024) tk >>= 1;
+  hipLaunchKernelGGL(k_synth_cols, dim3((g.ny + 1 + tk - 1) / tk, jn, 3), dim3(256),
+                     (size_t)tk * 4 * g.nx * sizeof(zd), st, g, t.out1, tk, j0, jn, tbuf, eout);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Aperture transforms E^1(u) = sum E1_mn C_m(-u1) S_n(-u2), E^2(u) = sum E2_mn S_m(-u1) C_n(-u2)
+// ---------------------------------------------------------------------------------
+__global__ void k_rcs_partial(Geo g, const zd* __restrict__ xap, double u1, double u2,
+                              zd* __restrict__ partial) {
+  __shared__ zd red[2][256];
+  zd s1 = mk(0.0, 0.0), s2 = mk(0.0, 0.0);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long mn = (long long)blockIdx.x * blockDim.x + threadIdx.x; mn < g.NM; mn += stride) {
+    const int m = (int)(mn / (g.N + 1)), n = (int)(mn % (g.N + 1));
+    const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
+    if (n >= 1) s1 = s1 + xap[mn] * (cos_proj(-u1, mu, g.a) * sin_proj(-u2, nu, g.b));
+    if (m >= 1) s2 = s2 + xap[g.NM + mn] * (sin_proj(-u1, mu, g.a) * cos_proj(-u2, nu, g.b));
+  }
+  red[0][threadIdx.x] = s1;
+  red[1][threadIdx.x] = s2;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[0][threadIdx.x] = red[0][threadIdx.x] + red[0][threadIdx.x + s];
+      red[1][threadIdx.x] = red[1][threadIdx.x] + red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = red[0][0];
+    partial[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+hipError_t launch_rcs_partial(const Geo& g, const zd* xap, double u1, double u2, zd* partial,
+                              int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_rcs_partial, dim3(nblk), dim3(256), 0, st, g, xap, u1, u2, partial);
+  return hipGetLastError();
+}
+
+// Padded (three mode grids) <-> compact paper order (E1 on N1, E2 on N2, E3 on N3).
+__device__ inline long long compact_index(const Geo& g, int c, int m, int n) {
+  const long long M = g.M, N = g.N;
+  if (c == 0) return (n >= 1) ? m * N + (n - 1) : -1;
+  if (c == 1) return (m >= 1) ? (M + 1) * N + (m - 1) * (N + 1) + n : -1;
+  return (m >= 1 && n >= 1) ? (M + 1) * N + M * (N + 1) + (m - 1) * N + (n - 1) : -1;
+}
+
+__global__ void k_pack(Geo g, const zd* __restrict__ xpad, zd* __restrict__ xc) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3LL * g.NM) return;
+  const int c = (int)(i / g.NM);
+  const int mn = (int)(i % g.NM);
+  const long long ci = compact_index(g, c, mn / (g.N + 1), mn % (g.N + 1));
+  if (ci >= 0) xc[ci] = xpad[i];
+}
+
+__global__ void k_unpack(Geo g, const zd* __restrict__ xc, zd* __restrict__ xpad) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3LL * g.NM) return;
+  const int c = (int)(i / g.NM);
+  const int mn = (int)(i % g.NM);
+  const long long ci = compact_index(g, c, mn / (g.N + 1), mn % (g.N + 1));
+  xpad[i] = ci >= 0 ? xc[ci] : mk(0.0, 0.0);
+}
+
+hipError_t launch_pack(const Geo& g, const zd* xpad, zd* xcompact, hipStream_t st) {
+  const long long n = 3LL * g.NM;
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, xpad,
+                     xcompact);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Geo& g, const zd* xcompact, zd* xpad, hipStream_t st) {
+  const long long n = 3LL * g.NM;
+  hipLaunchKernelGGL(k_unpack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, xcompact,
+                     xpad);
+  return hipGetLastError();
+}
+
+}  // namespace cav

@@ -1,0 +1,89 @@
+"""C-ABI library checks that need no GPU: the shared library loads, exports every entry
+point include/cavity.h declares, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2008_01966_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "cavity.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cavity_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    syms = declared_symbols()
+    for name in ("cavity_plan_create", "cavity_solve", "cavity_rcs", "cavity_solve_batch"):
+        assert name in syms
+    assert sorted(P.EXPORTS) == syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load_library()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_defaults_and_status_strings():
+    lib = P.load_library()
+    o = P.Opts()
+    assert lib.cavity_opts_default(ctypes.byref(o)) == 0
+    assert (o.precision, o.tbc_oversample, o.restart) == (0, 1, 60)
+    assert o.tol == 1e-12 and o.max_iter == 400
+    assert lib.cavity_status_string(0) == b"ok"
+    assert lib.cavity_status_string(3) == b"resonant z-elimination pivot"
+
+
+def _create(a=1.0, b=1.0, c=0.5, nx=16, ny=16, nz=8, eps=None, k=6.28, opts=None):
+    lib = P.load_library()
+    h = ctypes.c_void_p()
+    st = lib.cavity_plan_create(a, b, c, nx, ny, nz, eps, k,
+                                ctypes.byref(opts) if opts is not None else None,
+                                ctypes.byref(h))
+    return st, h, lib.cavity_last_error().decode()
+
+
+@pytest.mark.parametrize("kw", [dict(a=-1.0), dict(c=0.0), dict(k=0.0), dict(nx=1), dict(nz=0),
+                                dict(nx=14), dict(ny=7)])
+def test_invalid_arguments_rejected(kw):
+    st, h, msg = _create(**kw)
+    assert st == 1 and not h.value and msg
+
+
+def test_invalid_layers_rejected():
+    nzs = (ctypes.c_int * 2)(3, 4)
+    eps = (P.C128 * 2)(P.C128(1, 0), P.C128(2, 0))
+    stack = P.EpsStack(2, nzs, eps)
+    st, h, msg = _create(nz=8, eps=ctypes.pointer(stack))
+    assert st == 1 and "sum" in msg
+    nzs0 = (ctypes.c_int * 2)(0, 8)
+    st, h, msg = _create(nz=8, eps=ctypes.pointer(P.EpsStack(2, nzs0, eps)))
+    assert st == 1
+
+
+def test_invalid_options_rejected():
+    lib = P.load_library()
+    o = P.Opts()
+    lib.cavity_opts_default(ctypes.byref(o))
+    o.restart = 0
+    assert _create(opts=o)[0] == 1
+    lib.cavity_opts_default(ctypes.byref(o))
+    o.precision = 1
+    assert _create(opts=o)[0] == 6
+    lib.cavity_opts_default(ctypes.byref(o))
+    o.tbc_oversample = 0
+    assert _create(opts=o)[0] == 1
+
+
+def test_null_arguments_rejected():
+    lib = P.load_library()
+    assert lib.cavity_solve(None, 0.1, 0.0, 0, None) == 1
+    assert lib.cavity_rcs(None, 0, 0, None, None, None) == 1
+    assert lib.cavity_plan_info(None, None) == 1
+    lib.cavity_plan_destroy(None)

@@ -143,6 +143,22 @@ void cavity_plan_destroy(cavity_plan plan);
 const char* cavity_status_string(int status);
 const char* cavity_last_error(void);
 
+/* ---- Kernel timing probe (benchmarking) ------------------------------------------
+ * Process-wide.  cavity_probe_kernel(which, capacity) starts watching one kernel
+ * (CAVITY_K_*; which < 0 stops and frees the probe): each of its next `capacity`
+ * launches, from any plan, is bracketed by HIP events on its launch stream and tagged
+ * with its algorithmic byte count (the data the launch must read and write).
+ * cavity_probe_read() waits for the recorded events and returns the number of launches,
+ * their summed device time in ms and their summed algorithmic bytes.  Errors:
+ * CAVITY_EINVAL, CAVITY_ENOMEM (more launches than capacity), CAVITY_EDEVICE. */
+enum {
+  CAVITY_K_SPECTRUM = 0, CAVITY_K_ELIMINATION = 1, CAVITY_K_TBC_ROWS_FWD = 2,
+  CAVITY_K_TBC_COLS = 3, CAVITY_K_TBC_ROWS_BWD = 4, CAVITY_K_EPILOGUE = 5,
+  CAVITY_K_SYNTH_ROWS = 6, CAVITY_K_SYNTH_COLS = 7
+};
+int cavity_probe_kernel(int which, int capacity);
+int cavity_probe_read(int* launches, double* total_ms, double* total_bytes);
+
 /* ---- Inspection of individual steps (host in, host out; for parity testing) ------
  * Mode-grid arrays are (M+1) x (N+1), m-major; entries outside a component's mode set
  * are zero. */

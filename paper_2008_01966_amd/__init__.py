@@ -62,8 +62,11 @@ EXPORTS = [
     "cavity_rcs", "cavity_aperture", "cavity_plan_info", "cavity_plan_destroy",
     "cavity_status_string", "cavity_last_error", "cavity_debug_columns",
     "cavity_debug_profiles", "cavity_debug_spectrum", "cavity_debug_tbc",
-    "cavity_debug_operator", "cavity_debug_rhs",
+    "cavity_debug_operator", "cavity_debug_rhs", "cavity_probe_kernel", "cavity_probe_read",
 ]
+
+KERNELS = {"spectrum": 0, "elimination": 1, "tbc_rows_fwd": 2, "tbc_cols": 3,
+           "tbc_rows_bwd": 4, "epilogue": 5, "synth_rows": 6, "synth_cols": 7}
 
 _lib = None
 
@@ -100,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cavity_debug_tbc.argtypes = [vp, i, P(C128), P(C128)]
     lib.cavity_debug_operator.argtypes = [vp, P(C128), P(C128)]
     lib.cavity_debug_rhs.argtypes = [vp, d, d, i, P(C128), P(C128)]
+    lib.cavity_probe_kernel.argtypes = [i, i]
+    lib.cavity_probe_read.argtypes = [P(i), P(d), P(d)]
     for name in EXPORTS:
         if name not in ("cavity_plan_destroy", "cavity_status_string", "cavity_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -266,3 +271,17 @@ class Plan:
         _check(self._lib.cavity_debug_rhs(self._h, float(theta), float(phi), int(pol), _cbuf(g1),
                                           _cbuf(g2)))
         return g1, g2
+
+
+def probe_start(kernel: str, capacity: int = 100000):
+    """Start timing every launch of one kernel (HIP events on its launch stream)."""
+    _check(load_library().cavity_probe_kernel(KERNELS[kernel], int(capacity)))
+
+
+def probe_stop():
+    """Return (launches, total device ms, total algorithmic bytes) and stop the probe."""
+    lib = load_library()
+    n, ms, by = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    _check(lib.cavity_probe_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    _check(lib.cavity_probe_kernel(-1, 0))
+    return n.value, ms.value, by.value

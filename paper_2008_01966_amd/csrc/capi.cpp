@@ -59,6 +59,37 @@ cav::FftPlan make_fft_plan(int n) {
 
 }  // namespace
 
+// ---- kernel timing probe (process-wide) ------------------------------------------------
+namespace cav {
+namespace {
+struct ProbeState {
+  int which = -1;
+  std::vector<hipEvent_t> pool;       // pairs: 2i = start, 2i+1 = stop
+  std::vector<double> bytes;          // per recorded launch
+  size_t used = 0;                    // launches recorded
+  bool overflow = false;
+};
+ProbeState g_probe;
+}  // namespace
+
+void probe_begin(int id, hipStream_t st) {
+  if (id != g_probe.which) return;
+  if (2 * g_probe.used + 1 >= g_probe.pool.size()) {
+    g_probe.overflow = true;
+    return;
+  }
+  (void)hipEventRecord(g_probe.pool[2 * g_probe.used], st);
+}
+
+void probe_end(int id, hipStream_t st, double bytes) {
+  if (id != g_probe.which) return;
+  if (2 * g_probe.used + 1 >= g_probe.pool.size()) return;
+  (void)hipEventRecord(g_probe.pool[2 * g_probe.used + 1], st);
+  g_probe.bytes.push_back(bytes);
+  ++g_probe.used;
+}
+}  // namespace cav
+
 struct cavity_plan_s {
   cav::Geo g{};
   cav::Trig trig{};
@@ -663,6 +694,36 @@ int cavity_rcs(cavity_plan p, int idx, int n_obs, const double* th, const double
     sigma[2 * i] = k * k / M_PI * std::norm(phiL);
     sigma[2 * i + 1] = k * k / M_PI * std::norm(thL);
   }
+  return CAVITY_OK;
+}
+
+int cavity_probe_kernel(int which, int capacity) {
+  using cav::g_probe;
+  for (hipEvent_t e : g_probe.pool) (void)hipEventDestroy(e);
+  g_probe = cav::ProbeState();
+  if (which < 0) return CAVITY_OK;
+  if (which >= cav::K_COUNT || capacity < 1) return fail(CAVITY_EINVAL, "bad probe arguments");
+  g_probe.pool.resize(2 * (size_t)capacity + 2);
+  for (auto& e : g_probe.pool) HIPCHK(hipEventCreate(&e));
+  g_probe.which = which;
+  return CAVITY_OK;
+}
+
+int cavity_probe_read(int* launches, double* total_ms, double* total_bytes) {
+  using cav::g_probe;
+  if (!launches || !total_ms || !total_bytes) return fail(CAVITY_EINVAL, "NULL argument");
+  if (g_probe.overflow) return fail(CAVITY_ENOMEM, "probe capacity exceeded");
+  double ms = 0.0, by = 0.0;
+  for (size_t i = 0; i < g_probe.used; ++i) {
+    HIPCHK(hipEventSynchronize(g_probe.pool[2 * i + 1]));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, g_probe.pool[2 * i], g_probe.pool[2 * i + 1]));
+    ms += t;
+    by += g_probe.bytes[i];
+  }
+  *launches = (int)g_probe.used;
+  *total_ms = ms;
+  *total_bytes = by;
   return CAVITY_OK;
 }
 

@@ -45,6 +45,17 @@ struct Wave {
   double p1, p2, p3;
 };
 
+// ---- timing probe ----------------------------------------------------------------
+// Kernel identifiers for the benchmark probe (cavity_probe_* in the C ABI).
+enum KernelId {
+  K_SPECTRUM = 0, K_ELIMINATION = 1, K_TBC_ROWS_FWD = 2, K_TBC_COLS = 3, K_TBC_ROWS_BWD = 4,
+  K_EPILOGUE = 5, K_SYNTH_ROWS = 6, K_SYNTH_COLS = 7, K_COUNT = 8
+};
+// While the probe watches kernel `id`, these bracket its launches with HIP events on the
+// launch stream and record the launch's algorithmic bytes; otherwise they do nothing.
+void probe_begin(int id, hipStream_t st);
+void probe_end(int id, hipStream_t st, double bytes);
+
 // ---- plan-time kernels ------------------------------------------------------------
 hipError_t launch_spectrum(const Geo& g, double R, double scale, zd* khat, hipStream_t st);
 hipError_t launch_elimination(const Geo& g, const Layers& ly, zd* rho_d, zd* T, zd* rho_n,

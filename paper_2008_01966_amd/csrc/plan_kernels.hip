@@ -55,7 +55,9 @@ __global__ void k_spectrum(Geo g, double R, double scale, zd* __restrict__ khat)
 hipError_t launch_spectrum(const Geo& g, double R, double scale, zd* khat, hipStream_t st) {
   dim3 blk(64, 4);
   dim3 grd((g.P2 / 2 + 1 + blk.x - 1) / blk.x, (g.P1 / 2 + 1 + blk.y - 1) / blk.y);
+  probe_begin(K_SPECTRUM, st);
   hipLaunchKernelGGL(k_spectrum, grd, blk, 0, st, g, R, scale, khat);
+  probe_end(K_SPECTRUM, st, sizeof(zd) * (double)g.P1 * g.P2);
   return hipGetLastError();
 }
 
@@ -172,8 +174,12 @@ hipError_t launch_elimination(const Geo& g, const Layers& ly, zd* rho_d, zd* T, 
                               zd* pi_d, zd* theta_d, zd* pi_n, double* pivmin,
                               hipStream_t st) {
   const int blk = 128;
+  probe_begin(K_ELIMINATION, st);
   hipLaunchKernelGGL(k_elimination, dim3((g.NM + blk - 1) / blk), dim3(blk), 0, st, g, ly,
                      rho_d, T, rho_n, pi_d, theta_d, pi_n, pivmin);
+  // profiles written once (Pi, Pi3, and Theta when layered) plus the Schur data
+  probe_end(K_ELIMINATION, st,
+            sizeof(zd) * (double)g.NM * ((g.Nz + 1.0) * (ly.layered ? 3.0 : 2.0) + 3.0));
   return hipGetLastError();
 }
 

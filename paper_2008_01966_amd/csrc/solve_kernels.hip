@@ -266,18 +266,27 @@ static hipError_t launch_tbc_passes(const Geo& g, const Trig& t, const zd* khat,
                                     int precond, int fam_fixed, const zd* v, zd* X, zd* Y,
                                     zd* S, hipStream_t st) {
   const int nf = fam_fixed >= 0 ? 1 : 3;
+  const double zb = sizeof(zd);
+  const double xbytes = zb * nf * (g.M + 1) * (double)g.P2;   // one X or Y workspace
+  const double vin = zb * (fam_fixed >= 0 ? 1.0 : 3.0) * g.NM + (precond ? zb * 9.0 * g.NM : 0.0);
+  probe_begin(K_TBC_ROWS_FWD, st);
   hipLaunchKernelGGL(k_tbc_rows_fwd, dim3(g.M + 1, nf), dim3(256), 2 * g.P2 * sizeof(zd), st, g,
                      t.ext2, t.box2, pinv, precond, fam_fixed, v, X);
+  probe_end(K_TBC_ROWS_FWD, st, vin + xbytes);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int tk = cols_per_block(g.P1);
+  probe_begin(K_TBC_COLS, st);
   hipLaunchKernelGGL(k_tbc_cols, dim3((g.P2 + tk - 1) / tk, nf), dim3(256),
                      (size_t)tk * 2 * g.P1 * sizeof(zd), st, g, t.ext1, t.box1, khat, fam_fixed,
                      tk, X, Y);
+  probe_end(K_TBC_COLS, st, 2.0 * xbytes + zb * (double)g.P1 * g.P2);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  probe_begin(K_TBC_ROWS_BWD, st);
   hipLaunchKernelGGL(k_tbc_rows_bwd, dim3(g.M + 1, nf), dim3(256), 2 * g.P2 * sizeof(zd), st, g,
                      t.ext2, t.box2, fam_fixed, Y, S);
+  probe_end(K_TBC_ROWS_BWD, st, xbytes + zb * nf * g.NM);
   return hipGetLastError();
 }
 
@@ -287,8 +296,10 @@ hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const zd
   hipError_t e = launch_tbc_passes(g, t, khat, pinv, precond, -1, v, X, Y, S, st);
   if (e != hipSuccess) return e;
   const int blk = 256;
+  probe_begin(K_EPILOGUE, st);
   hipLaunchKernelGGL(k_operator_epilogue, dim3((g.NM + blk - 1) / blk), dim3(blk), 0, st, g,
                      rho_d, T, rho_n, pinv, precond, v, S, y);
+  probe_end(K_EPILOGUE, st, sizeof(zd) * (double)g.NM * (12.0 + (precond ? 9.0 : 0.0)));
   return hipGetLastError();
 }
 
@@ -558,14 +569,21 @@ hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const z
                             const zd* pi_n, const zd* xap, int j0, int j1, zd* tbuf, zd* eout,
                             hipStream_t st) {
   const int jn = j1 - j0;
+  const double zb = sizeof(zd);
+  const double tb = zb * 3.0 * jn * (g.M + 1) * (double)(g.ny + 1);   // staging slab
+  const double prof = zb * (double)jn * g.NM * (theta_d ? 3.0 : 2.0);
+  probe_begin(K_SYNTH_ROWS, st);
   hipLaunchKernelGGL(k_synth_rows, dim3(g.M + 1, jn, 3), dim3(256), 4 * g.ny * sizeof(zd), st, g,
                      t.out2, pi_d, theta_d, pi_n, xap, j0, jn, tbuf);
+  probe_end(K_SYNTH_ROWS, st, prof + zb * 3.0 * g.NM + tb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   int tk = 8;
   while (tk > 1 && (size_t)tk * 4 * g.nx * sizeof(zd) > 64 * 1024) tk >>= 1;
+  probe_begin(K_SYNTH_COLS, st);
   hipLaunchKernelGGL(k_synth_cols, dim3((g.ny + 1 + tk - 1) / tk, jn, 3), dim3(256),
                      (size_t)tk * 4 * g.nx * sizeof(zd), st, g, t.out1, tk, j0, jn, tbuf, eout);
+  probe_end(K_SYNTH_COLS, st, tb + zb * 3.0 * jn * (g.ny + 1) * (double)(g.nx + 1));
   return hipGetLastError();
 }
 

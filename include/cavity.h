@@ -86,6 +86,7 @@ typedef struct {
   int restart;          /* GMRES restart length, 1..200 (default 60) */
   size_t hbm_budget;    /* bytes the plan may allocate; 0 = 90 % of free device memory */
   void* stream;         /* hipStream_t for all work of the plan; NULL = default stream */
+  int batch;            /* right-hand sides iterated together in lockstep, 1..64 (default 8) */
 } cavity_opts;
 
 /* Plan description and the statistics of its last solve. */
@@ -121,8 +122,8 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
  * CAVITY_EDEVICE. */
 int cavity_solve(cavity_plan plan, double theta, double phi, int pol, cavity_c128* E_out);
 
-/* Solve nrhs plane waves (host arrays theta, phi, pol) one after another on the plan's
- * stream.  E_out (device) holds nrhs consecutive fields or is NULL; aperture_out
+/* Solve nrhs plane waves (host arrays theta, phi, pol) on the plan's stream, opts.batch
+ * of them at a time iterating together (every kernel launch serves the whole group).  E_out (device) holds nrhs consecutive fields or is NULL; aperture_out
  * (device) holds nrhs consecutive aperture vectors of n_ap entries or is NULL.  The plan
  * keeps every aperture solution (indices 0..nrhs-1) for cavity_rcs. */
 int cavity_solve_batch(cavity_plan plan, int nrhs, const double* theta, const double* phi,

@@ -43,7 +43,8 @@ class EpsStack(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("tbc_oversample", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
-                ("hbm_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+                ("hbm_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p),
+                ("batch", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -135,7 +136,8 @@ class Plan:
                  layer_nz: Optional[Sequence[int]] = None,
                  layer_eps: Optional[Sequence[complex]] = None, k: float = 2 * np.pi, *,
                  tol: float = 1e-12, restart: int = 60, max_iter: int = 400,
-                 oversample: int = 1, hbm_budget: int = 0, stream: Optional[int] = None):
+                 oversample: int = 1, hbm_budget: int = 0, stream: Optional[int] = None,
+                 batch: int = 8):
         lib = load_library()
         self._lib = lib
         self.a, self.b, self.c = float(a), float(b), float(c)
@@ -145,6 +147,7 @@ class Plan:
         opts.tol, opts.restart, opts.max_iter = float(tol), int(restart), int(max_iter)
         opts.tbc_oversample = int(oversample)
         opts.hbm_budget = int(hbm_budget)
+        opts.batch = int(batch)
         if stream is None:
             torch = _torch()
             stream = torch.cuda.current_stream().cuda_stream

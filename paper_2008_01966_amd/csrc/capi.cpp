@@ -7,7 +7,9 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -90,6 +92,104 @@ void probe_end(int id, hipStream_t st, double bytes) {
 }
 }  // namespace cav
 
+// ---- device memory: one arena per plan part, with a process-wide cache -------------
+// Freed arenas are kept (up to a bound) and handed to later plans of similar size, so
+// creating plans repeatedly (new geometries, served requests) does not pay hipMalloc.
+namespace {
+
+struct CachedBlock {
+  void* ptr;
+  size_t bytes;
+  int device;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;
+size_t g_cache_bytes = 0;
+const size_t kCacheLimit = (size_t)32 << 30;
+
+int arena_acquire(size_t bytes, void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int best = -1;
+    for (size_t i = 0; i < g_cache.size(); ++i) {
+      const CachedBlock& b = g_cache[i];
+      if (b.device == dev && b.bytes >= bytes && b.bytes <= 2 * bytes + ((size_t)64 << 20) &&
+          (best < 0 || b.bytes < g_cache[best].bytes))
+        best = (int)i;
+    }
+    if (best >= 0) {
+      *out = g_cache[best].ptr;
+      g_cache_bytes -= g_cache[best].bytes;
+      g_cache.erase(g_cache.begin() + best);
+      return CAVITY_OK;
+    }
+  }
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    // drop the cache and retry once
+    std::vector<CachedBlock> drop;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      drop.swap(g_cache);
+      g_cache_bytes = 0;
+    }
+    for (auto& b : drop) (void)hipFree(b.ptr);
+    e = hipMalloc(&q, bytes);
+    if (e != hipSuccess)
+      return fail(CAVITY_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  *out = q;
+  return CAVITY_OK;
+}
+
+// The caller guarantees that no work on the block is pending.
+void arena_release(void* ptr, size_t bytes) {
+  if (!ptr) return;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::vector<CachedBlock> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache.push_back({ptr, bytes, dev});
+    g_cache_bytes += bytes;
+    while (g_cache_bytes > kCacheLimit && !g_cache.empty()) {
+      drop.push_back(g_cache.front());
+      g_cache_bytes -= g_cache.front().bytes;
+      g_cache.erase(g_cache.begin());
+    }
+  }
+  for (auto& b : drop) (void)hipFree(b.ptr);
+}
+
+// Two-phase layout: register every buffer, then bind them into one arena.
+struct Layout {
+  struct Item {
+    void** slot;
+    size_t offset;
+  };
+  std::vector<Item> items;
+  size_t bytes = 0;
+  template <typename T>
+  void add(T** slot, size_t count) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    items.push_back({reinterpret_cast<void**>(slot), bytes});
+    bytes += std::max<size_t>(count, 1) * sizeof(T);
+  }
+  void bind(void* base) const {
+    for (const Item& it : items) *it.slot = static_cast<char*>(base) + it.offset;
+  }
+};
+
+struct Arena {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
 struct cavity_plan_s {
   cav::Geo g{};
   cav::Trig trig{};
@@ -98,209 +198,295 @@ struct cavity_plan_s {
   bool layered = false;
   int nlayers = 1;
   double R = 0.0;
-  std::vector<void*> allocs;
-  size_t bytes = 0;
-  // device data
+  Arena plan_arena, work_arena, sol_arena;
+  // plan data
   zd *khat = nullptr, *rho_d = nullptr, *T = nullptr, *rho_n = nullptr;
   zd *pi_d = nullptr, *theta_d = nullptr, *pi_n = nullptr, *pinv = nullptr, *diag = nullptr;
-  double* pivmin = nullptr;
+  double *pivmin = nullptr, *dmin = nullptr;
   int* node_code = nullptr;
-  zd *kappa2 = nullptr, *ratio = nullptr;
+  zd *kappa2 = nullptr, *ratio = nullptr, *twiddles = nullptr;
+  double *pw1 = nullptr, *pw2 = nullptr;
+  zd* ctmp = nullptr;
+  zd* tbuf = nullptr;
+  zd* r = nullptr;          // inspection scratch (max(3 NM, P1 P2))
+  zd* dbg_out = nullptr;    // inspection scratch (3 NM)
+  cav::Wave* dwave1 = nullptr;
+  int synth_chunk = 1;
+  // solve workspace (sized for nbwork right-hand sides)
+  int nbwork = 0;
   zd *X = nullptr, *Y = nullptr, *S = nullptr;
-  zd *V = nullptr, *w = nullptr, *bvec = nullptr, *r = nullptr;
+  zd *V = nullptr, *w = nullptr, *bvec = nullptr;
+  zd* dpart = nullptr;
+  double* dnpart = nullptr;
+  zd* h2 = nullptr;
+  cav::Krylov kv{};
+  cav::Wave* dwaves = nullptr;
+  // solutions
   zd* xsol = nullptr;
   int nsol_cap = 0, nsol = 0;
-  zd *dpart = nullptr, *dh = nullptr;
-  double *dnpart = nullptr, *dnorm = nullptr;
-  zd* tbuf = nullptr;
-  int synth_chunk = 1;
-  zd* dy = nullptr;
   // pinned host staging
-  zd* hh = nullptr;
+  int* hflags = nullptr;
   double* hn = nullptr;
-  int nblk_red = 256;
+  int nblk_red = 128;
   cavity_info info{};
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // phase timers, resolved lazily: spectrum, elimination, preconditioner, rhs, krylov, synth
+  hipEvent_t ev[12] = {};
+  bool ev_used[6] = {};
 
   long long nvec() const { return 3LL * g.NM; }
 };
 
 namespace {
 
-template <typename T>
-int dalloc(cavity_plan p, T** ptr, size_t count) {
-  void* q = nullptr;
-  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  hipError_t e = hipMalloc(&q, bytes);
-  if (e != hipSuccess) {
-    *ptr = nullptr;
-    return fail(CAVITY_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
-  }
-  p->allocs.push_back(q);
-  p->bytes += bytes;
-  *ptr = static_cast<T*>(q);
-  return CAVITY_OK;
-}
-
 void release(cavity_plan p) {
   if (!p) return;
   if (p->st) (void)hipStreamSynchronize(p->st);
-  for (void* q : p->allocs) (void)hipFree(q);
-  p->allocs.clear();
-  if (p->hh) (void)hipHostFree(p->hh);
+  else (void)hipDeviceSynchronize();
+  arena_release(p->plan_arena.ptr, p->plan_arena.bytes);
+  arena_release(p->work_arena.ptr, p->work_arena.bytes);
+  arena_release(p->sol_arena.ptr, p->sol_arena.bytes);
+  if (p->hflags) (void)hipHostFree(p->hflags);
   if (p->hn) (void)hipHostFree(p->hn);
-  if (p->ev0) (void)hipEventDestroy(p->ev0);
-  if (p->ev1) (void)hipEventDestroy(p->ev1);
+  for (hipEvent_t e : p->ev)
+    if (e) (void)hipEventDestroy(e);
   delete p;
 }
 
-double elapsed_ms(cavity_plan p) {
-  float ms = 0.f;
-  (void)hipEventSynchronize(p->ev1);
-  (void)hipEventElapsedTime(&ms, p->ev0, p->ev1);
-  return ms;
+int mark(cavity_plan p, int phase, bool end) {
+  HIPCHK(hipEventRecord(p->ev[2 * phase + (end ? 1 : 0)], p->st));
+  if (end) p->ev_used[phase] = true;
+  return CAVITY_OK;
 }
 
-int upload_fft(cavity_plan p, int n, cav::Fft* out) {
-  out->p = make_fft_plan(n);
-  std::vector<zd> tw(n);
+void resolve_timers(cavity_plan p) {
+  double* dst[6] = {&p->info.ms_spectrum, &p->info.ms_elimination, &p->info.ms_preconditioner,
+                    &p->info.ms_rhs, &p->info.ms_krylov, &p->info.ms_synthesis};
+  for (int i = 0; i < 6; ++i) {
+    if (!p->ev_used[i]) continue;
+    float ms = 0.f;
+    if (hipEventSynchronize(p->ev[2 * i + 1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]) == hipSuccess)
+      *dst[i] = ms;
+  }
+}
+
+void twiddle_table(int n, zd* out) {
   const long double two_pi = 6.283185307179586476925286766559L;
   for (int t = 0; t < n; ++t) {
     const long double ang = -two_pi * (long double)t / (long double)n;
-    tw[t] = cav::mk((double)cosl(ang), (double)sinl(ang));
+    out[t] = cav::mk((double)cosl(ang), (double)sinl(ang));
   }
-  zd* d = nullptr;
-  int s = dalloc(p, &d, n);
-  if (s) return s;
-  HIPCHK(hipMemcpy(d, tw.data(), n * sizeof(zd), hipMemcpyHostToDevice));
-  out->tw = d;
-  return CAVITY_OK;
 }
 
-size_t footprint(const cav::Geo& g, bool layered, int restart, int chunk) {
-  const size_t z = sizeof(zd);
+size_t plan_bytes(const cav::Geo& g, bool layered, int chunk, int nlayers, int* twn) {
+  Layout L;
+  zd* z = nullptr;
+  double* d = nullptr;
+  int* i = nullptr;
   const size_t NM = g.NM;
-  size_t b = 0;
-  b += (size_t)g.P1 * g.P2 * z;                       // spectrum
-  b += 3 * NM * z;                                     // Schur data
-  b += (size_t)(g.Nz + 1) * NM * z * (layered ? 3 : 2);  // profiles
-  b += 12 * NM * z;                                    // preconditioner + diagonals
-  b += NM * sizeof(double);
-  b += 2 * 3 * (size_t)(g.M + 1) * g.P2 * z;           // TBC workspaces
-  b += 3 * NM * z;                                     // S
-  b += (size_t)(restart + 1 + 4) * 3 * NM * z;          // Krylov basis, w, b, r, x
-  b += 3 * (size_t)chunk * (g.M + 1) * (g.ny + 1) * z; // synthesis staging
-  b += (size_t)2 * (g.M + 1) * g.P1 * 8 + (size_t)2 * g.P2 * (g.N + 1) * 8 +
-       (size_t)2 * g.P1 * (g.N + 1) * z;               // preconditioner build (transient)
-  return b;
+  L.add(&z, (size_t)g.P1 * g.P2);
+  L.add(&z, NM); L.add(&z, NM); L.add(&z, NM);
+  L.add(&z, (size_t)(g.Nz + 1) * NM);
+  L.add(&z, (size_t)(g.Nz + 1) * NM);
+  if (layered) L.add(&z, (size_t)(g.Nz + 1) * NM);
+  L.add(&z, 9 * NM); L.add(&z, 3 * NM);
+  L.add(&d, NM); L.add(&d, 1);
+  L.add(&i, g.Nz + 1); L.add(&z, nlayers); L.add(&z, nlayers);
+  L.add(&z, *twn);
+  L.add(&d, (size_t)2 * (g.M + 1) * g.P1); L.add(&d, (size_t)2 * g.P2 * (g.N + 1));
+  L.add(&z, (size_t)2 * g.P1 * (g.N + 1));
+  L.add(&z, (size_t)3 * chunk * (g.M + 1) * (g.ny + 1));
+  L.add(&z, std::max<size_t>(3 * NM, (size_t)g.P1 * g.P2));
+  L.add(&z, 3 * NM);
+  L.add(&z, 8);
+  return L.bytes;
 }
 
-int run_operator(cavity_plan p, int precond, const zd* v, zd* y) {
-  HIPCHK(cav::launch_operator(p->g, p->trig, p->khat, p->rho_d, p->T, p->rho_n, p->pinv, precond,
-                              v, p->X, p->Y, p->S, y, p->st));
-  return CAVITY_OK;
+size_t work_bytes(const cav::Geo& g, int restart, int nb, int nblk) {
+  const size_t n = 3ull * g.NM;
+  const size_t z = sizeof(zd);
+  return z * ((size_t)nb * 2 * 3 * (g.M + 1) * g.P2 + (size_t)nb * 3 * g.NM +
+              (size_t)(restart + 1) * nb * n + 2ull * nb * n + (size_t)nblk * (restart + 1) * nb +
+              (size_t)nb * (restart + 1) * 3 + (size_t)nb * restart * (restart + 4) + 64) +
+         sizeof(double) * ((size_t)nblk * nb + 2 * nb) + sizeof(int) * 3 * nb + 64 * 256;
 }
 
-int device_norm2(cavity_plan p, const zd* v, double* out) {
-  HIPCHK(cav::launch_norm2(v, p->nvec(), p->dnpart, p->nblk_red, p->dnorm, p->st));
-  HIPCHK(hipMemcpyAsync(p->hn, p->dnorm, sizeof(double), hipMemcpyDeviceToHost, p->st));
-  HIPCHK(hipStreamSynchronize(p->st));
-  *out = p->hn[0];
-  return CAVITY_OK;
-}
-
-// Right-preconditioned restarted GMRES with classical Gram-Schmidt applied twice.
-int gmres(cavity_plan p, zd* x) {
+// Solve workspace for nb right-hand sides iterating together.
+int ensure_work(cavity_plan p, int nb) {
+  if (nb <= p->nbwork) return CAVITY_OK;
+  const int R = p->opts.restart;
   const long long n = p->nvec();
-  const int restart = p->opts.restart;
-  const double tol = p->opts.tol;
-  HIPCHK(hipMemsetAsync(x, 0, n * sizeof(zd), p->st));
-  double bn2 = 0;
-  int s = device_norm2(p, p->bvec, &bn2);
+  Layout L;
+  L.add(&p->X, (size_t)nb * 3 * (p->g.M + 1) * p->g.P2);
+  L.add(&p->Y, (size_t)nb * 3 * (p->g.M + 1) * p->g.P2);
+  L.add(&p->S, (size_t)nb * 3 * p->g.NM);
+  L.add(&p->V, (size_t)(R + 1) * nb * n);
+  L.add(&p->w, (size_t)nb * n);
+  L.add(&p->bvec, (size_t)nb * n);
+  L.add(&p->dpart, (size_t)p->nblk_red * (R + 1) * nb);
+  L.add(&p->dnpart, (size_t)p->nblk_red * nb);
+  L.add(&p->h2, (size_t)nb * (R + 1));
+  L.add(&p->kv.H, (size_t)nb * R * (R + 1));
+  L.add(&p->kv.cs, (size_t)nb * R);
+  L.add(&p->kv.sn, (size_t)nb * R);
+  L.add(&p->kv.g, (size_t)nb * (R + 1));
+  L.add(&p->kv.y, (size_t)nb * R);
+  L.add(&p->kv.nrm2, (size_t)nb);
+  L.add(&p->kv.bnorm, (size_t)nb);
+  L.add(&p->kv.active, (size_t)nb);
+  L.add(&p->kv.incycle, (size_t)nb);
+  L.add(&p->kv.jcount, (size_t)nb);
+  L.add(&p->dwaves, (size_t)nb);
+  if (p->st) HIPCHK(hipStreamSynchronize(p->st));
+  else HIPCHK(hipDeviceSynchronize());
+  arena_release(p->work_arena.ptr, p->work_arena.bytes);
+  p->work_arena = Arena();
+  p->nbwork = 0;
+  void* base = nullptr;
+  int s = arena_acquire(L.bytes, &base);
   if (s) return s;
-  const double bn = std::sqrt(bn2);
-  p->info.last_iterations = 0;
-  p->info.last_rel_residual = 0.0;
-  if (bn == 0.0) return CAVITY_OK;
-  std::vector<std::complex<double>> H((size_t)(restart + 1) * restart), cs(restart), sn(restart),
-      gv(restart + 1), y(restart);
-  int total = 0;
-  bool first = true;
-  double relres = 1.0;
-  while (true) {
-    zd* v0 = p->V;
-    if (first) {
-      HIPCHK(hipMemcpyAsync(v0, p->bvec, n * sizeof(zd), hipMemcpyDeviceToDevice, p->st));
-    } else {
-      if ((s = run_operator(p, 0, x, p->w))) return s;
-      HIPCHK(cav::launch_sub(p->bvec, p->w, v0, n, p->st));
-    }
-    double beta2 = 0;
-    if ((s = device_norm2(p, v0, &beta2))) return s;
-    const double beta = std::sqrt(beta2);
-    relres = beta / bn;
-    if (relres <= tol || total >= p->opts.max_iter) break;
-    first = false;
-    HIPCHK(cav::launch_scale_copy(v0, p->dnorm, v0, n, p->st));
-    std::fill(gv.begin(), gv.end(), 0.0);
-    gv[0] = beta;
-    int jdone = 0;
-    for (int j = 0; j < restart; ++j) {
-      zd* vj = p->V + (long long)j * n;
-      zd* vn = p->V + (long long)(j + 1) * n;
-      if ((s = run_operator(p, 1, vj, p->w))) return s;
-      const int nv = j + 1;
-      for (int pass = 0; pass < 2; ++pass) {
-        zd* hcol = p->dh + pass * 256;
-        HIPCHK(cav::launch_dots(p->V, n, nv, p->w, n, p->dpart, p->nblk_red, hcol, p->st));
-        HIPCHK(cav::launch_update(p->V, n, nv, hcol, p->w, n, p->st));
-      }
-      HIPCHK(cav::launch_norm2(p->w, n, p->dnpart, p->nblk_red, p->dnorm, p->st));
-      HIPCHK(cav::launch_scale_copy(p->w, p->dnorm, vn, n, p->st));
-      HIPCHK(hipMemcpyAsync(p->hh, p->dh, 512 * sizeof(zd), hipMemcpyDeviceToHost, p->st));
-      HIPCHK(hipMemcpyAsync(p->hn, p->dnorm, sizeof(double), hipMemcpyDeviceToHost, p->st));
-      HIPCHK(hipStreamSynchronize(p->st));
-      auto Hc = [&](int i) -> std::complex<double>& { return H[(size_t)j * (restart + 1) + i]; };
-      for (int i = 0; i < nv; ++i)
-        Hc(i) = std::complex<double>(p->hh[i].re + p->hh[256 + i].re,
-                                     p->hh[i].im + p->hh[256 + i].im);
-      Hc(j + 1) = std::sqrt(std::max(p->hn[0], 0.0));
-      for (int i = 0; i < j; ++i) {
-        const std::complex<double> t = cs[i] * Hc(i) + sn[i] * Hc(i + 1);
-        Hc(i + 1) = -std::conj(sn[i]) * Hc(i) + std::conj(cs[i]) * Hc(i + 1);
-        Hc(i) = t;
-      }
-      const double den = std::sqrt(std::norm(Hc(j)) + std::norm(Hc(j + 1)));
-      if (den == 0.0) {
-        cs[j] = 1.0;
-        sn[j] = 0.0;
-      } else {
-        cs[j] = std::conj(Hc(j)) / den;
-        sn[j] = std::conj(Hc(j + 1)) / den;
-      }
-      Hc(j) = den;
-      Hc(j + 1) = 0.0;
-      gv[j + 1] = -std::conj(sn[j]) * gv[j];
-      gv[j] = cs[j] * gv[j];
-      ++total;
-      jdone = j + 1;
-      if (std::abs(gv[j + 1]) <= tol * bn || total >= p->opts.max_iter || den == 0.0) break;
-    }
-    // back-substitution for y on the jdone x jdone triangle
-    for (int i = jdone - 1; i >= 0; --i) {
-      std::complex<double> acc = gv[i];
-      for (int c = i + 1; c < jdone; ++c) acc -= H[(size_t)c * (restart + 1) + i] * y[c];
-      y[i] = acc / H[(size_t)i * (restart + 1) + i];
-    }
-    std::vector<zd> yh(jdone);
-    for (int i = 0; i < jdone; ++i) yh[i] = cav::mk(y[i].real(), y[i].imag());
-    HIPCHK(hipMemcpyAsync(p->dy, yh.data(), jdone * sizeof(zd), hipMemcpyHostToDevice, p->st));
-    HIPCHK(cav::launch_combine(p->g, p->V, n, jdone, p->dy, p->pinv, x, p->st));
-    HIPCHK(hipStreamSynchronize(p->st));
+  p->work_arena = {base, L.bytes};
+  L.bind(base);
+  p->kv.restart = R;
+  p->kv.tol = p->opts.tol;
+  p->nbwork = nb;
+  return CAVITY_OK;
+}
+
+int ensure_solutions(cavity_plan p, int count) {
+  if (count <= p->nsol_cap) return CAVITY_OK;
+  const size_t bytes = (size_t)count * p->nvec() * sizeof(zd);
+  void* base = nullptr;
+  int s = arena_acquire(bytes, &base);
+  if (s) return s;
+  if (p->xsol && p->nsol > 0)
+    HIPCHK(hipMemcpyAsync(base, p->xsol, (size_t)p->nsol * p->nvec() * sizeof(zd),
+                          hipMemcpyDeviceToDevice, p->st));
+  if (p->st) HIPCHK(hipStreamSynchronize(p->st));
+  else HIPCHK(hipDeviceSynchronize());
+  arena_release(p->sol_arena.ptr, p->sol_arena.bytes);
+  p->sol_arena = {base, bytes};
+  p->xsol = static_cast<zd*>(base);
+  p->nsol_cap = count;
+  return CAVITY_OK;
+}
+
+int run_operator(cavity_plan p, int precond, int nb, const zd* v, zd* y, const int* active) {
+  const long long n = p->nvec();
+  HIPCHK(cav::launch_operator(p->g, p->trig, p->khat, p->rho_d, p->T, p->rho_n, p->pinv, precond,
+                              nb, v, n, p->X, p->Y, p->S, y, n, active, p->st));
+  return CAVITY_OK;
+}
+
+// nrm2[r] = |v_r|^2 for r < nb, copied to the host array out.
+int device_norms(cavity_plan p, const zd* v, int nb, double* out) {
+  HIPCHK(cav::launch_norm2(v, p->nvec(), nb, p->dnpart, p->nblk_red, p->kv.nrm2, nullptr, p->st));
+  HIPCHK(hipMemcpyAsync(p->hn, p->kv.nrm2, nb * sizeof(double), hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  for (int r = 0; r < nb; ++r) out[r] = p->hn[r];
+  return CAVITY_OK;
+}
+
+// Right-preconditioned restarted GMRES with classical Gram-Schmidt applied twice, for nb
+// right-hand sides b (p->bvec) iterating in lockstep; solutions in x (nb x n).  The
+// Arnoldi step, the Givens rotations and the convergence test run on the device; the
+// host looks at the convergence flags every few iterations and once per restart cycle.
+int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
+                std::vector<int>* iters_out) {
+  const long long n = p->nvec();
+  const int R = p->opts.restart;
+  const double tol = p->opts.tol;
+  const long long ldj = (long long)p->nbwork * n;
+  cav::Krylov& kv = p->kv;
+  HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * n * sizeof(zd), p->st));
+  std::vector<double> bn2(nb), beta2(nb);
+  int s = device_norms(p, p->bvec, nb, bn2.data());
+  if (s) return s;
+  std::vector<double> bn(nb), relres(nb, 0.0);
+  std::vector<int> iters(nb, 0);
+  std::vector<char> done(nb, 0);
+  for (int r = 0; r < nb; ++r) {
+    bn[r] = std::sqrt(bn2[r]);
+    if (bn[r] == 0.0) done[r] = 1;
   }
-  p->info.last_iterations = total;
-  p->info.last_rel_residual = relres;
-  if (relres > tol) return fail(CAVITY_ENOCONV, "GMRES did not reach the tolerance");
+  HIPCHK(hipMemcpyAsync(kv.bnorm, bn.data(), nb * sizeof(double), hipMemcpyHostToDevice, p->st));
+  std::vector<zd> g0((size_t)nb * (R + 1));
+  std::vector<int> flags(nb);
+  bool first = true;
+  while (true) {
+    zd* v0 = p->V;  // basis vector 0 of rhs r at V + r n
+    if (first) {
+      HIPCHK(hipMemcpyAsync(v0, p->bvec, (size_t)nb * n * sizeof(zd), hipMemcpyDeviceToDevice,
+                            p->st));
+    } else {
+      if ((s = run_operator(p, 0, nb, x, p->w, nullptr))) return s;
+      HIPCHK(cav::launch_sub(p->bvec, p->w, v0, (long long)nb * n, p->st));
+    }
+    if ((s = device_norms(p, v0, nb, beta2.data()))) return s;
+    bool any = false;
+    for (int r = 0; r < nb; ++r) {
+      if (bn[r] == 0.0) continue;
+      relres[r] = std::sqrt(beta2[r]) / bn[r];
+      if (relres[r] <= tol || iters[r] >= p->opts.max_iter) done[r] = 1;
+      flags[r] = done[r] ? 0 : 1;
+      any = any || !done[r];
+    }
+    for (int r = 0; r < nb; ++r)
+      if (bn[r] == 0.0) flags[r] = 0;
+    if (std::getenv("CAVITY_TRACE")) {
+      std::fprintf(stderr, "[gmres] nb=%d cycle start:", nb);
+      for (int r = 0; r < nb; ++r) std::fprintf(stderr, " r%d it=%d res=%.3e", r, iters[r], relres[r]);
+      std::fprintf(stderr, "\n");
+    }
+    if (!any) break;
+    first = false;
+    std::fill(g0.begin(), g0.end(), cav::mk(0.0, 0.0));
+    for (int r = 0; r < nb; ++r) g0[(size_t)r * (R + 1)] = cav::mk(std::sqrt(beta2[r]), 0.0);
+    HIPCHK(hipMemcpyAsync(kv.g, g0.data(), g0.size() * sizeof(zd), hipMemcpyHostToDevice, p->st));
+    HIPCHK(hipMemcpyAsync(kv.active, flags.data(), nb * sizeof(int), hipMemcpyHostToDevice, p->st));
+    HIPCHK(hipMemcpyAsync(kv.incycle, flags.data(), nb * sizeof(int), hipMemcpyHostToDevice,
+                          p->st));
+    HIPCHK(cav::launch_scale_copy(v0, kv.nrm2, v0, n, n, nb, kv.active, p->st));
+    // at most max_iter - min(iters) iterations this cycle
+    int budget = R;
+    for (int r = 0; r < nb; ++r)
+      if (flags[r]) budget = std::min(budget, std::max(1, p->opts.max_iter - iters[r]));
+    for (int j = 0; j < budget; ++j) {
+      const zd* vj = p->V + (long long)j * ldj;
+      zd* vn = p->V + (long long)(j + 1) * ldj;
+      if ((s = run_operator(p, 1, nb, vj, p->w, kv.active))) return s;
+      const int nv = j + 1;
+      zd* hcol = kv.H + (long long)j * (R + 1);
+      const long long hstr = (long long)R * (R + 1);
+      HIPCHK(cav::launch_dots(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
+                              nullptr, 0, kv.active, p->st));
+      HIPCHK(cav::launch_update(p->V, ldj, nv, hcol, hstr, p->w, n, nb, kv.active, p->st));
+      HIPCHK(cav::launch_dots(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, p->h2,
+                              R + 1, hcol, hstr, kv.active, p->st));
+      HIPCHK(cav::launch_update(p->V, ldj, nv, p->h2, R + 1, p->w, n, nb, kv.active, p->st));
+      HIPCHK(cav::launch_norm2(p->w, n, nb, p->dnpart, p->nblk_red, kv.nrm2, kv.active, p->st));
+      HIPCHK(cav::launch_scale_copy(p->w, kv.nrm2, vn, n, n, nb, kv.active, p->st));
+      HIPCHK(cav::launch_givens(kv, j, nb, p->st));
+      if ((j + 1) % 4 == 0 || j + 1 == budget) {
+        HIPCHK(hipMemcpyAsync(p->hflags, kv.active, nb * sizeof(int), hipMemcpyDeviceToHost,
+                              p->st));
+        HIPCHK(hipStreamSynchronize(p->st));
+        bool still = false;
+        for (int r = 0; r < nb; ++r) still = still || p->hflags[r];
+        if (!still) break;
+      }
+    }
+    HIPCHK(cav::launch_solve_y(kv, nb, p->st));
+    HIPCHK(cav::launch_combine(p->g, kv, p->V, ldj, p->pinv, x, nb, p->st));
+    HIPCHK(hipMemcpyAsync(p->hflags, kv.jcount, nb * sizeof(int), hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    for (int r = 0; r < nb; ++r)
+      if (flags[r]) iters[r] += p->hflags[r];
+  }
+  if (relres_out) *relres_out = relres;
+  if (iters_out) *iters_out = iters;
+  for (int r = 0; r < nb; ++r)
+    if (relres[r] > tol) return fail(CAVITY_ENOCONV, "GMRES did not reach the tolerance");
   return CAVITY_OK;
 }
 
@@ -317,48 +503,49 @@ void wave_setup(double k, double theta, double phi, int pol, cav::Wave* wv) {
   }
 }
 
-int ensure_solutions(cavity_plan p, int count) {
-  if (count <= p->nsol_cap) return CAVITY_OK;
-  zd* nx = nullptr;
-  int s = dalloc(p, &nx, (size_t)count * p->nvec());
-  if (s) return s;
-  if (p->xsol && p->nsol > 0)
-    HIPCHK(hipMemcpyAsync(nx, p->xsol, (size_t)p->nsol * p->nvec() * sizeof(zd),
-                          hipMemcpyDeviceToDevice, p->st));
-  p->xsol = nx;
-  p->nsol_cap = count;
-  return CAVITY_OK;
+bool angles_ok(double theta, double phi, int pol) {
+  return theta >= 0.0 && theta <= 0.5 * M_PI + 1e-12 && std::isfinite(phi) &&
+         (pol == CAVITY_TM || pol == CAVITY_TE);
 }
 
-int solve_one(cavity_plan p, double theta, double phi, int pol, int slot, cavity_c128* E_out,
-              cavity_c128* ap_out) {
-  if (!(theta >= 0.0 && theta <= 0.5 * M_PI + 1e-12) || !std::isfinite(phi) ||
-      (pol != CAVITY_TM && pol != CAVITY_TE))
-    return fail(CAVITY_EINVAL, "theta must lie in [0, pi/2], phi finite, pol TM or TE");
-  cav::Wave wv;
-  wave_setup(p->g.k, theta, phi, pol, &wv);
-  HIPCHK(hipEventRecord(p->ev0, p->st));
-  HIPCHK(cav::launch_rhs(p->g, wv, p->bvec, p->st));
-  HIPCHK(hipEventRecord(p->ev1, p->st));
-  p->info.ms_rhs = elapsed_ms(p);
-  zd* x = p->xsol + (long long)slot * p->nvec();
-  HIPCHK(hipEventRecord(p->ev0, p->st));
-  int status = gmres(p, x);
+// Solve right-hand sides [i0, i0 + nb) of a batch into solution slots i0.., writing fields
+// and packed aperture vectors when asked.
+int solve_chunk(cavity_plan p, int i0, int nb, const double* theta, const double* phi,
+                const int* pol, cavity_c128* E_out, cavity_c128* ap_out) {
+  std::vector<cav::Wave> wv(nb);
+  for (int r = 0; r < nb; ++r) wave_setup(p->g.k, theta[r], phi[r], pol[r], &wv[r]);
+  HIPCHK(hipMemcpyAsync(p->dwaves, wv.data(), nb * sizeof(cav::Wave), hipMemcpyHostToDevice,
+                        p->st));
+  int s0;
+  if ((s0 = mark(p, 3, false))) return s0;
+  HIPCHK(cav::launch_rhs(p->g, p->dwaves, nb, p->bvec, p->st));
+  if ((s0 = mark(p, 3, true))) return s0;
+  zd* x = p->xsol + (long long)i0 * p->nvec();
+  std::vector<double> relres;
+  std::vector<int> iters;
+  if ((s0 = mark(p, 4, false))) return s0;
+  int status = gmres_batch(p, nb, x, &relres, &iters);
   if (status != CAVITY_OK && status != CAVITY_ENOCONV) return status;
-  HIPCHK(hipEventRecord(p->ev1, p->st));
-  p->info.ms_krylov = elapsed_ms(p);
+  if ((s0 = mark(p, 4, true))) return s0;
+  p->info.last_iterations = *std::max_element(iters.begin(), iters.end());
+  p->info.last_rel_residual = *std::max_element(relres.begin(), relres.end());
+  const long long field = 3LL * (p->g.Nz + 1) * (p->g.ny + 1) * (p->g.nx + 1);
   if (E_out) {
-    HIPCHK(hipEventRecord(p->ev0, p->st));
-    for (int j0 = 0; j0 <= p->g.Nz; j0 += p->synth_chunk) {
-      const int j1 = std::min(p->g.Nz + 1, j0 + p->synth_chunk);
-      HIPCHK(cav::launch_synthesis(p->g, p->trig, p->pi_d, p->layered ? p->theta_d : nullptr,
-                                   p->pi_n, x, j0, j1, p->tbuf, reinterpret_cast<zd*>(E_out),
-                                   p->st));
+    if ((s0 = mark(p, 5, false))) return s0;
+    for (int r = 0; r < nb; ++r) {
+      for (int j0 = 0; j0 <= p->g.Nz; j0 += p->synth_chunk) {
+        const int j1 = std::min(p->g.Nz + 1, j0 + p->synth_chunk);
+        HIPCHK(cav::launch_synthesis(p->g, p->trig, p->pi_d, p->layered ? p->theta_d : nullptr,
+                                     p->pi_n, x + (long long)r * p->nvec(), j0, j1, p->tbuf,
+                                     reinterpret_cast<zd*>(E_out) + r * field, p->st));
+      }
     }
-    HIPCHK(hipEventRecord(p->ev1, p->st));
-    p->info.ms_synthesis = elapsed_ms(p);
+    if ((s0 = mark(p, 5, true))) return s0;
   }
-  if (ap_out) HIPCHK(cav::launch_pack(p->g, x, reinterpret_cast<zd*>(ap_out), p->st));
+  if (ap_out)
+    for (int r = 0; r < nb; ++r)
+      HIPCHK(cav::launch_pack(p->g, x + (long long)r * p->nvec(),
+                              reinterpret_cast<zd*>(ap_out) + r * p->info.n_ap, p->st));
   return status;
 }
 
@@ -375,6 +562,7 @@ int cavity_opts_default(cavity_opts* o) {
   o->restart = 60;
   o->hbm_budget = 0;
   o->stream = nullptr;
+  o->batch = 8;
   return CAVITY_OK;
 }
 
@@ -411,10 +599,10 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     return fail(CAVITY_EINVAL, "tbc_oversample must be in 1..8");
   if (!(o.tol > 0 && o.tol < 1) || o.max_iter < 1 || o.restart < 1 || o.restart > 200)
     return fail(CAVITY_EINVAL, "tol in (0,1), max_iter >= 1, restart in 1..200");
+  if (o.batch < 1 || o.batch > 64) return fail(CAVITY_EINVAL, "batch must be in 1..64");
   const int s = o.tbc_oversample;
   if (!is_5smooth(2LL * s * Nx) || !is_5smooth(2LL * s * Ny))
     return fail(CAVITY_EINVAL, "2*s*Nx and 2*s*Ny must be products of 2, 3 and 5");
-  // layers
   std::vector<int> lnz;
   std::vector<std::complex<double>> leps;
   if (eps) {
@@ -463,16 +651,20 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     return fail(CAVITY_EINVAL, "FFT box too large for one block's LDS");
 
   const bool layered = lnz.size() > 1;
-  int chunk = 1;
   const size_t per_level = 3ull * (g.M + 1) * (g.ny + 1) * sizeof(zd);
-  chunk = (int)std::max<size_t>(1, (size_t)(32u << 20) / per_level);
+  int chunk = (int)std::max<size_t>(1, (size_t)(32u << 20) / per_level);
   chunk = std::min(chunk, Nz + 1);
-  const size_t need = footprint(g, layered, o.restart, chunk);
+  const int fft_len[6] = {2 * g.nq1, 2 * g.nq2, g.P1, g.P2, 2 * g.nx, 2 * g.ny};
+  int twn = 0;
+  for (int l : fft_len) twn += l;
+  const int nb0 = 1;
+  const size_t need = plan_bytes(g, layered, chunk, (int)lnz.size(), &twn) +
+                      work_bytes(g, o.restart, nb0, 128) + 3ull * g.NM * sizeof(zd);
   size_t budget = o.hbm_budget;
   if (budget == 0) {
     size_t fr = 0, tot = 0;
     HIPCHK(hipMemGetInfo(&fr, &tot));
-    budget = (size_t)(0.9 * (double)fr);
+    budget = (size_t)(0.9 * (double)(fr + g_cache_bytes));
   }
   if (need > budget)
     return fail(CAVITY_ENOMEM, "plan needs " + std::to_string(need) + " bytes, budget " +
@@ -486,47 +678,64 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   p->nlayers = (int)lnz.size();
   p->R = R;
   p->synth_chunk = chunk;
-  int st = CAVITY_OK;
   auto bail = [&](int code) {
     release(p);
     return code;
   };
-  if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
-    return bail(fail(CAVITY_EDEVICE, "hipEventCreate failed"));
-  if (hipHostMalloc((void**)&p->hh, 512 * sizeof(zd)) != hipSuccess ||
-      hipHostMalloc((void**)&p->hn, 8 * sizeof(double)) != hipSuccess)
+  for (auto& e : p->ev)
+    if (hipEventCreate(&e) != hipSuccess) return bail(fail(CAVITY_EDEVICE, "hipEventCreate failed"));
+  if (hipHostMalloc((void**)&p->hflags, 64 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc((void**)&p->hn, 64 * sizeof(double)) != hipSuccess)
     return bail(fail(CAVITY_EDEVICE, "hipHostMalloc failed"));
 
-  const long long NM = g.NM, n = 3LL * NM;
-  if ((st = dalloc(p, &p->khat, (size_t)g.P1 * g.P2)) || (st = dalloc(p, &p->rho_d, NM)) ||
-      (st = dalloc(p, &p->T, NM)) || (st = dalloc(p, &p->rho_n, NM)) ||
-      (st = dalloc(p, &p->pi_d, (size_t)(Nz + 1) * NM)) ||
-      (st = dalloc(p, &p->pi_n, (size_t)(Nz + 1) * NM)) ||
-      (layered && (st = dalloc(p, &p->theta_d, (size_t)(Nz + 1) * NM))) ||
-      (st = dalloc(p, &p->pinv, 9 * NM)) || (st = dalloc(p, &p->diag, 3 * NM)) ||
-      (st = dalloc(p, &p->pivmin, NM)) || (st = dalloc(p, &p->node_code, Nz + 1)) ||
-      (st = dalloc(p, &p->kappa2, lnz.size())) ||
-      (st = dalloc(p, &p->ratio, std::max<size_t>(1, lnz.size() - 1))) ||
-      (st = dalloc(p, &p->X, 3ull * (g.M + 1) * g.P2)) ||
-      (st = dalloc(p, &p->Y, 3ull * (g.M + 1) * g.P2)) || (st = dalloc(p, &p->S, 3 * NM)) ||
-      (st = dalloc(p, &p->V, (size_t)(o.restart + 1) * n)) || (st = dalloc(p, &p->w, n)) ||
-      (st = dalloc(p, &p->bvec, n)) || (st = dalloc(p, &p->r, n)) ||
-      (st = dalloc(p, &p->dpart, (size_t)p->nblk_red * 256)) || (st = dalloc(p, &p->dh, 512)) ||
-      (st = dalloc(p, &p->dnpart, p->nblk_red)) || (st = dalloc(p, &p->dnorm, 8)) ||
-      (st = dalloc(p, &p->dy, 256)) ||
-      (st = dalloc(p, &p->tbuf, (size_t)3 * chunk * (g.M + 1) * (g.ny + 1))))
-    return bail(st);
-  if ((st = ensure_solutions(p, 1))) return bail(st);
-  if ((st = upload_fft(p, 2 * g.nq1, &p->trig.ext1)) ||
-      (st = upload_fft(p, 2 * g.nq2, &p->trig.ext2)) ||
-      (st = upload_fft(p, g.P1, &p->trig.box1)) || (st = upload_fft(p, g.P2, &p->trig.box2)) ||
-      (st = upload_fft(p, 2 * g.nx, &p->trig.out1)) ||
-      (st = upload_fft(p, 2 * g.ny, &p->trig.out2)))
-    return bail(st);
+  // one arena for all plan data
+  const long long NM = g.NM;
+  Layout L;
+  L.add(&p->khat, (size_t)g.P1 * g.P2);
+  L.add(&p->rho_d, NM);
+  L.add(&p->T, NM);
+  L.add(&p->rho_n, NM);
+  L.add(&p->pi_d, (size_t)(Nz + 1) * NM);
+  L.add(&p->pi_n, (size_t)(Nz + 1) * NM);
+  if (layered) L.add(&p->theta_d, (size_t)(Nz + 1) * NM);
+  L.add(&p->pinv, 9 * NM);
+  L.add(&p->diag, 3 * NM);
+  L.add(&p->pivmin, NM);
+  L.add(&p->dmin, 1);
+  L.add(&p->node_code, Nz + 1);
+  L.add(&p->kappa2, lnz.size());
+  L.add(&p->ratio, lnz.size());
+  L.add(&p->twiddles, twn);
+  L.add(&p->pw1, (size_t)2 * (g.M + 1) * g.P1);
+  L.add(&p->pw2, (size_t)2 * g.P2 * (g.N + 1));
+  L.add(&p->ctmp, (size_t)2 * g.P1 * (g.N + 1));
+  L.add(&p->tbuf, (size_t)3 * chunk * (g.M + 1) * (g.ny + 1));
+  L.add(&p->r, std::max<size_t>(3 * NM, (size_t)g.P1 * g.P2));
+  L.add(&p->dbg_out, 3 * NM);
+  L.add(&p->dwave1, 8);
+  {
+    void* base = nullptr;
+    int st0 = arena_acquire(L.bytes, &base);
+    if (st0) return bail(st0);
+    p->plan_arena = {base, L.bytes};
+    L.bind(base);
+  }
 
-  // layer tables
+  // host tables: twiddles, node codes, k^2 eps per layer, eps ratios per interface
+  std::vector<zd> tw(twn);
+  {
+    int off = 0;
+    cav::Fft* dst[6] = {&p->trig.ext1, &p->trig.ext2, &p->trig.box1, &p->trig.box2,
+                        &p->trig.out1, &p->trig.out2};
+    for (int i = 0; i < 6; ++i) {
+      twiddle_table(fft_len[i], tw.data() + off);
+      dst[i]->p = make_fft_plan(fft_len[i]);
+      dst[i]->tw = p->twiddles + off;
+      off += fft_len[i];
+    }
+  }
   std::vector<int> code(Nz + 1, 0);
-  std::vector<zd> kap(lnz.size()), rat(std::max<size_t>(1, lnz.size() - 1), cav::mk(1.0, 0.0));
+  std::vector<zd> kap(lnz.size()), rat(lnz.size(), cav::mk(1.0, 0.0));
   {
     int start = 0;
     for (size_t l = 0; l < lnz.size(); ++l) {
@@ -545,13 +754,6 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
       kap[l] = cav::mk(k2.real(), k2.imag());
     }
   }
-  if (hipMemcpy(p->node_code, code.data(), code.size() * sizeof(int), hipMemcpyHostToDevice) !=
-          hipSuccess ||
-      hipMemcpy(p->kappa2, kap.data(), kap.size() * sizeof(zd), hipMemcpyHostToDevice) !=
-          hipSuccess ||
-      hipMemcpy(p->ratio, rat.data(), rat.size() * sizeof(zd), hipMemcpyHostToDevice) != hipSuccess)
-    return bail(fail(CAVITY_EDEVICE, "upload of layer tables failed"));
-
   auto chk = [&](hipError_t e, const char* what) {
     if (e != hipSuccess) {
       fail(CAVITY_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -559,56 +761,44 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     }
     return true;
   };
+  if (!chk(hipMemcpyAsync(p->twiddles, tw.data(), tw.size() * sizeof(zd), hipMemcpyHostToDevice,
+                          p->st), "twiddle upload") ||
+      !chk(hipMemcpyAsync(p->node_code, code.data(), code.size() * sizeof(int),
+                          hipMemcpyHostToDevice, p->st), "layer upload") ||
+      !chk(hipMemcpyAsync(p->kappa2, kap.data(), kap.size() * sizeof(zd), hipMemcpyHostToDevice,
+                          p->st), "layer upload") ||
+      !chk(hipMemcpyAsync(p->ratio, rat.data(), rat.size() * sizeof(zd), hipMemcpyHostToDevice,
+                          p->st), "layer upload"))
+    return bail(CAVITY_EDEVICE);
+
   // spectrum (scaled for the unnormalised inverse FFT and the grid cell)
   const double scale = 1.0 / (g.hq1 * g.hq2 * (double)g.P1 * (double)g.P2);
-  if (!chk(hipEventRecord(p->ev0, p->st), "event") ||
-      !chk(cav::launch_spectrum(g, R, scale, p->khat, p->st), "spectrum") ||
-      !chk(hipEventRecord(p->ev1, p->st), "event"))
-    return bail(CAVITY_EDEVICE);
-  p->info.ms_spectrum = elapsed_ms(p);
-  // elimination
+  int st = CAVITY_OK;
+  if ((st = mark(p, 0, false))) return bail(st);
+  if (!chk(cav::launch_spectrum(g, R, scale, p->khat, p->st), "spectrum")) return bail(CAVITY_EDEVICE);
+  if ((st = mark(p, 0, true))) return bail(st);
   cav::Layers ly{p->node_code, p->kappa2, p->ratio, layered ? 1 : 0};
-  if (!chk(hipEventRecord(p->ev0, p->st), "event") ||
-      !chk(cav::launch_elimination(g, ly, p->rho_d, p->T, p->rho_n, p->pi_d, p->theta_d, p->pi_n,
-                                   p->pivmin, p->st),
-           "elimination") ||
-      !chk(hipEventRecord(p->ev1, p->st), "event"))
+  if ((st = mark(p, 1, false))) return bail(st);
+  if (!chk(cav::launch_elimination(g, ly, p->rho_d, p->T, p->rho_n, p->pi_d, p->theta_d, p->pi_n,
+                                   p->pivmin, p->st), "elimination"))
     return bail(CAVITY_EDEVICE);
-  p->info.ms_elimination = elapsed_ms(p);
-  {
-    std::vector<double> pv(NM);
-    if (!chk(hipMemcpy(pv.data(), p->pivmin, NM * sizeof(double), hipMemcpyDeviceToHost),
-             "pivot copy"))
-      return bail(CAVITY_EDEVICE);
-    double mn = 1e300;
-    for (double v : pv) mn = std::min(mn, v);
-    p->info.min_pivot = mn;
-    if (!(mn > 1e-13)) return bail(fail(CAVITY_ERESONANT, "z-elimination pivot below 1e-13"));
-  }
-  // preconditioner: exact diagonals of the three single-layer families
-  {
-    double *pw1 = nullptr, *pw2 = nullptr;
-    zd* tmp = nullptr;
-    void* q = nullptr;
-    const size_t b1 = (size_t)2 * (g.M + 1) * g.P1 * sizeof(double);
-    const size_t b2 = (size_t)2 * g.P2 * (g.N + 1) * sizeof(double);
-    const size_t b3 = (size_t)2 * g.P1 * (g.N + 1) * sizeof(zd);
-    if (!chk(hipMalloc(&q, b1 + b2 + b3), "preconditioner scratch")) return bail(CAVITY_ENOMEM);
-    pw1 = static_cast<double*>(q);
-    pw2 = reinterpret_cast<double*>(static_cast<char*>(q) + b1);
-    tmp = reinterpret_cast<zd*>(static_cast<char*>(q) + b1 + b2);
-    bool ok = chk(hipEventRecord(p->ev0, p->st), "event") &&
-              chk(cav::launch_basis_power(g, p->trig, pw1, pw2, p->st), "basis power") &&
-              chk(cav::launch_diag_contract(g, p->khat, pw1, pw2, tmp, p->diag, p->st),
-                  "diagonal") &&
-              chk(cav::launch_precond_build(g, p->rho_d, p->T, p->rho_n, p->diag, p->pinv, p->st),
-                  "preconditioner") &&
-              chk(hipEventRecord(p->ev1, p->st), "event");
-    if (ok) p->info.ms_preconditioner = elapsed_ms(p);
-    (void)hipStreamSynchronize(p->st);
-    (void)hipFree(q);
-    if (!ok) return bail(CAVITY_EDEVICE);
-  }
+  if ((st = mark(p, 1, true))) return bail(st);
+  if ((st = mark(p, 2, false))) return bail(st);
+  if (!chk(cav::launch_basis_power(g, p->trig, p->pw1, p->pw2, p->st), "basis power") ||
+      !chk(cav::launch_diag_contract(g, p->khat, p->pw1, p->pw2, p->ctmp, p->diag, p->st),
+           "diagonal") ||
+      !chk(cav::launch_precond_build(g, p->rho_d, p->T, p->rho_n, p->diag, p->pinv, p->st),
+           "preconditioner"))
+    return bail(CAVITY_EDEVICE);
+  if ((st = mark(p, 2, true))) return bail(st);
+  if (!chk(cav::launch_min(p->pivmin, NM, p->dmin, p->st), "pivot minimum") ||
+      !chk(hipMemcpyAsync(p->hn, p->dmin, sizeof(double), hipMemcpyDeviceToHost, p->st),
+           "pivot copy") ||
+      !chk(hipStreamSynchronize(p->st), "plan sync"))
+    return bail(CAVITY_EDEVICE);
+  p->info.min_pivot = p->hn[0];
+  if (!(p->info.min_pivot > 1e-13))
+    return bail(fail(CAVITY_ERESONANT, "z-elimination pivot below 1e-13"));
   p->info.M = g.M;
   p->info.N = g.N;
   p->info.Nz = Nz;
@@ -616,7 +806,6 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   p->info.P2 = g.P2;
   p->info.n_ap = (long long)(g.M + 1) * g.N + (long long)g.M * (g.N + 1) + (long long)g.M * g.N;
   p->info.unknowns = p->info.n_ap * Nz;
-  p->info.device_bytes = p->bytes;
   *out = p;
   return CAVITY_OK;
 }
@@ -625,45 +814,52 @@ void cavity_plan_destroy(cavity_plan p) { release(p); }
 
 int cavity_plan_info(cavity_plan p, cavity_info* out) {
   if (!p || !out) return fail(CAVITY_EINVAL, "NULL argument");
-  p->info.device_bytes = p->bytes;
+  resolve_timers(p);
+  p->info.device_bytes = p->plan_arena.bytes + p->work_arena.bytes + p->sol_arena.bytes;
   *out = p->info;
   return CAVITY_OK;
 }
 
 int cavity_solve(cavity_plan p, double theta, double phi, int pol, cavity_c128* E_out) {
   if (!p) return fail(CAVITY_EINVAL, "NULL plan");
-  int s = solve_one(p, theta, phi, pol, 0, E_out, nullptr);
-  if (s == CAVITY_OK || s == CAVITY_ENOCONV) p->nsol = std::max(p->nsol, 1);
-  return s;
+  return cavity_solve_batch(p, 1, &theta, &phi, &pol, E_out, nullptr);
 }
 
 int cavity_solve_batch(cavity_plan p, int nrhs, const double* theta, const double* phi,
                        const int* pol, cavity_c128* E_out, cavity_c128* aperture_out) {
   if (!p || nrhs < 1 || !theta || !phi || !pol) return fail(CAVITY_EINVAL, "bad batch arguments");
+  for (int i = 0; i < nrhs; ++i)
+    if (!angles_ok(theta[i], phi[i], pol[i]))
+      return fail(CAVITY_EINVAL, "theta must lie in [0, pi/2], phi finite, pol TM or TE");
   int s = ensure_solutions(p, nrhs);
   if (s) return s;
+  if ((s = ensure_work(p, std::min(nrhs, p->opts.batch)))) return s;
   const long long field = 3LL * (p->g.Nz + 1) * (p->g.ny + 1) * (p->g.nx + 1);
   int worst = CAVITY_OK;
-  for (int i = 0; i < nrhs; ++i) {
-    s = solve_one(p, theta[i], phi[i], pol[i], i, E_out ? E_out + i * field : nullptr,
-                  aperture_out ? aperture_out + i * p->info.n_ap : nullptr);
+  int its = 0;
+  double res = 0.0;
+  for (int i0 = 0; i0 < nrhs; i0 += p->nbwork) {
+    const int nb = std::min(p->nbwork, nrhs - i0);
+    s = solve_chunk(p, i0, nb, theta + i0, phi + i0, pol + i0, E_out ? E_out + i0 * field : nullptr,
+                    aperture_out ? aperture_out + i0 * p->info.n_ap : nullptr);
     if (s != CAVITY_OK && s != CAVITY_ENOCONV) return s;
     if (s == CAVITY_ENOCONV) worst = s;
-    p->nsol = std::max(p->nsol, i + 1);
+    its = std::max(its, p->info.last_iterations);
+    res = std::max(res, p->info.last_rel_residual);
+    p->nsol = std::max(p->nsol, i0 + nb);
   }
-  return worst;
+  p->info.last_iterations = its;
+  p->info.last_rel_residual = res;
+  if (worst != CAVITY_OK) return fail(worst, "GMRES did not reach the tolerance");
+  return CAVITY_OK;
 }
 
 int cavity_aperture(cavity_plan p, int idx, cavity_c128* out_host) {
   if (!p || !out_host || idx < 0 || idx >= p->nsol) return fail(CAVITY_EINVAL, "no such solution");
-  zd* tmp = nullptr;
-  HIPCHK(hipMalloc(&tmp, p->info.n_ap * sizeof(zd)));
-  hipError_t e = cav::launch_pack(p->g, p->xsol + (long long)idx * p->nvec(), tmp, p->st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(out_host, tmp, p->info.n_ap * sizeof(zd), hipMemcpyDeviceToHost, p->st);
-  if (e == hipSuccess) e = hipStreamSynchronize(p->st);
-  (void)hipFree(tmp);
-  if (e != hipSuccess) return fail(CAVITY_EDEVICE, hipGetErrorString(e));
+  HIPCHK(cav::launch_pack(p->g, p->xsol + (long long)idx * p->nvec(), p->dbg_out, p->st));
+  HIPCHK(hipMemcpyAsync(out_host, p->dbg_out, p->info.n_ap * sizeof(zd), hipMemcpyDeviceToHost,
+                        p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
   return CAVITY_OK;
 }
 
@@ -673,13 +869,14 @@ int cavity_rcs(cavity_plan p, int idx, int n_obs, const double* th, const double
     return fail(CAVITY_EINVAL, "bad rcs arguments");
   const int nblk = 64;
   std::vector<zd> part(2 * nblk);
+  zd* dpart = p->dbg_out;
   const double k = p->g.k;
   const zd* x = p->xsol + (long long)idx * p->nvec();
   for (int i = 0; i < n_obs; ++i) {
     const double st = std::sin(th[i]), ct = std::cos(th[i]), sp = std::sin(ph[i]),
                  cp = std::cos(ph[i]);
-    HIPCHK(cav::launch_rcs_partial(p->g, x, k * st * cp, k * st * sp, p->dpart, nblk, p->st));
-    HIPCHK(hipMemcpyAsync(part.data(), p->dpart, 2 * nblk * sizeof(zd), hipMemcpyDeviceToHost,
+    HIPCHK(cav::launch_rcs_partial(p->g, x, k * st * cp, k * st * sp, dpart, nblk, p->st));
+    HIPCHK(hipMemcpyAsync(part.data(), dpart, 2 * nblk * sizeof(zd), hipMemcpyDeviceToHost,
                           p->st));
     HIPCHK(hipStreamSynchronize(p->st));
     std::complex<double> e1 = 0.0, e2 = 0.0;
@@ -774,18 +971,22 @@ int cavity_debug_spectrum(cavity_plan p, cavity_c128* khat) {
 int cavity_debug_tbc(cavity_plan p, int family, const cavity_c128* in, cavity_c128* out) {
   if (!p || !in || !out || family < 0 || family > 2) return fail(CAVITY_EINVAL, "bad arguments");
   const size_t NM = p->g.NM;
+  int s = ensure_work(p, 1);
+  if (s) return s;
   HIPCHK(hipMemcpy(p->r, in, NM * sizeof(zd), hipMemcpyHostToDevice));
-  HIPCHK(cav::launch_single_family(p->g, p->trig, p->khat, family, p->r, p->X, p->Y, p->w, p->st));
-  return copy_out(p, p->w, out, NM);
+  HIPCHK(cav::launch_single_family(p->g, p->trig, p->khat, family, p->r, p->X, p->Y, p->dbg_out,
+                                   p->st));
+  return copy_out(p, p->dbg_out, out, NM);
 }
 
 int cavity_debug_operator(cavity_plan p, const cavity_c128* in, cavity_c128* out) {
   if (!p || !in || !out) return fail(CAVITY_EINVAL, "NULL argument");
   const size_t n = 3 * (size_t)p->g.NM;
-  HIPCHK(hipMemcpy(p->r, in, n * sizeof(zd), hipMemcpyHostToDevice));
-  int s = run_operator(p, 0, p->r, p->w);
+  int s = ensure_work(p, 1);
   if (s) return s;
-  return copy_out(p, p->w, out, n);
+  HIPCHK(hipMemcpy(p->r, in, n * sizeof(zd), hipMemcpyHostToDevice));
+  if ((s = run_operator(p, 0, 1, p->r, p->dbg_out, nullptr))) return s;
+  return copy_out(p, p->dbg_out, out, n);
 }
 
 int cavity_debug_rhs(cavity_plan p, double theta, double phi, int pol, cavity_c128* g1,
@@ -793,7 +994,8 @@ int cavity_debug_rhs(cavity_plan p, double theta, double phi, int pol, cavity_c1
   if (!p || !g1 || !g2) return fail(CAVITY_EINVAL, "NULL argument");
   cav::Wave wv;
   wave_setup(p->g.k, theta, phi, pol, &wv);
-  HIPCHK(cav::launch_rhs(p->g, wv, p->r, p->st));
+  HIPCHK(hipMemcpy(p->dwave1, &wv, sizeof(wv), hipMemcpyHostToDevice));
+  HIPCHK(cav::launch_rhs(p->g, p->dwave1, 1, p->r, p->st));
   int s;
   if ((s = copy_out(p, p->r, g1, p->g.NM)) || (s = copy_out(p, p->r + p->g.NM, g2, p->g.NM)))
     return s;

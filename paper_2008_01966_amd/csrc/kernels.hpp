@@ -65,32 +65,52 @@ hipError_t launch_basis_power(const Geo& g, const Trig& t, double* pw1, double* 
                               hipStream_t st);
 hipError_t launch_diag_contract(const Geo& g, const zd* khat, const double* pw1,
                                 const double* pw2, zd* tmp, zd* diag, hipStream_t st);
+hipError_t launch_min(const double* v, long long n, double* out, hipStream_t st);
 hipError_t launch_precond_build(const Geo& g, const zd* rho_d, const zd* T, const zd* rho_n,
                                 const zd* diag, zd* pinv, hipStream_t st);
 
 // ---- solve-time kernels -----------------------------------------------------------
-hipError_t launch_rhs(const Geo& g, const Wave& w, zd* b, hipStream_t st);
-// y = A (P^{-1} v) when precond != 0, else y = A v.  X, Y: 3 x (M+1) x P2 workspaces,
-// S: 3 x NM workspace.
+// Device state of GMRES for nb right-hand sides iterating in lockstep (restart length R):
+// H[r][j][0..R] Hessenberg columns rotated in place into R, rotations cs/sn[r][0..R-1],
+// rotated right-hand side g[r][0..R], solution weights y[r][0..R-1], norms nrm2[r],
+// |b_r| in bnorm[r], active[r] (still iterating in this cycle), incycle[r] (started this
+// cycle), jcount[r] (columns built in this cycle).
+struct Krylov {
+  zd *H, *cs, *sn, *g, *y;
+  double *nrm2, *bnorm;
+  int *active, *incycle, *jcount;
+  int restart;
+  double tol;
+};
+
+hipError_t launch_rhs(const Geo& g, const Wave* waves, int nb, zd* b, hipStream_t st);
+// y_r = A (P^{-1} v_r) when precond != 0, else y_r = A v_r, for r < nb with active[r] (or all
+// when active is null).  v_r = v + r vs, y_r = y + r ys.  X, Y: nb x 3 x (M+1) x P2 and
+// S: nb x 3 x NM workspaces.
 hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const zd* rho_d,
-                           const zd* T, const zd* rho_n, const zd* pinv, int precond,
-                           const zd* v, zd* X, zd* Y, zd* S, zd* y, hipStream_t st);
+                           const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
+                           const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y, long long ys,
+                           const int* active, hipStream_t st);
 // One single-layer family on a coefficient grid (inspection path).
 hipError_t launch_single_family(const Geo& g, const Trig& t, const zd* khat, int family,
                                 const zd* in, zd* X, zd* Y, zd* out, hipStream_t st);
 
-// Krylov building blocks on vectors of length n.
-hipError_t launch_dots(const zd* V, long long ldv, int nv, const zd* w, long long n,
-                       zd* partial, int nblk, zd* h, hipStream_t st);
-hipError_t launch_update(const zd* V, long long ldv, int nv, const zd* h, zd* w, long long n,
-                         hipStream_t st);
-hipError_t launch_norm2(const zd* w, long long n, double* partial, int nblk, double* out,
-                        hipStream_t st);
+// Krylov building blocks: vector r of a set at base + r n; basis vector i of right-hand
+// side r at V + i ldj + r n.
+hipError_t launch_dots(const zd* V, long long ldj, int nv, int nvmax, const zd* w, long long n,
+                       int nb, zd* partial, int nblk, zd* out, long long ostride, zd* acc,
+                       long long astride, const int* active, hipStream_t st);
+hipError_t launch_update(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
+                         zd* w, long long n, int nb, const int* active, hipStream_t st);
+hipError_t launch_norm2(const zd* w, long long n, int nb, double* partial, int nblk, double* out,
+                        const int* active, hipStream_t st);
 hipError_t launch_scale_copy(const zd* w, const double* nrm2, zd* v, long long n,
-                             hipStream_t st);
-hipError_t launch_sub(const zd* b, const zd* w, zd* r, long long n, hipStream_t st);
-hipError_t launch_combine(const Geo& g, const zd* V, long long ldv, int nv, const zd* y,
-                          const zd* pinv, zd* x, hipStream_t st);
+                             long long vstride, int nb, const int* active, hipStream_t st);
+hipError_t launch_sub(const zd* b, const zd* w, zd* r, long long total, hipStream_t st);
+hipError_t launch_givens(const Krylov& kv, int j, int nb, hipStream_t st);
+hipError_t launch_solve_y(const Krylov& kv, int nb, hipStream_t st);
+hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long ldj,
+                          const zd* pinv, zd* x, int nb, hipStream_t st);
 
 // Back-substitution and synthesis of E_out for levels [j0, j1).
 hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const zd* theta_d,

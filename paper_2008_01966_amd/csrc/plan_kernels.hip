@@ -368,4 +368,23 @@ hipError_t launch_precond_build(const Geo& g, const zd* rho_d, const zd* T, cons
   return hipGetLastError();
 }
 
+// out[0] = min over pivmin[0..n) (one block).
+__global__ void k_min(const double* __restrict__ v, long long n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double m = 1e300;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) m = fmin(m, v[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+hipError_t launch_min(const double* v, long long n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_min, dim3(1), dim3(256), 0, st, v, n, out);
+  return hipGetLastError();
+}
+
 }  // namespace cav

@@ -36,10 +36,13 @@ __device__ inline zd sin_proj(double alpha, double f, double len) {
 // ---------------------------------------------------------------------------------
 // Right-hand side: g1 = (h/q) 2i (alpha1 p3 + beta p1) C_m(alpha1) S_n(alpha2) on N1,
 //                  g2 = (h/c) 2i (alpha2 p3 + beta p2) S_m(alpha1) C_n(alpha2) on N2.
+// One right-hand side per blockIdx.y; vectors of length 3 NM, consecutive.
 // ---------------------------------------------------------------------------------
-__global__ void k_rhs(Geo g, Wave wv, zd* __restrict__ b) {
+__global__ void k_rhs(Geo g, const Wave* __restrict__ waves, zd* __restrict__ b) {
   const int mn = blockIdx.x * blockDim.x + threadIdx.x;
   if (mn >= g.NM) return;
+  const Wave wv = waves[blockIdx.y];
+  zd* out = b + (long long)blockIdx.y * 3 * g.NM;
   const int m = mn / (g.N + 1), n = mn % (g.N + 1);
   const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
   zd g1 = mk(0.0, 0.0), g2 = mk(0.0, 0.0);
@@ -55,14 +58,14 @@ __global__ void k_rhs(Geo g, Wave wv, zd* __restrict__ b) {
     const zd pr = sin_proj(wv.alpha1, mu, g.a) * cos_proj(wv.alpha2, nu, g.b);
     g2 = mk(-amp * pr.im, amp * pr.re);
   }
-  b[mn] = g1;
-  b[g.NM + mn] = g2;
-  b[2LL * g.NM + mn] = mk(0.0, 0.0);
+  out[mn] = g1;
+  out[g.NM + mn] = g2;
+  out[2LL * g.NM + mn] = mk(0.0, 0.0);
 }
 
-hipError_t launch_rhs(const Geo& g, const Wave& w, zd* b, hipStream_t st) {
+hipError_t launch_rhs(const Geo& g, const Wave* waves, int nb, zd* b, hipStream_t st) {
   const int blk = 256;
-  hipLaunchKernelGGL(k_rhs, dim3((g.NM + blk - 1) / blk), dim3(blk), 0, st, g, w, b);
+  hipLaunchKernelGGL(k_rhs, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g, waves, b);
   return hipGetLastError();
 }
 
@@ -73,6 +76,8 @@ hipError_t launch_rhs(const Geo& g, const Wave& w, zd* b, hipStream_t st) {
 // on the (s Nx + 1) x (s Ny + 1) trapezoid grid, zero-padded to P1 x P2.
 // Three passes: rows forward (SYN along y, FFT along y), columns (SYN, FFT, multiply,
 // inverse FFT, ANA along x), rows backward (inverse FFT along y, ANA along y).
+// blockIdx.z selects the right-hand side; a block whose right-hand side is inactive
+// returns at once.
 // ---------------------------------------------------------------------------------
 __device__ inline bool fam_xcos(int f) { return f != 1; }
 __device__ inline bool fam_ycos(int f) { return f != 0; }
@@ -80,10 +85,15 @@ __device__ inline bool fam_ycos(int f) { return f != 0; }
 // Pass 1.  fam_fixed >= 0: `v` is the coefficient grid of that family (inspection path);
 // otherwise `v` is a padded aperture vector, optionally preconditioned first.
 __global__ void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2, const zd* __restrict__ pinv,
-                               int precond, int fam_fixed, const zd* __restrict__ v,
-                               zd* __restrict__ X) {
+                               int precond, int fam_fixed, const zd* __restrict__ vall,
+                               long long vs, zd* __restrict__ Xall, const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ zd c0s;
+  const int rhs = blockIdx.z;
+  if (active && !active[rhs]) return;
+  const zd* v = vall + rhs * vs;
+  const int nf = fam_fixed >= 0 ? 1 : 3;
+  zd* X = Xall + (long long)rhs * nf * (g.M + 1) * g.P2;
   const int m = blockIdx.x;
   const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
   const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
@@ -137,9 +147,16 @@ __global__ void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2, const zd* __restrict__
 
 // Pass 2: TK adjacent columns k2 per block, blockDim.x / TK threads per column.
 __global__ void k_tbc_cols(Geo g, Fft ext1, Fft box1, const zd* __restrict__ khat, int fam_fixed,
-                           int TK, const zd* __restrict__ X, zd* __restrict__ Y) {
+                           int TK, const zd* __restrict__ Xall, zd* __restrict__ Yall,
+                           const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ zd c0s[16];
+  const int rhs = blockIdx.z;
+  if (active && !active[rhs]) return;
+  const int nf = fam_fixed >= 0 ? 1 : 3;
+  const long long wsz = (long long)nf * (g.M + 1) * g.P2;
+  const zd* X = Xall + rhs * wsz;
+  zd* Y = Yall + rhs * wsz;
   const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
   const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
   const int tpc = blockDim.x / TK;
@@ -194,9 +211,14 @@ __global__ void k_tbc_cols(Geo g, Fft ext1, Fft box1, const zd* __restrict__ kha
 }
 
 // Pass 3: rows backward; writes S[slot][mn].
-__global__ void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed, const zd* __restrict__ Y,
-                               zd* __restrict__ S) {
+__global__ void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed, const zd* __restrict__ Yall,
+                               zd* __restrict__ Sall, const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
+  const int rhs = blockIdx.z;
+  if (active && !active[rhs]) return;
+  const int nf = fam_fixed >= 0 ? 1 : 3;
+  const zd* Y = Yall + (long long)rhs * nf * (g.M + 1) * g.P2;
+  zd* S = Sall + (long long)rhs * nf * g.NM;
   const int m = blockIdx.x;
   const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
   const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
@@ -227,10 +249,16 @@ __global__ void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed, const z
 //  r3 = (rho_n - 1) z3 + mu h z1 + nu h z2                                        on N3
 __global__ void k_operator_epilogue(Geo g, const zd* __restrict__ rho_d, const zd* __restrict__ T,
                                     const zd* __restrict__ rho_n, const zd* __restrict__ pinv,
-                                    int precond, const zd* __restrict__ v,
-                                    const zd* __restrict__ S, zd* __restrict__ y) {
+                                    int precond, const zd* __restrict__ vall, long long vs,
+                                    const zd* __restrict__ Sall, zd* __restrict__ yall,
+                                    long long ys, const int* __restrict__ active) {
+  const int rhs = blockIdx.y;
+  if (active && !active[rhs]) return;
   const int mn = blockIdx.x * blockDim.x + threadIdx.x;
   if (mn >= g.NM) return;
+  const zd* v = vall + rhs * vs;
+  const zd* S = Sall + 3LL * rhs * g.NM;
+  zd* y = yall + rhs * ys;
   const int m = mn / (g.N + 1), n = mn % (g.N + 1);
   const double mu = M_PI * m / g.a, nu = M_PI * n / g.b, h = g.h, k2 = g.k * g.k;
   zd z[3] = {v[mn], v[g.NM + mn], v[2LL * g.NM + mn]};
@@ -258,65 +286,74 @@ __global__ void k_operator_epilogue(Geo g, const zd* __restrict__ rho_d, const z
 
 static int cols_per_block(int P) {
   int tk = 8;
-  while (tk > 1 && (size_t)tk * 2 * P * sizeof(zd) > 80 * 1024) tk >>= 1;
+  while (tk > 1 && (size_t)tk * 2 * P * sizeof(zd) > 64 * 1024) tk >>= 1;
   return tk;
 }
 
 static hipError_t launch_tbc_passes(const Geo& g, const Trig& t, const zd* khat, const zd* pinv,
-                                    int precond, int fam_fixed, const zd* v, zd* X, zd* Y,
-                                    zd* S, hipStream_t st) {
+                                    int precond, int fam_fixed, int nb, const zd* v, long long vs,
+                                    zd* X, zd* Y, zd* S, const int* active, hipStream_t st) {
   const int nf = fam_fixed >= 0 ? 1 : 3;
   const double zb = sizeof(zd);
-  const double xbytes = zb * nf * (g.M + 1) * (double)g.P2;   // one X or Y workspace
-  const double vin = zb * (fam_fixed >= 0 ? 1.0 : 3.0) * g.NM + (precond ? zb * 9.0 * g.NM : 0.0);
+  const double xbytes = zb * nb * nf * (g.M + 1) * (double)g.P2;   // one X or Y workspace
+  const double vin = nb * (zb * (fam_fixed >= 0 ? 1.0 : 3.0) * g.NM) + (precond ? zb * 9.0 * g.NM : 0.0);
   probe_begin(K_TBC_ROWS_FWD, st);
-  hipLaunchKernelGGL(k_tbc_rows_fwd, dim3(g.M + 1, nf), dim3(256), 2 * g.P2 * sizeof(zd), st, g,
-                     t.ext2, t.box2, pinv, precond, fam_fixed, v, X);
+  hipLaunchKernelGGL(k_tbc_rows_fwd, dim3(g.M + 1, nf, nb), dim3(256), 2 * g.P2 * sizeof(zd), st,
+                     g, t.ext2, t.box2, pinv, precond, fam_fixed, v, vs, X, active);
   probe_end(K_TBC_ROWS_FWD, st, vin + xbytes);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int tk = cols_per_block(g.P1);
   probe_begin(K_TBC_COLS, st);
-  hipLaunchKernelGGL(k_tbc_cols, dim3((g.P2 + tk - 1) / tk, nf), dim3(256),
+  hipLaunchKernelGGL(k_tbc_cols, dim3((g.P2 + tk - 1) / tk, nf, nb), dim3(256),
                      (size_t)tk * 2 * g.P1 * sizeof(zd), st, g, t.ext1, t.box1, khat, fam_fixed,
-                     tk, X, Y);
+                     tk, X, Y, active);
   probe_end(K_TBC_COLS, st, 2.0 * xbytes + zb * (double)g.P1 * g.P2);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   probe_begin(K_TBC_ROWS_BWD, st);
-  hipLaunchKernelGGL(k_tbc_rows_bwd, dim3(g.M + 1, nf), dim3(256), 2 * g.P2 * sizeof(zd), st, g,
-                     t.ext2, t.box2, fam_fixed, Y, S);
-  probe_end(K_TBC_ROWS_BWD, st, xbytes + zb * nf * g.NM);
+  hipLaunchKernelGGL(k_tbc_rows_bwd, dim3(g.M + 1, nf, nb), dim3(256), 2 * g.P2 * sizeof(zd), st,
+                     g, t.ext2, t.box2, fam_fixed, Y, S, active);
+  probe_end(K_TBC_ROWS_BWD, st, xbytes + zb * nb * nf * g.NM);
   return hipGetLastError();
 }
 
 hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const zd* rho_d,
-                           const zd* T, const zd* rho_n, const zd* pinv, int precond,
-                           const zd* v, zd* X, zd* Y, zd* S, zd* y, hipStream_t st) {
-  hipError_t e = launch_tbc_passes(g, t, khat, pinv, precond, -1, v, X, Y, S, st);
+                           const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
+                           const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y, long long ys,
+                           const int* active, hipStream_t st) {
+  hipError_t e = launch_tbc_passes(g, t, khat, pinv, precond, -1, nb, v, vs, X, Y, S, active, st);
   if (e != hipSuccess) return e;
   const int blk = 256;
   probe_begin(K_EPILOGUE, st);
-  hipLaunchKernelGGL(k_operator_epilogue, dim3((g.NM + blk - 1) / blk), dim3(blk), 0, st, g,
-                     rho_d, T, rho_n, pinv, precond, v, S, y);
-  probe_end(K_EPILOGUE, st, sizeof(zd) * (double)g.NM * (12.0 + (precond ? 9.0 : 0.0)));
+  hipLaunchKernelGGL(k_operator_epilogue, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g,
+                     rho_d, T, rho_n, pinv, precond, v, vs, S, y, ys, active);
+  probe_end(K_EPILOGUE, st, sizeof(zd) * (double)g.NM * (nb * 9.0 + 3.0 + (precond ? 9.0 : 0.0)));
   return hipGetLastError();
 }
 
 hipError_t launch_single_family(const Geo& g, const Trig& t, const zd* khat, int family,
                                 const zd* in, zd* X, zd* Y, zd* out, hipStream_t st) {
-  return launch_tbc_passes(g, t, khat, nullptr, 0, family, in, X, Y, out, st);
+  return launch_tbc_passes(g, t, khat, nullptr, 0, family, 1, in, 0, X, Y, out, nullptr, st);
 }
 
 // ---------------------------------------------------------------------------------
-// Krylov building blocks (deterministic two-stage reductions).
+// Krylov building blocks for nb right-hand sides iterating in lockstep.  Vector r of a
+// set lives at base + r * n; basis vector i of right-hand side r at V + i * ldj + r * n.
+// Reductions are two-stage and deterministic.  Inactive right-hand sides are skipped.
 // ---------------------------------------------------------------------------------
 constexpr int kDotGroup = 8;
 
-__global__ void k_dots(const zd* __restrict__ V, long long ldv, int nv, const zd* __restrict__ w,
-                       long long n, zd* __restrict__ partial) {
+// partial[(r * nvmax + vi) * nblk + blk] = sum over the block's slice of conj(V_vi,r) w_r
+__global__ void k_dots(const zd* __restrict__ V, long long ldj, int nv, int nvmax,
+                       const zd* __restrict__ wall, long long n, zd* __restrict__ partial,
+                       const int* __restrict__ active) {
   __shared__ zd red[kDotGroup][256];
+  const int r = blockIdx.z;
+  if (active && !active[r]) return;
   const int grp = blockIdx.y;
+  const zd* w = wall + r * n;
+  const zd* Vr = V + r * n;
   zd acc[kDotGroup];
   for (int t = 0; t < kDotGroup; ++t) acc[t] = mk(0.0, 0.0);
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -324,7 +361,7 @@ __global__ void k_dots(const zd* __restrict__ V, long long ldv, int nv, const zd
     const zd wi = w[i];
     for (int t = 0; t < kDotGroup; ++t) {
       const int vi = grp * kDotGroup + t;
-      if (vi < nv) acc[t] = acc[t] + conj(V[vi * ldv + i]) * wi;
+      if (vi < nv) acc[t] = acc[t] + conj(Vr[vi * ldj + i]) * wi;
     }
   }
   for (int t = 0; t < kDotGroup; ++t) red[t][threadIdx.x] = acc[t];
@@ -337,57 +374,81 @@ __global__ void k_dots(const zd* __restrict__ V, long long ldv, int nv, const zd
   }
   if (threadIdx.x < kDotGroup) {
     const int vi = grp * kDotGroup + threadIdx.x;
-    if (vi < nv) partial[(long long)vi * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
+    if (vi < nv)
+      partial[((long long)r * nvmax + vi) * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
   }
 }
 
-__global__ void k_reduce_cols(const zd* __restrict__ partial, int nblk, zd* __restrict__ out) {
+// out[r * ostride + vi] = sum_b partial;  when acc is given the sum is also added into
+// acc[r * astride + vi]
+__global__ void k_reduce_cols(const zd* __restrict__ partial, int nblk, int nvmax,
+                              zd* __restrict__ out, long long ostride, zd* __restrict__ acc,
+                              long long astride, const int* __restrict__ active) {
   __shared__ zd red[256];
-  const int vi = blockIdx.x;
-  zd acc = mk(0.0, 0.0);
-  for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc = acc + partial[(long long)vi * nblk + i];
-  red[threadIdx.x] = acc;
+  const int vi = blockIdx.x, r = blockIdx.y;
+  if (active && !active[r]) return;
+  zd s = mk(0.0, 0.0);
+  const zd* p = partial + ((long long)r * nvmax + vi) * nblk;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) s = s + p[i];
+  red[threadIdx.x] = s;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[vi] = red[0];
-}
-
-hipError_t launch_dots(const zd* V, long long ldv, int nv, const zd* w, long long n,
-                       zd* partial, int nblk, zd* h, hipStream_t st) {
-  const int ng = (nv + kDotGroup - 1) / kDotGroup;
-  hipLaunchKernelGGL(k_dots, dim3(nblk, ng), dim3(256), 0, st, V, ldv, nv, w, n, partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_cols, dim3(nv), dim3(256), 0, st, partial, nblk, h);
-  return hipGetLastError();
-}
-
-__global__ void k_update(const zd* __restrict__ V, long long ldv, int nv, const zd* __restrict__ h,
-                         zd* __restrict__ w, long long n) {
-  __shared__ zd hs[256];
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[i];
-  __syncthreads();
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    zd acc = w[i];
-    for (int vi = 0; vi < nv; ++vi) acc = acc - hs[vi] * V[vi * ldv + i];
-    w[i] = acc;
+  if (threadIdx.x == 0) {
+    out[r * ostride + vi] = red[0];
+    if (acc) acc[r * astride + vi] = acc[r * astride + vi] + red[0];
   }
 }
 
-hipError_t launch_update(const zd* V, long long ldv, int nv, const zd* h, zd* w, long long n,
-                         hipStream_t st) {
-  int nblk = (int)((n + 255) / 256);
-  if (nblk > 2048) nblk = 2048;
-  hipLaunchKernelGGL(k_update, dim3(nblk), dim3(256), 0, st, V, ldv, nv, h, w, n);
+hipError_t launch_dots(const zd* V, long long ldj, int nv, int nvmax, const zd* w, long long n,
+                       int nb, zd* partial, int nblk, zd* out, long long ostride, zd* acc,
+                       long long astride, const int* active, hipStream_t st) {
+  const int ng = (nv + kDotGroup - 1) / kDotGroup;
+  hipLaunchKernelGGL(k_dots, dim3(nblk, ng, nb), dim3(256), 0, st, V, ldj, nv, nvmax, w, n,
+                     partial, active);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_cols, dim3(nv, nb), dim3(256), 0, st, partial, nblk, nvmax, out,
+                     ostride, acc, astride, active);
   return hipGetLastError();
 }
 
-__global__ void k_norm2(const zd* __restrict__ w, long long n, double* __restrict__ partial) {
+// w_r -= sum_i h[r * hstride + i] V_i,r
+__global__ void k_update(const zd* __restrict__ V, long long ldj, int nv, const zd* __restrict__ h,
+                         long long hstride, zd* __restrict__ wall, long long n,
+                         const int* __restrict__ active) {
+  __shared__ zd hs[256];
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[r * hstride + i];
+  __syncthreads();
+  zd* w = wall + r * n;
+  const zd* Vr = V + r * n;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    zd a = w[i];
+    for (int vi = 0; vi < nv; ++vi) a = a - hs[vi] * Vr[vi * ldj + i];
+    w[i] = a;
+  }
+}
+
+hipError_t launch_update(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
+                         zd* w, long long n, int nb, const int* active, hipStream_t st) {
+  int nblk = (int)((n + 255) / 256);
+  if (nblk > 1024) nblk = 1024;
+  hipLaunchKernelGGL(k_update, dim3(nblk, nb), dim3(256), 0, st, V, ldj, nv, h, hstride, w, n,
+                     active);
+  return hipGetLastError();
+}
+
+__global__ void k_norm2(const zd* __restrict__ wall, long long n, double* __restrict__ partial,
+                        const int* __restrict__ active) {
   __shared__ double red[256];
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const zd* w = wall + r * n;
   double acc = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
@@ -398,88 +459,166 @@ __global__ void k_norm2(const zd* __restrict__ w, long long n, double* __restric
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partial[(long long)r * gridDim.x + blockIdx.x] = red[0];
 }
 
-__global__ void k_reduce_d(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+__global__ void k_reduce_d(const double* __restrict__ partial, int nblk, double* __restrict__ out,
+                           const int* __restrict__ active) {
   __shared__ double red[256];
+  const int r = blockIdx.x;
+  if (active && !active[r]) return;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += partial[i];
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += partial[(long long)r * nblk + i];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (threadIdx.x == 0) out[r] = red[0];
 }
 
-hipError_t launch_norm2(const zd* w, long long n, double* partial, int nblk, double* out,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_norm2, dim3(nblk), dim3(256), 0, st, w, n, partial);
+hipError_t launch_norm2(const zd* w, long long n, int nb, double* partial, int nblk, double* out,
+                        const int* active, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm2, dim3(nblk, nb), dim3(256), 0, st, w, n, partial, active);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_d, dim3(1), dim3(256), 0, st, partial, nblk, out);
+  hipLaunchKernelGGL(k_reduce_d, dim3(nb), dim3(256), 0, st, partial, nblk, out, active);
   return hipGetLastError();
 }
 
-// v = w / sqrt(nrm2[0]); v may alias w (element-wise, same index).
-__global__ void k_scale_copy(const zd* w, const double* __restrict__ nrm2, zd* v, long long n) {
-  const double s2 = nrm2[0];
+// v_r = w_r / sqrt(nrm2[r]); v may alias w (element-wise, same index).
+__global__ void k_scale_copy(const zd* wall, const double* __restrict__ nrm2, zd* vall, long long n,
+                             long long vstride, const int* __restrict__ active) {
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const double s2 = nrm2[r];
   const double sc = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+  const zd* w = wall + r * n;
+  zd* v = vall + r * vstride;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
     v[i] = sc * w[i];
 }
 
 hipError_t launch_scale_copy(const zd* w, const double* nrm2, zd* v, long long n,
-                             hipStream_t st) {
+                             long long vstride, int nb, const int* active, hipStream_t st) {
   int nblk = (int)((n + 255) / 256);
-  if (nblk > 4096) nblk = 4096;
-  hipLaunchKernelGGL(k_scale_copy, dim3(nblk), dim3(256), 0, st, w, nrm2, v, n);
+  if (nblk > 2048) nblk = 2048;
+  hipLaunchKernelGGL(k_scale_copy, dim3(nblk, nb), dim3(256), 0, st, w, nrm2, v, n, vstride,
+                     active);
   return hipGetLastError();
 }
 
-__global__ void k_sub(const zd* __restrict__ b, const zd* __restrict__ w, zd* __restrict__ r,
-                      long long n) {
+__global__ void k_sub(const zd* __restrict__ b, const zd* __restrict__ w, zd* __restrict__ out,
+                      long long n, long long total) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    r[i] = b[i] - w[i];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
+    out[i] = b[i] - w[i];
 }
 
-hipError_t launch_sub(const zd* b, const zd* w, zd* r, long long n, hipStream_t st) {
-  int nblk = (int)((n + 255) / 256);
+hipError_t launch_sub(const zd* b, const zd* w, zd* r, long long total, hipStream_t st) {
+  int nblk = (int)((total + 255) / 256);
   if (nblk > 4096) nblk = 4096;
-  hipLaunchKernelGGL(k_sub, dim3(nblk), dim3(256), 0, st, b, w, r, n);
+  hipLaunchKernelGGL(k_sub, dim3(nblk), dim3(256), 0, st, b, w, r, total, total);
   return hipGetLastError();
 }
 
-// x += P^{-1} (sum_i y_i V_i)
-__global__ void k_combine(Geo g, const zd* __restrict__ V, long long ldv, int nv,
-                          const zd* __restrict__ y, const zd* __restrict__ pinv,
-                          zd* __restrict__ x) {
+// Givens step of GMRES for column j of every active right-hand side (one thread each).
+// H[(r * restart + j) * (restart + 1) + i]: column j of the Hessenberg matrix, rotated in
+// place into R.  Rotation [[c, s], [-conj(s), conj(c)]] with c = conj(a)/d, s = conj(b)/d.
+__global__ void k_givens(Krylov kv, int j, int nb) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nb || !kv.active[r]) return;
+  const int R = kv.restart;
+  zd* col = kv.H + ((long long)r * R + j) * (R + 1);
+  zd* cs = kv.cs + (long long)r * R;
+  zd* sn = kv.sn + (long long)r * R;
+  zd* gv = kv.g + (long long)r * (R + 1);
+  col[j + 1] = mk(sqrt(fmax(kv.nrm2[r], 0.0)), 0.0);
+  for (int i = 0; i < j; ++i) {
+    const zd t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = conj(sn[i]) * col[i] * mk(-1.0, 0.0) + conj(cs[i]) * col[i + 1];
+    col[i] = t;
+  }
+  const double den = sqrt(cabs2(col[j]) + cabs2(col[j + 1]));
+  zd c, s;
+  if (den == 0.0) {
+    c = mk(1.0, 0.0);
+    s = mk(0.0, 0.0);
+  } else {
+    c = (1.0 / den) * conj(col[j]);
+    s = (1.0 / den) * conj(col[j + 1]);
+  }
+  cs[j] = c;
+  sn[j] = s;
+  col[j] = mk(den, 0.0);
+  col[j + 1] = mk(0.0, 0.0);
+  const zd gj = gv[j];
+  gv[j + 1] = mk(-1.0, 0.0) * conj(s) * gj;
+  gv[j] = c * gj;
+  const bool conv = sqrt(cabs2(gv[j + 1])) <= kv.tol * kv.bnorm[r] || den == 0.0;
+  kv.jcount[r] = j + 1;
+  if (conv || j + 1 >= R) kv.active[r] = 0;
+}
+
+hipError_t launch_givens(const Krylov& kv, int j, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_givens, dim3((nb + 63) / 64), dim3(64), 0, st, kv, j, nb);
+  return hipGetLastError();
+}
+
+// Back-substitution R y = g on the first jcount[r] columns (one thread per rhs).
+__global__ void k_solve_y(Krylov kv, int nb) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nb || !kv.incycle[r]) return;
+  const int R = kv.restart;
+  const int jc = kv.jcount[r];
+  const zd* Hr = kv.H + (long long)r * R * (R + 1);
+  const zd* gv = kv.g + (long long)r * (R + 1);
+  zd* y = kv.y + (long long)r * R;
+  for (int i = jc - 1; i >= 0; --i) {
+    zd acc = gv[i];
+    for (int c = i + 1; c < jc; ++c) acc = acc - Hr[(long long)c * (R + 1) + i] * y[c];
+    y[i] = cdiv(acc, Hr[(long long)i * (R + 1) + i]);
+  }
+}
+
+hipError_t launch_solve_y(const Krylov& kv, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_solve_y, dim3((nb + 63) / 64), dim3(64), 0, st, kv, nb);
+  return hipGetLastError();
+}
+
+// x_r += P^{-1} (sum_{i < jcount[r]} y[r][i] V_i,r)
+__global__ void k_combine(Geo g, Krylov kv, const zd* __restrict__ V, long long ldj,
+                          const zd* __restrict__ pinv, zd* __restrict__ xall) {
   __shared__ zd ys[256];
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) ys[i] = y[i];
+  const int r = blockIdx.y;
+  if (!kv.incycle[r]) return;
+  const int jc = kv.jcount[r];
+  for (int i = threadIdx.x; i < jc; i += blockDim.x) ys[i] = kv.y[(long long)r * kv.restart + i];
   __syncthreads();
   const int mn = blockIdx.x * blockDim.x + threadIdx.x;
   if (mn >= g.NM) return;
+  const long long n = 3LL * g.NM;
+  const zd* Vr = V + r * n;
+  zd* x = xall + r * n;
   zd u[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
-  for (int vi = 0; vi < nv; ++vi) {
-    const zd* col = V + vi * ldv;
+  for (int vi = 0; vi < jc; ++vi) {
+    const zd* col = Vr + vi * ldj;
     for (int c = 0; c < 3; ++c) u[c] = u[c] + ys[vi] * col[(long long)c * g.NM + mn];
   }
-  for (int r = 0; r < 3; ++r) {
-    const zd z = pinv[(3 * r) * (long long)g.NM + mn] * u[0] +
-                 pinv[(3 * r + 1) * (long long)g.NM + mn] * u[1] +
-                 pinv[(3 * r + 2) * (long long)g.NM + mn] * u[2];
-    x[(long long)r * g.NM + mn] = x[(long long)r * g.NM + mn] + z;
+  for (int k = 0; k < 3; ++k) {
+    const zd z = pinv[(3 * k) * (long long)g.NM + mn] * u[0] +
+                 pinv[(3 * k + 1) * (long long)g.NM + mn] * u[1] +
+                 pinv[(3 * k + 2) * (long long)g.NM + mn] * u[2];
+    x[(long long)k * g.NM + mn] = x[(long long)k * g.NM + mn] + z;
   }
 }
 
-hipError_t launch_combine(const Geo& g, const zd* V, long long ldv, int nv, const zd* y,
-                          const zd* pinv, zd* x, hipStream_t st) {
+hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long ldj,
+                          const zd* pinv, zd* x, int nb, hipStream_t st) {
   const int blk = 256;
-  hipLaunchKernelGGL(k_combine, dim3((g.NM + blk - 1) / blk), dim3(blk), 0, st, g, V, ldv, nv, y,
+  hipLaunchKernelGGL(k_combine, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g, kv, V, ldj,
                      pinv, x);
   return hipGetLastError();
 }

@@ -47,3 +47,39 @@ def test_lossy_8x8x2_full_size():
         co = inc.pol
         assert abs(sig[i][co] - o[co]) <= 1e-9 * o[co]
     plan.close()
+
+
+@pytest.mark.timeout(900)
+def test_layered_16x16x4_against_stored_oracle():
+    """Three-layer 16 x 16 x 4 wavelength cavity on the 512 x 512 x 128 grid (P = 1250),
+    theta = 45 deg, phi = 0, both polarisations, against oracle values stored by
+    tests/golden/make_layered_16x16x4.py: 4000 sampled aperture coefficients and 20000
+    sampled field values per incidence, and the backscatter RCS."""
+    import os
+
+    import torch
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "layered_16x16x4.npz")
+    ref = np.load(path)
+    wl = W.layered_16x16x4()
+    print(f"\n[case] {wl.name}", flush=True)
+    incs = wl.incidences
+    plan = P.Plan.from_cavity(wl.cavity)
+    fields = plan.solve_batch([i.theta for i in incs], [i.phi for i in incs],
+                              [i.pol for i in incs])
+    torch.cuda.synchronize()
+    idx = torch.as_tensor(ref["field_idx"], device="cuda")
+    for i, inc in enumerate(incs):
+        ap = plan.aperture(i)[ref["ap_idx"]]
+        a_ref = ref[f"ap_{i}"]
+        err_a = np.linalg.norm(ap - a_ref) / np.linalg.norm(a_ref)
+        fs = fields[i].reshape(-1).index_select(0, idx).cpu().numpy()
+        f_ref = ref[f"field_{i}"]
+        err_f = np.linalg.norm(fs - f_ref) / np.linalg.norm(f_ref)
+        sig = plan.rcs(i, inc.theta, inc.phi)[0]
+        r_ref = ref[f"rcs_{i}"]
+        co = inc.pol
+        err_r = abs(sig[co] - r_ref[co]) / r_ref[co]
+        print(f"[compare] incidence {i}: aperture {err_a:.2e}, field {err_f:.2e}, "
+              f"rcs {err_r:.2e}", flush=True)
+        assert err_a <= 1e-10 and err_f <= 1e-10 and err_r <= 1e-9
+    plan.close()

@@ -143,48 +143,54 @@ __device__ inline void dft_r(cx<R>* v) {
   else dft5<R, INV>(v);
 }
 
-// One Stockham stage of radix RDX: combines RDX sub-transforms of length ns.
+// One Stockham stage of radix RDX over C interleaved transforms: element (pos, col) of
+// the batch sits at buf[pos * C + col].  Work item w = j * C + col, so consecutive
+// threads handle the same butterfly of consecutive transforms: LDS accesses are
+// contiguous and each twiddle is shared by C lanes.
 template <int RDX, typename R, bool INV>
 __device__ inline void fft_stage(const cx<R>* __restrict__ in, cx<R>* __restrict__ out, int n,
-                                 int ns, const zd* __restrict__ tw, int tid, int nthr) {
+                                 int ns, int C, const zd* __restrict__ tw, int tid, int nthr) {
   const int nb = n / RDX;
   const int tstep = n / (ns * RDX);
-  for (int j = tid; j < nb; j += nthr) {
+  const int total = nb * C;
+  for (int w = tid; w < total; w += nthr) {
+    const int j = w / C;
+    const int col = w - j * C;
     const int k = j % ns;
     cx<R> v[RDX];
 #pragma unroll
-    for (int r = 0; r < RDX; ++r) v[r] = in[j + r * nb];
+    for (int r = 0; r < RDX; ++r) v[r] = in[(j + r * nb) * C + col];
     if (k > 0) {
 #pragma unroll
       for (int r = 1; r < RDX; ++r) {
-        zd w = tw[r * k * tstep];
-        v[r] = v[r] * mk<R>((R)w.re, INV ? -(R)w.im : (R)w.im);
+        zd w2 = tw[r * k * tstep];
+        v[r] = v[r] * mk<R>((R)w2.re, INV ? -(R)w2.im : (R)w2.im);
       }
     }
     dft_r<RDX, R, INV>(v);
     const int d = (j / ns) * ns * RDX + k;
 #pragma unroll
-    for (int r = 0; r < RDX; ++r) out[d + r * ns] = v[r];
+    for (int r = 0; r < RDX; ++r) out[(d + r * ns) * C + col] = v[r];
   }
 }
 
-// One length-n transform held in LDS buffer `a` (scratch `b` of the same length).
+// C interleaved length-n transforms held in LDS buffer `a` (scratch `b` of the same size).
 // Threads tid = 0..nthr-1 cooperate; every thread of the block must call this with the
-// same plan (it contains __syncthreads).  Returns the buffer that holds the result.
+// same plan and C (it contains __syncthreads).  Returns the buffer that holds the result.
 // Forward: X_k = sum_j x_j e^{-2 pi i jk/n};  INV: e^{+2 pi i jk/n}, unnormalised.
 template <typename R, bool INV>
 __device__ cx<R>* fft_lds(cx<R>* a, cx<R>* b, const FftPlan& p, const zd* __restrict__ tw,
-                          int tid, int nthr) {
+                          int tid, int nthr, int C = 1) {
   int ns = 1;
   cx<R>* in = a;
   cx<R>* out = b;
   for (int s = 0; s < p.nst; ++s) {
     const int rdx = p.radix[s];
     switch (rdx) {
-      case 2: fft_stage<2, R, INV>(in, out, p.n, ns, tw, tid, nthr); break;
-      case 3: fft_stage<3, R, INV>(in, out, p.n, ns, tw, tid, nthr); break;
-      case 4: fft_stage<4, R, INV>(in, out, p.n, ns, tw, tid, nthr); break;
-      default: fft_stage<5, R, INV>(in, out, p.n, ns, tw, tid, nthr); break;
+      case 2: fft_stage<2, R, INV>(in, out, p.n, ns, C, tw, tid, nthr); break;
+      case 3: fft_stage<3, R, INV>(in, out, p.n, ns, C, tw, tid, nthr); break;
+      case 4: fft_stage<4, R, INV>(in, out, p.n, ns, C, tw, tid, nthr); break;
+      default: fft_stage<5, R, INV>(in, out, p.n, ns, C, tw, tid, nthr); break;
     }
     __syncthreads();
     cx<R>* t = in;
@@ -195,20 +201,20 @@ __device__ cx<R>* fft_lds(cx<R>* a, cx<R>* b, const FftPlan& p, const zd* __rest
   return in;
 }
 
-// Even (cos) or odd (sin) extension of x[0..len-1] (len <= L+1, missing entries zero)
-// into buf[0..2L-1].
+// Even (cos) or odd (sin) extension of entry idx (0 <= idx <= L) of transform col into a
+// length-2L batch buffer with C interleaved transforms (entries never stored stay zero).
 template <typename R>
-__device__ inline void store_extension(cx<R>* buf, int L, bool is_cos, int idx, cx<R> x) {
-  // caller guarantees 0 <= idx <= L
+__device__ inline void store_extension(cx<R>* buf, int L, bool is_cos, int idx, cx<R> x,
+                                       int C = 1, int col = 0) {
   if (is_cos) {
-    buf[idx] = x;
-    if (idx > 0 && idx < L) buf[2 * L - idx] = x;
+    buf[idx * C + col] = x;
+    if (idx > 0 && idx < L) buf[(2 * L - idx) * C + col] = x;
   } else {
     if (idx == 0 || idx == L) {
-      buf[idx] = mk<R>(0, 0);
+      buf[idx * C + col] = mk<R>(0, 0);
     } else {
-      buf[idx] = x;
-      buf[2 * L - idx] = mk<R>(-x.re, -x.im);
+      buf[idx * C + col] = x;
+      buf[(2 * L - idx) * C + col] = mk<R>(-x.re, -x.im);
     }
   }
 }

@@ -7,6 +7,8 @@
 // three such grids [E1 | E2 | E3]; entries outside N1, N2, N3 stay zero.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "kernels.hpp"
 
 namespace cav {
@@ -82,34 +84,43 @@ hipError_t launch_rhs(const Geo& g, const Wave* waves, int nb, zd* b, hipStream_
 __device__ inline bool fam_xcos(int f) { return f != 1; }
 __device__ inline bool fam_ycos(int f) { return f != 0; }
 
-// Pass 1.  fam_fixed >= 0: `v` is the coefficient grid of that family (inspection path);
-// otherwise `v` is a padded aperture vector, optionally preconditioned first.
+// Each FFT kernel holds C transforms of a block interleaved in LDS, element (pos, c) at
+// buf[pos * C + c]; global loads and stores map consecutive lanes to consecutive
+// addresses.  C is chosen on the host from the LDS budget; the last block of a grid may
+// hold fewer transforms (Cb).
+
+// Pass 1: rows m0 .. m0+Cb-1 of one family.  fam_fixed >= 0: `v` is the coefficient grid
+// of that family (inspection path); otherwise `v` is a padded aperture vector, optionally
+// preconditioned first.
 __global__ void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2, const zd* __restrict__ pinv,
-                               int precond, int fam_fixed, const zd* __restrict__ vall,
+                               int precond, int fam_fixed, int C, const zd* __restrict__ vall,
                                long long vs, zd* __restrict__ Xall, const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
-  __shared__ zd c0s;
+  __shared__ zd c0s[64];
   const int rhs = blockIdx.z;
   if (active && !active[rhs]) return;
   const zd* v = vall + rhs * vs;
   const int nf = fam_fixed >= 0 ? 1 : 3;
   zd* X = Xall + (long long)rhs * nf * (g.M + 1) * g.P2;
-  const int m = blockIdx.x;
+  const int m0 = blockIdx.x * C;
+  const int Cb = min(C, g.M + 1 - m0);
   const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
   const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
   const int L = g.nq2, P = g.P2;
   zd* a = reinterpret_cast<zd*>(smem_raw);
-  zd* b = a + P;
+  zd* b = a + (long long)P * C;
   const bool ycos = fam_ycos(f);
   const int tid = threadIdx.x, nt = blockDim.x;
-  const double mu = M_PI * m / g.a;
-  for (int i = tid; i < 2 * L; i += nt) a[i] = mk(0.0, 0.0);
+  for (int i = tid; i < 2 * L * Cb; i += nt) a[i] = mk(0.0, 0.0);
   __syncthreads();
-  for (int n = tid; n <= g.N; n += nt) {
-    const long long mn = (long long)m * (g.N + 1) + n;
-    zd c;
+  const int rowlen = g.N + 1;
+  for (int w = tid; w < rowlen * Cb; w += nt) {
+    const int c = w / rowlen, n = w - c * rowlen;
+    const int m = m0 + c;
+    const long long mn = (long long)m * rowlen + n;
+    zd val;
     if (fam_fixed >= 0) {
-      c = v[mn];
+      val = v[mn];
     } else {
       zd z[3] = {v[mn], v[g.NM + mn], v[2LL * g.NM + mn]};
       if (precond) {
@@ -120,126 +131,140 @@ __global__ void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2, const zd* __restrict__
                  pinv[(3 * r + 2) * (long long)g.NM + mn] * z[2];
         z[0] = y[0]; z[1] = y[1]; z[2] = y[2];
       }
-      const double nu = M_PI * n / g.b;
-      c = f == 0 ? z[0] : (f == 1 ? z[1] : (nu * z[0] - mu * z[1]));
+      const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
+      val = f == 0 ? z[0] : (f == 1 ? z[1] : (nu * z[0] - mu * z[1]));
     }
-    store_extension(a, L, ycos, n, c);
-    if (n == 0) c0s = c;
+    store_extension(a, L, ycos, n, val, Cb, c);
+    if (n == 0) c0s[c] = val;
   }
   __syncthreads();
-  zd* r = fft_lds<double, false>(a, b, ext2.p, ext2.tw, tid, nt);
+  zd* r = fft_lds<double, false>(a, b, ext2.p, ext2.tw, tid, nt, Cb);
   zd* o = (r == a) ? b : a;
-  for (int i = tid; i < P; i += nt) {
+  for (int w = tid; w < P * Cb; w += nt) {
+    const int i = w / Cb, c = w - i * Cb;
     zd val = mk(0.0, 0.0);
     if (i <= L) {
-      const zd F = r[i];
-      const zd s = ycos ? 0.5 * (F + c0s) : 0.5 * mul_i(F);
-      const double w = (i == 0 || i == L) ? 0.5 * g.hq2 : g.hq2;
-      val = w * s;
+      const zd F = r[w];
+      const zd sy = ycos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
+      const double wt = (i == 0 || i == L) ? 0.5 * g.hq2 : g.hq2;
+      val = wt * sy;
     }
-    o[i] = val;
+    o[w] = val;
   }
   __syncthreads();
-  zd* r2 = fft_lds<double, false>(o, r, box2.p, box2.tw, tid, nt);
-  zd* dst = X + ((long long)slot * (g.M + 1) + m) * g.P2;
-  for (int k = tid; k < P; k += nt) dst[k] = r2[k];
+  zd* r2 = fft_lds<double, false>(o, r, box2.p, box2.tw, tid, nt, Cb);
+  zd* dst = X + ((long long)slot * (g.M + 1) + m0) * g.P2;
+  for (int w = tid; w < P * Cb; w += nt) {
+    const int c = w / P, k = w - c * P;
+    dst[(long long)c * g.P2 + k] = r2[k * Cb + c];
+  }
 }
 
-// Pass 2: TK adjacent columns k2 per block, blockDim.x / TK threads per column.
+// Pass 2: columns k0 .. k0+Cb-1 of one family.
 __global__ void k_tbc_cols(Geo g, Fft ext1, Fft box1, const zd* __restrict__ khat, int fam_fixed,
-                           int TK, const zd* __restrict__ Xall, zd* __restrict__ Yall,
+                           int C, const zd* __restrict__ Xall, zd* __restrict__ Yall,
                            const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
-  __shared__ zd c0s[16];
+  __shared__ zd c0s[64];
   const int rhs = blockIdx.z;
   if (active && !active[rhs]) return;
   const int nf = fam_fixed >= 0 ? 1 : 3;
   const long long wsz = (long long)nf * (g.M + 1) * g.P2;
-  const zd* X = Xall + rhs * wsz;
-  zd* Y = Yall + rhs * wsz;
   const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
   const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
-  const int tpc = blockDim.x / TK;
-  const int sub = threadIdx.x / tpc, lt = threadIdx.x % tpc;
-  const int k2 = blockIdx.x * TK + sub;
-  const bool valid = k2 < g.P2;
+  const zd* X = Xall + rhs * wsz + (long long)slot * (g.M + 1) * g.P2;
+  zd* Y = Yall + rhs * wsz + (long long)slot * (g.M + 1) * g.P2;
+  const int k0 = blockIdx.x * C;
+  const int Cb = min(C, g.P2 - k0);
   const int L = g.nq1, P = g.P1;
-  zd* a = reinterpret_cast<zd*>(smem_raw) + (long long)sub * 2 * P;
-  zd* b = a + P;
+  zd* a = reinterpret_cast<zd*>(smem_raw);
+  zd* b = a + (long long)P * C;
   const bool xcos = fam_xcos(f);
-  const zd* src = X + (long long)slot * (g.M + 1) * g.P2;
-  for (int i = lt; i < 2 * L; i += tpc) a[i] = mk(0.0, 0.0);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < 2 * L * Cb; i += nt) a[i] = mk(0.0, 0.0);
   __syncthreads();
-  for (int m = lt; m <= g.M; m += tpc) {
-    const zd x = valid ? src[(long long)m * g.P2 + k2] : mk(0.0, 0.0);
-    store_extension(a, L, xcos, m, x);
-    if (m == 0) c0s[sub] = x;
+  for (int w = tid; w < (g.M + 1) * Cb; w += nt) {
+    const int m = w / Cb, c = w - m * Cb;
+    const zd x = X[(long long)m * g.P2 + k0 + c];
+    store_extension(a, L, xcos, m, x, Cb, c);
+    if (m == 0) c0s[c] = x;
   }
   __syncthreads();
-  zd* r = fft_lds<double, false>(a, b, ext1.p, ext1.tw, lt, tpc);
+  zd* r = fft_lds<double, false>(a, b, ext1.p, ext1.tw, tid, nt, Cb);
   zd* o = (r == a) ? b : a;
-  const zd c0 = c0s[sub];
-  for (int i = lt; i < P; i += tpc) {
+  for (int w = tid; w < P * Cb; w += nt) {
+    const int i = w / Cb, c = w - i * Cb;
     zd val = mk(0.0, 0.0);
     if (i <= L) {
-      const zd F = r[i];
-      const zd s = xcos ? 0.5 * (F + c0) : 0.5 * mul_i(F);
-      const double w = (i == 0 || i == L) ? 0.5 * g.hq1 : g.hq1;
-      val = w * s;
+      const zd F = r[w];
+      const zd sx = xcos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
+      const double wt = (i == 0 || i == L) ? 0.5 * g.hq1 : g.hq1;
+      val = wt * sx;
     }
-    o[i] = val;
+    o[w] = val;
   }
   __syncthreads();
-  zd* r2 = fft_lds<double, false>(o, r, box1.p, box1.tw, lt, tpc);
-  for (int k1 = lt; k1 < P; k1 += tpc)
-    r2[k1] = valid ? r2[k1] * khat[(long long)k1 * g.P2 + k2] : mk(0.0, 0.0);
+  zd* r2 = fft_lds<double, false>(o, r, box1.p, box1.tw, tid, nt, Cb);
+  for (int w = tid; w < P * Cb; w += nt) {
+    const int k1 = w / Cb, c = w - k1 * Cb;
+    r2[w] = r2[w] * khat[(long long)k1 * g.P2 + k0 + c];
+  }
   __syncthreads();
   zd* o2 = (r2 == a) ? b : a;
-  zd* r3 = fft_lds<double, true>(r2, o2, box1.p, box1.tw, lt, tpc);
+  zd* r3 = fft_lds<double, true>(r2, o2, box1.p, box1.tw, tid, nt, Cb);
   zd* o3 = (r3 == a) ? b : a;
-  for (int i = lt; i <= L; i += tpc) store_extension(o3, L, xcos, i, r3[i]);
+  for (int w = tid; w < (L + 1) * Cb; w += nt) {
+    const int i = w / Cb, c = w - i * Cb;
+    store_extension(o3, L, xcos, i, r3[w], Cb, c);
+  }
   __syncthreads();
-  zd* r4 = fft_lds<double, false>(o3, r3, ext1.p, ext1.tw, lt, tpc);
-  if (valid) {
-    zd* dst = Y + (long long)slot * (g.M + 1) * g.P2;
-    for (int m = lt; m <= g.M; m += tpc) {
-      const zd F = r4[m];
-      const zd s = xcos ? 0.5 * F : 0.5 * mul_i(F);
-      dst[(long long)m * g.P2 + k2] = g.hq1 * s;
-    }
+  zd* r4 = fft_lds<double, false>(o3, r3, ext1.p, ext1.tw, tid, nt, Cb);
+  for (int w = tid; w < (g.M + 1) * Cb; w += nt) {
+    const int m = w / Cb, c = w - m * Cb;
+    const zd F = r4[w];
+    const zd s = xcos ? 0.5 * F : 0.5 * mul_i(F);
+    Y[(long long)m * g.P2 + k0 + c] = g.hq1 * s;
   }
 }
 
-// Pass 3: rows backward; writes S[slot][mn].
-__global__ void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed, const zd* __restrict__ Yall,
-                               zd* __restrict__ Sall, const int* __restrict__ active) {
+// Pass 3: rows m0 .. m0+Cb-1 backward; writes S[slot][mn].
+__global__ void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed, int C,
+                               const zd* __restrict__ Yall, zd* __restrict__ Sall,
+                               const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
   const int rhs = blockIdx.z;
   if (active && !active[rhs]) return;
   const int nf = fam_fixed >= 0 ? 1 : 3;
-  const zd* Y = Yall + (long long)rhs * nf * (g.M + 1) * g.P2;
-  zd* S = Sall + (long long)rhs * nf * g.NM;
-  const int m = blockIdx.x;
   const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
   const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
+  const zd* Y = Yall + (long long)rhs * nf * (g.M + 1) * g.P2 + (long long)slot * (g.M + 1) * g.P2;
+  zd* S = Sall + (long long)rhs * nf * g.NM + (long long)slot * g.NM;
+  const int m0 = blockIdx.x * C;
+  const int Cb = min(C, g.M + 1 - m0);
   const int L = g.nq2, P = g.P2;
   zd* a = reinterpret_cast<zd*>(smem_raw);
-  zd* b = a + P;
+  zd* b = a + (long long)P * C;
   const bool ycos = fam_ycos(f);
   const int tid = threadIdx.x, nt = blockDim.x;
-  const zd* src = Y + ((long long)slot * (g.M + 1) + m) * g.P2;
-  for (int k = tid; k < P; k += nt) a[k] = src[k];
+  for (int w = tid; w < P * Cb; w += nt) {
+    const int c = w / P, k = w - c * P;
+    a[k * Cb + c] = Y[(long long)(m0 + c) * g.P2 + k];
+  }
   __syncthreads();
-  zd* r = fft_lds<double, true>(a, b, box2.p, box2.tw, tid, nt);
+  zd* r = fft_lds<double, true>(a, b, box2.p, box2.tw, tid, nt, Cb);
   zd* o = (r == a) ? b : a;
-  for (int i = tid; i <= L; i += nt) store_extension(o, L, ycos, i, r[i]);
+  for (int w = tid; w < (L + 1) * Cb; w += nt) {
+    const int i = w / Cb, c = w - i * Cb;
+    store_extension(o, L, ycos, i, r[w], Cb, c);
+  }
   __syncthreads();
-  zd* r2 = fft_lds<double, false>(o, r, ext2.p, ext2.tw, tid, nt);
-  zd* dst = S + (long long)slot * g.NM + (long long)m * (g.N + 1);
-  for (int n = tid; n <= g.N; n += nt) {
-    const zd F = r2[n];
+  zd* r2 = fft_lds<double, false>(o, r, ext2.p, ext2.tw, tid, nt, Cb);
+  const int rowlen = g.N + 1;
+  for (int w = tid; w < rowlen * Cb; w += nt) {
+    const int c = w / rowlen, n = w - c * rowlen;
+    const zd F = r2[n * Cb + c];
     const zd s = ycos ? 0.5 * F : 0.5 * mul_i(F);
-    dst[n] = g.hq2 * s;
+    S[(long long)(m0 + c) * rowlen + n] = g.hq2 * s;
   }
 }
 
@@ -284,10 +309,18 @@ __global__ void k_operator_epilogue(Geo g, const zd* __restrict__ rho_d, const z
   y[2LL * g.NM + mn] = r3;
 }
 
-static int cols_per_block(int P) {
-  int tk = 8;
-  while (tk > 1 && (size_t)tk * 2 * P * sizeof(zd) > 64 * 1024) tk >>= 1;
-  return tk;
+// Transforms per block for an FFT kernel whose two LDS buffers hold len elements each.
+static int batch_per_block(int len, int cap) {
+  static long long budget = -1;
+  if (budget < 0) {
+    const char* e = getenv("CAVITY_LDS_BUDGET");
+    budget = e ? atoll(e) : 40000;
+  }
+  int c = (int)(budget / (2LL * len * (long long)sizeof(zd)));
+  if (c < 1) c = 1;
+  if (c > cap) c = cap;
+  if (c > 64) c = 64;
+  return c;
 }
 
 static hipError_t launch_tbc_passes(const Geo& g, const Trig& t, const zd* khat, const zd* pinv,
@@ -297,23 +330,26 @@ static hipError_t launch_tbc_passes(const Geo& g, const Trig& t, const zd* khat,
   const double zb = sizeof(zd);
   const double xbytes = zb * nb * nf * (g.M + 1) * (double)g.P2;   // one X or Y workspace
   const double vin = nb * (zb * (fam_fixed >= 0 ? 1.0 : 3.0) * g.NM) + (precond ? zb * 9.0 * g.NM : 0.0);
+  const int cr = batch_per_block(g.P2, g.M + 1);
   probe_begin(K_TBC_ROWS_FWD, st);
-  hipLaunchKernelGGL(k_tbc_rows_fwd, dim3(g.M + 1, nf, nb), dim3(256), 2 * g.P2 * sizeof(zd), st,
-                     g, t.ext2, t.box2, pinv, precond, fam_fixed, v, vs, X, active);
+  hipLaunchKernelGGL(k_tbc_rows_fwd, dim3((g.M + 1 + cr - 1) / cr, nf, nb), dim3(256),
+                     2 * (size_t)g.P2 * cr * sizeof(zd), st, g, t.ext2, t.box2, pinv, precond,
+                     fam_fixed, cr, v, vs, X, active);
   probe_end(K_TBC_ROWS_FWD, st, vin + xbytes);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int tk = cols_per_block(g.P1);
+  const int cc = batch_per_block(g.P1, g.P2);
   probe_begin(K_TBC_COLS, st);
-  hipLaunchKernelGGL(k_tbc_cols, dim3((g.P2 + tk - 1) / tk, nf, nb), dim3(256),
-                     (size_t)tk * 2 * g.P1 * sizeof(zd), st, g, t.ext1, t.box1, khat, fam_fixed,
-                     tk, X, Y, active);
+  hipLaunchKernelGGL(k_tbc_cols, dim3((g.P2 + cc - 1) / cc, nf, nb), dim3(256),
+                     2 * (size_t)g.P1 * cc * sizeof(zd), st, g, t.ext1, t.box1, khat, fam_fixed,
+                     cc, X, Y, active);
   probe_end(K_TBC_COLS, st, 2.0 * xbytes + zb * (double)g.P1 * g.P2);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   probe_begin(K_TBC_ROWS_BWD, st);
-  hipLaunchKernelGGL(k_tbc_rows_bwd, dim3(g.M + 1, nf, nb), dim3(256), 2 * g.P2 * sizeof(zd), st,
-                     g, t.ext2, t.box2, fam_fixed, Y, S, active);
+  hipLaunchKernelGGL(k_tbc_rows_bwd, dim3((g.M + 1 + cr - 1) / cr, nf, nb), dim3(256),
+                     2 * (size_t)g.P2 * cr * sizeof(zd), st, g, t.ext2, t.box2, fam_fixed, cr, Y,
+                     S, active);
   probe_end(K_TBC_ROWS_BWD, st, xbytes + zb * nb * nf * g.NM);
   return hipGetLastError();
 }
@@ -630,77 +666,80 @@ hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long
 // columns along x with TK adjacent columns per block.
 // tbuf[l][jj][m][i2], jj = j - j0.
 // ---------------------------------------------------------------------------------
-__global__ void k_synth_rows(Geo g, Fft out2, const zd* __restrict__ pi_d,
+__global__ void k_synth_rows(Geo g, Fft out2, int C, const zd* __restrict__ pi_d,
                              const zd* __restrict__ theta_d, const zd* __restrict__ pi_n,
                              const zd* __restrict__ xap, int j0, int jn, zd* __restrict__ tbuf) {
   CAV_DYN_SMEM(smem_raw);
-  __shared__ zd c0s;
-  const int m = blockIdx.x, jj = blockIdx.y, l = blockIdx.z;
+  __shared__ zd c0s[64];
+  const int jj = blockIdx.y, l = blockIdx.z;
   const int j = j0 + jj;
+  const int m0 = blockIdx.x * C;
+  const int Cb = min(C, g.M + 1 - m0);
   const int L = g.ny;
   zd* a = reinterpret_cast<zd*>(smem_raw);
-  zd* b = a + 2 * L;
+  zd* b = a + 2LL * L * C;
   const bool ycos = (l == 1);  // E1: sin, E2: cos, E3: sin along y
   const int tid = threadIdx.x, nt = blockDim.x;
-  const double mu = M_PI * m / g.a;
-  for (int i = tid; i < 2 * L; i += nt) a[i] = mk(0.0, 0.0);
+  for (int i = tid; i < 2 * L * Cb; i += nt) a[i] = mk(0.0, 0.0);
   __syncthreads();
   const long long NM = g.NM;
-  for (int n = tid; n <= g.N; n += nt) {
-    const long long mn = (long long)m * (g.N + 1) + n;
-    zd c;
+  const int rowlen = g.N + 1;
+  for (int w = tid; w < rowlen * Cb; w += nt) {
+    const int c = w / rowlen, n = w - c * rowlen;
+    const int m = m0 + c;
+    const long long mn = (long long)m * rowlen + n;
+    zd val;
     if (l < 2) {
-      c = pi_d[(long long)j * NM + mn] * xap[l * NM + mn];
+      val = pi_d[(long long)j * NM + mn] * xap[l * NM + mn];
       if (theta_d) {
-        const double fac = l == 0 ? mu : M_PI * n / g.b;
-        c = c + fac * (theta_d[(long long)j * NM + mn] * xap[2 * NM + mn]);
+        const double fac = l == 0 ? M_PI * m / g.a : M_PI * n / g.b;
+        val = val + fac * (theta_d[(long long)j * NM + mn] * xap[2 * NM + mn]);
       }
     } else {
-      c = pi_n[(long long)j * NM + mn] * xap[2 * NM + mn];
+      val = pi_n[(long long)j * NM + mn] * xap[2 * NM + mn];
     }
-    store_extension(a, L, ycos, n, c);
-    if (n == 0) c0s = c;
+    store_extension(a, L, ycos, n, val, Cb, c);
+    if (n == 0) c0s[c] = val;
   }
   __syncthreads();
-  zd* r = fft_lds<double, false>(a, b, out2.p, out2.tw, tid, nt);
-  zd* dst = tbuf + (((long long)l * jn + jj) * (g.M + 1) + m) * (g.ny + 1);
-  for (int i = tid; i <= L; i += nt) {
-    const zd F = r[i];
-    dst[i] = ycos ? 0.5 * (F + c0s) : 0.5 * mul_i(F);
+  zd* r = fft_lds<double, false>(a, b, out2.p, out2.tw, tid, nt, Cb);
+  zd* dst = tbuf + (((long long)l * jn + jj) * (g.M + 1) + m0) * (g.ny + 1);
+  for (int w = tid; w < (L + 1) * Cb; w += nt) {
+    const int c = w / (L + 1), i = w - c * (L + 1);
+    const zd F = r[i * Cb + c];
+    dst[(long long)c * (g.ny + 1) + i] = ycos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
   }
 }
 
-__global__ void k_synth_cols(Geo g, Fft out1, int TK, int j0, int jn, const zd* __restrict__ tbuf,
+__global__ void k_synth_cols(Geo g, Fft out1, int C, int j0, int jn, const zd* __restrict__ tbuf,
                              zd* __restrict__ eout) {
   CAV_DYN_SMEM(smem_raw);
-  __shared__ zd c0s[16];
+  __shared__ zd c0s[64];
   const int jj = blockIdx.y, l = blockIdx.z;
   const int j = j0 + jj;
-  const int tpc = blockDim.x / TK;
-  const int sub = threadIdx.x / tpc, lt = threadIdx.x % tpc;
-  const int i2 = blockIdx.x * TK + sub;
-  const bool valid = i2 <= g.ny;
+  const int i0 = blockIdx.x * C;
+  const int Cb = min(C, g.ny + 1 - i0);
   const int L = g.nx;
-  zd* a = reinterpret_cast<zd*>(smem_raw) + (long long)sub * 4 * L;
-  zd* b = a + 2 * L;
+  zd* a = reinterpret_cast<zd*>(smem_raw);
+  zd* b = a + 2LL * L * C;
   const bool xcos = (l == 0);  // E1: cos, E2: sin, E3: sin along x
   const zd* src = tbuf + ((long long)l * jn + jj) * (g.M + 1) * (g.ny + 1);
-  for (int i = lt; i < 2 * L; i += tpc) a[i] = mk(0.0, 0.0);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < 2 * L * Cb; i += nt) a[i] = mk(0.0, 0.0);
   __syncthreads();
-  for (int m = lt; m <= g.M; m += tpc) {
-    const zd x = valid ? src[(long long)m * (g.ny + 1) + i2] : mk(0.0, 0.0);
-    store_extension(a, L, xcos, m, x);
-    if (m == 0) c0s[sub] = x;
+  for (int w = tid; w < (g.M + 1) * Cb; w += nt) {
+    const int m = w / Cb, c = w - m * Cb;
+    const zd x = src[(long long)m * (g.ny + 1) + i0 + c];
+    store_extension(a, L, xcos, m, x, Cb, c);
+    if (m == 0) c0s[c] = x;
   }
   __syncthreads();
-  zd* r = fft_lds<double, false>(a, b, out1.p, out1.tw, lt, tpc);
-  if (valid) {
-    const zd c0 = c0s[sub];
-    zd* dst = eout + (((long long)l * (g.Nz + 1) + j) * (g.ny + 1) + i2) * (g.nx + 1);
-    for (int i = lt; i <= L; i += tpc) {
-      const zd F = r[i];
-      dst[i] = xcos ? 0.5 * (F + c0) : 0.5 * mul_i(F);
-    }
+  zd* r = fft_lds<double, false>(a, b, out1.p, out1.tw, tid, nt, Cb);
+  zd* dst = eout + (((long long)l * (g.Nz + 1) + j) * (g.ny + 1) + i0) * (g.nx + 1);
+  for (int w = tid; w < (L + 1) * Cb; w += nt) {
+    const int c = w / (L + 1), i = w - c * (L + 1);
+    const zd F = r[i * Cb + c];
+    dst[(long long)c * (g.nx + 1) + i] = xcos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
   }
 }
 
@@ -711,17 +750,18 @@ hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const z
   const double zb = sizeof(zd);
   const double tb = zb * 3.0 * jn * (g.M + 1) * (double)(g.ny + 1);   // staging slab
   const double prof = zb * (double)jn * g.NM * (theta_d ? 3.0 : 2.0);
+  const int cr = batch_per_block(2 * g.ny, g.M + 1);
   probe_begin(K_SYNTH_ROWS, st);
-  hipLaunchKernelGGL(k_synth_rows, dim3(g.M + 1, jn, 3), dim3(256), 4 * g.ny * sizeof(zd), st, g,
-                     t.out2, pi_d, theta_d, pi_n, xap, j0, jn, tbuf);
+  hipLaunchKernelGGL(k_synth_rows, dim3((g.M + 1 + cr - 1) / cr, jn, 3), dim3(256),
+                     4 * (size_t)g.ny * cr * sizeof(zd), st, g, t.out2, cr, pi_d, theta_d, pi_n, xap,
+                     j0, jn, tbuf);
   probe_end(K_SYNTH_ROWS, st, prof + zb * 3.0 * g.NM + tb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int tk = 8;
-  while (tk > 1 && (size_t)tk * 4 * g.nx * sizeof(zd) > 64 * 1024) tk >>= 1;
+  const int cc = batch_per_block(2 * g.nx, g.ny + 1);
   probe_begin(K_SYNTH_COLS, st);
-  hipLaunchKernelGGL(k_synth_cols, dim3((g.ny + 1 + tk - 1) / tk, jn, 3), dim3(256),
-                     (size_t)tk * 4 * g.nx * sizeof(zd), st, g, t.out1, tk, j0, jn, tbuf, eout);
+  hipLaunchKernelGGL(k_synth_cols, dim3((g.ny + 1 + cc - 1) / cc, jn, 3), dim3(256),
+                     4 * (size_t)g.nx * cc * sizeof(zd), st, g, t.out1, cc, j0, jn, tbuf, eout);
   probe_end(K_SYNTH_COLS, st, tb + zb * 3.0 * jn * (g.ny + 1) * (double)(g.nx + 1));
   return hipGetLastError();
 }

@@ -73,6 +73,8 @@ def main() -> int:
     ap.add_argument("--workload", default="lossy_8x8x2_256x256x64")
     ap.add_argument("--probe", default="tbc_cols", help="kernel timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
+                    help="both: time the double-precision path, then the mixed one (headline)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -96,32 +98,61 @@ def main() -> int:
     fields = torch.empty((len(incs), 3, cav.nz + 1, cav.ny + 1, cav.nx + 1),
                          dtype=torch.complex128, device="cuda")
 
-    def step():
-        plan = P.Plan.from_cavity(cav)
-        plan.solve_batch(th, ph, po, out=fields)
-        sig = [plan.rcs(i, incs[i].theta, incs[i].phi)[0] for i in range(len(incs))]
-        info = plan.info()
-        plan.close()
-        return sig, info
+    def make_step(precision, out):
+        def step():
+            plan = P.Plan.from_cavity(cav, precision=precision)
+            plan.solve_batch(th, ph, po, out=out)
+            sig = [plan.rcs(i, incs[i].theta, incs[i].phi)[0] for i in range(len(incs))]
+            info = plan.info()
+            plan.close()
+            return sig, info
+        return step
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    P.probe_start(args.probe)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for _ in range(args.steps):
-        sig, info = step()
-        infos.append(info)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    launches, k_ms, k_bytes = P.probe_stop()
+    def timed(precision, out, probe):
+        """Warm up, then time `steps` steps; each step ends with host-side RCS values, so
+        the per-step wall times are step latencies."""
+        step = make_step(precision, out)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        if probe:
+            P.probe_start(args.probe)
+            torch.cuda.synchronize()
+        lat, infos = [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            sig, info = step()
+            lat.append(time.perf_counter() - ts)
+            infos.append(info)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        probe_res = P.probe_stop() if probe else None
+        unknowns_step = len(incs) * infos[-1].unknowns
+        res = {
+            "value": args.steps * unknowns_step / (t1 - t0),
+            "ms_per_step": 1e3 * (t1 - t0) / args.steps,
+            "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+            "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+            "gmres_iterations_last": int(infos[-1].last_iterations),
+        }
+        return res, sig, infos[-1], probe_res
 
-    info = infos[-1]
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    head = precisions[-1]
+    runs, sigs = {}, {}
+    fields_by = {}
+    for prec in precisions:
+        out = fields if prec == head else torch.empty_like(fields)
+        res, sig, info_p, probe_res = timed(prec, out, probe=(prec == head))
+        runs[prec] = res
+        sigs[prec] = sig
+        fields_by[prec] = out
+        if prec == head:
+            info, (launches, k_ms, k_bytes) = info_p, probe_res
+
     unknowns_step = len(incs) * info.unknowns
-    elapsed = t1 - t0
-    value = args.steps * unknowns_step / elapsed
+    value = runs[head]["value"]
     achieved = (k_bytes / (k_ms * 1e-3)) / 1e9 if k_ms > 0 else 0.0
     out = {
         "metric": METRIC,
@@ -130,11 +161,11 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": runs[head]["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": wl.name,
@@ -145,9 +176,12 @@ def main() -> int:
             "unknowns_per_rhs": int(info.unknowns),
             "aperture_unknowns": int(info.n_ap),
             "fft_box": [int(info.P1), int(info.P2)],
-            "precision": "fp64",
+            "precision": head,
             "step": "plan + all incidences (GMRES) + field synthesis + backscatter RCS",
         },
+        "latency_ms": {"p50": runs[head]["p50_ms"], "p99": runs[head]["p99_ms"],
+                       "of": "one step"},
+        "by_precision": runs,
         "gmres_iterations_last": int(info.last_iterations),
         "phases_ms_last_step": {
             "spectrum": info.ms_spectrum, "elimination": info.ms_elimination,
@@ -167,9 +201,18 @@ def main() -> int:
             "algorithmic_bytes_per_launch": k_bytes / max(launches, 1),
         },
     }
+    if "fp64" in fields_by and "mixed" in fields_by:
+        a64, amx = fields_by["fp64"], fields_by["mixed"]
+        errs = [float(torch.linalg.vector_norm(amx[i] - a64[i]) / torch.linalg.vector_norm(a64[i]))
+                for i in range(len(incs))]
+        out["mixed_vs_fp64_field_rel_err"] = max(errs)
+        out["mixed_vs_fp64_rcs_rel_err"] = max(
+            abs(sigs["mixed"][i][incs[i].pol] - sigs["fp64"][i][incs[i].pol]) /
+            abs(sigs["fp64"][i][incs[i].pol]) for i in range(len(incs)))
+        out["mixed_speedup_vs_fp64"] = runs["mixed"]["value"] / runs["fp64"]["value"]
     if not args.no_cpu_baseline:
         gpu_fields = [fields[i].cpu().numpy() for i in range(len(incs))]
-        base, ferr, rerr = cpu_baseline(wl, gpu_fields, sig)
+        base, ferr, rerr = cpu_baseline(wl, gpu_fields, sigs[head])
         out["cpu_baseline"] = base
         out["field_rel_err_vs_oracle"] = ferr
         out["rcs_rel_err_vs_oracle"] = rerr

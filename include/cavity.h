@@ -79,7 +79,12 @@ typedef struct {
 
 /* Solver options; cavity_opts_default() fills the defaults listed here. */
 typedef struct {
-  int precision;        /* CAVITY_FP64 (default); CAVITY_MIXED returns CAVITY_ENOTIMPL */
+  int precision;        /* CAVITY_FP64 (default), or CAVITY_MIXED: the three TBC convolutions
+                           inside the GMRES iterations run in single precision (transforms,
+                           spectrum, workspaces); each restart recomputes the residual with the
+                           double-precision operator (iterative refinement), so tol applies to
+                           the double-precision system.  Elimination, profiles, right-hand
+                           sides, Krylov vectors, synthesis and RCS stay double. */
   int tbc_oversample;   /* s >= 1: TBC quadrature grid has s*Nx x s*Ny intervals (default 1) */
   double tol;           /* relative residual of the aperture system (default 1e-12) */
   int max_iter;         /* total GMRES iterations per right-hand side (default 400) */

@@ -129,6 +129,11 @@ def _torch():
     return torch
 
 
+# CAVITY_FP64: every step in double.  CAVITY_MIXED: the TBC convolutions inside the
+# Krylov iterations in single precision, residuals (and everything else) in double.
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+
 class Plan:
     """One cavity geometry, grid and layer stack, with its resident device data."""
 
@@ -137,7 +142,7 @@ class Plan:
                  layer_eps: Optional[Sequence[complex]] = None, k: float = 2 * np.pi, *,
                  tol: float = 1e-12, restart: int = 60, max_iter: int = 400,
                  oversample: int = 1, hbm_budget: int = 0, stream: Optional[int] = None,
-                 batch: int = 8):
+                 batch: int = 8, precision: str = "fp64"):
         lib = load_library()
         self._lib = lib
         self.a, self.b, self.c = float(a), float(b), float(c)
@@ -148,6 +153,10 @@ class Plan:
         opts.tbc_oversample = int(oversample)
         opts.hbm_budget = int(hbm_budget)
         opts.batch = int(batch)
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        opts.precision = PRECISIONS[precision]
+        self.precision = precision
         if stream is None:
             torch = _torch()
             stream = torch.cuda.current_stream().cuda_stream

@@ -47,17 +47,7 @@ int next_5smooth(long long n) {
   return (int)n;
 }
 
-cav::FftPlan make_fft_plan(int n) {
-  cav::FftPlan p{};
-  p.n = n;
-  p.nst = 0;
-  int m = n;
-  while (m % 4 == 0) { p.radix[p.nst++] = 4; m /= 4; }
-  while (m % 2 == 0) { p.radix[p.nst++] = 2; m /= 2; }
-  while (m % 3 == 0) { p.radix[p.nst++] = 3; m /= 3; }
-  while (m % 5 == 0) { p.radix[p.nst++] = 5; m /= 5; }
-  return p;
-}
+cav::FftPlan make_fft_plan(int n) { return cav::plan_fft(n, cav::kMaxRadix); }
 
 }  // namespace
 
@@ -205,6 +195,8 @@ struct cavity_plan_s {
   double *pivmin = nullptr, *dmin = nullptr;
   int* node_code = nullptr;
   zd *kappa2 = nullptr, *ratio = nullptr, *twiddles = nullptr;
+  cav::zf* twiddles_f = nullptr;
+  cav::zf* khat_f = nullptr;   // single-precision spectrum for the mixed-precision inner solve
   double *pw1 = nullptr, *pw2 = nullptr;
   zd* ctmp = nullptr;
   zd* tbuf = nullptr;
@@ -293,6 +285,9 @@ size_t plan_bytes(const cav::Geo& g, bool layered, int chunk, int nlayers, int* 
   L.add(&d, NM); L.add(&d, 1);
   L.add(&i, g.Nz + 1); L.add(&z, nlayers); L.add(&z, nlayers);
   L.add(&z, *twn);
+  cav::zf* zf1 = nullptr;
+  L.add(&zf1, *twn);
+  L.add(&zf1, (size_t)g.P1 * g.P2);
   L.add(&d, (size_t)2 * (g.M + 1) * g.P1); L.add(&d, (size_t)2 * g.P2 * (g.N + 1));
   L.add(&z, (size_t)2 * g.P1 * (g.N + 1));
   L.add(&z, (size_t)3 * chunk * (g.M + 1) * (g.ny + 1));
@@ -308,7 +303,7 @@ size_t work_bytes(const cav::Geo& g, int restart, int nb, int nblk) {
   return z * ((size_t)nb * 2 * 3 * (g.M + 1) * g.P2 + (size_t)nb * 3 * g.NM +
               (size_t)(restart + 1) * nb * n + 2ull * nb * n + (size_t)nblk * (restart + 1) * nb +
               (size_t)nb * (restart + 1) * 3 + (size_t)nb * restart * (restart + 4) + 64) +
-         sizeof(double) * ((size_t)nblk * nb + 2 * nb) + sizeof(int) * 3 * nb + 64 * 256;
+         sizeof(double) * ((size_t)nblk * nb + 3 * nb) + sizeof(int) * 3 * nb + 64 * 256;
 }
 
 // Solve workspace for nb right-hand sides iterating together.
@@ -333,6 +328,7 @@ int ensure_work(cavity_plan p, int nb) {
   L.add(&p->kv.y, (size_t)nb * R);
   L.add(&p->kv.nrm2, (size_t)nb);
   L.add(&p->kv.bnorm, (size_t)nb);
+  L.add(&p->kv.thr, (size_t)nb);
   L.add(&p->kv.active, (size_t)nb);
   L.add(&p->kv.incycle, (size_t)nb);
   L.add(&p->kv.jcount, (size_t)nb);
@@ -371,11 +367,30 @@ int ensure_solutions(cavity_plan p, int count) {
   return CAVITY_OK;
 }
 
-int run_operator(cavity_plan p, int precond, int nb, const zd* v, zd* y, const int* active) {
+// y = A v (or A P^{-1} v); low selects the single-precision convolutions.
+int run_operator(cavity_plan p, int precond, int nb, const zd* v, zd* y, const int* active,
+                 bool low = false) {
   const long long n = p->nvec();
-  HIPCHK(cav::launch_operator(p->g, p->trig, p->khat, p->rho_d, p->T, p->rho_n, p->pinv, precond,
-                              nb, v, n, p->X, p->Y, p->S, y, n, active, p->st));
+  if (low)
+    HIPCHK(cav::launch_operator_f32(p->g, p->trig, p->khat_f, p->rho_d, p->T, p->rho_n, p->pinv,
+                                    precond, nb, v, n, reinterpret_cast<cav::zf*>(p->X),
+                                    reinterpret_cast<cav::zf*>(p->Y), p->S, y, n, active, p->st));
+  else
+    HIPCHK(cav::launch_operator(p->g, p->trig, p->khat, p->rho_d, p->T, p->rho_n, p->pinv,
+                                precond, nb, v, n, p->X, p->Y, p->S, y, n, active, p->st));
   return CAVITY_OK;
+}
+
+// Relative reduction a restart cycle of the mixed-precision solve aims for before the
+// residual is recomputed with the double-precision operator (iterative refinement).
+double mixed_inner_reduction() {
+  static double v = -1.0;
+  if (v < 0.0) {
+    const char* e = std::getenv("CAVITY_MIXED_INNER");
+    v = e ? std::atof(e) : 1e-5;
+    if (!(v > 0.0 && v < 1.0)) v = 1e-5;
+  }
+  return v;
 }
 
 // nrm2[r] = |v_r|^2 for r < nb, copied to the host array out.
@@ -391,11 +406,17 @@ int device_norms(cavity_plan p, const zd* v, int nb, double* out) {
 // right-hand sides b (p->bvec) iterating in lockstep; solutions in x (nb x n).  The
 // Arnoldi step, the Givens rotations and the convergence test run on the device; the
 // host looks at the convergence flags every few iterations and once per restart cycle.
+// Mixed precision: the Arnoldi steps apply the operator with single-precision
+// convolutions and a cycle ends once it has reduced its residual by the inner factor;
+// every restart recomputes the residual b - A x with the double-precision operator, so
+// the cycles are steps of iterative refinement and the final test is on that residual.
 int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
                 std::vector<int>* iters_out) {
   const long long n = p->nvec();
   const int R = p->opts.restart;
   const double tol = p->opts.tol;
+  const bool mixed = p->opts.precision == CAVITY_MIXED;
+  const double inner = mixed ? mixed_inner_reduction() : 0.0;
   const long long ldj = (long long)p->nbwork * n;
   cav::Krylov& kv = p->kv;
   HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * n * sizeof(zd), p->st));
@@ -411,6 +432,7 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
   }
   HIPCHK(hipMemcpyAsync(kv.bnorm, bn.data(), nb * sizeof(double), hipMemcpyHostToDevice, p->st));
   std::vector<zd> g0((size_t)nb * (R + 1));
+  std::vector<double> thr(nb);
   std::vector<int> flags(nb);
   bool first = true;
   while (true) {
@@ -441,8 +463,12 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
     if (!any) break;
     first = false;
     std::fill(g0.begin(), g0.end(), cav::mk(0.0, 0.0));
-    for (int r = 0; r < nb; ++r) g0[(size_t)r * (R + 1)] = cav::mk(std::sqrt(beta2[r]), 0.0);
+    for (int r = 0; r < nb; ++r) {
+      g0[(size_t)r * (R + 1)] = cav::mk(std::sqrt(beta2[r]), 0.0);
+      thr[r] = std::max(tol * bn[r], inner * std::sqrt(beta2[r]));
+    }
     HIPCHK(hipMemcpyAsync(kv.g, g0.data(), g0.size() * sizeof(zd), hipMemcpyHostToDevice, p->st));
+    HIPCHK(hipMemcpyAsync(kv.thr, thr.data(), nb * sizeof(double), hipMemcpyHostToDevice, p->st));
     HIPCHK(hipMemcpyAsync(kv.active, flags.data(), nb * sizeof(int), hipMemcpyHostToDevice, p->st));
     HIPCHK(hipMemcpyAsync(kv.incycle, flags.data(), nb * sizeof(int), hipMemcpyHostToDevice,
                           p->st));
@@ -454,7 +480,7 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
     for (int j = 0; j < budget; ++j) {
       const zd* vj = p->V + (long long)j * ldj;
       zd* vn = p->V + (long long)(j + 1) * ldj;
-      if ((s = run_operator(p, 1, nb, vj, p->w, kv.active))) return s;
+      if ((s = run_operator(p, 1, nb, vj, p->w, kv.active, mixed))) return s;
       const int nv = j + 1;
       zd* hcol = kv.H + (long long)j * (R + 1);
       const long long hstr = (long long)R * (R + 1);
@@ -593,8 +619,8 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   cavity_opts o;
   cavity_opts_default(&o);
   if (opts) o = *opts;
-  if (o.precision != CAVITY_FP64)
-    return fail(CAVITY_ENOTIMPL, "only CAVITY_FP64 precision is available");
+  if (o.precision != CAVITY_FP64 && o.precision != CAVITY_MIXED)
+    return fail(CAVITY_EINVAL, "precision must be CAVITY_FP64 or CAVITY_MIXED");
   if (o.tbc_oversample < 1 || o.tbc_oversample > 8)
     return fail(CAVITY_EINVAL, "tbc_oversample must be in 1..8");
   if (!(o.tol > 0 && o.tol < 1) || o.max_iter < 1 || o.restart < 1 || o.restart > 200)
@@ -706,6 +732,8 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   L.add(&p->kappa2, lnz.size());
   L.add(&p->ratio, lnz.size());
   L.add(&p->twiddles, twn);
+  L.add(&p->twiddles_f, twn);
+  L.add(&p->khat_f, (size_t)g.P1 * g.P2);
   L.add(&p->pw1, (size_t)2 * (g.M + 1) * g.P1);
   L.add(&p->pw2, (size_t)2 * g.P2 * (g.N + 1));
   L.add(&p->ctmp, (size_t)2 * g.P1 * (g.N + 1));
@@ -723,6 +751,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
 
   // host tables: twiddles, node codes, k^2 eps per layer, eps ratios per interface
   std::vector<zd> tw(twn);
+  std::vector<cav::zf> twf(twn);
   {
     int off = 0;
     cav::Fft* dst[6] = {&p->trig.ext1, &p->trig.ext2, &p->trig.box1, &p->trig.box2,
@@ -731,8 +760,10 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
       twiddle_table(fft_len[i], tw.data() + off);
       dst[i]->p = make_fft_plan(fft_len[i]);
       dst[i]->tw = p->twiddles + off;
+      dst[i]->twf = p->twiddles_f + off;
       off += fft_len[i];
     }
+    for (int t = 0; t < twn; ++t) twf[t] = cav::cvt<float>(tw[t]);
   }
   std::vector<int> code(Nz + 1, 0);
   std::vector<zd> kap(lnz.size()), rat(lnz.size(), cav::mk(1.0, 0.0));
@@ -763,6 +794,8 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   };
   if (!chk(hipMemcpyAsync(p->twiddles, tw.data(), tw.size() * sizeof(zd), hipMemcpyHostToDevice,
                           p->st), "twiddle upload") ||
+      !chk(hipMemcpyAsync(p->twiddles_f, twf.data(), twf.size() * sizeof(cav::zf),
+                          hipMemcpyHostToDevice, p->st), "twiddle upload") ||
       !chk(hipMemcpyAsync(p->node_code, code.data(), code.size() * sizeof(int),
                           hipMemcpyHostToDevice, p->st), "layer upload") ||
       !chk(hipMemcpyAsync(p->kappa2, kap.data(), kap.size() * sizeof(zd), hipMemcpyHostToDevice,
@@ -775,7 +808,9 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   const double scale = 1.0 / (g.hq1 * g.hq2 * (double)g.P1 * (double)g.P2);
   int st = CAVITY_OK;
   if ((st = mark(p, 0, false))) return bail(st);
-  if (!chk(cav::launch_spectrum(g, R, scale, p->khat, p->st), "spectrum")) return bail(CAVITY_EDEVICE);
+  if (!chk(cav::launch_spectrum(g, R, scale, p->khat, p->st), "spectrum") ||
+      !chk(cav::launch_to_f32(p->khat, p->khat_f, (long long)g.P1 * g.P2, p->st), "spectrum"))
+    return bail(CAVITY_EDEVICE);
   if ((st = mark(p, 0, true))) return bail(st);
   cav::Layers ly{p->node_code, p->kappa2, p->ratio, layered ? 1 : 0};
   if ((st = mark(p, 1, false))) return bail(st);

@@ -1,0 +1,360 @@
+// Batched complex FFTs in LDS for the sine/cosine transforms and the zero-padded
+// convolution of the cavity solver (the Fourier expansions (E123F) sampled on uniform
+// nodes, and the FFT evaluation of the singular integrals in Section 5).
+//
+// Engine: Stockham autosort stages whose radix may be composite (up to 32).  A composite
+// radix R = R1 R2 is computed in registers by one Cooley-Tukey split (R2 DFTs of length
+// R1, constant twiddles, R1 DFTs of length R2), so a length-625 transform takes two LDS
+// round trips (25 x 25) instead of four.  C transforms of a block are interleaved in LDS,
+// element (pos, col) at buf[pos * C + col] with C a power of two, so consecutive lanes
+// work on the same butterfly of consecutive transforms and share its twiddles.
+//
+// The sine/cosine series sampled on x_i = i len / L, i = 0..L, are transforms of type I:
+//   SYN_cos(c)_i = sum_m c_m cos(pi m i / L)        = (F(even ext of c)_i + c_0 + (-1)^i c_L) / 2
+//   SYN_sin(c)_i = sum_m c_m sin(pi m i / L)        = (i / 2) F(odd ext of c)_i
+//   ANA_cos(u)_m = sum_i tau_i u_i cos(pi m i / L)  = F(even ext of u)_m / 2   (tau = 1/2 at ends)
+//   ANA_sin(u)_m = sum_i u_i sin(pi m i / L)        = (i / 2) F(odd ext of u)_m
+// with F the forward DFT of length 2L of the even (or odd) extension.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "device.hpp"
+
+#ifndef CAV_FFT_TWPOW
+#define CAV_FFT_TWPOW 0
+#endif
+
+namespace cav {
+
+// ---- compile-time twiddles ---------------------------------------------------------
+// cos and sin of 2 pi e / R for small integers, evaluated by the compiler: the angle is
+// reduced exactly to |r| <= pi/4 around a multiple q of pi/2 (integer arithmetic), then
+// the Taylor series of sin and cos of r are summed to below one ulp.
+constexpr double ct_pi = 3.14159265358979323846264338327950288;
+constexpr double ct_sin_red(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int i = 1; i < 16; ++i) {
+    term *= -x2 / ((2.0 * i) * (2.0 * i + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ct_cos_red(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int i = 1; i < 16; ++i) {
+    term *= -x2 / ((2.0 * i - 1.0) * (2.0 * i));
+    sum += term;
+  }
+  return sum;
+}
+// angle 2 pi e / R = (pi/4) (8e/R) = q pi/2 + (pi/4)(8e - 2qR)/R
+constexpr int ct_quadrant(int e, int R) { return ((8 * (e % R) + R) / (2 * R)); }
+constexpr double ct_rem(int e, int R) {
+  return ct_pi * (double)(8 * (e % R) - 2 * ct_quadrant(e, R) * R) / (4.0 * R);
+}
+constexpr double ct_cos(int e, int R) {
+  const int q = ct_quadrant(e, R) & 3;
+  const double r = ct_rem(e, R);
+  return q == 0 ? ct_cos_red(r) : q == 1 ? -ct_sin_red(r) : q == 2 ? -ct_cos_red(r) : ct_sin_red(r);
+}
+constexpr double ct_sin(int e, int R) {
+  const int q = ct_quadrant(e, R) & 3;
+  const double r = ct_rem(e, R);
+  return q == 0 ? ct_sin_red(r) : q == 1 ? ct_cos_red(r) : q == 2 ? -ct_sin_red(r) : -ct_cos_red(r);
+}
+
+// ---- small DFTs in registers ---------------------------------------------------------
+// Forward: X_k = sum_j x_j e^{-2 pi i jk/R};  INV: e^{+2 pi i jk/R}.
+template <int R, typename T, bool INV>
+struct Dft;
+
+template <typename T, bool INV>
+struct Dft<1, T, INV> {
+  __device__ static inline void run(cx<T>*) {}
+};
+
+template <typename T, bool INV>
+struct Dft<2, T, INV> {
+  __device__ static inline void run(cx<T>* v) {
+    const cx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<3, T, INV> {
+  __device__ static inline void run(cx<T>* v) {
+    const T s3 = (T)0.86602540378443864676;  // sin(2 pi / 3)
+    const cx<T> t1 = v[1] + v[2];
+    const cx<T> t2 = v[0] - (T)0.5 * t1;
+    const cx<T> t3 = s3 * (v[1] - v[2]);
+    v[0] = v[0] + t1;
+    v[1] = INV ? t2 + mul_i(t3) : t2 + mul_mi(t3);
+    v[2] = INV ? t2 + mul_mi(t3) : t2 + mul_i(t3);
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<4, T, INV> {
+  __device__ static inline void run(cx<T>* v) {
+    const cx<T> a = v[0] + v[2], b = v[0] - v[2];
+    const cx<T> c = v[1] + v[3], d = v[1] - v[3];
+    v[0] = a + c;
+    v[2] = a - c;
+    v[1] = INV ? b + mul_i(d) : b + mul_mi(d);
+    v[3] = INV ? b + mul_mi(d) : b + mul_i(d);
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<5, T, INV> {
+  __device__ static inline void run(cx<T>* v) {
+    const T c1 = (T)0.30901699437494742410;   // cos(2 pi / 5)
+    const T c2 = (T)-0.80901699437494742410;  // cos(4 pi / 5)
+    const T s1 = (T)0.95105651629515357212;   // sin(2 pi / 5)
+    const T s2 = (T)0.58778525229247312917;   // sin(4 pi / 5)
+    const cx<T> a1 = v[1] + v[4], b1 = v[1] - v[4];
+    const cx<T> a2 = v[2] + v[3], b2 = v[2] - v[3];
+    const cx<T> x0 = v[0];
+    const cx<T> p1 = x0 + c1 * a1 + c2 * a2;
+    const cx<T> p2 = x0 + c2 * a1 + c1 * a2;
+    const cx<T> q1 = s1 * b1 + s2 * b2;
+    const cx<T> q2 = s2 * b1 - s1 * b2;
+    v[0] = x0 + a1 + a2;
+    v[1] = INV ? p1 + mul_i(q1) : p1 + mul_mi(q1);
+    v[4] = INV ? p1 + mul_mi(q1) : p1 + mul_i(q1);
+    v[2] = INV ? p2 + mul_i(q2) : p2 + mul_mi(q2);
+    v[3] = INV ? p2 + mul_mi(q2) : p2 + mul_i(q2);
+  }
+};
+
+// Multiply y[I] (I = r2 R1 + k1) by W_R^{r2 k1}, with the trivial factors 1, -1, +-i
+// done by sign and swap.
+template <int R1, int R2, typename T, bool INV, int I>
+__device__ inline void ct_twiddle_one(cx<T>* y) {
+  constexpr int R = R1 * R2;
+  constexpr int e = ((I / R1) * (I % R1)) % R;
+  if constexpr (e == 0) {
+    return;
+  } else if constexpr (2 * e == R) {
+    y[I] = mk<T>(-y[I].re, -y[I].im);
+  } else if constexpr (4 * e == R) {
+    y[I] = INV ? mul_i(y[I]) : mul_mi(y[I]);
+  } else if constexpr (4 * e == 3 * R) {
+    y[I] = INV ? mul_mi(y[I]) : mul_i(y[I]);
+  } else {
+    constexpr double c = ct_cos(e, R), s = ct_sin(e, R);
+    y[I] = y[I] * mk<T>((T)c, INV ? (T)s : (T)-s);
+  }
+}
+template <int R1, int R2, typename T, bool INV, int... I>
+__device__ inline void ct_twiddles(cx<T>* y, std::integer_sequence<int, I...>) {
+  (ct_twiddle_one<R1, R2, T, INV, I>(y), ...);
+}
+
+// DFT of length R1 R2 by one Cooley-Tukey split:
+//   X[k1 + R1 k2] = sum_{r2} W_{R2}^{r2 k2} W_R^{r2 k1} sum_{r1} x[R2 r1 + r2] W_{R1}^{r1 k1}.
+template <int R1, int R2, typename T, bool INV>
+struct DftCt {
+  __device__ static inline void run(cx<T>* v) {
+    constexpr int R = R1 * R2;
+    cx<T> y[R];
+#pragma unroll
+    for (int r2 = 0; r2 < R2; ++r2) {
+      cx<T> t[R1];
+#pragma unroll
+      for (int r1 = 0; r1 < R1; ++r1) t[r1] = v[R2 * r1 + r2];
+      Dft<R1, T, INV>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) y[r2 * R1 + k1] = t[k1];
+    }
+    ct_twiddles<R1, R2, T, INV>(y, std::make_integer_sequence<int, R>{});
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      cx<T> t[R2];
+#pragma unroll
+      for (int r2 = 0; r2 < R2; ++r2) t[r2] = y[r2 * R1 + k1];
+      Dft<R2, T, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+    }
+  }
+};
+
+template <typename T, bool INV> struct Dft<6, T, INV> : DftCt<2, 3, T, INV> {};
+template <typename T, bool INV> struct Dft<8, T, INV> : DftCt<2, 4, T, INV> {};
+template <typename T, bool INV> struct Dft<9, T, INV> : DftCt<3, 3, T, INV> {};
+template <typename T, bool INV> struct Dft<10, T, INV> : DftCt<2, 5, T, INV> {};
+template <typename T, bool INV> struct Dft<12, T, INV> : DftCt<3, 4, T, INV> {};
+template <typename T, bool INV> struct Dft<15, T, INV> : DftCt<3, 5, T, INV> {};
+template <typename T, bool INV> struct Dft<16, T, INV> : DftCt<4, 4, T, INV> {};
+template <typename T, bool INV> struct Dft<20, T, INV> : DftCt<4, 5, T, INV> {};
+template <typename T, bool INV> struct Dft<25, T, INV> : DftCt<5, 5, T, INV> {};
+template <typename T, bool INV> struct Dft<32, T, INV> : DftCt<4, 8, T, INV> {};
+
+// Radices the planner may choose (host and device agree on this list).
+#define CAV_FFT_RADICES(X) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(20) X(25) X(32)
+
+// ---- FFT plan -----------------------------------------------------------------------
+// Factorisation of n into the radices of its Stockham stages, applied in order.
+struct FftPlan {
+  int n;
+  int nst;
+  int radix[20];
+};
+// Twiddle table of a length-n transform: tw[t] = exp(-2 pi i t / n), t = 0..n-1.
+
+// One Stockham stage of radix R over C = 2^lc interleaved transforms of length n with
+// span ns: butterfly j (0 <= j < n/R) of transform col reads in[(j + r n/R) C + col],
+// scales input r by W_{ns R}^{r (j mod ns)}, and writes out[((j - k) R + k + r ns) C + col].
+template <int R, typename T, bool INV>
+__device__ inline void fft_stage(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int n,
+                                 int ns, int lc, const cx<T>* __restrict__ tw, int tid, int nthr) {
+  const int nb = n / R;
+  const int tstep = n / (ns * R);
+  const int total = nb << lc;
+  const int cmask = (1 << lc) - 1;
+  for (int w = tid; w < total; w += nthr) {
+    const int j = w >> lc;
+    const int col = w & cmask;
+    const int k = j % ns;
+    cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = in[((j + r * nb) << lc) + col];
+    if (ns > 1) {
+      const int step = k * tstep;
+#if CAV_FFT_TWPOW
+      // W^{r k} as powers of one table entry: one load per butterfly instead of R - 1
+      const cx<T> w1 = INV ? conj(tw[step]) : tw[step];
+      cx<T> wr = w1;
+      v[1] = v[1] * w1;
+#pragma unroll
+      for (int r = 2; r < R; ++r) {
+        wr = wr * w1;
+        v[r] = v[r] * wr;
+      }
+#else
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const cx<T> w2 = tw[r * step];
+        v[r] = v[r] * (INV ? conj(w2) : w2);
+      }
+#endif
+    }
+    Dft<R, T, INV>::run(v);
+    const int d = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[((d + r * ns) << lc) + col] = v[r];
+  }
+}
+
+// 2^lc interleaved length-n transforms held in LDS buffer `a` (scratch `b` of the same
+// size).  Every thread of the block must call this with the same plan and lc (it contains
+// __syncthreads).  Returns the buffer that holds the result.  Unnormalised.  Only radices
+// up to MAXR are compiled in (they set the register footprint of the calling kernel); the
+// plan must not use larger ones.
+template <typename T, bool INV, int MAXR = 32>
+__device__ cx<T>* fft_lds(cx<T>* a, cx<T>* b, const FftPlan& p, const cx<T>* __restrict__ tw,
+                          int tid, int nthr, int lc) {
+  int ns = 1;
+  cx<T>* in = a;
+  cx<T>* out = b;
+  for (int s = 0; s < p.nst; ++s) {
+    const int rdx = p.radix[s];
+    switch (rdx) {
+#define CAV_FFT_CASE(R)                                                 \
+  case R:                                                               \
+    if constexpr (R <= MAXR) fft_stage<R, T, INV>(in, out, p.n, ns, lc, tw, tid, nthr); \
+    break;
+      CAV_FFT_RADICES(CAV_FFT_CASE)
+#undef CAV_FFT_CASE
+      default: break;
+    }
+    __syncthreads();
+    cx<T>* t = in;
+    in = out;
+    out = t;
+    ns *= rdx;
+  }
+  return in;
+}
+
+// Even (cos) or odd (sin) extension of entry idx (0 <= idx <= L) of transform col into a
+// length-2L buffer of 2^lc interleaved transforms (entries never stored stay zero).
+template <typename T>
+__device__ inline void store_extension(cx<T>* buf, int L, bool is_cos, int idx, cx<T> x, int lc,
+                                       int col) {
+  if (is_cos) {
+    buf[(idx << lc) + col] = x;
+    if (idx > 0 && idx < L) buf[((2 * L - idx) << lc) + col] = x;
+  } else {
+    if (idx == 0 || idx == L) {
+      buf[(idx << lc) + col] = mk<T>(0, 0);
+    } else {
+      buf[(idx << lc) + col] = x;
+      buf[((2 * L - idx) << lc) + col] = mk<T>(-x.re, -x.im);
+    }
+  }
+}
+
+}  // namespace cav
+
+namespace cav {
+
+// Host planner: the factorisation of n into the fewest stages with radices from
+// CAV_FFT_RADICES not above max_radix, ties broken towards balanced radices (smallest sum
+// of squares); stages ordered by decreasing radix so the largest runs without twiddles.
+// Returns nst = 0 when n has a prime factor above 5 or does not fit.
+inline FftPlan plan_fft(int n, int max_radix) {
+  FftPlan p{};
+  p.n = n;
+  p.nst = 0;
+  static const int rad[] = {
+#define CAV_FFT_LIST(R) R,
+      CAV_FFT_RADICES(CAV_FFT_LIST)
+#undef CAV_FFT_LIST
+  };
+  const int nr = (int)(sizeof(rad) / sizeof(rad[0]));
+  if (n < 1) return p;
+  if (n == 1) return p;
+  // dynamic programme over the divisors of n (n is at most a few thousand)
+  struct Best { int stages; long long sq; int first; };
+  Best* best = new Best[n + 1];
+  for (int m = 0; m <= n; ++m) best[m] = {1 << 29, 0, 0};
+  best[1] = {0, 0, 0};
+  for (int m = 2; m <= n; ++m) {
+    if (n % m) continue;
+    for (int i = 0; i < nr; ++i) {
+      const int r = rad[i];
+      if (r > max_radix || m % r) continue;
+      const Best& s = best[m / r];
+      if (s.stages >= (1 << 29)) continue;
+      const Best cand{s.stages + 1, s.sq + (long long)r * r, r};
+      if (cand.stages < best[m].stages ||
+          (cand.stages == best[m].stages && cand.sq < best[m].sq))
+        best[m] = cand;
+    }
+  }
+  if (best[n].stages < (1 << 29) && best[n].stages <= 20) {
+    int m = n;
+    while (m > 1) {
+      p.radix[p.nst++] = best[m].first;
+      m /= best[m].first;
+    }
+    for (int i = 0; i < p.nst; ++i)
+      for (int j = i + 1; j < p.nst; ++j)
+        if (p.radix[j] > p.radix[i]) {
+          const int t = p.radix[i];
+          p.radix[i] = p.radix[j];
+          p.radix[j] = t;
+        }
+  }
+  delete[] best;
+  return p;
+}
+
+}  // namespace cav

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "fft.hpp"
 
 namespace cav {
 
@@ -18,11 +19,21 @@ struct Geo {
   double hq1, hq2;
 };
 
-// An FFT length with its device twiddle table.
+// An FFT length with its device twiddle tables (double and single precision).
 struct Fft {
   FftPlan p;
   const zd* tw;
+  const zf* twf;
 };
+template <typename T>
+__device__ inline const cx<T>* twiddles(const Fft& f);
+template <>
+__device__ inline const zd* twiddles<double>(const Fft& f) { return f.tw; }
+template <>
+__device__ inline const zf* twiddles<float>(const Fft& f) { return f.twf; }
+
+// Largest radix compiled into the FFT kernels (the planner's limit).
+constexpr int kMaxRadix = 16;
 
 // The transforms one plan needs.
 struct Trig {
@@ -77,7 +88,7 @@ hipError_t launch_precond_build(const Geo& g, const zd* rho_d, const zd* T, cons
 // cycle), jcount[r] (columns built in this cycle).
 struct Krylov {
   zd *H, *cs, *sn, *g, *y;
-  double *nrm2, *bnorm;
+  double *nrm2, *bnorm, *thr;   // thr[r]: a cycle of rhs r stops once |g_{j+1}| <= thr[r]
   int *active, *incycle, *jcount;
   int restart;
   double tol;
@@ -91,6 +102,15 @@ hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const zd
                            const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
                            const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y, long long ys,
                            const int* active, hipStream_t st);
+// The same operator with the three single-layer convolutions in single precision
+// (spectrum khat_f, workspaces Xf, Yf of the same element count as X, Y); the vectors v, y
+// and the local terms stay double.
+hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, const zd* rho_d,
+                               const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
+                               const zd* v, long long vs, zf* Xf, zf* Yf, zd* S, zd* y,
+                               long long ys, const int* active, hipStream_t st);
+// out[i] = (float) in[i]
+hipError_t launch_to_f32(const zd* in, zf* out, long long n, hipStream_t st);
 // One single-layer family on a coefficient grid (inspection path).
 hipError_t launch_single_family(const Geo& g, const Trig& t, const zd* khat, int family,
                                 const zd* in, zd* X, zd* Y, zd* out, hipStream_t st);

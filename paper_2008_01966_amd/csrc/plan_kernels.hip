@@ -215,7 +215,7 @@ __global__ void k_basis_power(Geo g, Fft box1, Fft box2, double* __restrict__ pw
     a[i] = v;
   }
   __syncthreads();
-  zd* r = fft_lds<double, false>(a, b, F.p, F.tw, threadIdx.x, blockDim.x);
+  zd* r = fft_lds<double, false, kMaxRadix>(a, b, F.p, F.tw, threadIdx.x, blockDim.x, 0);
   for (int j = threadIdx.x; j < P; j += blockDim.x) {
     const double p = cabs2(r[j]);
     if (axis == 0)

@@ -7,6 +7,7 @@
 // three such grids [E1 | E2 | E3]; entries outside N1, N2, N3 stay zero.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 
 #include "kernels.hpp"
@@ -84,34 +85,43 @@ hipError_t launch_rhs(const Geo& g, const Wave* waves, int nb, zd* b, hipStream_
 __device__ inline bool fam_xcos(int f) { return f != 1; }
 __device__ inline bool fam_ycos(int f) { return f != 0; }
 
-// Each FFT kernel holds C transforms of a block interleaved in LDS, element (pos, c) at
-// buf[pos * C + c]; global loads and stores map consecutive lanes to consecutive
-// addresses.  C is chosen on the host from the LDS budget; the last block of a grid may
-// hold fewer transforms (Cb).
+// Each FFT kernel holds C = 2^lc transforms of a block interleaved in LDS, element
+// (pos, c) at buf[(pos << lc) + c]; global loads and stores map consecutive lanes to
+// consecutive addresses, and blocks are renumbered so neighbouring strips share an XCD.
+// The last block of a grid may hold fewer live transforms (Cb); its other LDS columns
+// hold zeros and are never stored.  T is the precision of the workspaces X, Y and of the
+// transforms (double, or float for the mixed-precision inner solve); the aperture vectors
+// in and out stay double.
 
 // Pass 1: rows m0 .. m0+Cb-1 of one family.  fam_fixed >= 0: `v` is the coefficient grid
 // of that family (inspection path); otherwise `v` is a padded aperture vector, optionally
 // preconditioned first.
-__global__ void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2, const zd* __restrict__ pinv,
-                               int precond, int fam_fixed, int C, const zd* __restrict__ vall,
-                               long long vs, zd* __restrict__ Xall, const int* __restrict__ active) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
+                                                      const zd* __restrict__ pinv, int precond,
+                                                      int fam_fixed, int lc,
+                                                      const zd* __restrict__ vall, long long vs,
+                                                      cx<T>* __restrict__ Xall,
+                                                      const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
-  __shared__ zd c0s[64];
-  const int rhs = blockIdx.z;
+  __shared__ cx<T> c0s[64];
+  const BlockId bid = xcd_block();
+  const int rhs = bid.z;
   if (active && !active[rhs]) return;
   const zd* v = vall + rhs * vs;
   const int nf = fam_fixed >= 0 ? 1 : 3;
-  zd* X = Xall + (long long)rhs * nf * (g.M + 1) * g.P2;
-  const int m0 = blockIdx.x * C;
+  cx<T>* X = Xall + (long long)rhs * nf * (g.M + 1) * g.P2;
+  const int C = 1 << lc;
+  const int m0 = bid.x << lc;
   const int Cb = min(C, g.M + 1 - m0);
-  const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
-  const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
+  const int f = fam_fixed >= 0 ? fam_fixed : bid.y;
+  const int slot = fam_fixed >= 0 ? 0 : bid.y;
   const int L = g.nq2, P = g.P2;
-  zd* a = reinterpret_cast<zd*>(smem_raw);
-  zd* b = a + (long long)P * C;
+  cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* b = a + ((long long)P << lc);
   const bool ycos = fam_ycos(f);
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < 2 * L * Cb; i += nt) a[i] = mk(0.0, 0.0);
+  for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk<T>(0, 0);
   __syncthreads();
   const int rowlen = g.N + 1;
   for (int w = tid; w < rowlen * Cb; w += nt) {
@@ -134,136 +144,151 @@ __global__ void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2, const zd* __restrict__
       const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
       val = f == 0 ? z[0] : (f == 1 ? z[1] : (nu * z[0] - mu * z[1]));
     }
-    store_extension(a, L, ycos, n, val, Cb, c);
-    if (n == 0) c0s[c] = val;
+    const cx<T> tv = cvt<T>(val);
+    store_extension(a, L, ycos, n, tv, lc, c);
+    if (n == 0) c0s[c] = tv;
   }
   __syncthreads();
-  zd* r = fft_lds<double, false>(a, b, ext2.p, ext2.tw, tid, nt, Cb);
-  zd* o = (r == a) ? b : a;
-  for (int w = tid; w < P * Cb; w += nt) {
-    const int i = w / Cb, c = w - i * Cb;
-    zd val = mk(0.0, 0.0);
-    if (i <= L) {
-      const zd F = r[w];
-      const zd sy = ycos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
-      const double wt = (i == 0 || i == L) ? 0.5 * g.hq2 : g.hq2;
-      val = wt * sy;
+  cx<T>* r = fft_lds<T, false, kMaxRadix>(a, b, ext2.p, twiddles<T>(ext2), tid, nt, lc);
+  cx<T>* o = (r == a) ? b : a;
+  const T hq = (T)g.hq2;
+  for (int w = tid; w < P << lc; w += nt) {
+    const int i = w >> lc, c = w & (C - 1);
+    cx<T> val = mk<T>(0, 0);
+    if (i <= L && c < Cb) {
+      const cx<T> F = r[w];
+      const cx<T> sy = ycos ? (T)0.5 * (F + c0s[c]) : (T)0.5 * mul_i(F);
+      val = ((i == 0 || i == L) ? (T)0.5 * hq : hq) * sy;
     }
     o[w] = val;
   }
   __syncthreads();
-  zd* r2 = fft_lds<double, false>(o, r, box2.p, box2.tw, tid, nt, Cb);
-  zd* dst = X + ((long long)slot * (g.M + 1) + m0) * g.P2;
+  cx<T>* r2 = fft_lds<T, false, kMaxRadix>(o, r, box2.p, twiddles<T>(box2), tid, nt, lc);
+  cx<T>* dst = X + ((long long)slot * (g.M + 1) + m0) * g.P2;
   for (int w = tid; w < P * Cb; w += nt) {
     const int c = w / P, k = w - c * P;
-    dst[(long long)c * g.P2 + k] = r2[k * Cb + c];
+    dst[(long long)c * g.P2 + k] = r2[(k << lc) + c];
   }
 }
 
 // Pass 2: columns k0 .. k0+Cb-1 of one family.
-__global__ void k_tbc_cols(Geo g, Fft ext1, Fft box1, const zd* __restrict__ khat, int fam_fixed,
-                           int C, const zd* __restrict__ Xall, zd* __restrict__ Yall,
-                           const int* __restrict__ active) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
+                                                  const cx<T>* __restrict__ khat, int fam_fixed,
+                                                  int lc, const cx<T>* __restrict__ Xall,
+                                                  cx<T>* __restrict__ Yall,
+                                                  const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
-  __shared__ zd c0s[64];
-  const int rhs = blockIdx.z;
+  __shared__ cx<T> c0s[64];
+  const BlockId bid = xcd_block();
+  const int rhs = bid.z;
   if (active && !active[rhs]) return;
   const int nf = fam_fixed >= 0 ? 1 : 3;
   const long long wsz = (long long)nf * (g.M + 1) * g.P2;
-  const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
-  const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
-  const zd* X = Xall + rhs * wsz + (long long)slot * (g.M + 1) * g.P2;
-  zd* Y = Yall + rhs * wsz + (long long)slot * (g.M + 1) * g.P2;
-  const int k0 = blockIdx.x * C;
+  const int f = fam_fixed >= 0 ? fam_fixed : bid.y;
+  const int slot = fam_fixed >= 0 ? 0 : bid.y;
+  const cx<T>* X = Xall + rhs * wsz + (long long)slot * (g.M + 1) * g.P2;
+  cx<T>* Y = Yall + rhs * wsz + (long long)slot * (g.M + 1) * g.P2;
+  const int C = 1 << lc;
+  const int k0 = bid.x << lc;
   const int Cb = min(C, g.P2 - k0);
   const int L = g.nq1, P = g.P1;
-  zd* a = reinterpret_cast<zd*>(smem_raw);
-  zd* b = a + (long long)P * C;
+  cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* b = a + ((long long)P << lc);
   const bool xcos = fam_xcos(f);
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < 2 * L * Cb; i += nt) a[i] = mk(0.0, 0.0);
+  for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk<T>(0, 0);
   __syncthreads();
-  for (int w = tid; w < (g.M + 1) * Cb; w += nt) {
-    const int m = w / Cb, c = w - m * Cb;
-    const zd x = X[(long long)m * g.P2 + k0 + c];
-    store_extension(a, L, xcos, m, x, Cb, c);
+  for (int w = tid; w < (g.M + 1) << lc; w += nt) {
+    const int m = w >> lc, c = w & (C - 1);
+    if (c >= Cb) continue;
+    const cx<T> x = X[(long long)m * g.P2 + k0 + c];
+    store_extension(a, L, xcos, m, x, lc, c);
     if (m == 0) c0s[c] = x;
   }
   __syncthreads();
-  zd* r = fft_lds<double, false>(a, b, ext1.p, ext1.tw, tid, nt, Cb);
-  zd* o = (r == a) ? b : a;
-  for (int w = tid; w < P * Cb; w += nt) {
-    const int i = w / Cb, c = w - i * Cb;
-    zd val = mk(0.0, 0.0);
-    if (i <= L) {
-      const zd F = r[w];
-      const zd sx = xcos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
-      const double wt = (i == 0 || i == L) ? 0.5 * g.hq1 : g.hq1;
-      val = wt * sx;
+  const cx<T>* tw_e = twiddles<T>(ext1);
+  const cx<T>* tw_b = twiddles<T>(box1);
+  cx<T>* r = fft_lds<T, false, kMaxRadix>(a, b, ext1.p, tw_e, tid, nt, lc);
+  cx<T>* o = (r == a) ? b : a;
+  const T hq = (T)g.hq1;
+  for (int w = tid; w < P << lc; w += nt) {
+    const int i = w >> lc, c = w & (C - 1);
+    cx<T> val = mk<T>(0, 0);
+    if (i <= L && c < Cb) {
+      const cx<T> F = r[w];
+      const cx<T> sx = xcos ? (T)0.5 * (F + c0s[c]) : (T)0.5 * mul_i(F);
+      val = ((i == 0 || i == L) ? (T)0.5 * hq : hq) * sx;
     }
     o[w] = val;
   }
   __syncthreads();
-  zd* r2 = fft_lds<double, false>(o, r, box1.p, box1.tw, tid, nt, Cb);
-  for (int w = tid; w < P * Cb; w += nt) {
-    const int k1 = w / Cb, c = w - k1 * Cb;
-    r2[w] = r2[w] * khat[(long long)k1 * g.P2 + k0 + c];
+  cx<T>* r2 = fft_lds<T, false, kMaxRadix>(o, r, box1.p, tw_b, tid, nt, lc);
+  for (int w = tid; w < P << lc; w += nt) {
+    const int k1 = w >> lc, c = w & (C - 1);
+    if (c < Cb) r2[w] = r2[w] * khat[(long long)k1 * g.P2 + k0 + c];
   }
   __syncthreads();
-  zd* o2 = (r2 == a) ? b : a;
-  zd* r3 = fft_lds<double, true>(r2, o2, box1.p, box1.tw, tid, nt, Cb);
-  zd* o3 = (r3 == a) ? b : a;
-  for (int w = tid; w < (L + 1) * Cb; w += nt) {
-    const int i = w / Cb, c = w - i * Cb;
-    store_extension(o3, L, xcos, i, r3[w], Cb, c);
+  cx<T>* o2 = (r2 == a) ? b : a;
+  cx<T>* r3 = fft_lds<T, true, kMaxRadix>(r2, o2, box1.p, tw_b, tid, nt, lc);
+  cx<T>* o3 = (r3 == a) ? b : a;
+  for (int w = tid; w < (L + 1) << lc; w += nt) {
+    const int i = w >> lc, c = w & (C - 1);
+    store_extension(o3, L, xcos, i, r3[w], lc, c);
   }
   __syncthreads();
-  zd* r4 = fft_lds<double, false>(o3, r3, ext1.p, ext1.tw, tid, nt, Cb);
-  for (int w = tid; w < (g.M + 1) * Cb; w += nt) {
-    const int m = w / Cb, c = w - m * Cb;
-    const zd F = r4[w];
-    const zd s = xcos ? 0.5 * F : 0.5 * mul_i(F);
-    Y[(long long)m * g.P2 + k0 + c] = g.hq1 * s;
+  cx<T>* r4 = fft_lds<T, false, kMaxRadix>(o3, r3, ext1.p, tw_e, tid, nt, lc);
+  for (int w = tid; w < (g.M + 1) << lc; w += nt) {
+    const int m = w >> lc, c = w & (C - 1);
+    if (c >= Cb) continue;
+    const cx<T> F = r4[w];
+    const cx<T> s = xcos ? (T)0.5 * F : (T)0.5 * mul_i(F);
+    Y[(long long)m * g.P2 + k0 + c] = hq * s;
   }
 }
 
-// Pass 3: rows m0 .. m0+Cb-1 backward; writes S[slot][mn].
-__global__ void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed, int C,
-                               const zd* __restrict__ Yall, zd* __restrict__ Sall,
-                               const int* __restrict__ active) {
+// Pass 3: rows m0 .. m0+Cb-1 backward; writes S[slot][mn] in double.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed,
+                                                      int lc, const cx<T>* __restrict__ Yall,
+                                                      zd* __restrict__ Sall,
+                                                      const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
-  const int rhs = blockIdx.z;
+  const BlockId bid = xcd_block();
+  const int rhs = bid.z;
   if (active && !active[rhs]) return;
   const int nf = fam_fixed >= 0 ? 1 : 3;
-  const int f = fam_fixed >= 0 ? fam_fixed : blockIdx.y;
-  const int slot = fam_fixed >= 0 ? 0 : blockIdx.y;
-  const zd* Y = Yall + (long long)rhs * nf * (g.M + 1) * g.P2 + (long long)slot * (g.M + 1) * g.P2;
+  const int f = fam_fixed >= 0 ? fam_fixed : bid.y;
+  const int slot = fam_fixed >= 0 ? 0 : bid.y;
+  const cx<T>* Y =
+      Yall + (long long)rhs * nf * (g.M + 1) * g.P2 + (long long)slot * (g.M + 1) * g.P2;
   zd* S = Sall + (long long)rhs * nf * g.NM + (long long)slot * g.NM;
-  const int m0 = blockIdx.x * C;
+  const int C = 1 << lc;
+  const int m0 = bid.x << lc;
   const int Cb = min(C, g.M + 1 - m0);
   const int L = g.nq2, P = g.P2;
-  zd* a = reinterpret_cast<zd*>(smem_raw);
-  zd* b = a + (long long)P * C;
+  cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* b = a + ((long long)P << lc);
   const bool ycos = fam_ycos(f);
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int w = tid; w < P * Cb; w += nt) {
+  for (int w = tid; w < P << lc; w += nt) {
     const int c = w / P, k = w - c * P;
-    a[k * Cb + c] = Y[(long long)(m0 + c) * g.P2 + k];
+    a[(k << lc) + c] = c < Cb ? Y[(long long)(m0 + c) * g.P2 + k] : mk<T>(0, 0);
   }
   __syncthreads();
-  zd* r = fft_lds<double, true>(a, b, box2.p, box2.tw, tid, nt, Cb);
-  zd* o = (r == a) ? b : a;
-  for (int w = tid; w < (L + 1) * Cb; w += nt) {
-    const int i = w / Cb, c = w - i * Cb;
-    store_extension(o, L, ycos, i, r[w], Cb, c);
+  cx<T>* r = fft_lds<T, true, kMaxRadix>(a, b, box2.p, twiddles<T>(box2), tid, nt, lc);
+  cx<T>* o = (r == a) ? b : a;
+  for (int w = tid; w < (L + 1) << lc; w += nt) {
+    const int i = w >> lc, c = w & (C - 1);
+    store_extension(o, L, ycos, i, r[w], lc, c);
   }
   __syncthreads();
-  zd* r2 = fft_lds<double, false>(o, r, ext2.p, ext2.tw, tid, nt, Cb);
+  cx<T>* r2 = fft_lds<T, false, kMaxRadix>(o, r, ext2.p, twiddles<T>(ext2), tid, nt, lc);
   const int rowlen = g.N + 1;
   for (int w = tid; w < rowlen * Cb; w += nt) {
     const int c = w / rowlen, n = w - c * rowlen;
-    const zd F = r2[n * Cb + c];
-    const zd s = ycos ? 0.5 * F : 0.5 * mul_i(F);
+    const cx<T> F = r2[(n << lc) + c];
+    const zd s = widen(ycos ? (T)0.5 * F : (T)0.5 * mul_i(F));
     S[(long long)(m0 + c) * rowlen + n] = g.hq2 * s;
   }
 }
@@ -309,48 +334,71 @@ __global__ void k_operator_epilogue(Geo g, const zd* __restrict__ rho_d, const z
   y[2LL * g.NM + mn] = r3;
 }
 
-// Transforms per block for an FFT kernel whose two LDS buffers hold len elements each.
-static int batch_per_block(int len, int cap) {
+// log2 of the transforms per block for an FFT kernel whose two LDS buffers hold len
+// elements of elem bytes each: the largest power of two within the LDS budget (at least
+// one transform, at most the next power of two above `cap`, at most 64).
+static int batch_log2(int len, int elem, int cap) {
   static long long budget = -1;
   if (budget < 0) {
     const char* e = getenv("CAVITY_LDS_BUDGET");
     budget = e ? atoll(e) : 40000;
   }
-  int c = (int)(budget / (2LL * len * (long long)sizeof(zd)));
-  if (c < 1) c = 1;
-  if (c > cap) c = cap;
-  if (c > 64) c = 64;
-  return c;
+  int lc = 0;
+  while (lc < 6 && (1 << lc) < cap && 2LL * len * elem * (2LL << lc) <= budget) ++lc;
+  return lc;
+}
+
+template <typename T>
+static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, const zd* pinv,
+                             int precond, int fam_fixed, int nb, const zd* v, long long vs,
+                             cx<T>* X, cx<T>* Y, zd* S, const int* active, hipStream_t st) {
+  const int nf = fam_fixed >= 0 ? 1 : 3;
+  const double zb = sizeof(zd), tb = sizeof(cx<T>);
+  const double xbytes = tb * nb * nf * (g.M + 1) * (double)g.P2;   // one X or Y workspace
+  const double vin = nb * (zb * (fam_fixed >= 0 ? 1.0 : 3.0) * g.NM) + (precond ? zb * 9.0 * g.NM : 0.0);
+  const int lr = batch_log2(g.P2, (int)tb, g.M + 1);
+  const int gr = (g.M + 1 + (1 << lr) - 1) >> lr;
+  probe_begin(K_TBC_ROWS_FWD, st);
+  hipLaunchKernelGGL((k_tbc_rows_fwd<T>), dim3(gr, nf, nb), dim3(256),
+                     (size_t)2 * g.P2 * tb * (1 << lr), st, g, t.ext2, t.box2, pinv, precond,
+                     fam_fixed, lr, v, vs, X, active);
+  probe_end(K_TBC_ROWS_FWD, st, vin + xbytes);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int lcc = batch_log2(g.P1, (int)tb, g.P2);
+  probe_begin(K_TBC_COLS, st);
+  hipLaunchKernelGGL((k_tbc_cols<T>), dim3((g.P2 + (1 << lcc) - 1) >> lcc, nf, nb), dim3(256),
+                     (size_t)2 * g.P1 * tb * (1 << lcc), st, g, t.ext1, t.box1, khat, fam_fixed,
+                     lcc, X, Y, active);
+  probe_end(K_TBC_COLS, st, 2.0 * xbytes + tb * (double)g.P1 * g.P2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  probe_begin(K_TBC_ROWS_BWD, st);
+  hipLaunchKernelGGL((k_tbc_rows_bwd<T>), dim3(gr, nf, nb), dim3(256),
+                     (size_t)2 * g.P2 * tb * (1 << lr), st, g, t.ext2, t.box2, fam_fixed, lr, Y, S,
+                     active);
+  probe_end(K_TBC_ROWS_BWD, st, xbytes + zb * nb * nf * g.NM);
+  return hipGetLastError();
 }
 
 static hipError_t launch_tbc_passes(const Geo& g, const Trig& t, const zd* khat, const zd* pinv,
                                     int precond, int fam_fixed, int nb, const zd* v, long long vs,
                                     zd* X, zd* Y, zd* S, const int* active, hipStream_t st) {
-  const int nf = fam_fixed >= 0 ? 1 : 3;
-  const double zb = sizeof(zd);
-  const double xbytes = zb * nb * nf * (g.M + 1) * (double)g.P2;   // one X or Y workspace
-  const double vin = nb * (zb * (fam_fixed >= 0 ? 1.0 : 3.0) * g.NM) + (precond ? zb * 9.0 * g.NM : 0.0);
-  const int cr = batch_per_block(g.P2, g.M + 1);
-  probe_begin(K_TBC_ROWS_FWD, st);
-  hipLaunchKernelGGL(k_tbc_rows_fwd, dim3((g.M + 1 + cr - 1) / cr, nf, nb), dim3(256),
-                     2 * (size_t)g.P2 * cr * sizeof(zd), st, g, t.ext2, t.box2, pinv, precond,
-                     fam_fixed, cr, v, vs, X, active);
-  probe_end(K_TBC_ROWS_FWD, st, vin + xbytes);
-  hipError_t e = hipGetLastError();
+  return tbc_passes<double>(g, t, khat, pinv, precond, fam_fixed, nb, v, vs, X, Y, S, active, st);
+}
+
+template <typename T>
+static hipError_t operator_impl(const Geo& g, const Trig& t, const cx<T>* khat, const zd* rho_d,
+                                const zd* Tc, const zd* rho_n, const zd* pinv, int precond, int nb,
+                                const zd* v, long long vs, cx<T>* X, cx<T>* Y, zd* S, zd* y,
+                                long long ys, const int* active, hipStream_t st) {
+  hipError_t e = tbc_passes<T>(g, t, khat, pinv, precond, -1, nb, v, vs, X, Y, S, active, st);
   if (e != hipSuccess) return e;
-  const int cc = batch_per_block(g.P1, g.P2);
-  probe_begin(K_TBC_COLS, st);
-  hipLaunchKernelGGL(k_tbc_cols, dim3((g.P2 + cc - 1) / cc, nf, nb), dim3(256),
-                     2 * (size_t)g.P1 * cc * sizeof(zd), st, g, t.ext1, t.box1, khat, fam_fixed,
-                     cc, X, Y, active);
-  probe_end(K_TBC_COLS, st, 2.0 * xbytes + zb * (double)g.P1 * g.P2);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  probe_begin(K_TBC_ROWS_BWD, st);
-  hipLaunchKernelGGL(k_tbc_rows_bwd, dim3((g.M + 1 + cr - 1) / cr, nf, nb), dim3(256),
-                     2 * (size_t)g.P2 * cr * sizeof(zd), st, g, t.ext2, t.box2, fam_fixed, cr, Y,
-                     S, active);
-  probe_end(K_TBC_ROWS_BWD, st, xbytes + zb * nb * nf * g.NM);
+  const int blk = 256;
+  probe_begin(K_EPILOGUE, st);
+  hipLaunchKernelGGL(k_operator_epilogue, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g,
+                     rho_d, Tc, rho_n, pinv, precond, v, vs, S, y, ys, active);
+  probe_end(K_EPILOGUE, st, sizeof(zd) * (double)g.NM * (nb * 9.0 + 3.0 + (precond ? 9.0 : 0.0)));
   return hipGetLastError();
 }
 
@@ -358,13 +406,28 @@ hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const zd
                            const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
                            const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y, long long ys,
                            const int* active, hipStream_t st) {
-  hipError_t e = launch_tbc_passes(g, t, khat, pinv, precond, -1, nb, v, vs, X, Y, S, active, st);
-  if (e != hipSuccess) return e;
-  const int blk = 256;
-  probe_begin(K_EPILOGUE, st);
-  hipLaunchKernelGGL(k_operator_epilogue, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g,
-                     rho_d, T, rho_n, pinv, precond, v, vs, S, y, ys, active);
-  probe_end(K_EPILOGUE, st, sizeof(zd) * (double)g.NM * (nb * 9.0 + 3.0 + (precond ? 9.0 : 0.0)));
+  return operator_impl<double>(g, t, khat, rho_d, T, rho_n, pinv, precond, nb, v, vs, X, Y, S, y,
+                               ys, active, st);
+}
+
+hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, const zd* rho_d,
+                               const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
+                               const zd* v, long long vs, zf* Xf, zf* Yf, zd* S, zd* y,
+                               long long ys, const int* active, hipStream_t st) {
+  return operator_impl<float>(g, t, khat_f, rho_d, T, rho_n, pinv, precond, nb, v, vs, Xf, Yf, S,
+                              y, ys, active, st);
+}
+
+__global__ void k_to_f32(const zd* __restrict__ in, zf* __restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = cvt<float>(in[i]);
+}
+
+hipError_t launch_to_f32(const zd* in, zf* out, long long n, hipStream_t st) {
+  const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::max<long long>(blocks, 1)), dim3(256), 0, st,
+                     in, out, n);
   return hipGetLastError();
 }
 
@@ -593,7 +656,7 @@ __global__ void k_givens(Krylov kv, int j, int nb) {
   const zd gj = gv[j];
   gv[j + 1] = mk(-1.0, 0.0) * conj(s) * gj;
   gv[j] = c * gj;
-  const bool conv = sqrt(cabs2(gv[j + 1])) <= kv.tol * kv.bnorm[r] || den == 0.0;
+  const bool conv = sqrt(cabs2(gv[j + 1])) <= kv.thr[r] || den == 0.0;
   kv.jcount[r] = j + 1;
   if (conv || j + 1 >= R) kv.active[r] = 0;
 }
@@ -666,21 +729,26 @@ hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long
 // columns along x with TK adjacent columns per block.
 // tbuf[l][jj][m][i2], jj = j - j0.
 // ---------------------------------------------------------------------------------
-__global__ void k_synth_rows(Geo g, Fft out2, int C, const zd* __restrict__ pi_d,
-                             const zd* __restrict__ theta_d, const zd* __restrict__ pi_n,
-                             const zd* __restrict__ xap, int j0, int jn, zd* __restrict__ tbuf) {
+__global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc,
+                                                    const zd* __restrict__ pi_d,
+                                                    const zd* __restrict__ theta_d,
+                                                    const zd* __restrict__ pi_n,
+                                                    const zd* __restrict__ xap, int j0, int jn,
+                                                    zd* __restrict__ tbuf) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ zd c0s[64];
-  const int jj = blockIdx.y, l = blockIdx.z;
+  const BlockId bid = xcd_block();
+  const int jj = bid.y, l = bid.z;
   const int j = j0 + jj;
-  const int m0 = blockIdx.x * C;
+  const int C = 1 << lc;
+  const int m0 = bid.x << lc;
   const int Cb = min(C, g.M + 1 - m0);
   const int L = g.ny;
   zd* a = reinterpret_cast<zd*>(smem_raw);
-  zd* b = a + 2LL * L * C;
+  zd* b = a + ((2LL * L) << lc);
   const bool ycos = (l == 1);  // E1: sin, E2: cos, E3: sin along y
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < 2 * L * Cb; i += nt) a[i] = mk(0.0, 0.0);
+  for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk(0.0, 0.0);
   __syncthreads();
   const long long NM = g.NM;
   const int rowlen = g.N + 1;
@@ -698,47 +766,51 @@ __global__ void k_synth_rows(Geo g, Fft out2, int C, const zd* __restrict__ pi_d
     } else {
       val = pi_n[(long long)j * NM + mn] * xap[2 * NM + mn];
     }
-    store_extension(a, L, ycos, n, val, Cb, c);
+    store_extension(a, L, ycos, n, val, lc, c);
     if (n == 0) c0s[c] = val;
   }
   __syncthreads();
-  zd* r = fft_lds<double, false>(a, b, out2.p, out2.tw, tid, nt, Cb);
+  zd* r = fft_lds<double, false, kMaxRadix>(a, b, out2.p, out2.tw, tid, nt, lc);
   zd* dst = tbuf + (((long long)l * jn + jj) * (g.M + 1) + m0) * (g.ny + 1);
   for (int w = tid; w < (L + 1) * Cb; w += nt) {
     const int c = w / (L + 1), i = w - c * (L + 1);
-    const zd F = r[i * Cb + c];
+    const zd F = r[(i << lc) + c];
     dst[(long long)c * (g.ny + 1) + i] = ycos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
   }
 }
 
-__global__ void k_synth_cols(Geo g, Fft out1, int C, int j0, int jn, const zd* __restrict__ tbuf,
-                             zd* __restrict__ eout) {
+__global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int j0, int jn,
+                                                    const zd* __restrict__ tbuf,
+                                                    zd* __restrict__ eout) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ zd c0s[64];
-  const int jj = blockIdx.y, l = blockIdx.z;
+  const BlockId bid = xcd_block();
+  const int jj = bid.y, l = bid.z;
   const int j = j0 + jj;
-  const int i0 = blockIdx.x * C;
+  const int C = 1 << lc;
+  const int i0 = bid.x << lc;
   const int Cb = min(C, g.ny + 1 - i0);
   const int L = g.nx;
   zd* a = reinterpret_cast<zd*>(smem_raw);
-  zd* b = a + 2LL * L * C;
+  zd* b = a + ((2LL * L) << lc);
   const bool xcos = (l == 0);  // E1: cos, E2: sin, E3: sin along x
   const zd* src = tbuf + ((long long)l * jn + jj) * (g.M + 1) * (g.ny + 1);
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < 2 * L * Cb; i += nt) a[i] = mk(0.0, 0.0);
+  for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk(0.0, 0.0);
   __syncthreads();
-  for (int w = tid; w < (g.M + 1) * Cb; w += nt) {
-    const int m = w / Cb, c = w - m * Cb;
+  for (int w = tid; w < (g.M + 1) << lc; w += nt) {
+    const int m = w >> lc, c = w & (C - 1);
+    if (c >= Cb) continue;
     const zd x = src[(long long)m * (g.ny + 1) + i0 + c];
-    store_extension(a, L, xcos, m, x, Cb, c);
+    store_extension(a, L, xcos, m, x, lc, c);
     if (m == 0) c0s[c] = x;
   }
   __syncthreads();
-  zd* r = fft_lds<double, false>(a, b, out1.p, out1.tw, tid, nt, Cb);
+  zd* r = fft_lds<double, false, kMaxRadix>(a, b, out1.p, out1.tw, tid, nt, lc);
   zd* dst = eout + (((long long)l * (g.Nz + 1) + j) * (g.ny + 1) + i0) * (g.nx + 1);
   for (int w = tid; w < (L + 1) * Cb; w += nt) {
     const int c = w / (L + 1), i = w - c * (L + 1);
-    const zd F = r[i * Cb + c];
+    const zd F = r[(i << lc) + c];
     dst[(long long)c * (g.nx + 1) + i] = xcos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
   }
 }
@@ -750,18 +822,19 @@ hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const z
   const double zb = sizeof(zd);
   const double tb = zb * 3.0 * jn * (g.M + 1) * (double)(g.ny + 1);   // staging slab
   const double prof = zb * (double)jn * g.NM * (theta_d ? 3.0 : 2.0);
-  const int cr = batch_per_block(2 * g.ny, g.M + 1);
+  const int lr = batch_log2(2 * g.ny, (int)sizeof(zd), g.M + 1);
   probe_begin(K_SYNTH_ROWS, st);
-  hipLaunchKernelGGL(k_synth_rows, dim3((g.M + 1 + cr - 1) / cr, jn, 3), dim3(256),
-                     4 * (size_t)g.ny * cr * sizeof(zd), st, g, t.out2, cr, pi_d, theta_d, pi_n, xap,
-                     j0, jn, tbuf);
+  hipLaunchKernelGGL(k_synth_rows, dim3((g.M + 1 + (1 << lr) - 1) >> lr, jn, 3), dim3(256),
+                     (size_t)4 * g.ny * sizeof(zd) * (1 << lr), st, g, t.out2, lr, pi_d, theta_d,
+                     pi_n, xap, j0, jn, tbuf);
   probe_end(K_SYNTH_ROWS, st, prof + zb * 3.0 * g.NM + tb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int cc = batch_per_block(2 * g.nx, g.ny + 1);
+  const int lcc = batch_log2(2 * g.nx, (int)sizeof(zd), g.ny + 1);
   probe_begin(K_SYNTH_COLS, st);
-  hipLaunchKernelGGL(k_synth_cols, dim3((g.ny + 1 + cc - 1) / cc, jn, 3), dim3(256),
-                     4 * (size_t)g.nx * cc * sizeof(zd), st, g, t.out1, cc, j0, jn, tbuf, eout);
+  hipLaunchKernelGGL(k_synth_cols, dim3((g.ny + 1 + (1 << lcc) - 1) >> lcc, jn, 3), dim3(256),
+                     (size_t)4 * g.nx * sizeof(zd) * (1 << lcc), st, g, t.out1, lcc, j0, jn, tbuf,
+                     eout);
   probe_end(K_SYNTH_COLS, st, tb + zb * 3.0 * jn * (g.ny + 1) * (double)(g.nx + 1));
   return hipGetLastError();
 }

@@ -50,6 +50,35 @@ def test_lossy_8x8x2_full_size():
 
 
 @pytest.mark.timeout(900)
+def test_lossy_8x8x2_mixed_precision_full_size():
+    """The same workload solved with single-precision convolutions inside GMRES and
+    double-precision refinement residuals: whole field and RCS within 1e-8 of the oracle."""
+    import torch
+    wl = W.lossy_8x8x2()
+    cav = wl.cavity
+    print(f"\n[case] {wl.name} mixed", flush=True)
+    incs = wl.incidences
+    plan = P.Plan.from_cavity(cav, precision="mixed")
+    fields = plan.solve_batch([i.theta for i in incs], [i.phi for i in incs],
+                              [i.pol for i in incs])
+    torch.cuda.synchronize()
+    sig = [plan.rcs(i, incs[i].theta, incs[i].phi)[0] for i in range(len(incs))]
+    print(f"[gpu] done, last GMRES iterations {plan.info().last_iterations}", flush=True)
+    ora = solver.plan(Problem.from_cavity(cav))
+    for i, inc in enumerate(incs):
+        ref = solver.solve(ora, inc.theta, inc.phi, inc.pol, tol=1e-13)
+        oe = solver.field_out(ora, ref)
+        err = np.linalg.norm(fields[i].cpu().numpy() - oe) / np.linalg.norm(oe)
+        o = solver.backscatter(ora, ref, inc.theta, inc.phi)
+        co = inc.pol
+        err_r = abs(sig[i][co] - o[co]) / o[co]
+        print(f"[compare] mixed incidence {i}: field rel err {err:.2e}, rcs {err_r:.2e}",
+              flush=True)
+        assert err <= 1e-8 and err_r <= 1e-8
+    plan.close()
+
+
+@pytest.mark.timeout(900)
 def test_layered_16x16x4_against_stored_oracle():
     """Three-layer 16 x 16 x 4 wavelength cavity on the 512 x 512 x 128 grid (P = 1250),
     theta = 45 deg, phi = 0, both polarisations, against oracle values stored by

@@ -132,6 +132,31 @@ def test_batch_matches_single(pair):
         assert float((fields[i] - single).abs().max()) <= 1e-13 * float(single.abs().max())
 
 
+def test_mixed_precision_solve(pair):
+    """Mixed precision (single-precision convolutions inside GMRES, double-precision
+    residuals at every restart): the field and RCS against the double-precision oracle
+    within 1e-8 relative, the stated target of the refined solve, and a batch of
+    incidences equal to the single solves."""
+    wl, prob, gpu, ora = pair
+    mix = P.Plan.from_cavity(wl.cavity, precision="mixed")
+    incs = list(wl.incidences) + [W.Incidence(0.9, 0.4, W.TE)]
+    fields = mix.solve_batch([i.theta for i in incs], [i.phi for i in incs],
+                             [i.pol for i in incs])
+    assert mix.info().last_rel_residual <= 1e-12
+    for i, inc in enumerate(incs):
+        ref = solver.solve(ora, inc.theta, inc.phi, inc.pol, tol=1e-13)
+        oe = solver.field_out(ora, ref)
+        err = np.linalg.norm(fields[i].cpu().numpy() - oe) / np.linalg.norm(oe)
+        print(f"[compare] mixed incidence {i}: field rel err {err:.2e}", flush=True)
+        assert err <= 1e-8
+        sig = mix.rcs(i, [inc.theta], [inc.phi])[0]
+        o = solver.backscatter(ora, ref, inc.theta, inc.phi)
+        assert np.abs(sig - np.array(o)).max() <= 1e-8 * max(o)
+        single = mix.solve(inc.theta, inc.phi, inc.pol)
+        assert float((fields[i] - single).abs().max()) <= 1e-13 * float(single.abs().max())
+    mix.close()
+
+
 def test_no_convergence_reported():
     cav = W.vacuum_1x1x05().cavity
     gpu = P.Plan.from_cavity(cav, max_iter=1)

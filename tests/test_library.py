@@ -74,8 +74,8 @@ def test_invalid_options_rejected():
     o.restart = 0
     assert _create(opts=o)[0] == 1
     lib.cavity_opts_default(ctypes.byref(o))
-    o.precision = 1
-    assert _create(opts=o)[0] == 6
+    o.precision = 7
+    assert _create(opts=o)[0] == 1
     lib.cavity_opts_default(ctypes.byref(o))
     o.tbc_oversample = 0
     assert _create(opts=o)[0] == 1

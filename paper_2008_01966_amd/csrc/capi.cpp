@@ -49,6 +49,9 @@ int next_5smooth(long long n) {
 
 cav::FftPlan make_fft_plan(int n) { return cav::plan_fft(n, cav::kMaxRadix); }
 
+// Blocks per right-hand side of the fused update + norm pass of the Arnoldi step.
+constexpr int kNormBlocks = 1024;
+
 }  // namespace
 
 // ---- kernel timing probe (process-wide) ------------------------------------------------
@@ -208,6 +211,8 @@ struct cavity_plan_s {
   int nbwork = 0;
   zd *X = nullptr, *Y = nullptr, *S = nullptr;
   zd *V = nullptr, *w = nullptr, *bvec = nullptr;
+  zd* zb = nullptr;          // preconditioned current basis vector P^{-1} v_j per rhs
+  int* counters = nullptr;   // per-rhs arrival counters of the fused reductions (zero at rest)
   zd* dpart = nullptr;
   double* dnpart = nullptr;
   zd* h2 = nullptr;
@@ -224,6 +229,7 @@ struct cavity_plan_s {
   // phase timers, resolved lazily: spectrum, elimination, preconditioner, rhs, krylov, synth
   hipEvent_t ev[12] = {};
   bool ev_used[6] = {};
+  std::vector<hipEvent_t> poll_ev;   // one per Arnoldi step of a cycle (convergence polling)
 
   long long nvec() const { return 3LL * g.NM; }
 };
@@ -240,6 +246,8 @@ void release(cavity_plan p) {
   if (p->hflags) (void)hipHostFree(p->hflags);
   if (p->hn) (void)hipHostFree(p->hn);
   for (hipEvent_t e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->poll_ev)
     if (e) (void)hipEventDestroy(e);
   delete p;
 }
@@ -301,9 +309,10 @@ size_t work_bytes(const cav::Geo& g, int restart, int nb, int nblk) {
   const size_t n = 3ull * g.NM;
   const size_t z = sizeof(zd);
   return z * ((size_t)nb * 2 * 3 * (g.M + 1) * g.P2 + (size_t)nb * 3 * g.NM +
-              (size_t)(restart + 1) * nb * n + 2ull * nb * n + (size_t)nblk * (restart + 1) * nb +
+              (size_t)(restart + 1) * nb * n + 3ull * nb * n +
+              (size_t)std::max(nblk, cav::kDotBlocksHost) * (restart + 1) * nb +
               (size_t)nb * (restart + 1) * 3 + (size_t)nb * restart * (restart + 4) + 64) +
-         sizeof(double) * ((size_t)nblk * nb + 3 * nb) + sizeof(int) * 3 * nb + 64 * 256;
+         sizeof(double) * ((size_t)kNormBlocks * nb + 4 * nb) + sizeof(int) * 5 * nb + 64 * 256;
 }
 
 // Solve workspace for nb right-hand sides iterating together.
@@ -318,8 +327,10 @@ int ensure_work(cavity_plan p, int nb) {
   L.add(&p->V, (size_t)(R + 1) * nb * n);
   L.add(&p->w, (size_t)nb * n);
   L.add(&p->bvec, (size_t)nb * n);
-  L.add(&p->dpart, (size_t)p->nblk_red * (R + 1) * nb);
-  L.add(&p->dnpart, (size_t)p->nblk_red * nb);
+  L.add(&p->zb, (size_t)nb * n);
+  L.add(&p->counters, (size_t)nb);
+  L.add(&p->dpart, (size_t)std::max(p->nblk_red, cav::kDotBlocksHost) * (R + 1) * nb);
+  L.add(&p->dnpart, (size_t)kNormBlocks * nb);
   L.add(&p->h2, (size_t)nb * (R + 1));
   L.add(&p->kv.H, (size_t)nb * R * (R + 1));
   L.add(&p->kv.cs, (size_t)nb * R);
@@ -329,6 +340,8 @@ int ensure_work(cavity_plan p, int nb) {
   L.add(&p->kv.nrm2, (size_t)nb);
   L.add(&p->kv.bnorm, (size_t)nb);
   L.add(&p->kv.thr, (size_t)nb);
+  L.add(&p->kv.relres, (size_t)nb);
+  L.add(&p->kv.iters, (size_t)nb);
   L.add(&p->kv.active, (size_t)nb);
   L.add(&p->kv.incycle, (size_t)nb);
   L.add(&p->kv.jcount, (size_t)nb);
@@ -343,6 +356,7 @@ int ensure_work(cavity_plan p, int nb) {
   if (s) return s;
   p->work_arena = {base, L.bytes};
   L.bind(base);
+  HIPCHK(hipMemsetAsync(p->counters, 0, (size_t)nb * sizeof(int), p->st));
   p->kv.restart = R;
   p->kv.tol = p->opts.tol;
   p->nbwork = nb;
@@ -393,15 +407,6 @@ double mixed_inner_reduction() {
   return v;
 }
 
-// nrm2[r] = |v_r|^2 for r < nb, copied to the host array out.
-int device_norms(cavity_plan p, const zd* v, int nb, double* out) {
-  HIPCHK(cav::launch_norm2(v, p->nvec(), nb, p->dnpart, p->nblk_red, p->kv.nrm2, nullptr, p->st));
-  HIPCHK(hipMemcpyAsync(p->hn, p->kv.nrm2, nb * sizeof(double), hipMemcpyDeviceToHost, p->st));
-  HIPCHK(hipStreamSynchronize(p->st));
-  for (int r = 0; r < nb; ++r) out[r] = p->hn[r];
-  return CAVITY_OK;
-}
-
 // Right-preconditioned restarted GMRES with classical Gram-Schmidt applied twice, for nb
 // right-hand sides b (p->bvec) iterating in lockstep; solutions in x (nb x n).  The
 // Arnoldi step, the Givens rotations and the convergence test run on the device; the
@@ -414,26 +419,30 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
                 std::vector<int>* iters_out) {
   const long long n = p->nvec();
   const int R = p->opts.restart;
-  const double tol = p->opts.tol;
   const bool mixed = p->opts.precision == CAVITY_MIXED;
   const double inner = mixed ? mixed_inner_reduction() : 0.0;
   const long long ldj = (long long)p->nbwork * n;
   cav::Krylov& kv = p->kv;
-  HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * n * sizeof(zd), p->st));
-  std::vector<double> bn2(nb), beta2(nb);
-  int s = device_norms(p, p->bvec, nb, bn2.data());
-  if (s) return s;
-  std::vector<double> bn(nb), relres(nb, 0.0);
-  std::vector<int> iters(nb, 0);
-  std::vector<char> done(nb, 0);
-  for (int r = 0; r < nb; ++r) {
-    bn[r] = std::sqrt(bn2[r]);
-    if (bn[r] == 0.0) done[r] = 1;
+  // How many Arnoldi steps the host may run ahead of the last convergence flags it has seen.
+  constexpr int kLag = 1;
+  if ((int)p->poll_ev.size() < R) {
+    const size_t old = p->poll_ev.size();
+    p->poll_ev.resize(R, nullptr);
+    for (size_t i = old; i < p->poll_ev.size(); ++i)
+      HIPCHK(hipEventCreateWithFlags(&p->poll_ev[i], hipEventDisableTiming));
   }
-  HIPCHK(hipMemcpyAsync(kv.bnorm, bn.data(), nb * sizeof(double), hipMemcpyHostToDevice, p->st));
-  std::vector<zd> g0((size_t)nb * (R + 1));
-  std::vector<double> thr(nb);
-  std::vector<int> flags(nb);
+  int* hstat = p->hflags;   // pinned: [0, nb) active, [nb, 2 nb) iterations, then per step
+  {
+    int* dev = nullptr;
+    HIPCHK(hipHostGetDevicePointer((void**)&dev, hstat, 0));
+    kv.hflags = dev + 2 * nb;
+    kv.nbh = nb;
+  }
+  HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * n * sizeof(zd), p->st));
+  HIPCHK(cav::launch_norm2(p->bvec, n, nb, p->dnpart, p->nblk_red, kv.nrm2, nullptr, p->st));
+  HIPCHK(cav::launch_krylov_init(kv, nb, p->st));
+  const int nblk_u = (int)std::min<long long>(kNormBlocks, (n + 255) / 256);
+  int s;
   bool first = true;
   while (true) {
     zd* v0 = p->V;  // basis vector 0 of rhs r at V + r n
@@ -441,78 +450,95 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
       HIPCHK(hipMemcpyAsync(v0, p->bvec, (size_t)nb * n * sizeof(zd), hipMemcpyDeviceToDevice,
                             p->st));
     } else {
+      // residual with the double-precision operator (the refinement step when mixed)
       if ((s = run_operator(p, 0, nb, x, p->w, nullptr))) return s;
       HIPCHK(cav::launch_sub(p->bvec, p->w, v0, (long long)nb * n, p->st));
     }
-    if ((s = device_norms(p, v0, nb, beta2.data()))) return s;
+    first = false;
+    HIPCHK(cav::launch_norm2(v0, n, nb, p->dnpart, p->nblk_red, kv.nrm2, nullptr, p->st));
+    HIPCHK(cav::launch_cycle_start(kv, nb, p->opts.max_iter, inner, p->st));
+    HIPCHK(hipMemcpyAsync(hstat, kv.active, nb * sizeof(int), hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipMemcpyAsync(hstat + nb, kv.iters, nb * sizeof(int), hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
     bool any = false;
-    for (int r = 0; r < nb; ++r) {
-      if (bn[r] == 0.0) continue;
-      relres[r] = std::sqrt(beta2[r]) / bn[r];
-      if (relres[r] <= tol || iters[r] >= p->opts.max_iter) done[r] = 1;
-      flags[r] = done[r] ? 0 : 1;
-      any = any || !done[r];
-    }
+    int budget = R;
     for (int r = 0; r < nb; ++r)
-      if (bn[r] == 0.0) flags[r] = 0;
+      if (hstat[r]) {
+        any = true;
+        budget = std::min(budget, std::max(1, p->opts.max_iter - hstat[nb + r]));
+      }
     if (std::getenv("CAVITY_TRACE")) {
+      std::vector<double> rr(nb);
+      HIPCHK(hipMemcpy(rr.data(), kv.relres, nb * sizeof(double), hipMemcpyDeviceToHost));
       std::fprintf(stderr, "[gmres] nb=%d cycle start:", nb);
-      for (int r = 0; r < nb; ++r) std::fprintf(stderr, " r%d it=%d res=%.3e", r, iters[r], relres[r]);
+      for (int r = 0; r < nb; ++r)
+        std::fprintf(stderr, " r%d it=%d res=%.3e", r, hstat[nb + r], rr[r]);
       std::fprintf(stderr, "\n");
     }
     if (!any) break;
-    first = false;
-    std::fill(g0.begin(), g0.end(), cav::mk(0.0, 0.0));
-    for (int r = 0; r < nb; ++r) {
-      g0[(size_t)r * (R + 1)] = cav::mk(std::sqrt(beta2[r]), 0.0);
-      thr[r] = std::max(tol * bn[r], inner * std::sqrt(beta2[r]));
-    }
-    HIPCHK(hipMemcpyAsync(kv.g, g0.data(), g0.size() * sizeof(zd), hipMemcpyHostToDevice, p->st));
-    HIPCHK(hipMemcpyAsync(kv.thr, thr.data(), nb * sizeof(double), hipMemcpyHostToDevice, p->st));
-    HIPCHK(hipMemcpyAsync(kv.active, flags.data(), nb * sizeof(int), hipMemcpyHostToDevice, p->st));
-    HIPCHK(hipMemcpyAsync(kv.incycle, flags.data(), nb * sizeof(int), hipMemcpyHostToDevice,
-                          p->st));
-    HIPCHK(cav::launch_scale_copy(v0, kv.nrm2, v0, n, n, nb, kv.active, p->st));
-    // at most max_iter - min(iters) iterations this cycle
-    int budget = R;
-    for (int r = 0; r < nb; ++r)
-      if (flags[r]) budget = std::min(budget, std::max(1, p->opts.max_iter - iters[r]));
+    // per-step flag slots start at -1 ("not written yet"); the device writes 0 or 1
+    for (size_t i = (size_t)2 * nb; i < (size_t)(2 + R) * nb; ++i) hstat[i] = -1;
+    // v_0 = r / |r| and z = P^{-1} v_0 (norms already in kv.nrm2)
+    HIPCHK(cav::launch_next_vector(p->g, kv, -1, nullptr, 0, v0, v0, n, p->pinv, p->zb, nb, p->st));
+    int seen = 0;   // first step whose flags the host has not looked at
     for (int j = 0; j < budget; ++j) {
-      const zd* vj = p->V + (long long)j * ldj;
       zd* vn = p->V + (long long)(j + 1) * ldj;
-      if ((s = run_operator(p, 1, nb, vj, p->w, kv.active, mixed))) return s;
+      // w = A z_j = A P^{-1} v_j
+      if ((s = run_operator(p, 0, nb, p->zb, p->w, kv.active, mixed))) return s;
       const int nv = j + 1;
       zd* hcol = kv.H + (long long)j * (R + 1);
       const long long hstr = (long long)R * (R + 1);
-      HIPCHK(cav::launch_dots(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
-                              nullptr, 0, kv.active, p->st));
+      // classical Gram-Schmidt, twice; the second pass's coefficients are added into H
+      HIPCHK(cav::launch_dots_fused(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->counters,
+                                    hcol, hstr, nullptr, 0, kv.active, p->st));
       HIPCHK(cav::launch_update(p->V, ldj, nv, hcol, hstr, p->w, n, nb, kv.active, p->st));
-      HIPCHK(cav::launch_dots(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, p->h2,
-                              R + 1, hcol, hstr, kv.active, p->st));
-      HIPCHK(cav::launch_update(p->V, ldj, nv, p->h2, R + 1, p->w, n, nb, kv.active, p->st));
-      HIPCHK(cav::launch_norm2(p->w, n, nb, p->dnpart, p->nblk_red, kv.nrm2, kv.active, p->st));
-      HIPCHK(cav::launch_scale_copy(p->w, kv.nrm2, vn, n, n, nb, kv.active, p->st));
-      HIPCHK(cav::launch_givens(kv, j, nb, p->st));
-      if ((j + 1) % 4 == 0 || j + 1 == budget) {
-        HIPCHK(hipMemcpyAsync(p->hflags, kv.active, nb * sizeof(int), hipMemcpyDeviceToHost,
-                              p->st));
-        HIPCHK(hipStreamSynchronize(p->st));
-        bool still = false;
-        for (int r = 0; r < nb; ++r) still = still || p->hflags[r];
-        if (!still) break;
+      HIPCHK(cav::launch_dots_fused(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->counters,
+                                    p->h2, R + 1, hcol, hstr, kv.active, p->st));
+      HIPCHK(cav::launch_update_norm(p->V, ldj, nv, p->h2, R + 1, p->w, n, nb, p->dnpart, nblk_u,
+                                     kv.active, p->st));
+      // Givens step of column j, then v_{j+1} = w / |w| and z = P^{-1} v_{j+1}
+      HIPCHK(cav::launch_next_vector(p->g, kv, j, p->dnpart, nblk_u, p->w, vn, n, p->pinv, p->zb,
+                                     nb, p->st));
+      // the Givens step published this step's flags in host memory; the event marks them ready
+      HIPCHK(hipEventRecord(p->poll_ev[j], p->st));
+      bool stop = false;
+      while (seen <= j && !stop) {
+        if (j - seen >= kLag) {
+          HIPCHK(hipEventSynchronize(p->poll_ev[seen]));
+        } else {
+          const hipError_t q = hipEventQuery(p->poll_ev[seen]);
+          if (q == hipErrorNotReady) break;
+          HIPCHK(q);
+        }
+        const volatile int* fl = hstat + (size_t)(2 + seen) * nb;
+        bool still = false, written = true;
+        for (int r = 0; r < nb; ++r) {
+          still = still || fl[r] == 1;
+          written = written && fl[r] >= 0;
+        }
+        if (!written) break;   // host view not updated yet: look again after the next step
+        stop = !still;
+        ++seen;
       }
+      if (stop) break;
     }
     HIPCHK(cav::launch_solve_y(kv, nb, p->st));
     HIPCHK(cav::launch_combine(p->g, kv, p->V, ldj, p->pinv, x, nb, p->st));
-    HIPCHK(hipMemcpyAsync(p->hflags, kv.jcount, nb * sizeof(int), hipMemcpyDeviceToHost, p->st));
-    HIPCHK(hipStreamSynchronize(p->st));
-    for (int r = 0; r < nb; ++r)
-      if (flags[r]) iters[r] += p->hflags[r];
+    HIPCHK(cav::launch_cycle_end(kv, nb, p->st));
+  }
+  std::vector<double> relres(nb);
+  std::vector<int> iters(nb);
+  HIPCHK(hipMemcpyAsync(p->hn, kv.relres, nb * sizeof(double), hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipMemcpyAsync(hstat, kv.iters, nb * sizeof(int), hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  for (int r = 0; r < nb; ++r) {
+    relres[r] = p->hn[r];
+    iters[r] = hstat[r];
   }
   if (relres_out) *relres_out = relres;
   if (iters_out) *iters_out = iters;
   for (int r = 0; r < nb; ++r)
-    if (relres[r] > tol) return fail(CAVITY_ENOCONV, "GMRES did not reach the tolerance");
+    if (relres[r] > p->opts.tol) return fail(CAVITY_ENOCONV, "GMRES did not reach the tolerance");
   return CAVITY_OK;
 }
 
@@ -710,7 +736,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   };
   for (auto& e : p->ev)
     if (hipEventCreate(&e) != hipSuccess) return bail(fail(CAVITY_EDEVICE, "hipEventCreate failed"));
-  if (hipHostMalloc((void**)&p->hflags, 64 * sizeof(int)) != hipSuccess ||
+  if (hipHostMalloc((void**)&p->hflags, (size_t)(o.restart + 2) * 64 * sizeof(int)) != hipSuccess ||
       hipHostMalloc((void**)&p->hn, 64 * sizeof(double)) != hipSuccess)
     return bail(fail(CAVITY_EDEVICE, "hipHostMalloc failed"));
 

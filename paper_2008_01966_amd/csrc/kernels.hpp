@@ -89,7 +89,11 @@ hipError_t launch_precond_build(const Geo& g, const zd* rho_d, const zd* T, cons
 struct Krylov {
   zd *H, *cs, *sn, *g, *y;
   double *nrm2, *bnorm, *thr;   // thr[r]: a cycle of rhs r stops once |g_{j+1}| <= thr[r]
+  double* relres;               // relative residual of rhs r at the start of the last cycle
   int *active, *incycle, *jcount;
+  int* iters;                   // iterations done by rhs r over all cycles
+  int* hflags;                  // host-mapped: after step j, hflags[j * nbh + r] = active[r]
+  int nbh;
   int restart;
   double tol;
 };
@@ -128,7 +132,31 @@ hipError_t launch_scale_copy(const zd* w, const double* nrm2, zd* v, long long n
                              long long vstride, int nb, const int* active, hipStream_t st);
 hipError_t launch_sub(const zd* b, const zd* w, zd* r, long long total, hipStream_t st);
 hipError_t launch_givens(const Krylov& kv, int j, int nb, hipStream_t st);
+// Fused Arnoldi steps (the cross-block sums finish inside the launch; counters: nb ints,
+// zero between launches).  partial: nb x nvmax x kDotBlocksHost complex.
+constexpr int kDotBlocksHost = 128;
+hipError_t launch_dots_fused(const zd* V, long long ldj, int nv, int nvmax, const zd* w,
+                             long long n, int nb, zd* partial, int* counters, zd* out,
+                             long long ostride, zd* acc, long long astride, const int* active,
+                             hipStream_t st);
+// w_r -= V h_r, with nblk partial sums of |w_r|^2 in npart[r * nblk + b].
+hipError_t launch_update_norm(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
+                              zd* w, long long n, int nb, double* npart, int nblk,
+                              const int* active, hipStream_t st);
+// |w_r|^2 (from nparts partials, or kv.nrm2 when nparts == 0), Givens step of column j
+// (j >= 0), v_r = w_r / |w_r| (v_r at v + r vstride) and z_r = P^{-1} v_r (z_r at z + r n).
+hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
+                              int nparts, const zd* w, zd* v, long long vstride, const zd* pinv,
+                              zd* z, int nb, hipStream_t st);
 hipError_t launch_solve_y(const Krylov& kv, int nb, hipStream_t st);
+// Restart bookkeeping on the device.  init: |b_r| = sqrt(nrm2[r]), iterations zero.
+// cycle_start (after nrm2[r] = |r_r|^2 of the current residual): relative residual, stop
+// test (tol, max_iter), active/incycle flags, g = (|r_r|, 0, ...), cycle threshold
+// thr = max(tol |b_r|, inner |r_r|).  cycle_end: iterations += columns built.
+hipError_t launch_krylov_init(const Krylov& kv, int nb, hipStream_t st);
+hipError_t launch_cycle_start(const Krylov& kv, int nb, int max_iter, double inner,
+                              hipStream_t st);
+hipError_t launch_cycle_end(const Krylov& kv, int nb, hipStream_t st);
 hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long ldj,
                           const zd* pinv, zd* x, int nb, hipStream_t st);
 

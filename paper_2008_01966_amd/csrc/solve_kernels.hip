@@ -626,15 +626,13 @@ hipError_t launch_sub(const zd* b, const zd* w, zd* r, long long total, hipStrea
 // Givens step of GMRES for column j of every active right-hand side (one thread each).
 // H[(r * restart + j) * (restart + 1) + i]: column j of the Hessenberg matrix, rotated in
 // place into R.  Rotation [[c, s], [-conj(s), conj(c)]] with c = conj(a)/d, s = conj(b)/d.
-__global__ void k_givens(Krylov kv, int j, int nb) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nb || !kv.active[r]) return;
+__device__ inline void givens_step(const Krylov& kv, int r, int j, double nrm2) {
   const int R = kv.restart;
   zd* col = kv.H + ((long long)r * R + j) * (R + 1);
   zd* cs = kv.cs + (long long)r * R;
   zd* sn = kv.sn + (long long)r * R;
   zd* gv = kv.g + (long long)r * (R + 1);
-  col[j + 1] = mk(sqrt(fmax(kv.nrm2[r], 0.0)), 0.0);
+  col[j + 1] = mk(sqrt(fmax(nrm2, 0.0)), 0.0);
   for (int i = 0; i < j; ++i) {
     const zd t = cs[i] * col[i] + sn[i] * col[i + 1];
     col[i + 1] = conj(sn[i]) * col[i] * mk(-1.0, 0.0) + conj(cs[i]) * col[i + 1];
@@ -658,11 +656,65 @@ __global__ void k_givens(Krylov kv, int j, int nb) {
   gv[j] = c * gj;
   const bool conv = sqrt(cabs2(gv[j + 1])) <= kv.thr[r] || den == 0.0;
   kv.jcount[r] = j + 1;
-  if (conv || j + 1 >= R) kv.active[r] = 0;
+  const bool stop = conv || j + 1 >= R;
+  if (stop) kv.active[r] = 0;
+  if (kv.hflags) kv.hflags[(long long)j * kv.nbh + r] = stop ? 0 : 1;
+}
+
+__global__ void k_givens(Krylov kv, int j, int nb) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nb || !kv.active[r]) return;
+  givens_step(kv, r, j, kv.nrm2[r]);
 }
 
 hipError_t launch_givens(const Krylov& kv, int j, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_givens, dim3((nb + 63) / 64), dim3(64), 0, st, kv, j, nb);
+  return hipGetLastError();
+}
+
+__global__ void k_krylov_init(Krylov kv, int nb) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nb) return;
+  kv.bnorm[r] = sqrt(fmax(kv.nrm2[r], 0.0));
+  kv.iters[r] = 0;
+  kv.relres[r] = 0.0;
+  kv.jcount[r] = 0;
+}
+
+__global__ void k_cycle_start(Krylov kv, int nb, int max_iter, double inner) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nb) return;
+  const double b = kv.bnorm[r];
+  const double beta = sqrt(fmax(kv.nrm2[r], 0.0));
+  const double rel = b > 0.0 ? beta / b : 0.0;
+  kv.relres[r] = rel;
+  const bool done = b == 0.0 || rel <= kv.tol || kv.iters[r] >= max_iter;
+  kv.active[r] = done ? 0 : 1;
+  kv.incycle[r] = done ? 0 : 1;
+  kv.jcount[r] = 0;
+  kv.g[(long long)r * (kv.restart + 1)] = mk(beta, 0.0);
+  kv.thr[r] = fmax(kv.tol * b, inner * beta);
+}
+
+__global__ void k_cycle_end(Krylov kv, int nb) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nb || !kv.incycle[r]) return;
+  kv.iters[r] += kv.jcount[r];
+}
+
+hipError_t launch_krylov_init(const Krylov& kv, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_krylov_init, dim3((nb + 63) / 64), dim3(64), 0, st, kv, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_cycle_start(const Krylov& kv, int nb, int max_iter, double inner,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_cycle_start, dim3((nb + 63) / 64), dim3(64), 0, st, kv, nb, max_iter, inner);
+  return hipGetLastError();
+}
+
+hipError_t launch_cycle_end(const Krylov& kv, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_cycle_end, dim3((nb + 63) / 64), dim3(64), 0, st, kv, nb);
   return hipGetLastError();
 }
 
@@ -719,6 +771,205 @@ hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long
   const int blk = 256;
   hipLaunchKernelGGL(k_combine, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g, kv, V, ldj,
                      pinv, x);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Fused Arnoldi steps.  A reduction that spans the blocks of a launch finishes inside the
+// same launch: every block publishes its partial result, then counts itself in a per-rhs
+// counter; the block that arrives last sums the partials in block order (the result does
+// not depend on scheduling) and resets the counter to zero for the next launch.
+// ---------------------------------------------------------------------------------
+constexpr int kDotBlocks = 128;  // blocks per (group, rhs) in the fused dot products
+
+__device__ inline bool arrive_last(int* counter, int total) {
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(counter, 1) == total - 1;
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last != 0;
+}
+
+__device__ inline double load_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// h = V^H w for the first nv basis vectors of each active rhs (kDotBlocks x groups of
+// kDotGroup vectors per rhs); out[r * ostride + vi] = h_vi, and acc[r * astride + vi] += h_vi
+// when acc is given.  partial: nb x nvmax x kDotBlocks.
+__global__ __launch_bounds__(256) void k_dots_fused(const zd* __restrict__ V, long long ldj,
+                                                    int nv, int nvmax, const zd* __restrict__ wall,
+                                                    long long n, zd* __restrict__ partial,
+                                                    int* __restrict__ counters,
+                                                    zd* __restrict__ out, long long ostride,
+                                                    zd* __restrict__ acc, long long astride,
+                                                    const int* __restrict__ active) {
+  __shared__ zd red[kDotGroup][4];
+  const int r = blockIdx.z;
+  if (active && !active[r]) return;
+  const int grp = blockIdx.y;
+  const zd* w = wall + r * n;
+  const zd* Vr = V + r * n;
+  zd a[kDotGroup];
+  for (int t = 0; t < kDotGroup; ++t) a[t] = mk(0.0, 0.0);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const int nvg = min(kDotGroup, nv - grp * kDotGroup);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const zd wi = w[i];
+#pragma unroll
+    for (int t = 0; t < kDotGroup; ++t)
+      if (t < nvg) a[t] = a[t] + conj(Vr[(grp * kDotGroup + t) * ldj + i]) * wi;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < kDotGroup; ++t) {
+    const zd s = mk(wave_sum(a[t].re), wave_sum(a[t].im));
+    if (lane == 0) red[t][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < nvg) {
+    const int t = threadIdx.x;
+    const zd s = red[t][0] + red[t][1] + red[t][2] + red[t][3];
+    partial[((long long)r * nvmax + grp * kDotGroup + t) * kDotBlocks + blockIdx.x] = s;
+  }
+  if (!arrive_last(&counters[r], gridDim.x * gridDim.y)) return;
+  // last block: wave wv sums the kDotBlocks partials of vectors wv, wv + 4, ...
+  for (int vi = wv; vi < nv; vi += 4) {
+    const zd* p = partial + ((long long)r * nvmax + vi) * kDotBlocks;
+    double re = 0.0, im = 0.0;
+    for (int b = lane; b < kDotBlocks; b += 64) {
+      re += load_agent(&p[b].re);
+      im += load_agent(&p[b].im);
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) {
+      out[r * ostride + vi] = mk(re, im);
+      if (acc) acc[r * astride + vi] = acc[r * astride + vi] + mk(re, im);
+    }
+  }
+  if (threadIdx.x == 0) counters[r] = 0;
+}
+
+hipError_t launch_dots_fused(const zd* V, long long ldj, int nv, int nvmax, const zd* w,
+                             long long n, int nb, zd* partial, int* counters, zd* out,
+                             long long ostride, zd* acc, long long astride, const int* active,
+                             hipStream_t st) {
+  const int ng = (nv + kDotGroup - 1) / kDotGroup;
+  hipLaunchKernelGGL(k_dots_fused, dim3(kDotBlocks, ng, nb), dim3(256), 0, st, V, ldj, nv, nvmax,
+                     w, n, partial, counters, out, ostride, acc, astride, active);
+  return hipGetLastError();
+}
+
+// w_r -= sum_i h[r * hstride + i] V_i,r, then partial[r * gridDim.x + block] = block's
+// share of |w_r|^2.
+__global__ __launch_bounds__(256) void k_update_norm(const zd* __restrict__ V, long long ldj, int nv,
+                                                     const zd* __restrict__ h, long long hstride,
+                                                     zd* __restrict__ wall, long long n,
+                                                     double* __restrict__ partial,
+                                                     const int* __restrict__ active) {
+  __shared__ zd hs[256];
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[r * hstride + i];
+  __syncthreads();
+  zd* w = wall + r * n;
+  const zd* Vr = V + r * n;
+  double nrm = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    zd a = w[i];
+    for (int vi = 0; vi < nv; ++vi) a = a - hs[vi] * Vr[vi * ldj + i];
+    w[i] = a;
+    nrm += cabs2(a);
+  }
+  nrm = wave_sum(nrm);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    partial[(long long)r * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t launch_update_norm(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
+                              zd* w, long long n, int nb, double* partial, int nblk,
+                              const int* active, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_norm, dim3(nblk, nb), dim3(256), 0, st, V, ldj, nv, h, hstride, w,
+                     n, partial, active);
+  return hipGetLastError();
+}
+
+// Next basis vector: |w_r|^2 from the nparts partials of k_update_norm (nparts == 0: from
+// kv.nrm2), then (j >= 0) the Givens step of column j by block 0, and v_r = w_r / |w_r|
+// with its preconditioned copy z_r = P^{-1} v_r.  Threads run over modes; vectors are
+// component-major.  Blocks read the active flag before block 0 may clear it; a rhs that
+// stops here never uses the vector written for it.
+__global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
+                                                     const double* __restrict__ npart, int nparts,
+                                                     const zd* wall, zd* vall, long long vstride,
+                                                     const zd* __restrict__ pinv,
+                                                     zd* __restrict__ zall) {
+  __shared__ double red[4];
+  __shared__ double s_nrm;
+  const int r = blockIdx.y;
+  if (!kv.active[r]) {
+    if (j >= 0 && kv.hflags && blockIdx.x == 0 && threadIdx.x == 0)
+      kv.hflags[(long long)j * kv.nbh + r] = 0;
+    return;
+  }
+  if (nparts > 0) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += npart[(long long)r * nparts + i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) s_nrm = red[0] + red[1] + red[2] + red[3];
+  } else if (threadIdx.x == 0) {
+    s_nrm = kv.nrm2[r];
+  }
+  __syncthreads();
+  const double nrm2 = s_nrm;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    kv.nrm2[r] = nrm2;
+    if (j >= 0) givens_step(kv, r, j, nrm2);
+  }
+  const double sc = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+  const long long n = 3LL * g.NM;
+  const zd* w = wall + r * n;
+  zd* v = vall + r * vstride;
+  zd* z = zall + r * n;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long mn = (long long)blockIdx.x * blockDim.x + threadIdx.x; mn < g.NM; mn += stride) {
+    zd u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      u[c] = sc * w[c * g.NM + mn];
+      v[c * g.NM + mn] = u[c];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      z[k * g.NM + mn] = pinv[(3 * k) * (long long)g.NM + mn] * u[0] +
+                         pinv[(3 * k + 1) * (long long)g.NM + mn] * u[1] +
+                         pinv[(3 * k + 2) * (long long)g.NM + mn] * u[2];
+  }
+}
+
+hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
+                              int nparts, const zd* w, zd* v, long long vstride, const zd* pinv,
+                              zd* z, int nb, hipStream_t st) {
+  int nblk = (g.NM + 255) / 256;
+  if (nblk > 1024) nblk = 1024;
+  hipLaunchKernelGGL(k_next_vector, dim3(nblk, nb), dim3(256), 0, st, g, kv, j, npart, nparts, w, v,
+                     vstride, pinv, z);
   return hipGetLastError();
 }
 

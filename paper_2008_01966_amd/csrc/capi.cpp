@@ -212,7 +212,6 @@ struct cavity_plan_s {
   zd *X = nullptr, *Y = nullptr, *S = nullptr;
   zd *V = nullptr, *w = nullptr, *bvec = nullptr;
   zd* zb = nullptr;          // preconditioned current basis vector P^{-1} v_j per rhs
-  int* counters = nullptr;   // per-rhs arrival counters of the fused reductions (zero at rest)
   zd* dpart = nullptr;
   double* dnpart = nullptr;
   zd* h2 = nullptr;
@@ -310,7 +309,7 @@ size_t work_bytes(const cav::Geo& g, int restart, int nb, int nblk) {
   const size_t z = sizeof(zd);
   return z * ((size_t)nb * 2 * 3 * (g.M + 1) * g.P2 + (size_t)nb * 3 * g.NM +
               (size_t)(restart + 1) * nb * n + 3ull * nb * n +
-              (size_t)std::max(nblk, cav::kDotBlocksHost) * (restart + 1) * nb +
+              (size_t)nblk * (restart + 1) * nb +
               (size_t)nb * (restart + 1) * 3 + (size_t)nb * restart * (restart + 4) + 64) +
          sizeof(double) * ((size_t)kNormBlocks * nb + 4 * nb) + sizeof(int) * 5 * nb + 64 * 256;
 }
@@ -328,8 +327,7 @@ int ensure_work(cavity_plan p, int nb) {
   L.add(&p->w, (size_t)nb * n);
   L.add(&p->bvec, (size_t)nb * n);
   L.add(&p->zb, (size_t)nb * n);
-  L.add(&p->counters, (size_t)nb);
-  L.add(&p->dpart, (size_t)std::max(p->nblk_red, cav::kDotBlocksHost) * (R + 1) * nb);
+  L.add(&p->dpart, (size_t)p->nblk_red * (R + 1) * nb);
   L.add(&p->dnpart, (size_t)kNormBlocks * nb);
   L.add(&p->h2, (size_t)nb * (R + 1));
   L.add(&p->kv.H, (size_t)nb * R * (R + 1));
@@ -356,7 +354,6 @@ int ensure_work(cavity_plan p, int nb) {
   if (s) return s;
   p->work_arena = {base, L.bytes};
   L.bind(base);
-  HIPCHK(hipMemsetAsync(p->counters, 0, (size_t)nb * sizeof(int), p->st));
   p->kv.restart = R;
   p->kv.tol = p->opts.tol;
   p->nbwork = nb;
@@ -489,11 +486,11 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
       zd* hcol = kv.H + (long long)j * (R + 1);
       const long long hstr = (long long)R * (R + 1);
       // classical Gram-Schmidt, twice; the second pass's coefficients are added into H
-      HIPCHK(cav::launch_dots_fused(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->counters,
-                                    hcol, hstr, nullptr, 0, kv.active, p->st));
+      HIPCHK(cav::launch_dots(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
+                              nullptr, 0, kv.active, p->st));
       HIPCHK(cav::launch_update(p->V, ldj, nv, hcol, hstr, p->w, n, nb, kv.active, p->st));
-      HIPCHK(cav::launch_dots_fused(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->counters,
-                                    p->h2, R + 1, hcol, hstr, kv.active, p->st));
+      HIPCHK(cav::launch_dots(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, p->h2,
+                              R + 1, hcol, hstr, kv.active, p->st));
       HIPCHK(cav::launch_update_norm(p->V, ldj, nv, p->h2, R + 1, p->w, n, nb, p->dnpart, nblk_u,
                                      kv.active, p->st));
       // Givens step of column j, then v_{j+1} = w / |w| and z = P^{-1} v_{j+1}

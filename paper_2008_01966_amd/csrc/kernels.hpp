@@ -132,13 +132,6 @@ hipError_t launch_scale_copy(const zd* w, const double* nrm2, zd* v, long long n
                              long long vstride, int nb, const int* active, hipStream_t st);
 hipError_t launch_sub(const zd* b, const zd* w, zd* r, long long total, hipStream_t st);
 hipError_t launch_givens(const Krylov& kv, int j, int nb, hipStream_t st);
-// Fused Arnoldi steps (the cross-block sums finish inside the launch; counters: nb ints,
-// zero between launches).  partial: nb x nvmax x kDotBlocksHost complex.
-constexpr int kDotBlocksHost = 128;
-hipError_t launch_dots_fused(const zd* V, long long ldj, int nv, int nvmax, const zd* w,
-                             long long n, int nb, zd* partial, int* counters, zd* out,
-                             long long ostride, zd* acc, long long astride, const int* active,
-                             hipStream_t st);
 // w_r -= V h_r, with nblk partial sums of |w_r|^2 in npart[r * nblk + b].
 hipError_t launch_update_norm(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
                               zd* w, long long n, int nb, double* npart, int nblk,

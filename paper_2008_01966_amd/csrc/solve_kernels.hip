@@ -775,99 +775,12 @@ hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long
 }
 
 // ---------------------------------------------------------------------------------
-// Fused Arnoldi steps.  A reduction that spans the blocks of a launch finishes inside the
-// same launch: every block publishes its partial result, then counts itself in a per-rhs
-// counter; the block that arrives last sums the partials in block order (the result does
-// not depend on scheduling) and resets the counter to zero for the next launch.
+// Fused Arnoldi steps: the second Gram-Schmidt update with the norm of the result, and the
+// normalisation with the Givens step and the preconditioner.
 // ---------------------------------------------------------------------------------
-constexpr int kDotBlocks = 128;  // blocks per (group, rhs) in the fused dot products
-
-__device__ inline bool arrive_last(int* counter, int total) {
-  __shared__ int last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    last = atomicAdd(counter, 1) == total - 1;
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last != 0;
-}
-
-__device__ inline double load_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
-}
-
-// h = V^H w for the first nv basis vectors of each active rhs (kDotBlocks x groups of
-// kDotGroup vectors per rhs); out[r * ostride + vi] = h_vi, and acc[r * astride + vi] += h_vi
-// when acc is given.  partial: nb x nvmax x kDotBlocks.
-__global__ __launch_bounds__(256) void k_dots_fused(const zd* __restrict__ V, long long ldj,
-                                                    int nv, int nvmax, const zd* __restrict__ wall,
-                                                    long long n, zd* __restrict__ partial,
-                                                    int* __restrict__ counters,
-                                                    zd* __restrict__ out, long long ostride,
-                                                    zd* __restrict__ acc, long long astride,
-                                                    const int* __restrict__ active) {
-  __shared__ zd red[kDotGroup][4];
-  const int r = blockIdx.z;
-  if (active && !active[r]) return;
-  const int grp = blockIdx.y;
-  const zd* w = wall + r * n;
-  const zd* Vr = V + r * n;
-  zd a[kDotGroup];
-  for (int t = 0; t < kDotGroup; ++t) a[t] = mk(0.0, 0.0);
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  const int nvg = min(kDotGroup, nv - grp * kDotGroup);
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const zd wi = w[i];
-#pragma unroll
-    for (int t = 0; t < kDotGroup; ++t)
-      if (t < nvg) a[t] = a[t] + conj(Vr[(grp * kDotGroup + t) * ldj + i]) * wi;
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int t = 0; t < kDotGroup; ++t) {
-    const zd s = mk(wave_sum(a[t].re), wave_sum(a[t].im));
-    if (lane == 0) red[t][wv] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < nvg) {
-    const int t = threadIdx.x;
-    const zd s = red[t][0] + red[t][1] + red[t][2] + red[t][3];
-    partial[((long long)r * nvmax + grp * kDotGroup + t) * kDotBlocks + blockIdx.x] = s;
-  }
-  if (!arrive_last(&counters[r], gridDim.x * gridDim.y)) return;
-  // last block: wave wv sums the kDotBlocks partials of vectors wv, wv + 4, ...
-  for (int vi = wv; vi < nv; vi += 4) {
-    const zd* p = partial + ((long long)r * nvmax + vi) * kDotBlocks;
-    double re = 0.0, im = 0.0;
-    for (int b = lane; b < kDotBlocks; b += 64) {
-      re += load_agent(&p[b].re);
-      im += load_agent(&p[b].im);
-    }
-    re = wave_sum(re);
-    im = wave_sum(im);
-    if (lane == 0) {
-      out[r * ostride + vi] = mk(re, im);
-      if (acc) acc[r * astride + vi] = acc[r * astride + vi] + mk(re, im);
-    }
-  }
-  if (threadIdx.x == 0) counters[r] = 0;
-}
-
-hipError_t launch_dots_fused(const zd* V, long long ldj, int nv, int nvmax, const zd* w,
-                             long long n, int nb, zd* partial, int* counters, zd* out,
-                             long long ostride, zd* acc, long long astride, const int* active,
-                             hipStream_t st) {
-  const int ng = (nv + kDotGroup - 1) / kDotGroup;
-  hipLaunchKernelGGL(k_dots_fused, dim3(kDotBlocks, ng, nb), dim3(256), 0, st, V, ldj, nv, nvmax,
-                     w, n, partial, counters, out, ostride, acc, astride, active);
-  return hipGetLastError();
 }
 
 // w_r -= sum_i h[r * hstride + i] V_i,r, then partial[r * gridDim.x + block] = block's

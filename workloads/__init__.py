@@ -54,6 +54,8 @@ class Workload:
     name: str
     cavity: Cavity
     incidences: Tuple[Incidence, ...]
+    tol: float = 1e-12      # relative residual the solves stop at
+    batch: int = 8          # right-hand sides iterated together
 
 
 def deg(x: float) -> float:
@@ -109,7 +111,8 @@ def batched_layered_8x8x2() -> Workload:
         for ph in range(0, 360, 45):
             for pol in (TM, TE):
                 inc.append(Incidence(float(th), deg(ph), pol))
-    return Workload("batched_layered_8x8x2_256x256x64_x128", cav, tuple(inc))
+    return Workload("batched_layered_8x8x2_256x256x64_x128", cav, tuple(inc), tol=1e-10,
+                    batch=32)
 
 
 @dataclasses.dataclass(frozen=True)

@@ -70,13 +70,50 @@ def cpu_baseline(wl, gpu_fields, gpu_sigma, sample):
     }, max(errs), max(rerr)
 
 
+def sources_sha256() -> str:
+    """Hash of the native sources; a traffic measurement is only used while it matches."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2008_01966_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed hardware-counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None when
+    there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None, None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    rel = os.path.relpath(path, ROOT)
+    if kv.get("source_sha256") != sources_sha256():
+        return None, rel + " (stale: kernel sources changed since)"
+    return float(kv["traffic_bytes_per_launch"]), rel
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="lossy_8x8x2_256x256x64")
-    ap.add_argument("--probe", default="tbc_cols", help="kernel timed for the roofline")
+    ap.add_argument("--probe", default=None,
+                    help="kernel timed for the roofline (default: the column pass of the TBC "
+                         "convolution in the headline precision)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes three times (reference "
+                         "kernel for scaling hardware traffic counters) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
                     help="right-hand sides iterated together (0: the workload's choice)")
@@ -93,6 +130,16 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration // 16
+        a = torch.ones(n, dtype=torch.complex128, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": int(n * 16), "launches": 3}), flush=True)
+        return 0
 
     import paper_2008_01966_amd as P
     import workloads as W
@@ -157,6 +204,8 @@ def main() -> int:
 
     precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     head = precisions[-1]
+    if args.probe is None:
+        args.probe = "tbc_cols_f32" if head == "mixed" else "tbc_cols"
     runs, sigs = {}, {}
     fields_by = {}
     for prec in precisions:
@@ -170,6 +219,7 @@ def main() -> int:
 
     unknowns_step = len(incs) * info.unknowns
     value = runs[head]["value"]
+    traffic, traffic_src = measured_traffic(args.probe, wl.name)
     achieved = (k_bytes / (k_ms * 1e-3)) / 1e9 if k_ms > 0 else 0.0
     out = {
         "metric": METRIC,
@@ -217,7 +267,8 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_source": traffic_src,
             "launches": launches,
             "avg_launch_ms": k_ms / max(launches, 1),
             "algorithmic_bytes_per_launch": k_bytes / max(launches, 1),

@@ -160,7 +160,9 @@ const char* cavity_last_error(void);
 enum {
   CAVITY_K_SPECTRUM = 0, CAVITY_K_ELIMINATION = 1, CAVITY_K_TBC_ROWS_FWD = 2,
   CAVITY_K_TBC_COLS = 3, CAVITY_K_TBC_ROWS_BWD = 4, CAVITY_K_EPILOGUE = 5,
-  CAVITY_K_SYNTH_ROWS = 6, CAVITY_K_SYNTH_COLS = 7
+  CAVITY_K_SYNTH_ROWS = 6, CAVITY_K_SYNTH_COLS = 7,
+  /* the three TBC passes in single precision (CAVITY_MIXED inner iterations) */
+  CAVITY_K_TBC_ROWS_FWD_F32 = 8, CAVITY_K_TBC_COLS_F32 = 9, CAVITY_K_TBC_ROWS_BWD_F32 = 10
 };
 int cavity_probe_kernel(int which, int capacity);
 int cavity_probe_read(int* launches, double* total_ms, double* total_bytes);

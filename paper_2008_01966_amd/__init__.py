@@ -67,7 +67,8 @@ EXPORTS = [
 ]
 
 KERNELS = {"spectrum": 0, "elimination": 1, "tbc_rows_fwd": 2, "tbc_cols": 3,
-           "tbc_rows_bwd": 4, "epilogue": 5, "synth_rows": 6, "synth_cols": 7}
+           "tbc_rows_bwd": 4, "epilogue": 5, "synth_rows": 6, "synth_cols": 7,
+           "tbc_rows_fwd_f32": 8, "tbc_cols_f32": 9, "tbc_rows_bwd_f32": 10}
 
 _lib = None
 

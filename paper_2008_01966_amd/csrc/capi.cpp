@@ -223,6 +223,7 @@ struct cavity_plan_s {
   // pinned host staging
   int* hflags = nullptr;
   double* hn = nullptr;
+  double* hratio = nullptr;   // pinned, host-mapped: per step and rhs, |g_{j+1}| / threshold
   int nblk_red = 128;
   cavity_info info{};
   // phase timers, resolved lazily: spectrum, elimination, preconditioner, rhs, krylov, synth
@@ -244,6 +245,7 @@ void release(cavity_plan p) {
   arena_release(p->sol_arena.ptr, p->sol_arena.bytes);
   if (p->hflags) (void)hipHostFree(p->hflags);
   if (p->hn) (void)hipHostFree(p->hn);
+  if (p->hratio) (void)hipHostFree(p->hratio);
   for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->poll_ev)
@@ -431,8 +433,11 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
   int* hstat = p->hflags;   // pinned: [0, nb) active, [nb, 2 nb) iterations, then per step
   {
     int* dev = nullptr;
+    double* devr = nullptr;
     HIPCHK(hipHostGetDevicePointer((void**)&dev, hstat, 0));
+    HIPCHK(hipHostGetDevicePointer((void**)&devr, p->hratio, 0));
     kv.hflags = dev + 2 * nb;
+    kv.hratio = devr;
     kv.nbh = nb;
   }
   HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * n * sizeof(zd), p->st));
@@ -500,7 +505,24 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
       HIPCHK(hipEventRecord(p->poll_ev[j], p->st));
       bool stop = false;
       while (seen <= j && !stop) {
-        if (j - seen >= kLag) {
+        // wait for a step when the host is kLag steps ahead of it, or when it is the step
+        // just queued and the last two residual ratios predict that every rhs still
+        // iterating converges in it (so no step is queued after convergence)
+        bool wait = j - seen >= kLag;
+        if (!wait && seen == j && j >= 2) {
+          bool all = true;
+          for (int r = 0; r < nb && all; ++r) {
+            const volatile int* f1 = hstat + (size_t)(2 + j - 1) * nb;
+            if (f1[r] != 1) continue;
+            const volatile double* q1 = p->hratio + (size_t)(j - 1) * nb;
+            const volatile double* q2 = p->hratio + (size_t)(j - 2) * nb;
+            const double a1 = q1[r], a2 = q2[r];
+            const double pred = a1 * (a1 / std::max(a2, 1e-300));
+            all = pred <= 1.0;
+          }
+          wait = all;
+        }
+        if (wait) {
           HIPCHK(hipEventSynchronize(p->poll_ev[seen]));
         } else {
           const hipError_t q = hipEventQuery(p->poll_ev[seen]);
@@ -734,6 +756,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   for (auto& e : p->ev)
     if (hipEventCreate(&e) != hipSuccess) return bail(fail(CAVITY_EDEVICE, "hipEventCreate failed"));
   if (hipHostMalloc((void**)&p->hflags, (size_t)(o.restart + 2) * 64 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc((void**)&p->hratio, (size_t)(o.restart + 2) * 64 * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void**)&p->hn, 64 * sizeof(double)) != hipSuccess)
     return bail(fail(CAVITY_EDEVICE, "hipHostMalloc failed"));
 

@@ -23,10 +23,6 @@
 
 #include "device.hpp"
 
-#ifndef CAV_FFT_TWPOW
-#define CAV_FFT_TWPOW 0
-#endif
-
 namespace cav {
 
 // ---- compile-time twiddles ---------------------------------------------------------
@@ -227,23 +223,11 @@ __device__ inline void fft_stage(const cx<T>* __restrict__ in, cx<T>* __restrict
     for (int r = 0; r < R; ++r) v[r] = in[((j + r * nb) << lc) + col];
     if (ns > 1) {
       const int step = k * tstep;
-#if CAV_FFT_TWPOW
-      // W^{r k} as powers of one table entry: one load per butterfly instead of R - 1
-      const cx<T> w1 = INV ? conj(tw[step]) : tw[step];
-      cx<T> wr = w1;
-      v[1] = v[1] * w1;
-#pragma unroll
-      for (int r = 2; r < R; ++r) {
-        wr = wr * w1;
-        v[r] = v[r] * wr;
-      }
-#else
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         const cx<T> w2 = tw[r * step];
         v[r] = v[r] * (INV ? conj(w2) : w2);
       }
-#endif
     }
     Dft<R, T, INV>::run(v);
     const int d = (j - k) * R + k;

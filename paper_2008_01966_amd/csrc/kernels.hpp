@@ -60,7 +60,8 @@ struct Wave {
 // Kernel identifiers for the benchmark probe (cavity_probe_* in the C ABI).
 enum KernelId {
   K_SPECTRUM = 0, K_ELIMINATION = 1, K_TBC_ROWS_FWD = 2, K_TBC_COLS = 3, K_TBC_ROWS_BWD = 4,
-  K_EPILOGUE = 5, K_SYNTH_ROWS = 6, K_SYNTH_COLS = 7, K_COUNT = 8
+  K_EPILOGUE = 5, K_SYNTH_ROWS = 6, K_SYNTH_COLS = 7, K_TBC_ROWS_FWD_F32 = 8,
+  K_TBC_COLS_F32 = 9, K_TBC_ROWS_BWD_F32 = 10, K_COUNT = 11
 };
 // While the probe watches kernel `id`, these bracket its launches with HIP events on the
 // launch stream and record the launch's algorithmic bytes; otherwise they do nothing.
@@ -93,6 +94,7 @@ struct Krylov {
   int *active, *incycle, *jcount;
   int* iters;                   // iterations done by rhs r over all cycles
   int* hflags;                  // host-mapped: after step j, hflags[j * nbh + r] = active[r]
+  double* hratio;               // host-mapped: after step j, |g_{j+1}| / thr[r] of rhs r
   int nbh;
   int restart;
   double tol;

@@ -358,26 +358,30 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
   const double vin = nb * (zb * (fam_fixed >= 0 ? 1.0 : 3.0) * g.NM) + (precond ? zb * 9.0 * g.NM : 0.0);
   const int lr = batch_log2(g.P2, (int)tb, g.M + 1);
   const int gr = (g.M + 1 + (1 << lr) - 1) >> lr;
-  probe_begin(K_TBC_ROWS_FWD, st);
+  const bool single = sizeof(T) == sizeof(float);
+  const int id_fwd = single ? K_TBC_ROWS_FWD_F32 : K_TBC_ROWS_FWD;
+  const int id_cols = single ? K_TBC_COLS_F32 : K_TBC_COLS;
+  const int id_bwd = single ? K_TBC_ROWS_BWD_F32 : K_TBC_ROWS_BWD;
+  probe_begin(id_fwd, st);
   hipLaunchKernelGGL((k_tbc_rows_fwd<T>), dim3(gr, nf, nb), dim3(256),
                      (size_t)2 * g.P2 * tb * (1 << lr), st, g, t.ext2, t.box2, pinv, precond,
                      fam_fixed, lr, v, vs, X, active);
-  probe_end(K_TBC_ROWS_FWD, st, vin + xbytes);
+  probe_end(id_fwd, st, vin + xbytes);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int lcc = batch_log2(g.P1, (int)tb, g.P2);
-  probe_begin(K_TBC_COLS, st);
+  probe_begin(id_cols, st);
   hipLaunchKernelGGL((k_tbc_cols<T>), dim3((g.P2 + (1 << lcc) - 1) >> lcc, nf, nb), dim3(256),
                      (size_t)2 * g.P1 * tb * (1 << lcc), st, g, t.ext1, t.box1, khat, fam_fixed,
                      lcc, X, Y, active);
-  probe_end(K_TBC_COLS, st, 2.0 * xbytes + tb * (double)g.P1 * g.P2);
+  probe_end(id_cols, st, 2.0 * xbytes + tb * (double)g.P1 * g.P2);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  probe_begin(K_TBC_ROWS_BWD, st);
+  probe_begin(id_bwd, st);
   hipLaunchKernelGGL((k_tbc_rows_bwd<T>), dim3(gr, nf, nb), dim3(256),
                      (size_t)2 * g.P2 * tb * (1 << lr), st, g, t.ext2, t.box2, fam_fixed, lr, Y, S,
                      active);
-  probe_end(K_TBC_ROWS_BWD, st, xbytes + zb * nb * nf * g.NM);
+  probe_end(id_bwd, st, xbytes + zb * nb * nf * g.NM);
   return hipGetLastError();
 }
 
@@ -658,7 +662,10 @@ __device__ inline void givens_step(const Krylov& kv, int r, int j, double nrm2) 
   kv.jcount[r] = j + 1;
   const bool stop = conv || j + 1 >= R;
   if (stop) kv.active[r] = 0;
-  if (kv.hflags) kv.hflags[(long long)j * kv.nbh + r] = stop ? 0 : 1;
+  if (kv.hflags) {
+    kv.hflags[(long long)j * kv.nbh + r] = stop ? 0 : 1;
+    kv.hratio[(long long)j * kv.nbh + r] = sqrt(cabs2(gv[j + 1])) / fmax(kv.thr[r], 1e-300);
+  }
 }
 
 __global__ void k_givens(Krylov kv, int j, int nb) {

@@ -102,6 +102,130 @@ def measured_traffic(kernel, workload):
     return float(kv["traffic_bytes_per_launch"]), rel
 
 
+
+SERVED = "served_stream_2000_poisson40"
+
+
+def served_main(args) -> int:
+    """Replay the served stream in real time: each request (random cavity, one incidence)
+    is submitted to the library's request server at its seeded Poisson arrival time; the
+    latency of a request runs from its arrival to its field and backscatter RCS being
+    ready.  value = unknowns of all requests / (last completion - first arrival)."""
+    import numpy as np
+    import torch
+
+    import paper_2008_01966_amd as P
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    stream = W.served_stream(args.requests)
+    # warm-up on a cavity outside the stream (loads the kernels; no aperture of the stream)
+    warm = P.Plan(0.75, 0.75, 0.25, 24, 24, 8, precision="mixed")
+    warm.solve(0.2, 0.1, 0)
+    warm.close()
+    torch.cuda.synchronize()
+    prec = "mixed" if args.precision in ("mixed", "both") else "fp64"
+    srv = P.Server(streams=args.streams, precision=prec)
+    tickets = []
+    t_origin = srv.now_ms() + 50.0
+    for req in stream:
+        due = t_origin + 1e3 * req.arrival_s
+        while True:
+            now = srv.now_ms()
+            if now >= due:
+                break
+            time.sleep(min(0.002, (due - now) * 1e-3))
+        inc = req.workload.incidences[0]
+        tickets.append((srv.submit(req.workload.cavity, inc.theta, inc.phi, inc.pol), due))
+    res = []
+    for t, due in tickets:
+        r = srv.wait(t)
+        res.append((r, due))
+        srv.release(t)
+    srv.close()
+    bad = [k for k, (r, _) in enumerate(res) if r.status != 0]
+    lat = np.array([r.t_done_ms - due for r, due in res])
+    queue = np.array([r.t_start_ms - due for r, due in res])
+    unknowns = float(sum(r.unknowns for r, _ in res))
+    span_s = (max(r.t_done_ms for r, _ in res) - t_origin) * 1e-3
+    its = [r.iterations for r, _ in res]
+    out = {
+        "metric": METRIC,
+        "value": unknowns / span_s,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": len(res),
+        "warmup": 1,
+        "ms_per_step": float(np.mean(lat)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": SERVED,
+            "requests": len(res),
+            "arrivals": "Poisson 40/s, seed 200801966, replayed in real time",
+            "streams": args.streams,
+            "precision": prec,
+            "step": "one request: plan (aperture data from the cache when seen before) + "
+                    "GMRES + field on all nodes + backscatter RCS",
+        },
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max()), "of": "arrival to field and RCS ready"},
+        "queueing_ms": {"p50": float(np.percentile(queue, 50)),
+                        "p99": float(np.percentile(queue, 99))},
+        "failed_requests": bad,
+        "gmres_iterations": {"min": int(min(its)), "max": int(max(its))},
+        "span_s": span_s,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["oracle_check"] = served_oracle(stream, res, prec)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def served_oracle(stream, res, prec):
+    """The oracle serves the stream's requests in order, serially, for about 20 s of host
+    time (at least one); the same requests are solved alone on the GPU with their field
+    kept and compared with the oracle's field and RCS."""
+    import numpy as np
+    import torch
+    from threadpoolctl import threadpool_info
+
+    import paper_2008_01966_amd as P
+    from oracle import solver
+    from oracle.problem import Problem
+
+    t0 = time.perf_counter()
+    done, unknowns, errs = 0, 0, []
+    for req, (r, _) in zip(stream, res):
+        cav = req.workload.cavity
+        inc = req.workload.incidences[0]
+        prob = Problem.from_cavity(cav)
+        pl = solver.plan(prob)
+        sol = solver.solve(pl, inc.theta, inc.phi, inc.pol, tol=1e-13)
+        field = solver.field_out(pl, sol)
+        sig = solver.backscatter(pl, sol, inc.theta, inc.phi)
+        done += 1
+        unknowns += prob.unknowns
+        plan = P.Plan.from_cavity(cav, precision=prec, batch=1)
+        g = plan.solve(inc.theta, inc.phi, inc.pol).cpu().numpy()
+        plan.close()
+        co = inc.pol
+        errs.append({"request": done - 1, "side": cav.a, "grid": [cav.nx, cav.ny, cav.nz],
+                     "field_rel_err": float(np.linalg.norm(g - field) / np.linalg.norm(field)),
+                     "rcs_rel_err_server": float(abs(r.sigma[co] - sig[co]) / sig[co])})
+        if time.perf_counter() - t0 > 20.0:
+            break
+    t1 = time.perf_counter()
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    torch.cuda.synchronize()
+    return ({"value": unknowns / (t1 - t0), "unit": "unknowns/s", "cores": int(threads),
+             "kind": "oracle",
+             "sample": f"first {done} requests of the stream served serially, {t1 - t0:.1f} s "
+                       "wall (includes the GPU re-solve of each for the field check)"}, errs)
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +243,8 @@ def main() -> int:
                     help="right-hand sides iterated together (0: the workload's choice)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="incidences the CPU oracle solves (0: all when at most 2, else 1)")
+    ap.add_argument("--requests", type=int, default=2000, help="served stream: requests")
+    ap.add_argument("--streams", type=int, default=4, help="served stream: concurrent requests")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
                     help="both: time the double-precision path, then the mixed one (headline)")
     args = ap.parse_args()
@@ -140,6 +266,9 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": int(n * 16), "launches": 3}), flush=True)
         return 0
+
+    if args.workload == SERVED:
+        return served_main(args)
 
     import paper_2008_01966_amd as P
     import workloads as W

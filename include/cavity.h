@@ -144,10 +144,79 @@ int cavity_rcs(cavity_plan plan, int rhs_index, int n_obs, const double* theta_o
 /* Copy stored aperture solution rhs_index to host memory (n_ap entries, paper order). */
 int cavity_aperture(cavity_plan plan, int rhs_index, cavity_c128* out_host);
 
+/* Device bytes cavity_plan_create would allocate for these arguments with one right-hand
+ * side in flight (plan data, solve workspace, one solution), without allocating anything.
+ * Same validation and errors as cavity_plan_create (CAVITY_EINVAL). */
+int cavity_plan_footprint(double a, double b, double c, int Nx, int Ny, int Nz,
+                          const cavity_eps* eps, double k, const cavity_opts* opts,
+                          size_t* bytes);
+
 int cavity_plan_info(cavity_plan plan, cavity_info* out);
 void cavity_plan_destroy(cavity_plan plan);
 const char* cavity_status_string(int status);
 const char* cavity_last_error(void);
+
+/* ---- Request server (serving many cavities) ---------------------------------------
+ * A request is one cavity (geometry, grid, layers, k) and one incidence; its result is
+ * the field on all nodes (the E_out of cavity_solve) and the backscatter RCS.  The server
+ * runs requests on `streams` worker threads, each with its own HIP stream on the device
+ * that was current when the server was created, so requests overlap on the GPU.  A
+ * request is admitted in arrival order once a worker is free and its device footprint
+ * (cavity_plan_footprint, plus its field when the server holds it) fits in what the
+ * budget leaves; requests larger
+ * than the whole budget fail with CAVITY_ENOMEM.  The kernel spectrum and operator
+ * diagonal of an aperture are cached across plans (Section 5 quantities depend on a, b,
+ * k, Nx, Ny only).  Results are independent of the mix: a request computes exactly what
+ * cavity_plan_create + cavity_solve + cavity_rcs compute for it alone.  All functions
+ * are thread-safe. */
+typedef struct cavity_server_s* cavity_server;
+
+typedef struct {
+  int streams;          /* concurrent requests (worker threads / HIP streams), 1..16 (default 4) */
+  size_t hbm_budget;    /* device bytes all admitted requests hold together; 0 = 80 % of the
+                           free device memory at creation */
+  int precision;        /* CAVITY_FP64 or CAVITY_MIXED (default) */
+  double tol;           /* GMRES tolerance (default 1e-12) */
+} cavity_server_opts;
+
+typedef struct {
+  double a, b, c;
+  int Nx, Ny, Nz;
+  int n_layers;                 /* 0 = vacuum, else layer_nz / eps_r as in cavity_eps */
+  const int* layer_nz;          /* host, copied at submission */
+  const cavity_c128* eps_r;     /* host, copied at submission */
+  double k, theta, phi;
+  int pol;
+  cavity_c128* E_out;           /* device, caller-owned, [3][Nz+1][Ny+1][Nx+1]: complete when
+                                   cavity_server_wait returns; NULL: the field is computed into
+                                   a temporary server buffer (counted in the budget) */
+} cavity_request;
+
+typedef struct {
+  int status;                   /* CAVITY_OK or the request's error */
+  double sigma[2];              /* backscatter {sigma_theta, sigma_phi} */
+  int iterations;
+  double rel_residual;
+  long long unknowns;           /* n_ap * Nz */
+  size_t device_bytes;          /* bytes the request held while running */
+  double t_submit_ms, t_start_ms, t_done_ms;   /* server clock: ms since creation */
+} cavity_result;
+
+int cavity_server_opts_default(cavity_server_opts* opts);
+/* Errors: CAVITY_EINVAL (opts out of range), CAVITY_EDEVICE. */
+int cavity_server_create(const cavity_server_opts* opts, cavity_server* out);
+/* Queue a request; *ticket identifies it.  Errors: CAVITY_EINVAL (argument validation as
+ * cavity_plan_create, or a server being destroyed). */
+int cavity_server_submit(cavity_server server, const cavity_request* req, long long* ticket);
+/* Block until request `ticket` has completed and copy its result (the request's own
+ * status is in out->status; the call returns CAVITY_EINVAL for an unknown ticket). */
+int cavity_server_wait(cavity_server server, long long ticket, cavity_result* out);
+/* Forget a completed request (its ticket becomes unknown). */
+int cavity_server_release(cavity_server server, long long ticket);
+/* Milliseconds on the server clock (steady clock since creation). */
+double cavity_server_now_ms(cavity_server server);
+/* Finish every queued request, stop the workers and free everything. */
+void cavity_server_destroy(cavity_server server);
 
 /* ---- Kernel timing probe (benchmarking) ------------------------------------------
  * Process-wide.  cavity_probe_kernel(which, capacity) starts watching one kernel

@@ -58,13 +58,40 @@ class Info(ctypes.Structure):
                 ("ms_synthesis", ctypes.c_double)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_int), ("hbm_budget", ctypes.c_size_t),
+                ("precision", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double),
+                ("Nx", ctypes.c_int), ("Ny", ctypes.c_int), ("Nz", ctypes.c_int),
+                ("n_layers", ctypes.c_int), ("layer_nz", ctypes.POINTER(ctypes.c_int)),
+                ("eps_r", ctypes.POINTER(C128)), ("k", ctypes.c_double),
+                ("theta", ctypes.c_double), ("phi", ctypes.c_double), ("pol", ctypes.c_int),
+                ("E_out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("sigma", ctypes.c_double * 2),
+                ("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("unknowns", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t),
+                ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double)]
+
+
 EXPORTS = [
     "cavity_opts_default", "cavity_plan_create", "cavity_solve", "cavity_solve_batch",
-    "cavity_rcs", "cavity_aperture", "cavity_plan_info", "cavity_plan_destroy",
-    "cavity_status_string", "cavity_last_error", "cavity_debug_columns",
+    "cavity_rcs", "cavity_aperture", "cavity_plan_footprint", "cavity_plan_info",
+    "cavity_plan_destroy", "cavity_status_string", "cavity_last_error",
+    "cavity_server_opts_default", "cavity_server_create", "cavity_server_submit",
+    "cavity_server_wait", "cavity_server_release", "cavity_server_now_ms",
+    "cavity_server_destroy", "cavity_debug_columns",
     "cavity_debug_profiles", "cavity_debug_spectrum", "cavity_debug_tbc",
     "cavity_debug_operator", "cavity_debug_rhs", "cavity_probe_kernel", "cavity_probe_read",
 ]
+_NOT_INT = ("cavity_plan_destroy", "cavity_status_string", "cavity_last_error",
+            "cavity_server_destroy", "cavity_server_now_ms")
 
 KERNELS = {"spectrum": 0, "elimination": 1, "tbc_rows_fwd": 2, "tbc_cols": 3,
            "tbc_rows_bwd": 4, "epilogue": 5, "synth_rows": 6, "synth_cols": 7,
@@ -107,8 +134,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cavity_debug_rhs.argtypes = [vp, d, d, i, P(C128), P(C128)]
     lib.cavity_probe_kernel.argtypes = [i, i]
     lib.cavity_probe_read.argtypes = [P(i), P(d), P(d)]
+    lib.cavity_plan_footprint.argtypes = [d, d, d, i, i, i, P(EpsStack), d, P(Opts),
+                                          P(ctypes.c_size_t)]
+    lib.cavity_server_opts_default.argtypes = [P(ServerOpts)]
+    lib.cavity_server_create.argtypes = [P(ServerOpts), P(vp)]
+    lib.cavity_server_submit.argtypes = [vp, P(Request), P(ctypes.c_longlong)]
+    lib.cavity_server_wait.argtypes = [vp, ctypes.c_longlong, P(Result)]
+    lib.cavity_server_release.argtypes = [vp, ctypes.c_longlong]
+    lib.cavity_server_now_ms.argtypes = [vp]
+    lib.cavity_server_now_ms.restype = d
+    lib.cavity_server_destroy.argtypes = [vp]
+    lib.cavity_server_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("cavity_plan_destroy", "cavity_status_string", "cavity_last_error"):
+        if name not in _NOT_INT:
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -298,3 +336,67 @@ def probe_stop():
     _check(lib.cavity_probe_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
     _check(lib.cavity_probe_kernel(-1, 0))
     return n.value, ms.value, by.value
+
+
+class Server:
+    """Request server of the library: cavities of any size solved for one incidence each,
+    several in flight on the GPU, admitted in arrival order within a device-memory budget.
+    Results carry the backscatter RCS, iteration count and timestamps; the field goes to
+    the caller's device tensor when one is given to submit()."""
+
+    def __init__(self, streams: int = 4, hbm_budget: int = 0, precision: str = "mixed",
+                 tol: float = 1e-12):
+        lib = load_library()
+        self._lib = lib
+        o = ServerOpts()
+        _check(lib.cavity_server_opts_default(ctypes.byref(o)))
+        o.streams, o.hbm_budget, o.tol = int(streams), int(hbm_budget), float(tol)
+        o.precision = PRECISIONS[precision]
+        h = ctypes.c_void_p()
+        _check(lib.cavity_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, cav, theta: float, phi: float, pol: int, out=None) -> int:
+        """Queue cavity `cav` (a workloads.Cavity-like object) at one incidence; `out`: an
+        optional complex128 device tensor of shape (3, Nz+1, Ny+1, Nx+1) for the field,
+        which must stay alive until wait() returns."""
+        nzs = (ctypes.c_int * len(cav.layer_nz))(*[int(v) for v in cav.layer_nz])
+        eps = (C128 * len(cav.layer_eps))(*[C128(complex(e).real, complex(e).imag)
+                                            for e in cav.layer_eps])
+        eptr = None
+        if out is not None:
+            torch = _torch()
+            assert out.dtype == torch.complex128 and out.is_cuda and out.is_contiguous()
+            assert tuple(out.shape) == (3, cav.nz + 1, cav.ny + 1, cav.nx + 1)
+            eptr = out.data_ptr()
+        r = Request(cav.a, cav.b, cav.c, cav.nx, cav.ny, cav.nz, len(cav.layer_nz), nzs, eps,
+                    cav.k, float(theta), float(phi), int(pol), eptr)
+        t = ctypes.c_longlong()
+        _check(self._lib.cavity_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = out
+        return t.value
+
+    def wait(self, ticket: int) -> Result:
+        out = Result()
+        _check(self._lib.cavity_server_wait(self._h, ctypes.c_longlong(ticket), ctypes.byref(out)))
+        return out
+
+    def release(self, ticket: int):
+        _check(self._lib.cavity_server_release(self._h, ctypes.c_longlong(ticket)))
+        self._keep.pop(ticket, None)
+
+    def now_ms(self) -> float:
+        return float(self._lib.cavity_server_now_ms(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.cavity_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -15,6 +15,7 @@
 
 #include "cavity.h"
 #include "kernels.hpp"
+#include "runtime.hpp"
 
 using cav::zd;
 
@@ -48,6 +49,10 @@ int next_5smooth(long long n) {
 }
 
 cav::FftPlan make_fft_plan(int n) { return cav::plan_fft(n, cav::kMaxRadix); }
+
+// LDS of one workgroup on gfx950 (160 KiB); every FFT kernel needs two buffers of its
+// longest transform for at least one column.
+constexpr size_t kMaxLdsPerBlock = 160 * 1024;
 
 // Blocks per right-hand side of the fused update + norm pass of the Arnoldi step.
 constexpr int kNormBlocks = 1024;
@@ -182,6 +187,12 @@ struct Arena {
 };
 
 }  // namespace
+
+namespace cav {
+int device_block_acquire(size_t bytes, void** out) { return arena_acquire(bytes, out); }
+void device_block_release(void* ptr, size_t bytes) { arena_release(ptr, bytes); }
+int record_error(int status, const char* msg) { return fail(status, msg); }
+}  // namespace cav
 
 struct cavity_plan_s {
   cav::Geo g{};
@@ -622,41 +633,149 @@ int solve_chunk(cavity_plan p, int i0, int nb, const double* theta, const double
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int cavity_opts_default(cavity_opts* o) {
-  if (!o) return fail(CAVITY_EINVAL, "NULL opts");
-  o->precision = CAVITY_FP64;
-  o->tbc_oversample = 1;
-  o->tol = 1e-12;
-  o->max_iter = 400;
-  o->restart = 60;
-  o->hbm_budget = 0;
-  o->stream = nullptr;
-  o->batch = 8;
-  return CAVITY_OK;
+// ---- aperture cache ----------------------------------------------------------------
+// The kernel spectrum (Section 5) and the exact diagonal of the three single-layer
+// operators depend only on the aperture: a, b, k, Nx, Ny and the quadrature oversampling.
+// Plans with an equal aperture (a served stream sees a handful of apertures for thousands
+// of cavities) copy them from this process-wide cache instead of recomputing them.  Entries
+// live in their own device blocks, filled asynchronously on the stream of the plan that
+// computed them; a ready event orders every later copy after the fill.  Least recently
+// used entries go when the cache exceeds its byte limit (CAVITY_APERTURE_CACHE_BYTES,
+// default 1 GiB; 0 disables it); the device is synchronised before such a free because
+// copies from the entry may still be queued on other streams.
+struct ApertureEntry {
+  double a, b, k;
+  int nx, ny, s, dev;
+  void* mem;
+  size_t bytes;
+  hipEvent_t ready;
+  unsigned long long last_use;
+};
+std::mutex g_ap_mu;
+std::vector<ApertureEntry> g_ap;
+size_t g_ap_bytes = 0;
+unsigned long long g_ap_clock = 0;
+
+size_t aperture_cache_limit() {
+  static long long v = -2;
+  if (v == -2) {
+    const char* e = std::getenv("CAVITY_APERTURE_CACHE_BYTES");
+    v = e ? std::atoll(e) : (1LL << 30);
+    if (v < 0) v = 0;
+  }
+  return (size_t)v;
 }
 
-const char* cavity_status_string(int s) {
-  switch (s) {
-    case CAVITY_OK: return "ok";
-    case CAVITY_EINVAL: return "invalid argument";
-    case CAVITY_ENOMEM: return "out of device memory / over budget";
-    case CAVITY_ERESONANT: return "resonant z-elimination pivot";
-    case CAVITY_ENOCONV: return "GMRES did not converge";
-    case CAVITY_EDEVICE: return "HIP device error";
-    case CAVITY_ENOTIMPL: return "not implemented";
-    default: return "unknown status";
+size_t aperture_bytes(const cav::Geo& g) {
+  return (size_t)g.P1 * g.P2 * (sizeof(zd) + sizeof(cav::zf)) + 3ull * g.NM * sizeof(zd);
+}
+
+bool aperture_match(const ApertureEntry& e, const cav::Geo& g, int s, int dev) {
+  return e.dev == dev && e.a == g.a && e.b == g.b && e.k == g.k && e.nx == g.nx &&
+         e.ny == g.ny && e.s == s;
+}
+
+// On a hit, queue copies of the cached spectrum, its single-precision copy and the
+// diagonal into the plan's arrays on stream st and return true.
+bool aperture_lookup(const cav::Geo& g, int s, zd* khat, cav::zf* khat_f, zd* diag,
+                     hipStream_t st) {
+  if (aperture_cache_limit() == 0) return false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(g_ap_mu);
+  for (ApertureEntry& e : g_ap) {
+    if (!aperture_match(e, g, s, dev)) continue;
+    const size_t nk = (size_t)g.P1 * g.P2;
+    char* base = static_cast<char*>(e.mem);
+    if (hipStreamWaitEvent(st, e.ready, 0) != hipSuccess ||
+        hipMemcpyAsync(khat, base, nk * sizeof(zd), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(khat_f, base + nk * sizeof(zd), nk * sizeof(cav::zf),
+                       hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(diag, base + nk * (sizeof(zd) + sizeof(cav::zf)),
+                       3ull * g.NM * sizeof(zd), hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return false;
+    e.last_use = ++g_ap_clock;
+    return true;
+  }
+  return false;
+}
+
+// Store a freshly computed aperture (queued on st after its computation).  Best effort:
+// any failure leaves the cache unchanged.
+void aperture_insert(const cav::Geo& g, int s, const zd* khat, const cav::zf* khat_f,
+                     const zd* diag, hipStream_t st) {
+  const size_t limit = aperture_cache_limit();
+  const size_t bytes = aperture_bytes(g);
+  if (limit == 0 || bytes > limit) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  {
+    std::lock_guard<std::mutex> lk(g_ap_mu);
+    for (const ApertureEntry& e : g_ap)
+      if (aperture_match(e, g, s, dev)) return;   // another plan stored it meanwhile
+  }
+  void* mem = nullptr;
+  if (hipMalloc(&mem, bytes) != hipSuccess) return;
+  hipEvent_t ev = nullptr;
+  const size_t nk = (size_t)g.P1 * g.P2;
+  char* base = static_cast<char*>(mem);
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+      hipMemcpyAsync(base, khat, nk * sizeof(zd), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(base + nk * sizeof(zd), khat_f, nk * sizeof(cav::zf),
+                     hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(base + nk * (sizeof(zd) + sizeof(cav::zf)), diag, 3ull * g.NM * sizeof(zd),
+                     hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipEventRecord(ev, st) != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipFree(mem);
+    return;
+  }
+  std::vector<ApertureEntry> evict;
+  {
+    std::lock_guard<std::mutex> lk(g_ap_mu);
+    while (!g_ap.empty() && g_ap_bytes + bytes > limit) {
+      size_t lru = 0;
+      for (size_t i = 1; i < g_ap.size(); ++i)
+        if (g_ap[i].last_use < g_ap[lru].last_use) lru = i;
+      evict.push_back(g_ap[lru]);
+      g_ap_bytes -= g_ap[lru].bytes;
+      g_ap.erase(g_ap.begin() + lru);
+    }
+    g_ap.push_back({g.a, g.b, g.k, g.nx, g.ny, s, dev, mem, bytes, ev, ++g_ap_clock});
+    g_ap_bytes += bytes;
+  }
+  if (!evict.empty()) {
+    (void)hipDeviceSynchronize();
+    for (ApertureEntry& e : evict) {
+      (void)hipEventDestroy(e.ready);
+      (void)hipFree(e.mem);
+    }
   }
 }
 
-const char* cavity_last_error(void) { return g_err.c_str(); }
+}  // namespace
 
-int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
-                       const cavity_eps* eps, double k, const cavity_opts* opts,
-                       cavity_plan* out) {
-  if (!out) return fail(CAVITY_EINVAL, "NULL plan output");
-  *out = nullptr;
+namespace {
+
+// Validated arguments and derived sizes of a plan.
+struct PlanSpec {
+  cav::Geo g{};
+  cavity_opts o{};
+  std::vector<int> lnz;
+  std::vector<std::complex<double>> leps;
+  bool layered = false;
+  double R = 0.0;
+  int chunk = 1;
+  int fft_len[6] = {};
+  int twn = 0;
+  size_t need = 0;     // device bytes of the plan with one right-hand side in flight
+};
+
+int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cavity_eps* eps,
+                 double k, const cavity_opts* opts, PlanSpec* ps) {
   if (!(a > 0 && b > 0 && c > 0 && k > 0) || !std::isfinite(a) || !std::isfinite(b) ||
       !std::isfinite(c) || !std::isfinite(k))
     return fail(CAVITY_EINVAL, "a, b, c, k must be positive and finite");
@@ -714,11 +833,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   g.P1 = next_5smooth((long long)std::ceil((a + R) / g.hq1));
   g.P2 = next_5smooth((long long)std::ceil((b + R) / g.hq2));
 
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
-  int lds_max = 0;
-  HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  if ((size_t)2 * std::max(g.P1, g.P2) * sizeof(zd) > (size_t)lds_max)
+  if ((size_t)2 * std::max(g.P1, g.P2) * sizeof(zd) > (size_t)kMaxLdsPerBlock)
     return fail(CAVITY_EINVAL, "FFT box too large for one block's LDS");
 
   const bool layered = lnz.size() > 1;
@@ -731,6 +846,82 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   const int nb0 = 1;
   const size_t need = plan_bytes(g, layered, chunk, (int)lnz.size(), &twn) +
                       work_bytes(g, o.restart, nb0, 128) + 3ull * g.NM * sizeof(zd);
+  ps->g = g;
+  ps->o = o;
+  ps->lnz = lnz;
+  ps->leps = leps;
+  ps->layered = layered;
+  ps->R = R;
+  ps->chunk = chunk;
+  for (int i = 0; i < 6; ++i) ps->fft_len[i] = fft_len[i];
+  ps->twn = twn;
+  ps->need = need;
+  return CAVITY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cavity_opts_default(cavity_opts* o) {
+  if (!o) return fail(CAVITY_EINVAL, "NULL opts");
+  o->precision = CAVITY_FP64;
+  o->tbc_oversample = 1;
+  o->tol = 1e-12;
+  o->max_iter = 400;
+  o->restart = 60;
+  o->hbm_budget = 0;
+  o->stream = nullptr;
+  o->batch = 8;
+  return CAVITY_OK;
+}
+
+const char* cavity_status_string(int s) {
+  switch (s) {
+    case CAVITY_OK: return "ok";
+    case CAVITY_EINVAL: return "invalid argument";
+    case CAVITY_ENOMEM: return "out of device memory / over budget";
+    case CAVITY_ERESONANT: return "resonant z-elimination pivot";
+    case CAVITY_ENOCONV: return "GMRES did not converge";
+    case CAVITY_EDEVICE: return "HIP device error";
+    case CAVITY_ENOTIMPL: return "not implemented";
+    default: return "unknown status";
+  }
+}
+
+const char* cavity_last_error(void) { return g_err.c_str(); }
+
+int cavity_plan_footprint(double a, double b, double c, int Nx, int Ny, int Nz,
+                          const cavity_eps* eps, double k, const cavity_opts* opts,
+                          size_t* bytes) {
+  if (!bytes) return fail(CAVITY_EINVAL, "NULL output");
+  PlanSpec ps;
+  const int st = prepare_plan(a, b, c, Nx, Ny, Nz, eps, k, opts, &ps);
+  if (st) return st;
+  *bytes = ps.need;
+  return CAVITY_OK;
+}
+
+int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
+                       const cavity_eps* eps, double k, const cavity_opts* opts,
+                       cavity_plan* out) {
+  if (!out) return fail(CAVITY_EINVAL, "NULL plan output");
+  *out = nullptr;
+  PlanSpec ps;
+  {
+    const int st0 = prepare_plan(a, b, c, Nx, Ny, Nz, eps, k, opts, &ps);
+    if (st0) return st0;
+  }
+  const cav::Geo& g = ps.g;
+  const cavity_opts& o = ps.o;
+  const std::vector<int>& lnz = ps.lnz;
+  const std::vector<std::complex<double>>& leps = ps.leps;
+  const bool layered = ps.layered;
+  const double R = ps.R;
+  const int chunk = ps.chunk;
+  const int* fft_len = ps.fft_len;
+  const int twn = ps.twn;
+  const size_t need = ps.need;
   size_t budget = o.hbm_budget;
   if (budget == 0) {
     size_t fr = 0, tot = 0;
@@ -854,8 +1045,10 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   const double scale = 1.0 / (g.hq1 * g.hq2 * (double)g.P1 * (double)g.P2);
   int st = CAVITY_OK;
   if ((st = mark(p, 0, false))) return bail(st);
-  if (!chk(cav::launch_spectrum(g, R, scale, p->khat, p->st), "spectrum") ||
-      !chk(cav::launch_to_f32(p->khat, p->khat_f, (long long)g.P1 * g.P2, p->st), "spectrum"))
+  const bool cached = aperture_lookup(g, o.tbc_oversample, p->khat, p->khat_f, p->diag, p->st);
+  if (!cached &&
+      (!chk(cav::launch_spectrum(g, R, scale, p->khat, p->st), "spectrum") ||
+       !chk(cav::launch_to_f32(p->khat, p->khat_f, (long long)g.P1 * g.P2, p->st), "spectrum")))
     return bail(CAVITY_EDEVICE);
   if ((st = mark(p, 0, true))) return bail(st);
   cav::Layers ly{p->node_code, p->kappa2, p->ratio, layered ? 1 : 0};
@@ -865,10 +1058,13 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     return bail(CAVITY_EDEVICE);
   if ((st = mark(p, 1, true))) return bail(st);
   if ((st = mark(p, 2, false))) return bail(st);
-  if (!chk(cav::launch_basis_power(g, p->trig, p->pw1, p->pw2, p->st), "basis power") ||
-      !chk(cav::launch_diag_contract(g, p->khat, p->pw1, p->pw2, p->ctmp, p->diag, p->st),
-           "diagonal") ||
-      !chk(cav::launch_precond_build(g, p->rho_d, p->T, p->rho_n, p->diag, p->pinv, p->st),
+  if (!cached &&
+      (!chk(cav::launch_basis_power(g, p->trig, p->pw1, p->pw2, p->st), "basis power") ||
+       !chk(cav::launch_diag_contract(g, p->khat, p->pw1, p->pw2, p->ctmp, p->diag, p->st),
+            "diagonal")))
+    return bail(CAVITY_EDEVICE);
+  if (!cached) aperture_insert(g, o.tbc_oversample, p->khat, p->khat_f, p->diag, p->st);
+  if (!chk(cav::launch_precond_build(g, p->rho_d, p->T, p->rho_n, p->diag, p->pinv, p->st),
            "preconditioner"))
     return bail(CAVITY_EDEVICE);
   if ((st = mark(p, 2, true))) return bail(st);

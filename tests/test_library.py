@@ -87,3 +87,48 @@ def test_null_arguments_rejected():
     assert lib.cavity_rcs(None, 0, 0, None, None, None) == 1
     assert lib.cavity_plan_info(None, None) == 1
     lib.cavity_plan_destroy(None)
+
+
+def _footprint(a=1.0, b=1.0, c=0.5, nx=16, ny=16, nz=8, eps=None, k=6.28, opts=None):
+    lib = P.load_library()
+    out = ctypes.c_size_t()
+    st = lib.cavity_plan_footprint(a, b, c, nx, ny, nz, eps, k,
+                                   ctypes.byref(opts) if opts is not None else None,
+                                   ctypes.byref(out))
+    return st, out.value
+
+
+def test_footprint_needs_no_device_and_scales():
+    """The device footprint is computed on the host: it grows with the grid, counts the
+    Krylov basis of the restart length and the profiles of every level, and validates like
+    plan creation."""
+    st, small = _footprint()
+    assert st == 0 and small > 0
+    st, big = _footprint(a=8.0, b=8.0, c=2.0, nx=256, ny=256, nz=64)
+    assert st == 0
+    nm = 256 * 256
+    assert big >= 16 * 2 * 65 * nm          # two profile arrays of 65 levels
+    assert big >= 16 * 61 * 3 * nm          # restart 60: 61 basis vectors
+    assert big < 4 << 30
+    o = P.Opts()
+    P.load_library().cavity_opts_default(ctypes.byref(o))
+    o.restart = 20
+    st, short = _footprint(a=8.0, b=8.0, c=2.0, nx=256, ny=256, nz=64, opts=o)
+    assert st == 0 and short < big
+    assert _footprint(nx=14)[0] == 1 and _footprint(c=-1.0)[0] == 1
+
+
+def test_server_arguments_rejected_without_device():
+    lib = P.load_library()
+    o = P.ServerOpts()
+    assert lib.cavity_server_opts_default(ctypes.byref(o)) == 0
+    assert (o.streams, o.precision, o.tol) == (4, 1, 1e-12)
+    h = ctypes.c_void_p()
+    o.streams = 0
+    assert lib.cavity_server_create(ctypes.byref(o), ctypes.byref(h)) == 1 and not h.value
+    r = P.Request()
+    t = ctypes.c_longlong()
+    assert lib.cavity_server_submit(None, ctypes.byref(r), ctypes.byref(t)) == 1
+    assert lib.cavity_server_wait(None, 1, None) == 1
+    assert lib.cavity_server_release(None, 1) == 1
+    lib.cavity_server_destroy(None)

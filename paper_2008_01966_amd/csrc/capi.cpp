@@ -223,6 +223,7 @@ struct cavity_plan_s {
   zd *X = nullptr, *Y = nullptr, *S = nullptr;
   zd *V = nullptr, *w = nullptr, *bvec = nullptr;
   zd* zb = nullptr;          // preconditioned current basis vector P^{-1} v_j per rhs
+  zd* rbuf = nullptr;        // residual at the start of a cycle, per rhs
   zd* dpart = nullptr;
   double* dnpart = nullptr;
   zd* h2 = nullptr;
@@ -321,7 +322,7 @@ size_t work_bytes(const cav::Geo& g, int restart, int nb, int nblk) {
   const size_t n = 3ull * g.NM;
   const size_t z = sizeof(zd);
   return z * ((size_t)nb * 2 * 3 * (g.M + 1) * g.P2 + (size_t)nb * 3 * g.NM +
-              (size_t)(restart + 1) * nb * n + 3ull * nb * n +
+              (size_t)(restart + 1) * nb * n + 4ull * nb * n +
               (size_t)nblk * (restart + 1) * nb +
               (size_t)nb * (restart + 1) * 3 + (size_t)nb * restart * (restart + 4) + 64) +
          sizeof(double) * ((size_t)kNormBlocks * nb + 4 * nb) + sizeof(int) * 5 * nb + 64 * 256;
@@ -340,6 +341,7 @@ int ensure_work(cavity_plan p, int nb) {
   L.add(&p->w, (size_t)nb * n);
   L.add(&p->bvec, (size_t)nb * n);
   L.add(&p->zb, (size_t)nb * n);
+  L.add(&p->rbuf, (size_t)nb * n);
   L.add(&p->dpart, (size_t)p->nblk_red * (R + 1) * nb);
   L.add(&p->dnpart, (size_t)kNormBlocks * nb);
   L.add(&p->h2, (size_t)nb * (R + 1));
@@ -425,8 +427,9 @@ double mixed_inner_reduction() {
 // convolutions and a cycle ends once it has reduced its residual by the inner factor;
 // every restart recomputes the residual b - A x with the double-precision operator, so
 // the cycles are steps of iterative refinement and the final test is on that residual.
-int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
-                std::vector<int>* iters_out) {
+template <typename VT>
+int gmres_batch_t(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
+                  std::vector<int>* iters_out, cav::cx<VT>* V) {
   const long long n = p->nvec();
   const int R = p->opts.restart;
   const bool mixed = p->opts.precision == CAVITY_MIXED;
@@ -458,17 +461,17 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
   int s;
   bool first = true;
   while (true) {
-    zd* v0 = p->V;  // basis vector 0 of rhs r at V + r n
+    zd* r0 = p->rbuf;   // residual of rhs r at rbuf + r n
     if (first) {
-      HIPCHK(hipMemcpyAsync(v0, p->bvec, (size_t)nb * n * sizeof(zd), hipMemcpyDeviceToDevice,
+      HIPCHK(hipMemcpyAsync(r0, p->bvec, (size_t)nb * n * sizeof(zd), hipMemcpyDeviceToDevice,
                             p->st));
     } else {
       // residual with the double-precision operator (the refinement step when mixed)
       if ((s = run_operator(p, 0, nb, x, p->w, nullptr))) return s;
-      HIPCHK(cav::launch_sub(p->bvec, p->w, v0, (long long)nb * n, p->st));
+      HIPCHK(cav::launch_sub(p->bvec, p->w, r0, (long long)nb * n, p->st));
     }
     first = false;
-    HIPCHK(cav::launch_norm2(v0, n, nb, p->dnpart, p->nblk_red, kv.nrm2, nullptr, p->st));
+    HIPCHK(cav::launch_norm2(r0, n, nb, p->dnpart, p->nblk_red, kv.nrm2, nullptr, p->st));
     HIPCHK(cav::launch_cycle_start(kv, nb, p->opts.max_iter, inner, p->st));
     HIPCHK(hipMemcpyAsync(hstat, kv.active, nb * sizeof(int), hipMemcpyDeviceToHost, p->st));
     HIPCHK(hipMemcpyAsync(hstat + nb, kv.iters, nb * sizeof(int), hipMemcpyDeviceToHost, p->st));
@@ -492,22 +495,22 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
     // per-step flag slots start at -1 ("not written yet"); the device writes 0 or 1
     for (size_t i = (size_t)2 * nb; i < (size_t)(2 + R) * nb; ++i) hstat[i] = -1;
     // v_0 = r / |r| and z = P^{-1} v_0 (norms already in kv.nrm2)
-    HIPCHK(cav::launch_next_vector(p->g, kv, -1, nullptr, 0, v0, v0, n, p->pinv, p->zb, nb, p->st));
+    HIPCHK(cav::launch_next_vector(p->g, kv, -1, nullptr, 0, r0, V, n, p->pinv, p->zb, nb, p->st));
     int seen = 0;   // first step whose flags the host has not looked at
     for (int j = 0; j < budget; ++j) {
-      zd* vn = p->V + (long long)(j + 1) * ldj;
+      cav::cx<VT>* vn = V + (long long)(j + 1) * ldj;
       // w = A z_j = A P^{-1} v_j
       if ((s = run_operator(p, 0, nb, p->zb, p->w, kv.active, mixed))) return s;
       const int nv = j + 1;
       zd* hcol = kv.H + (long long)j * (R + 1);
       const long long hstr = (long long)R * (R + 1);
       // classical Gram-Schmidt, twice; the second pass's coefficients are added into H
-      HIPCHK(cav::launch_dots(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
+      HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
                               nullptr, 0, kv.active, p->st));
-      HIPCHK(cav::launch_update(p->V, ldj, nv, hcol, hstr, p->w, n, nb, kv.active, p->st));
-      HIPCHK(cav::launch_dots(p->V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, p->h2,
+      HIPCHK(cav::launch_update(V, ldj, nv, hcol, hstr, p->w, n, nb, kv.active, p->st));
+      HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, p->h2,
                               R + 1, hcol, hstr, kv.active, p->st));
-      HIPCHK(cav::launch_update_norm(p->V, ldj, nv, p->h2, R + 1, p->w, n, nb, p->dnpart, nblk_u,
+      HIPCHK(cav::launch_update_norm(V, ldj, nv, p->h2, R + 1, p->w, n, nb, p->dnpart, nblk_u,
                                      kv.active, p->st));
       // Givens step of column j, then v_{j+1} = w / |w| and z = P^{-1} v_{j+1}
       HIPCHK(cav::launch_next_vector(p->g, kv, j, p->dnpart, nblk_u, p->w, vn, n, p->pinv, p->zb,
@@ -553,7 +556,7 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
       if (stop) break;
     }
     HIPCHK(cav::launch_solve_y(kv, nb, p->st));
-    HIPCHK(cav::launch_combine(p->g, kv, p->V, ldj, p->pinv, x, nb, p->st));
+    HIPCHK(cav::launch_combine(p->g, kv, V, ldj, p->pinv, x, nb, p->st));
     HIPCHK(cav::launch_cycle_end(kv, nb, p->st));
   }
   std::vector<double> relres(nb);
@@ -570,6 +573,17 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
   for (int r = 0; r < nb; ++r)
     if (relres[r] > p->opts.tol) return fail(CAVITY_ENOCONV, "GMRES did not reach the tolerance");
   return CAVITY_OK;
+}
+
+// The Krylov basis is stored in double precision, or in single precision for the
+// mixed-precision solve (its cycles only need to reduce the residual by the inner factor;
+// the refinement residuals stay double).
+int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
+                std::vector<int>* iters_out) {
+  if (p->opts.precision == CAVITY_MIXED)
+    return gmres_batch_t<float>(p, nb, x, relres_out, iters_out,
+                                reinterpret_cast<cav::zf*>(p->V));
+  return gmres_batch_t<double>(p, nb, x, relres_out, iters_out, p->V);
 }
 
 void wave_setup(double k, double theta, double phi, int pol, cav::Wave* wv) {

@@ -123,10 +123,17 @@ hipError_t launch_single_family(const Geo& g, const Trig& t, const zd* khat, int
 
 // Krylov building blocks: vector r of a set at base + r n; basis vector i of right-hand
 // side r at V + i ldj + r n.
+// The basis V is double, or single precision (zf) in the mixed-precision solve; w, h and
+// the results stay double.
 hipError_t launch_dots(const zd* V, long long ldj, int nv, int nvmax, const zd* w, long long n,
                        int nb, zd* partial, int nblk, zd* out, long long ostride, zd* acc,
                        long long astride, const int* active, hipStream_t st);
+hipError_t launch_dots(const zf* V, long long ldj, int nv, int nvmax, const zd* w, long long n,
+                       int nb, zd* partial, int nblk, zd* out, long long ostride, zd* acc,
+                       long long astride, const int* active, hipStream_t st);
 hipError_t launch_update(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
+                         zd* w, long long n, int nb, const int* active, hipStream_t st);
+hipError_t launch_update(const zf* V, long long ldj, int nv, const zd* h, long long hstride,
                          zd* w, long long n, int nb, const int* active, hipStream_t st);
 hipError_t launch_norm2(const zd* w, long long n, int nb, double* partial, int nblk, double* out,
                         const int* active, hipStream_t st);
@@ -138,10 +145,16 @@ hipError_t launch_givens(const Krylov& kv, int j, int nb, hipStream_t st);
 hipError_t launch_update_norm(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
                               zd* w, long long n, int nb, double* npart, int nblk,
                               const int* active, hipStream_t st);
+hipError_t launch_update_norm(const zf* V, long long ldj, int nv, const zd* h, long long hstride,
+                              zd* w, long long n, int nb, double* npart, int nblk,
+                              const int* active, hipStream_t st);
 // |w_r|^2 (from nparts partials, or kv.nrm2 when nparts == 0), Givens step of column j
 // (j >= 0), v_r = w_r / |w_r| (v_r at v + r vstride) and z_r = P^{-1} v_r (z_r at z + r n).
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
                               int nparts, const zd* w, zd* v, long long vstride, const zd* pinv,
+                              zd* z, int nb, hipStream_t st);
+hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
+                              int nparts, const zd* w, zf* v, long long vstride, const zd* pinv,
                               zd* z, int nb, hipStream_t st);
 hipError_t launch_solve_y(const Krylov& kv, int nb, hipStream_t st);
 // Restart bookkeeping on the device.  init: |b_r| = sqrt(nrm2[r]), iterations zero.
@@ -153,6 +166,8 @@ hipError_t launch_cycle_start(const Krylov& kv, int nb, int max_iter, double inn
                               hipStream_t st);
 hipError_t launch_cycle_end(const Krylov& kv, int nb, hipStream_t st);
 hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long ldj,
+                          const zd* pinv, zd* x, int nb, hipStream_t st);
+hipError_t launch_combine(const Geo& g, const Krylov& kv, const zf* V, long long ldj,
                           const zd* pinv, zd* x, int nb, hipStream_t st);
 
 // Back-substitution and synthesis of E_out for levels [j0, j1).

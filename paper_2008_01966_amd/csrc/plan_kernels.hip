@@ -2,6 +2,8 @@
 // (Sections 3-4), and the per-mode block preconditioner of the aperture system.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace cav {
@@ -368,22 +370,32 @@ hipError_t launch_precond_build(const Geo& g, const zd* rho_d, const zd* T, cons
   return hipGetLastError();
 }
 
-// out[0] = min over pivmin[0..n) (one block).
+// out[0] = min over v[0..n) of non-negative values: block minima combined by an atomic
+// minimum on the IEEE bit patterns (which order like the values for non-negative doubles);
+// out[0] starts as a large positive value.
 __global__ void k_min(const double* __restrict__ v, long long n, double* __restrict__ out) {
   __shared__ double red[256];
   double m = 1e300;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) m = fmin(m, v[i]);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    m = fmin(m, v[i]);
   red[threadIdx.x] = m;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (threadIdx.x == 0)
+    atomicMin(reinterpret_cast<unsigned long long*>(out),
+              (unsigned long long)__double_as_longlong(red[0]));
 }
 
 hipError_t launch_min(const double* v, long long n, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_min, dim3(1), dim3(256), 0, st, v, n, out);
+  hipError_t e = hipMemsetAsync(out, 0x7f, sizeof(double), st);
+  if (e != hipSuccess) return e;
+  const long long blocks = std::min<long long>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_min, dim3((unsigned)std::max<long long>(blocks, 1)), dim3(256), 0, st, v,
+                     n, out);
   return hipGetLastError();
 }
 

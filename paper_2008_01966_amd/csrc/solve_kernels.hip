@@ -447,38 +447,46 @@ hipError_t launch_single_family(const Geo& g, const Trig& t, const zd* khat, int
 // ---------------------------------------------------------------------------------
 constexpr int kDotGroup = 8;
 
-// partial[(r * nvmax + vi) * nblk + blk] = sum over the block's slice of conj(V_vi,r) w_r
-__global__ void k_dots(const zd* __restrict__ V, long long ldj, int nv, int nvmax,
-                       const zd* __restrict__ wall, long long n, zd* __restrict__ partial,
-                       const int* __restrict__ active) {
-  __shared__ zd red[kDotGroup][256];
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+
+// partial[(r * nvmax + vi) * nblk + blk] = sum over the block's slice of conj(V_vi,r) w_r.
+// VT: precision of the stored basis (double, or float in the mixed-precision solve).
+template <typename VT>
+__global__ __launch_bounds__(256) void k_dots(const cx<VT>* __restrict__ V, long long ldj, int nv,
+                                              int nvmax, const zd* __restrict__ wall, long long n,
+                                              zd* __restrict__ partial,
+                                              const int* __restrict__ active) {
+  __shared__ zd red[kDotGroup][4];
   const int r = blockIdx.z;
   if (active && !active[r]) return;
   const int grp = blockIdx.y;
   const zd* w = wall + r * n;
-  const zd* Vr = V + r * n;
+  const cx<VT>* Vr = V + r * n;
+  const int nvg = min(kDotGroup, nv - grp * kDotGroup);
   zd acc[kDotGroup];
   for (int t = 0; t < kDotGroup; ++t) acc[t] = mk(0.0, 0.0);
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const zd wi = w[i];
-    for (int t = 0; t < kDotGroup; ++t) {
-      const int vi = grp * kDotGroup + t;
-      if (vi < nv) acc[t] = acc[t] + conj(Vr[vi * ldj + i]) * wi;
-    }
+#pragma unroll
+    for (int t = 0; t < kDotGroup; ++t)
+      if (t < nvg) acc[t] = acc[t] + conj(widen(Vr[(grp * kDotGroup + t) * ldj + i])) * wi;
   }
-  for (int t = 0; t < kDotGroup; ++t) red[t][threadIdx.x] = acc[t];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < kDotGroup; ++t) {
+    const zd sum = mk(wave_sum(acc[t].re), wave_sum(acc[t].im));
+    if (lane == 0) red[t][wv] = sum;
+  }
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s)
-      for (int t = 0; t < kDotGroup; ++t)
-        red[t][threadIdx.x] = red[t][threadIdx.x] + red[t][threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x < kDotGroup) {
-    const int vi = grp * kDotGroup + threadIdx.x;
-    if (vi < nv)
-      partial[((long long)r * nvmax + vi) * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < nvg) {
+    const int t = threadIdx.x;
+    partial[((long long)r * nvmax + grp * kDotGroup + t) * gridDim.x + blockIdx.x] =
+        red[t][0] + red[t][1] + red[t][2] + red[t][3];
   }
 }
 
@@ -505,11 +513,13 @@ __global__ void k_reduce_cols(const zd* __restrict__ partial, int nblk, int nvma
   }
 }
 
-hipError_t launch_dots(const zd* V, long long ldj, int nv, int nvmax, const zd* w, long long n,
-                       int nb, zd* partial, int nblk, zd* out, long long ostride, zd* acc,
-                       long long astride, const int* active, hipStream_t st) {
+template <typename VT>
+static hipError_t dots_impl(const cx<VT>* V, long long ldj, int nv, int nvmax, const zd* w,
+                            long long n, int nb, zd* partial, int nblk, zd* out,
+                            long long ostride, zd* acc, long long astride, const int* active,
+                            hipStream_t st) {
   const int ng = (nv + kDotGroup - 1) / kDotGroup;
-  hipLaunchKernelGGL(k_dots, dim3(nblk, ng, nb), dim3(256), 0, st, V, ldj, nv, nvmax, w, n,
+  hipLaunchKernelGGL((k_dots<VT>), dim3(nblk, ng, nb), dim3(256), 0, st, V, ldj, nv, nvmax, w, n,
                      partial, active);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -518,32 +528,60 @@ hipError_t launch_dots(const zd* V, long long ldj, int nv, int nvmax, const zd* 
   return hipGetLastError();
 }
 
+hipError_t launch_dots(const zd* V, long long ldj, int nv, int nvmax, const zd* w, long long n,
+                       int nb, zd* partial, int nblk, zd* out, long long ostride, zd* acc,
+                       long long astride, const int* active, hipStream_t st) {
+  return dots_impl<double>(V, ldj, nv, nvmax, w, n, nb, partial, nblk, out, ostride, acc,
+                           astride, active, st);
+}
+
+hipError_t launch_dots(const zf* V, long long ldj, int nv, int nvmax, const zd* w, long long n,
+                       int nb, zd* partial, int nblk, zd* out, long long ostride, zd* acc,
+                       long long astride, const int* active, hipStream_t st) {
+  return dots_impl<float>(V, ldj, nv, nvmax, w, n, nb, partial, nblk, out, ostride, acc,
+                          astride, active, st);
+}
+
 // w_r -= sum_i h[r * hstride + i] V_i,r
-__global__ void k_update(const zd* __restrict__ V, long long ldj, int nv, const zd* __restrict__ h,
-                         long long hstride, zd* __restrict__ wall, long long n,
-                         const int* __restrict__ active) {
+template <typename VT>
+__global__ __launch_bounds__(256) void k_update(const cx<VT>* __restrict__ V, long long ldj, int nv,
+                                                const zd* __restrict__ h, long long hstride,
+                                                zd* __restrict__ wall, long long n,
+                                                const int* __restrict__ active) {
   __shared__ zd hs[256];
   const int r = blockIdx.y;
   if (active && !active[r]) return;
   for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[r * hstride + i];
   __syncthreads();
   zd* w = wall + r * n;
-  const zd* Vr = V + r * n;
+  const cx<VT>* Vr = V + r * n;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     zd a = w[i];
-    for (int vi = 0; vi < nv; ++vi) a = a - hs[vi] * Vr[vi * ldj + i];
+    for (int vi = 0; vi < nv; ++vi) a = a - hs[vi] * widen(Vr[vi * ldj + i]);
     w[i] = a;
   }
 }
 
-hipError_t launch_update(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
-                         zd* w, long long n, int nb, const int* active, hipStream_t st) {
+template <typename VT>
+static hipError_t update_impl(const cx<VT>* V, long long ldj, int nv, const zd* h,
+                              long long hstride, zd* w, long long n, int nb, const int* active,
+                              hipStream_t st) {
   int nblk = (int)((n + 255) / 256);
   if (nblk > 1024) nblk = 1024;
-  hipLaunchKernelGGL(k_update, dim3(nblk, nb), dim3(256), 0, st, V, ldj, nv, h, hstride, w, n,
-                     active);
+  hipLaunchKernelGGL((k_update<VT>), dim3(nblk, nb), dim3(256), 0, st, V, ldj, nv, h, hstride, w,
+                     n, active);
   return hipGetLastError();
+}
+
+hipError_t launch_update(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
+                         zd* w, long long n, int nb, const int* active, hipStream_t st) {
+  return update_impl<double>(V, ldj, nv, h, hstride, w, n, nb, active, st);
+}
+
+hipError_t launch_update(const zf* V, long long ldj, int nv, const zd* h, long long hstride,
+                         zd* w, long long n, int nb, const int* active, hipStream_t st) {
+  return update_impl<float>(V, ldj, nv, h, hstride, w, n, nb, active, st);
 }
 
 __global__ void k_norm2(const zd* __restrict__ wall, long long n, double* __restrict__ partial,
@@ -747,7 +785,8 @@ hipError_t launch_solve_y(const Krylov& kv, int nb, hipStream_t st) {
 }
 
 // x_r += P^{-1} (sum_{i < jcount[r]} y[r][i] V_i,r)
-__global__ void k_combine(Geo g, Krylov kv, const zd* __restrict__ V, long long ldj,
+template <typename VT>
+__global__ void k_combine(Geo g, Krylov kv, const cx<VT>* __restrict__ V, long long ldj,
                           const zd* __restrict__ pinv, zd* __restrict__ xall) {
   __shared__ zd ys[256];
   const int r = blockIdx.y;
@@ -758,12 +797,12 @@ __global__ void k_combine(Geo g, Krylov kv, const zd* __restrict__ V, long long 
   const int mn = blockIdx.x * blockDim.x + threadIdx.x;
   if (mn >= g.NM) return;
   const long long n = 3LL * g.NM;
-  const zd* Vr = V + r * n;
+  const cx<VT>* Vr = V + r * n;
   zd* x = xall + r * n;
   zd u[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
   for (int vi = 0; vi < jc; ++vi) {
-    const zd* col = Vr + vi * ldj;
-    for (int c = 0; c < 3; ++c) u[c] = u[c] + ys[vi] * col[(long long)c * g.NM + mn];
+    const cx<VT>* col = Vr + vi * ldj;
+    for (int c = 0; c < 3; ++c) u[c] = u[c] + ys[vi] * widen(col[(long long)c * g.NM + mn]);
   }
   for (int k = 0; k < 3; ++k) {
     const zd z = pinv[(3 * k) * (long long)g.NM + mn] * u[0] +
@@ -773,26 +812,33 @@ __global__ void k_combine(Geo g, Krylov kv, const zd* __restrict__ V, long long 
   }
 }
 
+template <typename VT>
+static hipError_t combine_impl(const Geo& g, const Krylov& kv, const cx<VT>* V, long long ldj,
+                               const zd* pinv, zd* x, int nb, hipStream_t st) {
+  const int blk = 256;
+  hipLaunchKernelGGL((k_combine<VT>), dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g, kv,
+                     V, ldj, pinv, x);
+  return hipGetLastError();
+}
+
 hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long ldj,
                           const zd* pinv, zd* x, int nb, hipStream_t st) {
-  const int blk = 256;
-  hipLaunchKernelGGL(k_combine, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g, kv, V, ldj,
-                     pinv, x);
-  return hipGetLastError();
+  return combine_impl<double>(g, kv, V, ldj, pinv, x, nb, st);
+}
+
+hipError_t launch_combine(const Geo& g, const Krylov& kv, const zf* V, long long ldj,
+                          const zd* pinv, zd* x, int nb, hipStream_t st) {
+  return combine_impl<float>(g, kv, V, ldj, pinv, x, nb, st);
 }
 
 // ---------------------------------------------------------------------------------
 // Fused Arnoldi steps: the second Gram-Schmidt update with the norm of the result, and the
 // normalisation with the Givens step and the preconditioner.
 // ---------------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // w_r -= sum_i h[r * hstride + i] V_i,r, then partial[r * gridDim.x + block] = block's
 // share of |w_r|^2.
-__global__ __launch_bounds__(256) void k_update_norm(const zd* __restrict__ V, long long ldj, int nv,
+template <typename VT>
+__global__ __launch_bounds__(256) void k_update_norm(const cx<VT>* __restrict__ V, long long ldj, int nv,
                                                      const zd* __restrict__ h, long long hstride,
                                                      zd* __restrict__ wall, long long n,
                                                      double* __restrict__ partial,
@@ -804,12 +850,12 @@ __global__ __launch_bounds__(256) void k_update_norm(const zd* __restrict__ V, l
   for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[r * hstride + i];
   __syncthreads();
   zd* w = wall + r * n;
-  const zd* Vr = V + r * n;
+  const cx<VT>* Vr = V + r * n;
   double nrm = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     zd a = w[i];
-    for (int vi = 0; vi < nv; ++vi) a = a - hs[vi] * Vr[vi * ldj + i];
+    for (int vi = 0; vi < nv; ++vi) a = a - hs[vi] * widen(Vr[vi * ldj + i]);
     w[i] = a;
     nrm += cabs2(a);
   }
@@ -820,12 +866,25 @@ __global__ __launch_bounds__(256) void k_update_norm(const zd* __restrict__ V, l
     partial[(long long)r * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+template <typename VT>
+static hipError_t update_norm_impl(const cx<VT>* V, long long ldj, int nv, const zd* h,
+                                   long long hstride, zd* w, long long n, int nb, double* partial,
+                                   int nblk, const int* active, hipStream_t st) {
+  hipLaunchKernelGGL((k_update_norm<VT>), dim3(nblk, nb), dim3(256), 0, st, V, ldj, nv, h, hstride,
+                     w, n, partial, active);
+  return hipGetLastError();
+}
+
 hipError_t launch_update_norm(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
                               zd* w, long long n, int nb, double* partial, int nblk,
                               const int* active, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_norm, dim3(nblk, nb), dim3(256), 0, st, V, ldj, nv, h, hstride, w,
-                     n, partial, active);
-  return hipGetLastError();
+  return update_norm_impl<double>(V, ldj, nv, h, hstride, w, n, nb, partial, nblk, active, st);
+}
+
+hipError_t launch_update_norm(const zf* V, long long ldj, int nv, const zd* h, long long hstride,
+                              zd* w, long long n, int nb, double* partial, int nblk,
+                              const int* active, hipStream_t st) {
+  return update_norm_impl<float>(V, ldj, nv, h, hstride, w, n, nb, partial, nblk, active, st);
 }
 
 // Next basis vector: |w_r|^2 from the nparts partials of k_update_norm (nparts == 0: from
@@ -833,9 +892,11 @@ hipError_t launch_update_norm(const zd* V, long long ldj, int nv, const zd* h, l
 // with its preconditioned copy z_r = P^{-1} v_r.  Threads run over modes; vectors are
 // component-major.  Blocks read the active flag before block 0 may clear it; a rhs that
 // stops here never uses the vector written for it.
+template <typename VT>
 __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
                                                      const double* __restrict__ npart, int nparts,
-                                                     const zd* wall, zd* vall, long long vstride,
+                                                     const zd* __restrict__ wall,
+                                                     cx<VT>* __restrict__ vall, long long vstride,
                                                      const zd* __restrict__ pinv,
                                                      zd* __restrict__ zall) {
   __shared__ double red[4];
@@ -865,15 +926,16 @@ __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
   const double sc = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
   const long long n = 3LL * g.NM;
   const zd* w = wall + r * n;
-  zd* v = vall + r * vstride;
+  cx<VT>* v = vall + r * vstride;
   zd* z = zall + r * n;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long mn = (long long)blockIdx.x * blockDim.x + threadIdx.x; mn < g.NM; mn += stride) {
     zd u[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      u[c] = sc * w[c * g.NM + mn];
-      v[c * g.NM + mn] = u[c];
+      const cx<VT> t = cvt<VT>(sc * w[c * g.NM + mn]);
+      v[c * g.NM + mn] = t;
+      u[c] = widen(t);   // z from the stored (possibly rounded) basis vector
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -883,14 +945,27 @@ __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
   }
 }
 
+template <typename VT>
+static hipError_t next_vector_impl(const Geo& g, const Krylov& kv, int j, const double* npart,
+                                   int nparts, const zd* w, cx<VT>* v, long long vstride,
+                                   const zd* pinv, zd* z, int nb, hipStream_t st) {
+  int nblk = (g.NM + 255) / 256;
+  if (nblk > 1024) nblk = 1024;
+  hipLaunchKernelGGL((k_next_vector<VT>), dim3(nblk, nb), dim3(256), 0, st, g, kv, j, npart, nparts,
+                     w, v, vstride, pinv, z);
+  return hipGetLastError();
+}
+
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
                               int nparts, const zd* w, zd* v, long long vstride, const zd* pinv,
                               zd* z, int nb, hipStream_t st) {
-  int nblk = (g.NM + 255) / 256;
-  if (nblk > 1024) nblk = 1024;
-  hipLaunchKernelGGL(k_next_vector, dim3(nblk, nb), dim3(256), 0, st, g, kv, j, npart, nparts, w, v,
-                     vstride, pinv, z);
-  return hipGetLastError();
+  return next_vector_impl<double>(g, kv, j, npart, nparts, w, v, vstride, pinv, z, nb, st);
+}
+
+hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
+                              int nparts, const zd* w, zf* v, long long vstride, const zd* pinv,
+                              zd* z, int nb, hipStream_t st) {
+  return next_vector_impl<float>(g, kv, j, npart, nparts, w, v, vstride, pinv, z, nb, st);
 }
 
 // ---------------------------------------------------------------------------------

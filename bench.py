@@ -333,6 +333,7 @@ def main() -> int:
             "plan_ms": plan_ms[0],
             "plan_ms_same_aperture": plan_ms[-1],
             "gmres_iterations_last": int(infos[-1].last_iterations),
+            "lds_budget": int(infos[-1].lds_budget),
         }
         return res, sig, infos[-1], probe_res
 

@@ -106,6 +106,9 @@ typedef struct {
   double last_rel_residual;    /* true relative residual of the last solve */
   double ms_spectrum, ms_elimination, ms_preconditioner; /* plan phases (device time) */
   double ms_rhs, ms_krylov, ms_synthesis;                /* last solve phases */
+  int lds_budget;              /* LDS bytes per block the TBC FFT kernels are sized for
+                                  (chosen by timing at the first plan of a shape; 0 = the
+                                  default 40000 or CAVITY_LDS_BUDGET) */
 } cavity_info;
 
 int cavity_opts_default(cavity_opts* opts);

@@ -55,7 +55,7 @@ class Info(ctypes.Structure):
                 ("last_rel_residual", ctypes.c_double), ("ms_spectrum", ctypes.c_double),
                 ("ms_elimination", ctypes.c_double), ("ms_preconditioner", ctypes.c_double),
                 ("ms_rhs", ctypes.c_double), ("ms_krylov", ctypes.c_double),
-                ("ms_synthesis", ctypes.c_double)]
+                ("ms_synthesis", ctypes.c_double), ("lds_budget", ctypes.c_int)]
 
 
 class ServerOpts(ctypes.Structure):

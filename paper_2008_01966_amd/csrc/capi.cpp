@@ -9,7 +9,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -404,6 +406,82 @@ int run_operator(cavity_plan p, int precond, int nb, const zd* v, zd* y, const i
   else
     HIPCHK(cav::launch_operator(p->g, p->trig, p->khat, p->rho_d, p->T, p->rho_n, p->pinv,
                                 precond, nb, v, n, p->X, p->Y, p->S, y, n, active, p->st));
+  return CAVITY_OK;
+}
+
+// ---- autotuning of the TBC kernels' LDS batch ------------------------------------------
+// The FFT kernels batch 2^lc transforms per block, sized from an LDS budget.  The best
+// budget depends on the transform lengths and the precision (occupancy against strip width
+// of the strided column accesses), so the first plan of each (P1, P2, s Nx, s Ny,
+// precision) in a process times the operator apply of its Krylov iterations for a few
+// budgets and keeps the fastest; later plans of the same shape reuse the choice.
+// CAVITY_AUTOTUNE=0 turns this off (default budget), CAVITY_LDS_BUDGET fixes the budget.
+struct TuneKey {
+  int P1, P2, nq1, nq2, single;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(P1, P2, nq1, nq2, single) < std::tie(o.P1, o.P2, o.nq1, o.nq2, o.single);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+int autotune_lds(cavity_plan p) {
+  const char* e = std::getenv("CAVITY_AUTOTUNE");
+  if ((e && std::atoi(e) == 0) || std::getenv("CAVITY_LDS_BUDGET")) return CAVITY_OK;
+  const bool single = p->opts.precision == CAVITY_MIXED;
+  const TuneKey key{p->g.P1, p->g.P2, p->g.nq1, p->g.nq2, single ? 1 : 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      p->g.lds_budget = it->second;
+      p->info.lds_budget = it->second;
+      return CAVITY_OK;
+    }
+  }
+  // timed with two right-hand sides in flight (the smallest lockstep group of a batch)
+  const int nbt = std::min(2, p->opts.batch);
+  int s = ensure_work(p, nbt);
+  if (s) return s;
+  const long long n = p->nvec();
+  HIPCHK(hipMemsetAsync(p->zb, 0, (size_t)nbt * n * sizeof(zd), p->st));
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  // two sweeps over the candidates, each timing 4 applies after a warm-up; the fastest
+  // sweep of each budget counts (guards against a noisy first measurement)
+  const int budgets[3] = {20000, 40000, 80000};
+  float ms_best[3] = {1e30f, 1e30f, 1e30f};
+  for (int sweep = 0; sweep < 2 && !s; ++sweep) {
+    for (int bi = 0; bi < 3 && !s; ++bi) {
+      p->g.lds_budget = budgets[bi];
+      if ((s = run_operator(p, 0, nbt, p->zb, p->w, nullptr, single))) break;   // warm-up
+      if (hipEventRecord(t0, p->st) != hipSuccess) { s = CAVITY_EDEVICE; break; }
+      for (int r = 0; r < 4 && !s; ++r) s = run_operator(p, 0, nbt, p->zb, p->w, nullptr, single);
+      if (s) break;
+      float ms = 0.f;
+      if (hipEventRecord(t1, p->st) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+          hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+        s = CAVITY_EDEVICE;
+        break;
+      }
+      ms_best[bi] = std::min(ms_best[bi], ms);
+    }
+  }
+  int best = 40000;
+  float best_ms = 1e30f;
+  for (int bi = 0; bi < 3; ++bi)
+    if (ms_best[bi] < best_ms) {
+      best_ms = ms_best[bi];
+      best = budgets[bi];
+    }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (s) return s;
+  p->g.lds_budget = best;
+  p->info.lds_budget = best;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = best;
   return CAVITY_OK;
 }
 
@@ -1090,6 +1168,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   p->info.min_pivot = p->hn[0];
   if (!(p->info.min_pivot > 1e-13))
     return bail(fail(CAVITY_ERESONANT, "z-elimination pivot below 1e-13"));
+  if ((st = autotune_lds(p))) return bail(st);
   p->info.M = g.M;
   p->info.N = g.N;
   p->info.Nz = Nz;

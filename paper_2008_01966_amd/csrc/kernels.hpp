@@ -17,6 +17,7 @@ struct Geo {
   int nx, ny;           // output grid intervals (Nx, Ny)
   double a, b, h, k;
   double hq1, hq2;
+  int lds_budget;       // LDS bytes per block the TBC FFT kernels size their batch for (0: default)
 };
 
 // An FFT length with its device twiddle tables (double and single precision).

@@ -336,13 +336,15 @@ __global__ void k_operator_epilogue(Geo g, const zd* __restrict__ rho_d, const z
 
 // log2 of the transforms per block for an FFT kernel whose two LDS buffers hold len
 // elements of elem bytes each: the largest power of two within the LDS budget (at least
-// one transform, at most the next power of two above `cap`, at most 64).
-static int batch_log2(int len, int elem, int cap) {
-  static long long budget = -1;
-  if (budget < 0) {
+// one transform, at most the next power of two above `cap`, at most 64).  budget 0: the
+// default (40000 bytes, or CAVITY_LDS_BUDGET).
+static int batch_log2(int len, int elem, int cap, int budget_bytes = 0) {
+  static long long deflt = -1;
+  if (deflt < 0) {
     const char* e = getenv("CAVITY_LDS_BUDGET");
-    budget = e ? atoll(e) : 40000;
+    deflt = e ? atoll(e) : 40000;
   }
+  const long long budget = budget_bytes > 0 ? budget_bytes : deflt;
   int lc = 0;
   while (lc < 6 && (1 << lc) < cap && 2LL * len * elem * (2LL << lc) <= budget) ++lc;
   return lc;
@@ -356,7 +358,7 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
   const double zb = sizeof(zd), tb = sizeof(cx<T>);
   const double xbytes = tb * nb * nf * (g.M + 1) * (double)g.P2;   // one X or Y workspace
   const double vin = nb * (zb * (fam_fixed >= 0 ? 1.0 : 3.0) * g.NM) + (precond ? zb * 9.0 * g.NM : 0.0);
-  const int lr = batch_log2(g.P2, (int)tb, g.M + 1);
+  const int lr = batch_log2(g.P2, (int)tb, g.M + 1, g.lds_budget);
   const int gr = (g.M + 1 + (1 << lr) - 1) >> lr;
   const bool single = sizeof(T) == sizeof(float);
   const int id_fwd = single ? K_TBC_ROWS_FWD_F32 : K_TBC_ROWS_FWD;
@@ -369,7 +371,7 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
   probe_end(id_fwd, st, vin + xbytes);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int lcc = batch_log2(g.P1, (int)tb, g.P2);
+  const int lcc = batch_log2(g.P1, (int)tb, g.P2, g.lds_budget);
   probe_begin(id_cols, st);
   hipLaunchKernelGGL((k_tbc_cols<T>), dim3((g.P2 + (1 << lcc) - 1) >> lcc, nf, nb), dim3(256),
                      (size_t)2 * g.P1 * tb * (1 << lcc), st, g, t.ext1, t.box1, khat, fam_fixed,

@@ -49,11 +49,13 @@ def cpu_baseline(wl, gpu_fields, gpu_sigma, sample):
     incs = wl.incidences[:sample]
     for inc in incs:
         sol = solver.solve(pl, inc.theta, inc.phi, inc.pol, tol=1e-13)
-        fields.append(solver.field_out(pl, sol))
+        if gpu_fields is not None:
+            fields.append(solver.field_out(pl, sol))
         sig.append(solver.backscatter(pl, sol, inc.theta, inc.phi))
     t1 = time.perf_counter()
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    errs = [float(np.linalg.norm(g - o) / np.linalg.norm(o)) for g, o in zip(gpu_fields, fields)]
+    errs = ([float(np.linalg.norm(g - o) / np.linalg.norm(o)) for g, o in zip(gpu_fields, fields)]
+            if gpu_fields is not None else [])
     rerr = []
     for i, (g, o) in enumerate(zip(gpu_sigma, sig)):
         co = int(wl.incidences[i].pol)      # co-polarised component of this incidence
@@ -64,10 +66,10 @@ def cpu_baseline(wl, gpu_fields, gpu_sigma, sample):
     return {
         "value": unknowns / (t1 - t0), "unit": "unknowns/s", "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"{what}: plan + {len(incs)} solves + fields + RCS, "
-                   f"{t1 - t0:.1f} s wall"),
+        "sample": (f"{what}: plan + {len(incs)} solves + "
+                   f"{'fields + ' if gpu_fields is not None else ''}RCS, {t1 - t0:.1f} s wall"),
         "phases_s": {"spectrum": pl.timers["spectrum"], "assemble": pl.timers["assemble"]},
-    }, max(errs), max(rerr)
+    }, (max(errs) if errs else None), max(rerr)
 
 
 # Sources that define the TBC kernels: a traffic measurement is only used while they match.
@@ -284,8 +286,8 @@ def main() -> int:
     th = [i.theta for i in incs]
     ph = [i.phi for i in incs]
     po = [i.pol for i in incs]
-    fields = torch.empty((len(incs), 3, cav.nz + 1, cav.ny + 1, cav.nx + 1),
-                         dtype=torch.complex128, device="cuda")
+    fields = (torch.empty((len(incs), 3, cav.nz + 1, cav.ny + 1, cav.nx + 1),
+                          dtype=torch.complex128, device="cuda") if wl.fields else None)
 
     def timed(precision, out, probe):
         """Create the plan (timed on its own, outside the step: the first creation computes
@@ -303,7 +305,7 @@ def main() -> int:
                 plan.close()
 
         def step():
-            plan.solve_batch(th, ph, po, out=out)
+            plan.solve_batch(th, ph, po, out=out, field=out is not None)
             sig = [plan.rcs(i, incs[i].theta, incs[i].phi)[0] for i in range(len(incs))]
             return sig, plan.info()
 
@@ -344,7 +346,7 @@ def main() -> int:
     runs, sigs = {}, {}
     fields_by = {}
     for prec in precisions:
-        out = fields if prec == head else torch.empty_like(fields)
+        out = None if fields is None else (fields if prec == head else torch.empty_like(fields))
         res, sig, info_p, probe_res = timed(prec, out, probe=(prec == head))
         runs[prec] = res
         sigs[prec] = sig
@@ -381,7 +383,9 @@ def main() -> int:
             "precision": head,
             "tol": wl.tol,
             "batch": batch,
-            "step": ("all incidences (RHS, GMRES) + field synthesis + backscatter RCS; the plan "
+            "fields": bool(wl.fields),
+            "step": ("all incidences (RHS, GMRES) + field synthesis (when fields) + backscatter "
+                     "RCS; the plan "
                      "(spectrum, elimination, preconditioner) is built once before the timed "
                      "region and its time reported as plan_ms"),
         },
@@ -412,9 +416,10 @@ def main() -> int:
     }
     if "fp64" in fields_by and "mixed" in fields_by:
         a64, amx = fields_by["fp64"], fields_by["mixed"]
-        errs = [float(torch.linalg.vector_norm(amx[i] - a64[i]) / torch.linalg.vector_norm(a64[i]))
-                for i in range(len(incs))]
-        out["mixed_vs_fp64_field_rel_err"] = max(errs)
+        if a64 is not None:
+            errs = [float(torch.linalg.vector_norm(amx[i] - a64[i]) /
+                          torch.linalg.vector_norm(a64[i])) for i in range(len(incs))]
+            out["mixed_vs_fp64_field_rel_err"] = max(errs)
         out["mixed_vs_fp64_rcs_rel_err"] = max(
             abs(sigs["mixed"][i][incs[i].pol] - sigs["fp64"][i][incs[i].pol]) /
             abs(sigs["fp64"][i][incs[i].pol]) for i in range(len(incs)))
@@ -422,7 +427,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         sample = args.cpu_sample or (len(incs) if len(incs) <= 2 else 1)
         sample = min(sample, len(incs))
-        gpu_fields = [fields[i].cpu().numpy() for i in range(sample)]
+        gpu_fields = ([fields[i].cpu().numpy() for i in range(sample)] if fields is not None
+                      else None)
         base, ferr, rerr = cpu_baseline(wl, gpu_fields, sigs[head][:sample], sample)
         out["cpu_baseline"] = base
         out["field_rel_err_vs_oracle"] = ferr

@@ -1,0 +1,52 @@
+"""Backscatter RCS sweeps on the geometries of the paper's numerical examples (Section 8):
+one plan per geometry, many incidences solved together without field output, RCS from the
+stored aperture solutions.  Each geometry: the GPU sweep against the oracle at two angles
+(1e-9 relative, both polarisations), the mixed-precision sweep against the double one
+(1e-8), and the phi = 0 mirror rule (the cross-polarised backscatter vanishes)."""
+import numpy as np
+import pytest
+
+import paper_2008_01966_amd as P
+import workloads as W
+from oracle import solver
+from oracle.problem import Problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("make", [W.example1_sweep, W.example2_sweep, W.example3_sweep],
+                         ids=["example1", "example2", "example3"])
+def test_sweep_against_oracle(make):
+    import torch
+    wl = make()
+    # every tenth angle, both polarisations (incidences alternate TM, TE per angle)
+    incs = [inc for k, inc in enumerate(wl.incidences) if (k // 2) % 10 == 0]
+    print(f"\n[case] {wl.name}: {len(incs)} of {len(wl.incidences)} incidences", flush=True)
+    th = [i.theta for i in incs]
+    ph = [i.phi for i in incs]
+    po = [i.pol for i in incs]
+    res = {}
+    for prec in ("fp64", "mixed"):
+        plan = P.Plan.from_cavity(wl.cavity, precision=prec, batch=16)
+        plan.solve_batch(th, ph, po, field=False)
+        res[prec] = np.array([plan.rcs(i, t, f)[0] for i, (t, f) in enumerate(zip(th, ph))])
+        its = plan.info().last_iterations
+        plan.close()
+        print(f"[gpu] {prec}: last iterations {its}", flush=True)
+    torch.cuda.synchronize()
+    for i, inc in enumerate(incs):
+        co, cross = inc.pol, 1 - inc.pol
+        s64, smx = res["fp64"][i], res["mixed"][i]
+        assert abs(smx[co] - s64[co]) <= 1e-8 * s64[co]
+        assert s64[cross] <= 1e-12 * s64[co] + 1e-300, (i, s64)
+    ora = solver.plan(Problem.from_cavity(wl.cavity))
+    for i in (2, len(incs) - 1):          # a TM and a TE incidence
+        inc = incs[i]
+        ref = solver.solve(ora, inc.theta, inc.phi, inc.pol, tol=1e-13)
+        o = solver.backscatter(ora, ref, inc.theta, inc.phi)
+        co = inc.pol
+        err = abs(res["fp64"][i][co] - o[co]) / o[co]
+        print(f"[compare] theta {np.degrees(inc.theta):.1f} pol {inc.pol}: rcs rel err {err:.2e}",
+              flush=True)
+        assert err <= 1e-9

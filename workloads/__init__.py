@@ -56,6 +56,7 @@ class Workload:
     incidences: Tuple[Incidence, ...]
     tol: float = 1e-12      # relative residual the solves stop at
     batch: int = 8          # right-hand sides iterated together
+    fields: bool = True     # False: a step needs the RCS only, not the field on all nodes
 
 
 def deg(x: float) -> float:
@@ -113,6 +114,39 @@ def batched_layered_8x8x2() -> Workload:
                 inc.append(Incidence(float(th), deg(ph), pol))
     return Workload("batched_layered_8x8x2_256x256x64_x128", cav, tuple(inc), tol=1e-10,
                     batch=32)
+
+
+# -- backscatter RCS sweeps on the geometries of the paper's numerical examples ---------
+# (Section 8: phi = 0, theta stepped by 0.5 degrees, both polarisations; the paper's mode
+# counts where 2 Nx is a product of 2, 3 and 5, and its number of z-partition points).
+
+def _sweep(n_theta: int) -> Tuple[Incidence, ...]:
+    return tuple(Incidence(deg(0.5 * i), 0.0, pol) for i in range(n_theta) for pol in (TM, TE))
+
+
+def example1_sweep() -> Workload:
+    """Example 1: 10 x 10 x 30 wavelength cavity, homogeneous (vacuum), M = N = 15
+    (16 x 16 nodes), J + 1 = 1000 z-intervals, 100 angles x 2 polarisations."""
+    cav = Cavity(10.0, 10.0, 30.0, 16, 16, 1000, (1000,), (1.0 + 0j,))
+    return Workload("example1_sweep_10x10x30_16x16x1000", cav, _sweep(100), batch=32,
+                    fields=False)
+
+
+def example2_sweep() -> Workload:
+    """Example 2: 1 x 0.25 x 0.25 wavelength cavity, eps_r = 7 + 1.5i, M = N = 15,
+    1000 z-intervals, 180 angles x 2 polarisations."""
+    cav = Cavity(1.0, 0.25, 0.25, 16, 16, 1000, (1000,), (7.0 + 1.5j,))
+    return Workload("example2_sweep_1x0.25x0.25_16x16x1000", cav, _sweep(180), batch=32,
+                    fields=False)
+
+
+def example3_sweep() -> Workload:
+    """Example 3: 1 x 1 x 3 wavelength cavity, bottom layer 2 wavelengths of
+    eps_r = 3 + 0.05i, top layer 1 wavelength of eps_r = 7 + 1.5i (one h: 2000 + 1000
+    intervals), M = N = 19 (20 x 20 nodes; 2 Nx must be 5-smooth), 180 angles x 2."""
+    cav = Cavity(1.0, 1.0, 3.0, 20, 20, 3000, (2000, 1000), (3.0 + 0.05j, 7.0 + 1.5j))
+    return Workload("example3_sweep_1x1x3_20x20x3000", cav, _sweep(180), batch=32,
+                    fields=False)
 
 
 @dataclasses.dataclass(frozen=True)
@@ -174,5 +208,6 @@ def small_cases() -> List[Workload]:
 
 def by_name(name: str) -> Workload:
     table = {w.name: w for w in [vacuum_1x1x05(), lossy_8x8x2(), layered_16x16x4(),
-                                 batched_layered_8x8x2()] + small_cases()}
+                                 batched_layered_8x8x2(), example1_sweep(), example2_sweep(),
+                                 example3_sweep()] + small_cases()}
     return table[name]

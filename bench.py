@@ -239,7 +239,8 @@ def main() -> int:
     ap.add_argument("--workload", default="lossy_8x8x2_256x256x64")
     ap.add_argument("--probe", default=None,
                     help="kernel timed for the roofline (default: the column pass of the TBC "
-                         "convolution in the headline precision)")
+                         "convolution in the headline precision); none: no probe (the "
+                         "Arnoldi steps may then run as captured graphs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (reference "
                          "kernel for scaling hardware traffic counters) and exit")
@@ -312,6 +313,7 @@ def main() -> int:
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
+        probe = probe and args.probe != "none"
         if probe:
             P.probe_start(args.probe)
             torch.cuda.synchronize()
@@ -324,7 +326,7 @@ def main() -> int:
             infos.append(info)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        probe_res = P.probe_stop() if probe else None
+        probe_res = P.probe_stop() if probe else (0, 0.0, 0.0)
         plan.close()
         unknowns_step = len(incs) * infos[-1].unknowns
         res = {
@@ -357,7 +359,7 @@ def main() -> int:
     unknowns_step = len(incs) * info.unknowns
     value = runs[head]["value"]
     traffic, traffic_src = measured_traffic(args.probe, wl.name)
-    achieved = (k_bytes / (k_ms * 1e-3)) / 1e9 if k_ms > 0 else 0.0
+    achieved = (k_bytes / (k_ms * 1e-3)) / 1e9 if k_ms > 0 else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -406,7 +408,7 @@ def main() -> int:
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
             "traffic": traffic,
             "traffic_source": traffic_src,
             "launches": launches,

@@ -74,6 +74,8 @@ struct ProbeState {
 ProbeState g_probe;
 }  // namespace
 
+bool g_probe_active() { return g_probe.which >= 0; }
+
 void probe_begin(int id, hipStream_t st) {
   if (id != g_probe.which) return;
   if (2 * g_probe.used + 1 >= g_probe.pool.size()) {
@@ -244,6 +246,10 @@ struct cavity_plan_s {
   hipEvent_t ev[12] = {};
   bool ev_used[6] = {};
   std::vector<hipEvent_t> poll_ev;   // one per Arnoldi step of a cycle (convergence polling)
+  // Arnoldi steps captured as HIP graphs, keyed by (lockstep group size, step index); valid
+  // while the solve workspace stays where it is.  Captured on a private stream.
+  hipStream_t cap_st = nullptr;
+  std::map<long long, hipGraphExec_t> step_graphs;
 
   long long nvec() const { return 3LL * g.NM; }
 };
@@ -264,6 +270,8 @@ void release(cavity_plan p) {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->poll_ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& kv : p->step_graphs) (void)hipGraphExecDestroy(kv.second);
+  if (p->cap_st) (void)hipStreamDestroy(p->cap_st);
   delete p;
 }
 
@@ -363,6 +371,8 @@ int ensure_work(cavity_plan p, int nb) {
   L.add(&p->dwaves, (size_t)nb);
   if (p->st) HIPCHK(hipStreamSynchronize(p->st));
   else HIPCHK(hipDeviceSynchronize());
+  for (auto& g : p->step_graphs) (void)hipGraphExecDestroy(g.second);
+  p->step_graphs.clear();
   arena_release(p->work_arena.ptr, p->work_arena.bytes);
   p->work_arena = Arena();
   p->nbwork = 0;
@@ -397,15 +407,16 @@ int ensure_solutions(cavity_plan p, int count) {
 
 // y = A v (or A P^{-1} v); low selects the single-precision convolutions.
 int run_operator(cavity_plan p, int precond, int nb, const zd* v, zd* y, const int* active,
-                 bool low = false) {
+                 bool low = false, hipStream_t stream = nullptr) {
   const long long n = p->nvec();
+  hipStream_t st = stream ? stream : p->st;
   if (low)
     HIPCHK(cav::launch_operator_f32(p->g, p->trig, p->khat_f, p->rho_d, p->T, p->rho_n, p->pinv,
                                     precond, nb, v, n, reinterpret_cast<cav::zf*>(p->X),
-                                    reinterpret_cast<cav::zf*>(p->Y), p->S, y, n, active, p->st));
+                                    reinterpret_cast<cav::zf*>(p->Y), p->S, y, n, active, st));
   else
     HIPCHK(cav::launch_operator(p->g, p->trig, p->khat, p->rho_d, p->T, p->rho_n, p->pinv,
-                                precond, nb, v, n, p->X, p->Y, p->S, y, n, active, p->st));
+                                precond, nb, v, n, p->X, p->Y, p->S, y, n, active, st));
   return CAVITY_OK;
 }
 
@@ -497,6 +508,75 @@ double mixed_inner_reduction() {
   return v;
 }
 
+// One Arnoldi step j for the lockstep group (kernels only, on stream st): w = A z_j,
+// classical Gram-Schmidt twice (the second pass's coefficients added into H), the Givens
+// step of column j, v_{j+1} = w / |w| and z = P^{-1} v_{j+1}.
+template <typename VT>
+int arnoldi_step(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipStream_t st) {
+  const long long n = p->nvec();
+  const int R = p->opts.restart;
+  const long long ldj = (long long)p->nbwork * n;
+  const int nblk_u = (int)std::min<long long>(kNormBlocks, (n + 255) / 256);
+  cav::Krylov& kv = p->kv;
+  const bool mixed = p->opts.precision == CAVITY_MIXED;
+  cav::cx<VT>* vn = V + (long long)(j + 1) * ldj;
+  int s;
+  if ((s = run_operator(p, 0, nb, p->zb, p->w, kv.active, mixed, st))) return s;
+  const int nv = j + 1;
+  zd* hcol = kv.H + (long long)j * (R + 1);
+  const long long hstr = (long long)R * (R + 1);
+  HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
+                          nullptr, 0, kv.active, st));
+  HIPCHK(cav::launch_update(V, ldj, nv, hcol, hstr, p->w, n, nb, kv.active, st));
+  HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, p->h2, R + 1,
+                          hcol, hstr, kv.active, st));
+  HIPCHK(cav::launch_update_norm(V, ldj, nv, p->h2, R + 1, p->w, n, nb, p->dnpart, nblk_u,
+                                 kv.active, st));
+  HIPCHK(cav::launch_next_vector(p->g, kv, j, p->dnpart, nblk_u, p->w, vn, n, p->pinv, p->zb, nb,
+                                 st));
+  return CAVITY_OK;
+}
+
+// Whether the Arnoldi steps run as captured graphs (one capture per step index and group
+// size, replayed by later cycles, groups and solve calls): only with CAVITY_GRAPHS=1, and
+// never while the kernel probe is watching (its events belong to individual launches).
+// Off by default: the host queues launches far enough ahead that the GPU does not wait
+// for them, and a graph launch measured 2-4 % slower than the step's direct launches.
+bool use_step_graphs() {
+  if (cav::g_probe_active()) return false;
+  const char* e = std::getenv("CAVITY_GRAPHS");
+  return e && std::atoi(e) == 1;
+}
+
+// The executable graph of step j for group size nb, captured on first use.
+template <typename VT>
+int step_graph(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipGraphExec_t* out) {
+  const long long key = ((long long)nb << 20) | j;
+  auto it = p->step_graphs.find(key);
+  if (it != p->step_graphs.end()) {
+    *out = it->second;
+    return CAVITY_OK;
+  }
+  if (!p->cap_st) HIPCHK(hipStreamCreateWithFlags(&p->cap_st, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(p->cap_st, hipStreamCaptureModeThreadLocal));
+  const int s = arnoldi_step<VT>(p, nb, j, V, p->cap_st);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(p->cap_st, &graph);
+  if (s) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (ec != hipSuccess) return fail(CAVITY_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess)
+    return fail(CAVITY_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+  p->step_graphs[key] = exec;
+  *out = exec;
+  return CAVITY_OK;
+}
+
 // Right-preconditioned restarted GMRES with classical Gram-Schmidt applied twice, for nb
 // right-hand sides b (p->bvec) iterating in lockstep; solutions in x (nb x n).  The
 // Arnoldi step, the Givens rotations and the convergence test run on the device; the
@@ -575,24 +655,15 @@ int gmres_batch_t(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
     // v_0 = r / |r| and z = P^{-1} v_0 (norms already in kv.nrm2)
     HIPCHK(cav::launch_next_vector(p->g, kv, -1, nullptr, 0, r0, V, n, p->pinv, p->zb, nb, p->st));
     int seen = 0;   // first step whose flags the host has not looked at
+    const bool graphs = use_step_graphs();
     for (int j = 0; j < budget; ++j) {
-      cav::cx<VT>* vn = V + (long long)(j + 1) * ldj;
-      // w = A z_j = A P^{-1} v_j
-      if ((s = run_operator(p, 0, nb, p->zb, p->w, kv.active, mixed))) return s;
-      const int nv = j + 1;
-      zd* hcol = kv.H + (long long)j * (R + 1);
-      const long long hstr = (long long)R * (R + 1);
-      // classical Gram-Schmidt, twice; the second pass's coefficients are added into H
-      HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
-                              nullptr, 0, kv.active, p->st));
-      HIPCHK(cav::launch_update(V, ldj, nv, hcol, hstr, p->w, n, nb, kv.active, p->st));
-      HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, p->h2,
-                              R + 1, hcol, hstr, kv.active, p->st));
-      HIPCHK(cav::launch_update_norm(V, ldj, nv, p->h2, R + 1, p->w, n, nb, p->dnpart, nblk_u,
-                                     kv.active, p->st));
-      // Givens step of column j, then v_{j+1} = w / |w| and z = P^{-1} v_{j+1}
-      HIPCHK(cav::launch_next_vector(p->g, kv, j, p->dnpart, nblk_u, p->w, vn, n, p->pinv, p->zb,
-                                     nb, p->st));
+      if (graphs) {
+        hipGraphExec_t g = nullptr;
+        if ((s = step_graph<VT>(p, nb, j, V, &g))) return s;
+        HIPCHK(hipGraphLaunch(g, p->st));
+      } else if ((s = arnoldi_step<VT>(p, nb, j, V, p->st))) {
+        return s;
+      }
       // the Givens step published this step's flags in host memory; the event marks them ready
       HIPCHK(hipEventRecord(p->poll_ev[j], p->st));
       bool stop = false;

@@ -67,6 +67,7 @@ enum KernelId {
 // While the probe watches kernel `id`, these bracket its launches with HIP events on the
 // launch stream and record the launch's algorithmic bytes; otherwise they do nothing.
 void probe_begin(int id, hipStream_t st);
+bool g_probe_active();   // a kernel is being watched
 void probe_end(int id, hipStream_t st, double bytes);
 
 // ---- plan-time kernels ------------------------------------------------------------

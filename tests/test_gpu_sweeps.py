@@ -50,3 +50,44 @@ def test_sweep_against_oracle(make):
         print(f"[compare] theta {np.degrees(inc.theta):.1f} pol {inc.pol}: rcs rel err {err:.2e}",
               flush=True)
         assert err <= 1e-9
+
+
+@pytest.mark.timeout(600)
+def test_graph_replays_match_direct_launches():
+    """With CAVITY_GRAPHS=1 the Arnoldi steps run as captured graphs (one per step index and
+    group size, replayed across lockstep groups, restarts and solve calls); they give the
+    same RCS as direct launches, bit for bit, on every replay: three solve calls in a row,
+    with eager work and synchronisations between them."""
+    import os
+
+    import torch
+    wl = W.example2_sweep()
+    incs = [inc for k, inc in enumerate(wl.incidences) if (k // 2) % 6 == 0][:48]
+    th = [i.theta for i in incs]
+    ph = [i.phi for i in incs]
+    po = [i.pol for i in incs]
+    out = {}
+    old = os.environ.get("CAVITY_GRAPHS")
+    try:
+        for mode in ("0", "1"):
+            os.environ["CAVITY_GRAPHS"] = mode
+            plan = P.Plan.from_cavity(wl.cavity, precision="mixed", batch=16)
+            runs = []
+            for rep in range(3):
+                plan.solve_batch(th, ph, po, field=False)
+                runs.append(np.array([plan.rcs(i, t, f)[0] for i, (t, f) in enumerate(zip(th, ph))]))
+                torch.cuda.synchronize()
+                _ = (torch.ones(1000, device="cuda") * 2).sum().item()   # eager work between
+            plan.close()
+            out[mode] = runs
+    finally:
+        if old is None:
+            os.environ.pop("CAVITY_GRAPHS", None)
+        else:
+            os.environ["CAVITY_GRAPHS"] = old
+    ref = out["0"][0]
+    for mode in ("0", "1"):
+        for rep, r in enumerate(out[mode]):
+            d = float(np.abs(r - ref).max() / ref.max())
+            print(f"[compare] graphs={mode} call {rep}: max rel diff {d:.1e}", flush=True)
+            assert d == 0.0

@@ -251,6 +251,9 @@ def main() -> int:
                     help="incidences the CPU oracle solves (0: all when at most 2, else 1)")
     ap.add_argument("--requests", type=int, default=2000, help="served stream: requests")
     ap.add_argument("--streams", type=int, default=4, help="served stream: concurrent requests")
+    ap.add_argument("--direct", choices=["auto", "always", "never"], default="auto",
+                    help="direct solve of the aperture system (inverse built once per plan, "
+                         "in the warm-up; its time is reported as direct_factor_ms)")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
                     help="both: time the double-precision path, then the mixed one (headline)")
     args = ap.parse_args()
@@ -299,7 +302,8 @@ def main() -> int:
         for _ in range(2):
             torch.cuda.synchronize()
             tp = time.perf_counter()
-            plan = P.Plan.from_cavity(cav, precision=precision, tol=wl.tol, batch=batch)
+            plan = P.Plan.from_cavity(cav, precision=precision, tol=wl.tol, batch=batch,
+                                      direct=args.direct)
             torch.cuda.synchronize()
             plan_ms.append(1e3 * (time.perf_counter() - tp))
             if len(plan_ms) < 2:
@@ -307,7 +311,7 @@ def main() -> int:
 
         def step():
             plan.solve_batch(th, ph, po, out=out, field=out is not None)
-            sig = [plan.rcs(i, incs[i].theta, incs[i].phi)[0] for i in range(len(incs))]
+            sig = list(plan.rcs_many(np.arange(len(incs)), th, ph))
             return sig, plan.info()
 
         for _ in range(args.warmup):
@@ -338,6 +342,8 @@ def main() -> int:
             "plan_ms_same_aperture": plan_ms[-1],
             "gmres_iterations_last": int(infos[-1].last_iterations),
             "lds_budget": int(infos[-1].lds_budget),
+            "direct": bool(infos[-1].last_direct),
+            "direct_factor_ms": float(infos[-1].ms_factor),
         }
         return res, sig, infos[-1], probe_res
 
@@ -386,10 +392,12 @@ def main() -> int:
             "tol": wl.tol,
             "batch": batch,
             "fields": bool(wl.fields),
-            "step": ("all incidences (RHS, GMRES) + field synthesis (when fields) + backscatter "
-                     "RCS; the plan "
-                     "(spectrum, elimination, preconditioner) is built once before the timed "
-                     "region and its time reported as plan_ms"),
+            "step": ("all incidences (RHS, GMRES or the direct solve) + field synthesis (when "
+                     "fields) + backscatter RCS; the plan (spectrum, elimination, "
+                     "preconditioner) is built once before the timed region and its time "
+                     "reported as plan_ms; when the direct solve is taken, its inverse is "
+                     "built once in the warm-up and its time reported as direct_factor_ms"),
+            "direct": args.direct,
         },
         "latency_ms": {"p50": runs[head]["p50_ms"], "p99": runs[head]["p99_ms"],
                        "of": "one step"},

@@ -92,6 +92,15 @@ typedef struct {
   size_t hbm_budget;    /* bytes the plan may allocate; 0 = 90 % of free device memory */
   void* stream;         /* hipStream_t for all work of the plan; NULL = default stream */
   int batch;            /* right-hand sides iterated together in lockstep, 1..64 (default 8) */
+  int direct;           /* direct solve (the paper's Steps 1 and 3, Section 6: the aperture
+                           matrix assembled from the operator and inverted once per plan by
+                           Gauss-Jordan elimination with partial pivoting, 2 (3 Nx Ny)^2 x 16
+                           bytes while it is built, half that kept; each right-hand side is
+                           then one product with the inverse plus a residual check):
+                           0 = automatic (default): used when 3 Nx Ny <= 2048 and a call solves
+                           at least 32 right-hand sides, and for every call once the inverse
+                           exists; 1 = always (3 Nx Ny <= 4096, else CAVITY_EINVAL at plan
+                           creation); -1 = never (GMRES only) */
 } cavity_opts;
 
 /* Plan description and the statistics of its last solve. */
@@ -109,6 +118,10 @@ typedef struct {
   int lds_budget;              /* LDS bytes per block the TBC FFT kernels are sized for
                                   (chosen by timing at the first plan of a shape; 0 = the
                                   default 40000 or CAVITY_LDS_BUDGET) */
+  int last_direct;             /* 1 when the last solve call used the direct solve
+                                  (last_iterations is then 0) */
+  double ms_factor;            /* device time of assembling and inverting the aperture
+                                  matrix for the direct solve (0 until it is built) */
 } cavity_info;
 
 int cavity_opts_default(cavity_opts* opts);
@@ -143,6 +156,15 @@ int cavity_solve_batch(cavity_plan plan, int nrhs, const double* theta, const do
  * Errors: CAVITY_EINVAL (no such solution), CAVITY_EDEVICE. */
 int cavity_rcs(cavity_plan plan, int rhs_index, int n_obs, const double* theta_o,
                const double* phi_o, double* sigma);
+
+/* The same for n (solution, direction) pairs at once, e.g. the backscatter of every
+ * incidence of a sweep: pair i is stored solution rhs_index[i] seen from (theta_o[i],
+ * phi_o[i]); sigma[2 i], sigma[2 i + 1] = {sigma_theta, sigma_phi}.  One kernel launch and
+ * one device-to-host copy for all pairs (cavity_rcs with n_obs directions is this call
+ * with a repeated index; results are identical).  The plan keeps a device buffer of at
+ * most 2.1 KB per pair of its largest call.  Errors: CAVITY_EINVAL, CAVITY_EDEVICE. */
+int cavity_rcs_many(cavity_plan plan, int n, const int* rhs_index, const double* theta_o,
+                    const double* phi_o, double* sigma);
 
 /* Copy stored aperture solution rhs_index to host memory (n_ap entries, paper order). */
 int cavity_aperture(cavity_plan plan, int rhs_index, cavity_c128* out_host);

@@ -44,7 +44,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("tbc_oversample", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
                 ("hbm_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p),
-                ("batch", ctypes.c_int)]
+                ("batch", ctypes.c_int), ("direct", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -55,7 +55,8 @@ class Info(ctypes.Structure):
                 ("last_rel_residual", ctypes.c_double), ("ms_spectrum", ctypes.c_double),
                 ("ms_elimination", ctypes.c_double), ("ms_preconditioner", ctypes.c_double),
                 ("ms_rhs", ctypes.c_double), ("ms_krylov", ctypes.c_double),
-                ("ms_synthesis", ctypes.c_double), ("lds_budget", ctypes.c_int)]
+                ("ms_synthesis", ctypes.c_double), ("lds_budget", ctypes.c_int),
+                ("last_direct", ctypes.c_int), ("ms_factor", ctypes.c_double)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -82,7 +83,7 @@ class Result(ctypes.Structure):
 
 EXPORTS = [
     "cavity_opts_default", "cavity_plan_create", "cavity_solve", "cavity_solve_batch",
-    "cavity_rcs", "cavity_aperture", "cavity_plan_footprint", "cavity_plan_info",
+    "cavity_rcs", "cavity_rcs_many", "cavity_aperture", "cavity_plan_footprint", "cavity_plan_info",
     "cavity_plan_destroy", "cavity_status_string", "cavity_last_error",
     "cavity_server_opts_default", "cavity_server_create", "cavity_server_submit",
     "cavity_server_wait", "cavity_server_release", "cavity_server_now_ms",
@@ -118,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cavity_solve.argtypes = [vp, d, d, i, vp]
     lib.cavity_solve_batch.argtypes = [vp, i, P(d), P(d), P(i), vp, vp]
     lib.cavity_rcs.argtypes = [vp, i, i, P(d), P(d), P(d)]
+    lib.cavity_rcs_many.argtypes = [vp, i, P(i), P(d), P(d), P(d)]
     lib.cavity_aperture.argtypes = [vp, i, P(C128)]
     lib.cavity_plan_info.argtypes = [vp, P(Info)]
     lib.cavity_plan_destroy.argtypes = [vp]
@@ -171,6 +173,8 @@ def _torch():
 # CAVITY_FP64: every step in double.  CAVITY_MIXED: the TBC convolutions inside the
 # Krylov iterations in single precision, residuals (and everything else) in double.
 PRECISIONS = {"fp64": 0, "mixed": 1}
+# direct solve of the aperture system: automatic, always, never (GMRES only)
+DIRECT = {"auto": 0, "always": 1, "never": -1}
 
 
 class Plan:
@@ -181,7 +185,7 @@ class Plan:
                  layer_eps: Optional[Sequence[complex]] = None, k: float = 2 * np.pi, *,
                  tol: float = 1e-12, restart: int = 60, max_iter: int = 400,
                  oversample: int = 1, hbm_budget: int = 0, stream: Optional[int] = None,
-                 batch: int = 8, precision: str = "fp64"):
+                 batch: int = 8, precision: str = "fp64", direct: str = "auto"):
         lib = load_library()
         self._lib = lib
         self.a, self.b, self.c = float(a), float(b), float(c)
@@ -192,6 +196,9 @@ class Plan:
         opts.tbc_oversample = int(oversample)
         opts.hbm_budget = int(hbm_budget)
         opts.batch = int(batch)
+        if direct not in DIRECT:
+            raise ValueError(f"direct must be one of {sorted(DIRECT)}")
+        opts.direct = DIRECT[direct]
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         opts.precision = PRECISIONS[precision]
@@ -279,6 +286,22 @@ class Plan:
         dp = ctypes.POINTER(ctypes.c_double)
         _check(self._lib.cavity_rcs(self._h, int(index), th.size, th.ctypes.data_as(dp),
                                     ph.ctypes.data_as(dp), sig.ctypes.data_as(dp)))
+        return sig
+
+    def rcs_many(self, indices, theta_o, phi_o) -> np.ndarray:
+        """RCS of stored solution indices[i] at direction (theta_o[i], phi_o[i]) for every i,
+        in one call; rows {sigma_theta, sigma_phi}."""
+        idx = np.ascontiguousarray(np.atleast_1d(indices), dtype=np.int32)
+        th = np.ascontiguousarray(np.atleast_1d(theta_o), dtype=np.float64)
+        ph = np.ascontiguousarray(np.atleast_1d(phi_o), dtype=np.float64)
+        if not idx.size == th.size == ph.size:
+            raise ValueError("indices, theta_o and phi_o differ in length")
+        sig = np.zeros((th.size, 2))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(self._lib.cavity_rcs_many(self._h, idx.size,
+                                         idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                         th.ctypes.data_as(dp), ph.ctypes.data_as(dp),
+                                         sig.ctypes.data_as(dp)))
         return sig
 
     def aperture(self, index: int = 0) -> np.ndarray:

@@ -59,6 +59,27 @@ constexpr size_t kMaxLdsPerBlock = 160 * 1024;
 // Blocks per right-hand side of the fused update + norm pass of the Arnoldi step.
 constexpr int kNormBlocks = 1024;
 
+// Blocks per right-hand side (and group of basis vectors) of the dot-product pass: four
+// elements per thread (loaded together), 64 to kNormBlocks blocks.
+int dot_blocks(long long n) {
+  return (int)std::max<long long>(64, std::min<long long>(kNormBlocks, (n + 1023) / 1024));
+}
+
+// Most blocks per query of the aperture-transform reduction behind the RCS.
+constexpr int kRcsBlocks = 64;
+
+// Direct solve limits on n = 3 Nx Ny: the largest system it accepts, and the largest it
+// picks by itself (for calls with at least kDenseAutoRhs right-hand sides).
+constexpr long long kDenseMax = 4096;
+constexpr long long kDenseAuto = 2048;
+constexpr int kDenseAutoRhs = 32;
+// Right-hand sides per product with the inverse (and per residual check).
+constexpr int kDenseGroup = 64;
+
+// Device bytes of the staging slab between the two synthesis passes; the levels of one
+// slab are synthesised by one pair of launches.
+constexpr size_t kSynthStagingBytes = (size_t)256 << 20;
+
 }  // namespace
 
 // ---- kernel timing probe (process-wide) ------------------------------------------------
@@ -240,7 +261,7 @@ struct cavity_plan_s {
   int* hflags = nullptr;
   double* hn = nullptr;
   double* hratio = nullptr;   // pinned, host-mapped: per step and rhs, |g_{j+1}| / threshold
-  int nblk_red = 128;
+  int nblk_red = 128;                // blocks per rhs of the dot-product and norm passes
   cavity_info info{};
   // phase timers, resolved lazily: spectrum, elimination, preconditioner, rhs, krylov, synth
   hipEvent_t ev[12] = {};
@@ -250,6 +271,12 @@ struct cavity_plan_s {
   // while the solve workspace stays where it is.  Captured on a private stream.
   hipStream_t cap_st = nullptr;
   std::map<long long, hipGraphExec_t> step_graphs;
+  // direct solve: (P A)^{-1} column-major and the row permutation, built on first use
+  Arena dense_arena;
+  Arena rcs_arena;                   // RCS queries and partial sums
+  zd* dense_F = nullptr;
+  int* dense_perm = nullptr;
+  bool dense_now = false;            // the current solve call uses the direct solve
 
   long long nvec() const { return 3LL * g.NM; }
 };
@@ -263,6 +290,8 @@ void release(cavity_plan p) {
   arena_release(p->plan_arena.ptr, p->plan_arena.bytes);
   arena_release(p->work_arena.ptr, p->work_arena.bytes);
   arena_release(p->sol_arena.ptr, p->sol_arena.bytes);
+  arena_release(p->dense_arena.ptr, p->dense_arena.bytes);
+  arena_release(p->rcs_arena.ptr, p->rcs_arena.bytes);
   if (p->hflags) (void)hipHostFree(p->hflags);
   if (p->hn) (void)hipHostFree(p->hn);
   if (p->hratio) (void)hipHostFree(p->hratio);
@@ -735,6 +764,158 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
   return gmres_batch_t<double>(p, nb, x, relres_out, iters_out, p->V);
 }
 
+// RCS of n (stored solution, observation direction) pairs: one launch for all of them
+// (queries and per-block partial sums in a plan-owned device buffer), one copy back, and
+// the block sums reduced on the host in a fixed order.
+//   L = (-E^2, E^1, 0);  sigma_theta = k^2/pi |phi^ . L|^2,  sigma_phi = k^2/pi |theta^ . L|^2
+int rcs_queries(cavity_plan p, int n, const int* rhs, const double* th, const double* ph,
+                double* sigma) {
+  if (n == 0) return CAVITY_OK;
+  const int nblk = (int)std::max<long long>(1, std::min<long long>(kRcsBlocks,
+                                                                   (p->g.NM + 255) / 256));
+  const size_t qbytes = ((size_t)n * sizeof(cav::RcsQuery) + 255) / 256 * 256;
+  const size_t need = qbytes + (size_t)n * 2 * nblk * sizeof(zd);
+  if (need > p->rcs_arena.bytes) {
+    if (p->st) HIPCHK(hipStreamSynchronize(p->st));
+    arena_release(p->rcs_arena.ptr, p->rcs_arena.bytes);
+    p->rcs_arena = Arena();
+    void* base = nullptr;
+    const int s = arena_acquire(need, &base);
+    if (s) return s;
+    p->rcs_arena = {base, need};
+  }
+  auto* dq = static_cast<cav::RcsQuery*>(p->rcs_arena.ptr);
+  zd* dpart = reinterpret_cast<zd*>(static_cast<char*>(p->rcs_arena.ptr) + qbytes);
+  const double k = p->g.k;
+  std::vector<cav::RcsQuery> q(n);
+  for (int i = 0; i < n; ++i)
+    q[i] = {rhs[i], k * std::sin(th[i]) * std::cos(ph[i]), k * std::sin(th[i]) * std::sin(ph[i])};
+  std::vector<zd> part((size_t)n * 2 * nblk);
+  HIPCHK(hipMemcpyAsync(dq, q.data(), n * sizeof(cav::RcsQuery), hipMemcpyHostToDevice, p->st));
+  HIPCHK(cav::launch_rcs_partial(p->g, p->xsol, p->nvec(), dq, n, dpart, nblk, p->st));
+  HIPCHK(hipMemcpyAsync(part.data(), dpart, part.size() * sizeof(zd), hipMemcpyDeviceToHost,
+                        p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  for (int i = 0; i < n; ++i) {
+    std::complex<double> e1 = 0.0, e2 = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      const zd* pb = &part[2 * ((size_t)i * nblk + b)];
+      e1 += std::complex<double>(pb[0].re, pb[0].im);
+      e2 += std::complex<double>(pb[1].re, pb[1].im);
+    }
+    const double st = std::sin(th[i]), ct = std::cos(th[i]), sp = std::sin(ph[i]),
+                 cp = std::cos(ph[i]);
+    const std::complex<double> L1 = -e2, L2 = e1;
+    const std::complex<double> phiL = -sp * L1 + cp * L2;
+    const std::complex<double> thL = ct * cp * L1 + ct * sp * L2;
+    sigma[2 * i] = k * k / M_PI * std::norm(phiL);
+    sigma[2 * i + 1] = k * k / M_PI * std::norm(thL);
+  }
+  return CAVITY_OK;
+}
+
+// Direct solve, plan part (the paper's Steps 1 and 3, Section 6): the aperture matrix A is
+// assembled column by column by applying the operator to unit vectors (the same TBC
+// convolutions and local blocks GMRES applies, in double precision), the entries of absent
+// modes get a unit diagonal, and Gauss-Jordan elimination with partial pivoting leaves
+// (P A)^{-1} and the row permutation in the plan.
+int dense_factor(cavity_plan p) {
+  if (p->dense_F) return CAVITY_OK;
+  const long long n = p->nvec();
+  const size_t mat = (size_t)n * n * sizeof(zd);
+  const size_t keep = mat + 2 * (size_t)n * sizeof(int) + 256;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  void* a = nullptr;
+  void* b = nullptr;
+  int s = arena_acquire(keep, &a);
+  if (!s) s = arena_acquire(mat, &b);
+  auto done = [&](int code) {
+    if (b) arena_release(b, mat);
+    if (code && a) arena_release(a, keep);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return code;
+  };
+  if (s) return done(s);
+  zd* A = static_cast<zd*>(a);
+  int* piv = reinterpret_cast<int*>(static_cast<char*>(a) + mat);
+  int* perm = piv + n;
+  if (hipEventRecord(e0, p->st) != hipSuccess) return done(fail(CAVITY_EDEVICE, "event"));
+  for (long long k0 = 0; k0 < n; k0 += p->nbwork) {
+    const int nb = (int)std::min<long long>(p->nbwork, n - k0);
+    if (cav::launch_unit_vectors(n, k0, nb, p->rbuf, p->st) != hipSuccess)
+      return done(fail(CAVITY_EDEVICE, "unit vectors"));
+    if ((s = run_operator(p, 0, nb, p->rbuf, A + k0 * n, nullptr))) return done(s);
+  }
+  zd* F = nullptr;
+  if (cav::launch_dense_fix(p->g, A, p->st) != hipSuccess ||
+      cav::launch_gj_invert(A, static_cast<zd*>(b), n, piv, &F, p->st) != hipSuccess)
+    return done(fail(CAVITY_EDEVICE, std::string("Gauss-Jordan: ") +
+                                         hipGetErrorString(hipGetLastError())));
+  if (F != A &&
+      hipMemcpyAsync(A, F, mat, hipMemcpyDeviceToDevice, p->st) != hipSuccess)
+    return done(fail(CAVITY_EDEVICE, "copy of the inverse"));
+  std::vector<int> hp(n), hperm(n);
+  if (hipMemcpyAsync(hp.data(), piv, n * sizeof(int), hipMemcpyDeviceToHost, p->st) !=
+          hipSuccess ||
+      hipEventRecord(e1, p->st) != hipSuccess || hipStreamSynchronize(p->st) != hipSuccess)
+    return done(fail(CAVITY_EDEVICE, "pivot readback"));
+  for (long long k = 0; k < n; ++k) hperm[k] = (int)k;
+  for (long long k = 0; k < n; ++k) {
+    if (hp[k] < k || hp[k] >= n)
+      return done(fail(CAVITY_ERESONANT, "aperture matrix is singular (no pivot at column " +
+                                             std::to_string(k) + ")"));
+    std::swap(hperm[k], hperm[hp[k]]);
+  }
+  if (hipMemcpy(perm, hperm.data(), n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return done(fail(CAVITY_EDEVICE, "permutation upload"));
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) p->info.ms_factor = ms;
+  p->dense_arena = {a, keep};
+  p->dense_F = A;
+  p->dense_perm = perm;
+  p->info.device_bytes += keep;
+  return done(CAVITY_OK);
+}
+
+// Direct solve, per right-hand side: x = A^{-1} b for the nb right-hand sides in p->bvec,
+// then the true residual b - A x with the operator; up to two refinement steps
+// x += A^{-1} r while a residual is above the tolerance.
+int dense_solve(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
+                std::vector<int>* iters_out) {
+  const long long n = p->nvec();
+  cav::Krylov& kv = p->kv;
+  HIPCHK(cav::launch_dense_apply(p->dense_F, p->dense_perm, n, p->bvec, nb, p->zb, x, p->st));
+  HIPCHK(cav::launch_norm2(p->bvec, n, nb, p->dnpart, p->nblk_red, kv.bnorm, nullptr, p->st));
+  std::vector<double> b2(nb), r2(nb);
+  HIPCHK(hipMemcpyAsync(b2.data(), kv.bnorm, nb * sizeof(double), hipMemcpyDeviceToHost, p->st));
+  std::vector<double> rel(nb, 0.0);
+  for (int pass = 0; pass < 3; ++pass) {
+    int s;
+    if ((s = run_operator(p, 0, nb, x, p->w, nullptr))) return s;
+    HIPCHK(cav::launch_sub(p->bvec, p->w, p->rbuf, (long long)nb * n, p->st));
+    HIPCHK(cav::launch_norm2(p->rbuf, n, nb, p->dnpart, p->nblk_red, kv.nrm2, nullptr, p->st));
+    HIPCHK(hipMemcpyAsync(r2.data(), kv.nrm2, nb * sizeof(double), hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    bool ok = true;
+    for (int r = 0; r < nb; ++r) {
+      rel[r] = b2[r] > 0.0 ? std::sqrt(r2[r] / b2[r]) : 0.0;
+      ok = ok && rel[r] <= p->opts.tol;
+    }
+    if (ok || pass == 2) break;
+    HIPCHK(cav::launch_dense_apply(p->dense_F, p->dense_perm, n, p->rbuf, nb, p->zb, p->w,
+                                   p->st));
+    HIPCHK(cav::launch_add(x, p->w, (long long)nb * n, p->st));
+  }
+  *relres_out = rel;
+  iters_out->assign(nb, 0);
+  for (double v : rel)
+    if (!(v <= p->opts.tol)) return CAVITY_ENOCONV;
+  return CAVITY_OK;
+}
+
 void wave_setup(double k, double theta, double phi, int pol, cav::Wave* wv) {
   const double st = std::sin(theta), ct = std::cos(theta), sp = std::sin(phi), cp = std::cos(phi);
   wv->alpha1 = -k * st * cp;
@@ -769,7 +950,8 @@ int solve_chunk(cavity_plan p, int i0, int nb, const double* theta, const double
   std::vector<double> relres;
   std::vector<int> iters;
   if ((s0 = mark(p, 4, false))) return s0;
-  int status = gmres_batch(p, nb, x, &relres, &iters);
+  int status = p->dense_now ? dense_solve(p, nb, x, &relres, &iters)
+                            : gmres_batch(p, nb, x, &relres, &iters);
   if (status != CAVITY_OK && status != CAVITY_ENOCONV) return status;
   if ((s0 = mark(p, 4, true))) return s0;
   p->info.last_iterations = *std::max_element(iters.begin(), iters.end());
@@ -953,6 +1135,9 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   if (!(o.tol > 0 && o.tol < 1) || o.max_iter < 1 || o.restart < 1 || o.restart > 200)
     return fail(CAVITY_EINVAL, "tol in (0,1), max_iter >= 1, restart in 1..200");
   if (o.batch < 1 || o.batch > 64) return fail(CAVITY_EINVAL, "batch must be in 1..64");
+  if (o.direct < -1 || o.direct > 1) return fail(CAVITY_EINVAL, "direct must be -1, 0 or 1");
+  if (o.direct == 1 && 3LL * Nx * Ny > kDenseMax)
+    return fail(CAVITY_EINVAL, "direct solve needs 3 Nx Ny <= " + std::to_string(kDenseMax));
   const int s = o.tbc_oversample;
   if (!is_5smooth(2LL * s * Nx) || !is_5smooth(2LL * s * Ny))
     return fail(CAVITY_EINVAL, "2*s*Nx and 2*s*Ny must be products of 2, 3 and 5");
@@ -1001,14 +1186,15 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
 
   const bool layered = lnz.size() > 1;
   const size_t per_level = 3ull * (g.M + 1) * (g.ny + 1) * sizeof(zd);
-  int chunk = (int)std::max<size_t>(1, (size_t)(32u << 20) / per_level);
+  int chunk = (int)std::max<size_t>(1, kSynthStagingBytes / per_level);
   chunk = std::min(chunk, Nz + 1);
   const int fft_len[6] = {2 * g.nq1, 2 * g.nq2, g.P1, g.P2, 2 * g.nx, 2 * g.ny};
   int twn = 0;
   for (int l : fft_len) twn += l;
   const int nb0 = 1;
   const size_t need = plan_bytes(g, layered, chunk, (int)lnz.size(), &twn) +
-                      work_bytes(g, o.restart, nb0, 128) + 3ull * g.NM * sizeof(zd);
+                      work_bytes(g, o.restart, nb0, dot_blocks(3LL * g.NM)) +
+                      3ull * g.NM * sizeof(zd);
   ps->g = g;
   ps->o = o;
   ps->lnz = lnz;
@@ -1036,6 +1222,7 @@ int cavity_opts_default(cavity_opts* o) {
   o->hbm_budget = 0;
   o->stream = nullptr;
   o->batch = 8;
+  o->direct = 0;
   return CAVITY_OK;
 }
 
@@ -1102,6 +1289,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   p->layered = layered;
   p->nlayers = (int)lnz.size();
   p->R = R;
+  p->nblk_red = dot_blocks(p->nvec());
   p->synth_chunk = chunk;
   auto bail = [&](int code) {
     release(p);
@@ -1274,7 +1462,14 @@ int cavity_solve_batch(cavity_plan p, int nrhs, const double* theta, const doubl
       return fail(CAVITY_EINVAL, "theta must lie in [0, pi/2], phi finite, pol TM or TE");
   int s = ensure_solutions(p, nrhs);
   if (s) return s;
-  if ((s = ensure_work(p, std::min(nrhs, p->opts.batch)))) return s;
+  const long long n = p->nvec();
+  const int dm = p->opts.direct;
+  p->dense_now = dm == 1 || (dm == 0 && n <= kDenseAuto &&
+                             (p->dense_F != nullptr || nrhs >= kDenseAutoRhs));
+  const int group = p->dense_now ? kDenseGroup : p->opts.batch;
+  if ((s = ensure_work(p, std::min(nrhs, group)))) return s;
+  if (p->dense_now && (s = dense_factor(p))) return s;
+  p->info.last_direct = p->dense_now ? 1 : 0;
   const long long field = 3LL * (p->g.Nz + 1) * (p->g.ny + 1) * (p->g.nx + 1);
   int worst = CAVITY_OK;
   int its = 0;
@@ -1291,7 +1486,9 @@ int cavity_solve_batch(cavity_plan p, int nrhs, const double* theta, const doubl
   }
   p->info.last_iterations = its;
   p->info.last_rel_residual = res;
-  if (worst != CAVITY_OK) return fail(worst, "GMRES did not reach the tolerance");
+  if (worst != CAVITY_OK)
+    return fail(worst, p->dense_now ? "direct solve did not reach the tolerance"
+                                    : "GMRES did not reach the tolerance");
   return CAVITY_OK;
 }
 
@@ -1308,31 +1505,17 @@ int cavity_rcs(cavity_plan p, int idx, int n_obs, const double* th, const double
                double* sigma) {
   if (!p || idx < 0 || idx >= p->nsol || n_obs < 0 || (n_obs > 0 && (!th || !ph || !sigma)))
     return fail(CAVITY_EINVAL, "bad rcs arguments");
-  const int nblk = 64;
-  std::vector<zd> part(2 * nblk);
-  zd* dpart = p->dbg_out;
-  const double k = p->g.k;
-  const zd* x = p->xsol + (long long)idx * p->nvec();
-  for (int i = 0; i < n_obs; ++i) {
-    const double st = std::sin(th[i]), ct = std::cos(th[i]), sp = std::sin(ph[i]),
-                 cp = std::cos(ph[i]);
-    HIPCHK(cav::launch_rcs_partial(p->g, x, k * st * cp, k * st * sp, dpart, nblk, p->st));
-    HIPCHK(hipMemcpyAsync(part.data(), dpart, 2 * nblk * sizeof(zd), hipMemcpyDeviceToHost,
-                          p->st));
-    HIPCHK(hipStreamSynchronize(p->st));
-    std::complex<double> e1 = 0.0, e2 = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-      e1 += std::complex<double>(part[2 * b].re, part[2 * b].im);
-      e2 += std::complex<double>(part[2 * b + 1].re, part[2 * b + 1].im);
-    }
-    // L = (-E^2, E^1, 0); sigma_theta = k^2/pi |phi^.L|^2, sigma_phi = k^2/pi |theta^.L|^2
-    const std::complex<double> L1 = -e2, L2 = e1;
-    const std::complex<double> phiL = -sp * L1 + cp * L2;
-    const std::complex<double> thL = ct * cp * L1 + ct * sp * L2;
-    sigma[2 * i] = k * k / M_PI * std::norm(phiL);
-    sigma[2 * i + 1] = k * k / M_PI * std::norm(thL);
-  }
-  return CAVITY_OK;
+  std::vector<int> rhs(n_obs, idx);
+  return rcs_queries(p, n_obs, rhs.data(), th, ph, sigma);
+}
+
+int cavity_rcs_many(cavity_plan p, int n, const int* rhs_index, const double* th,
+                    const double* ph, double* sigma) {
+  if (!p || n < 0 || (n > 0 && (!rhs_index || !th || !ph || !sigma)))
+    return fail(CAVITY_EINVAL, "bad rcs arguments");
+  for (int i = 0; i < n; ++i)
+    if (rhs_index[i] < 0 || rhs_index[i] >= p->nsol) return fail(CAVITY_EINVAL, "no such solution");
+  return rcs_queries(p, n, rhs_index, th, ph, sigma);
 }
 
 int cavity_probe_kernel(int which, int capacity) {

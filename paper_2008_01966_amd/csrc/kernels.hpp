@@ -57,6 +57,13 @@ struct Wave {
   double p1, p2, p3;
 };
 
+// One aperture-transform evaluation behind an RCS value: stored solution rhs at the
+// transform point (u1, u2) = k sin(theta_o) (cos(phi_o), sin(phi_o)).
+struct RcsQuery {
+  int rhs;
+  double u1, u2;
+};
+
 // ---- timing probe ----------------------------------------------------------------
 // Kernel identifiers for the benchmark probe (cavity_probe_* in the C ABI).
 enum KernelId {
@@ -176,10 +183,23 @@ hipError_t launch_combine(const Geo& g, const Krylov& kv, const zf* V, long long
 hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const zd* theta_d,
                             const zd* pi_n, const zd* xap, int j0, int j1, zd* tbuf,
                             zd* eout, hipStream_t st);
-// Aperture transforms E^1(u), E^2(u): per-block partial sums (2 complex per block).
-hipError_t launch_rcs_partial(const Geo& g, const zd* xap, double u1, double u2, zd* partial,
-                              int nblk, hipStream_t st);
+// Aperture transforms E^1(u), E^2(u) for nq queries: per-block partial sums (2 complex per
+// block and query); solution r at xall + r * n.
+hipError_t launch_rcs_partial(const Geo& g, const zd* xall, long long n, const RcsQuery* queries,
+                              int nq, zd* partial, int nblk, hipStream_t st);
 hipError_t launch_pack(const Geo& g, const zd* xpad, zd* xcompact, hipStream_t st);
 hipError_t launch_unpack(const Geo& g, const zd* xcompact, zd* xpad, hipStream_t st);
+
+// Direct solve for small cavities (n = 3 NM, column-major n x n matrices).
+hipError_t launch_unit_vectors(long long n, long long k0, int nb, zd* x, hipStream_t st);
+hipError_t launch_dense_fix(const Geo& g, zd* A, hipStream_t st);
+// Gauss-Jordan inversion with partial pivoting of A (overwritten; B is scratch of the same
+// size): *result = (P A)^{-1} (A or B), piv[k] = row exchanged with row k at step k, or -1
+// from the first step that found no nonzero pivot on.
+hipError_t launch_gj_invert(zd* A, zd* B, long long n, int* piv, zd** result, hipStream_t st);
+// x_r = F (P b_r) for r < nb, perm[i] = source row of (P b)_i; pb: nb x n scratch.
+hipError_t launch_dense_apply(const zd* F, const int* perm, long long n, const zd* b, int nb,
+                              zd* pb, zd* x, hipStream_t st);
+hipError_t launch_add(zd* x, const zd* y, long long total, hipStream_t st);
 
 }  // namespace cav

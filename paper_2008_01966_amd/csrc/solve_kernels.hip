@@ -448,6 +448,7 @@ hipError_t launch_single_family(const Geo& g, const Trig& t, const zd* khat, int
 // Reductions are two-stage and deterministic.  Inactive right-hand sides are skipped.
 // ---------------------------------------------------------------------------------
 constexpr int kDotGroup = 8;
+constexpr int kDotUnroll = 4;
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -469,14 +470,32 @@ __global__ __launch_bounds__(256) void k_dots(const cx<VT>* __restrict__ V, long
   const zd* w = wall + r * n;
   const cx<VT>* Vr = V + r * n;
   const int nvg = min(kDotGroup, nv - grp * kDotGroup);
+  const cx<VT>* Vg = Vr + (long long)grp * kDotGroup * ldj;
   zd acc[kDotGroup];
   for (int t = 0; t < kDotGroup; ++t) acc[t] = mk(0.0, 0.0);
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // kDotUnroll elements per thread per trip, every load of a trip issued before the products
+  for (; i + (kDotUnroll - 1) * stride < n; i += kDotUnroll * stride) {
+    zd wi[kDotUnroll];
+#pragma unroll
+    for (int u = 0; u < kDotUnroll; ++u) wi[u] = w[i + u * stride];
+#pragma unroll
+    for (int t = 0; t < kDotGroup; ++t) {
+      if (t < nvg) {
+        cx<VT> v[kDotUnroll];
+#pragma unroll
+        for (int u = 0; u < kDotUnroll; ++u) v[u] = Vg[t * ldj + i + u * stride];
+#pragma unroll
+        for (int u = 0; u < kDotUnroll; ++u) acc[t] = acc[t] + conj(widen(v[u])) * wi[u];
+      }
+    }
+  }
+  for (; i < n; i += stride) {
     const zd wi = w[i];
 #pragma unroll
     for (int t = 0; t < kDotGroup; ++t)
-      if (t < nvg) acc[t] = acc[t] + conj(widen(Vr[(grp * kDotGroup + t) * ldj + i])) * wi;
+      if (t < nvg) acc[t] = acc[t] + conj(widen(Vg[t * ldj + i])) * wi;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -1090,9 +1109,14 @@ hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const z
 // ---------------------------------------------------------------------------------
 // Aperture transforms E^1(u) = sum E1_mn C_m(-u1) S_n(-u2), E^2(u) = sum E2_mn S_m(-u1) C_n(-u2)
 // ---------------------------------------------------------------------------------
-__global__ void k_rcs_partial(Geo g, const zd* __restrict__ xap, double u1, double u2,
-                              zd* __restrict__ partial) {
+// Query q (blockIdx.y): solution q.rhs (at xall + rhs * n) at transform point (u1, u2);
+// partial[(q * gridDim.x + block) * 2 + {0, 1}] = this block's share of (E^1, E^2).
+__global__ void k_rcs_partial(Geo g, const zd* __restrict__ xall, long long n,
+                              const RcsQuery* __restrict__ queries, zd* __restrict__ partial) {
   __shared__ zd red[2][256];
+  const RcsQuery q = queries[blockIdx.y];
+  const zd* xap = xall + (long long)q.rhs * n;
+  const double u1 = q.u1, u2 = q.u2;
   zd s1 = mk(0.0, 0.0), s2 = mk(0.0, 0.0);
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long mn = (long long)blockIdx.x * blockDim.x + threadIdx.x; mn < g.NM; mn += stride) {
@@ -1112,14 +1136,16 @@ __global__ void k_rcs_partial(Geo g, const zd* __restrict__ xap, double u1, doub
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = red[0][0];
-    partial[2 * blockIdx.x + 1] = red[1][0];
+    zd* out = partial + 2 * ((long long)blockIdx.y * gridDim.x + blockIdx.x);
+    out[0] = red[0][0];
+    out[1] = red[1][0];
   }
 }
 
-hipError_t launch_rcs_partial(const Geo& g, const zd* xap, double u1, double u2, zd* partial,
-                              int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_rcs_partial, dim3(nblk), dim3(256), 0, st, g, xap, u1, u2, partial);
+hipError_t launch_rcs_partial(const Geo& g, const zd* xall, long long n, const RcsQuery* queries,
+                              int nq, zd* partial, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_rcs_partial, dim3(nblk, nq), dim3(256), 0, st, g, xall, n, queries,
+                     partial);
   return hipGetLastError();
 }
 

@@ -132,3 +132,16 @@ def test_server_arguments_rejected_without_device():
     assert lib.cavity_server_wait(None, 1, None) == 1
     assert lib.cavity_server_release(None, 1) == 1
     lib.cavity_server_destroy(None)
+
+
+def test_direct_option_validated_without_device():
+    """The direct-solve switch takes -1, 0 or 1; forcing it needs 3 Nx Ny <= 4096."""
+    lib = P.load_library()
+    o = P.Opts()
+    lib.cavity_opts_default(ctypes.byref(o))
+    assert o.direct == 0
+    for val, nx, ny, want in ((2, 16, 16, 1), (-2, 16, 16, 1), (1, 16, 16, 0), (-1, 16, 16, 0),
+                              (1, 40, 40, 1), (0, 40, 40, 0), (1, 32, 40, 0)):
+        o.direct = val
+        st, _ = _footprint(nx=nx, ny=ny, opts=o)
+        assert st == want, (val, nx, ny, st)

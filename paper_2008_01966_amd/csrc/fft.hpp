@@ -214,25 +214,35 @@ __device__ inline void fft_stage(const cx<T>* __restrict__ in, cx<T>* __restrict
   const int tstep = n / (ns * R);
   const int total = nb << lc;
   const int cmask = (1 << lc) - 1;
+  // Uniform strides: input r of work item w sits at w + r istride, output r at
+  // (d << lc) + col + r ostride, so each access is one add to a per-thread base.
+  const int istride = nb << lc, ostride = ns << lc;
+  // j / ns from a float reciprocal: (j + 1/2) / ns lies at least 1/(2 ns) from an integer
+  // and the float rounding error stays below (j + ns) 2^-23 / ns, so the quotient is exact
+  // while j + ns < 2^22 (transforms here have at most a few thousand points).
+  const float inv_ns = 1.0f / (float)ns;
   for (int w = tid; w < total; w += nthr) {
     const int j = w >> lc;
     const int col = w & cmask;
-    const int k = j % ns;
+    const int q = (int)(((float)j + 0.5f) * inv_ns);
+    const int k = j - q * ns;
+    const cx<T>* ip = in + w;
     cx<T> v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = in[((j + r * nb) << lc) + col];
+    for (int r = 0; r < R; ++r) v[r] = ip[r * istride];
     if (ns > 1) {
+      const cx<T>* tp = tw + k * tstep;
       const int step = k * tstep;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const cx<T> w2 = tw[r * step];
+        const cx<T> w2 = tp[(r - 1) * step];
         v[r] = v[r] * (INV ? conj(w2) : w2);
       }
     }
     Dft<R, T, INV>::run(v);
-    const int d = (j - k) * R + k;
+    cx<T>* op = out + ((((q * R) * ns + k) << lc) + col);
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[((d + r * ns) << lc) + col] = v[r];
+    for (int r = 0; r < R; ++r) op[r * ostride] = v[r];
   }
 }
 

@@ -1525,7 +1525,10 @@ int cavity_probe_kernel(int which, int capacity) {
   if (which < 0) return CAVITY_OK;
   if (which >= cav::K_COUNT || capacity < 1) return fail(CAVITY_EINVAL, "bad probe arguments");
   g_probe.pool.resize(2 * (size_t)capacity + 2);
-  for (auto& e : g_probe.pool) HIPCHK(hipEventCreate(&e));
+  // timing only: no system-scope fence (cache writeback and invalidate) at each record,
+  // which would slow the work around the probed launches
+  for (auto& e : g_probe.pool)
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   g_probe.which = which;
   return CAVITY_OK;
 }

@@ -59,6 +59,17 @@ __host__ __device__ inline zd widen(cx<T> a) { return zd{(double)a.re, (double)a
 // Logical block index of a 3D grid, renumbered so that each of the 8 XCDs (which receive
 // workgroups round-robin in linear dispatch order) runs one contiguous range of logical
 // blocks: neighbouring strips of an array then meet in the same L2.
+// Quotient and remainder by a runtime divisor d from a float reciprocal: (w + 1/2) / d lies
+// at least 1/(2 d) from an integer and the float rounding error is below (w + d) 2^-23 / d,
+// so the quotient is exact while w + d < 2^22 (a few instructions instead of an integer
+// division in the load and store loops of the transform kernels).
+struct DivBy {
+  int d;
+  float inv;
+  __device__ explicit DivBy(int dd) : d(dd), inv(1.0f / (float)dd) {}
+  __device__ int quot(int w) const { return (int)(((float)w + 0.5f) * inv); }
+};
+
 struct BlockId {
   int x, y, z;
 };

@@ -117,6 +117,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
   const int f = fam_fixed >= 0 ? fam_fixed : bid.y;
   const int slot = fam_fixed >= 0 ? 0 : bid.y;
   const int L = g.nq2, P = g.P2;
+  const DivBy div_p(P);
   cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* b = a + ((long long)P << lc);
   const bool ycos = fam_ycos(f);
@@ -124,8 +125,9 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
   for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk<T>(0, 0);
   __syncthreads();
   const int rowlen = g.N + 1;
+  const DivBy div_row(rowlen);
   for (int w = tid; w < rowlen * Cb; w += nt) {
-    const int c = w / rowlen, n = w - c * rowlen;
+    const int c = div_row.quot(w), n = w - c * div_row.d;
     const int m = m0 + c;
     const long long mn = (long long)m * rowlen + n;
     zd val;
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
   cx<T>* r2 = fft_lds<T, false, kMaxRadix>(o, r, box2.p, twiddles<T>(box2), tid, nt, lc);
   cx<T>* dst = X + ((long long)slot * (g.M + 1) + m0) * g.P2;
   for (int w = tid; w < P * Cb; w += nt) {
-    const int c = w / P, k = w - c * P;
+    const int c = div_p.quot(w), k = w - c * div_p.d;
     dst[(long long)c * g.P2 + k] = r2[(k << lc) + c];
   }
 }
@@ -267,12 +269,13 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
   const int m0 = bid.x << lc;
   const int Cb = min(C, g.M + 1 - m0);
   const int L = g.nq2, P = g.P2;
+  const DivBy div_p(P);
   cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* b = a + ((long long)P << lc);
   const bool ycos = fam_ycos(f);
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int w = tid; w < P << lc; w += nt) {
-    const int c = w / P, k = w - c * P;
+    const int c = div_p.quot(w), k = w - c * div_p.d;
     a[(k << lc) + c] = c < Cb ? Y[(long long)(m0 + c) * g.P2 + k] : mk<T>(0, 0);
   }
   __syncthreads();
@@ -285,8 +288,9 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
   __syncthreads();
   cx<T>* r2 = fft_lds<T, false, kMaxRadix>(o, r, ext2.p, twiddles<T>(ext2), tid, nt, lc);
   const int rowlen = g.N + 1;
+  const DivBy div_row(rowlen);
   for (int w = tid; w < rowlen * Cb; w += nt) {
-    const int c = w / rowlen, n = w - c * rowlen;
+    const int c = div_row.quot(w), n = w - c * div_row.d;
     const cx<T> F = r2[(n << lc) + c];
     const zd s = widen(ycos ? (T)0.5 * F : (T)0.5 * mul_i(F));
     S[(long long)(m0 + c) * rowlen + n] = g.hq2 * s;
@@ -1011,6 +1015,7 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc,
   const int m0 = bid.x << lc;
   const int Cb = min(C, g.M + 1 - m0);
   const int L = g.ny;
+  const DivBy div_l1(L + 1);
   zd* a = reinterpret_cast<zd*>(smem_raw);
   zd* b = a + ((2LL * L) << lc);
   const bool ycos = (l == 1);  // E1: sin, E2: cos, E3: sin along y
@@ -1019,8 +1024,9 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc,
   __syncthreads();
   const long long NM = g.NM;
   const int rowlen = g.N + 1;
+  const DivBy div_row(rowlen);
   for (int w = tid; w < rowlen * Cb; w += nt) {
-    const int c = w / rowlen, n = w - c * rowlen;
+    const int c = div_row.quot(w), n = w - c * div_row.d;
     const int m = m0 + c;
     const long long mn = (long long)m * rowlen + n;
     zd val;
@@ -1040,7 +1046,7 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc,
   zd* r = fft_lds<double, false, kMaxRadix>(a, b, out2.p, out2.tw, tid, nt, lc);
   zd* dst = tbuf + (((long long)l * jn + jj) * (g.M + 1) + m0) * (g.ny + 1);
   for (int w = tid; w < (L + 1) * Cb; w += nt) {
-    const int c = w / (L + 1), i = w - c * (L + 1);
+    const int c = div_l1.quot(w), i = w - c * div_l1.d;
     const zd F = r[(i << lc) + c];
     dst[(long long)c * (g.ny + 1) + i] = ycos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
   }
@@ -1058,6 +1064,7 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
   const int i0 = bid.x << lc;
   const int Cb = min(C, g.ny + 1 - i0);
   const int L = g.nx;
+  const DivBy div_l1(L + 1);
   zd* a = reinterpret_cast<zd*>(smem_raw);
   zd* b = a + ((2LL * L) << lc);
   const bool xcos = (l == 0);  // E1: cos, E2: sin, E3: sin along x
@@ -1076,7 +1083,7 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
   zd* r = fft_lds<double, false, kMaxRadix>(a, b, out1.p, out1.tw, tid, nt, lc);
   zd* dst = eout + (((long long)l * (g.Nz + 1) + j) * (g.ny + 1) + i0) * (g.nx + 1);
   for (int w = tid; w < (L + 1) * Cb; w += nt) {
-    const int c = w / (L + 1), i = w - c * (L + 1);
+    const int c = div_l1.quot(w), i = w - c * div_l1.d;
     const zd F = r[(i << lc) + c];
     dst[(long long)c * (g.nx + 1) + i] = xcos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
   }

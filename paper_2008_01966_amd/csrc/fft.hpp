@@ -277,6 +277,77 @@ __device__ cx<T>* fft_lds(cx<T>* a, cx<T>* b, const FftPlan& p, const cx<T>* __r
   return in;
 }
 
+// In-place form of a Stockham stage for one LDS buffer: work item w < (n/R) 2^lc (at most
+// one per thread) loads its R inputs, applies the twiddles and the butterfly in registers,
+// the block synchronises, and the outputs overwrite the buffer.  Half the LDS of the
+// ping-pong form for one more barrier per stage.
+template <int R, typename T, bool INV>
+__device__ inline void fft_stage_ip(cx<T>* buf, int n, int ns, int lc,
+                                    const cx<T>* __restrict__ tw, int tid) {
+  const int nb = n / R;
+  const int tstep = n / (ns * R);
+  const int total = nb << lc;
+  const int istride = nb << lc, ostride = ns << lc;
+  const bool act = tid < total;
+  cx<T> v[R];
+  cx<T>* op = buf;
+  if (act) {
+    const int j = tid >> lc;
+    const int col = tid & ((1 << lc) - 1);
+    const int q = (int)(((float)j + 0.5f) * (1.0f / (float)ns));
+    const int k = j - q * ns;
+    const cx<T>* ip = buf + tid;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = ip[r * istride];
+    if (ns > 1) {
+      const int step = k * tstep;
+      const cx<T>* tp = tw + step;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const cx<T> w2 = tp[(r - 1) * step];
+        v[r] = v[r] * (INV ? conj(w2) : w2);
+      }
+    }
+    Dft<R, T, INV>::run(v);
+    op = buf + ((((q * R) * ns + k) << lc) + col);
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) op[r * ostride] = v[r];
+  }
+}
+
+// 2^lc interleaved length-n transforms in place in LDS buffer `buf`; needs
+// (n / smallest radix) 2^lc <= blockDim.x (see fft_max_items).  Same calling rules as
+// fft_lds; the result is in buf.
+template <typename T, bool INV, int MAXR = 32>
+__device__ void fft_lds_ip(cx<T>* buf, const FftPlan& p, const cx<T>* __restrict__ tw, int tid,
+                           int lc) {
+  int ns = 1;
+  for (int s = 0; s < p.nst; ++s) {
+    const int rdx = p.radix[s];
+    switch (rdx) {
+#define CAV_FFT_CASE_IP(R)                                                         \
+  case R:                                                                          \
+    if constexpr (R <= MAXR) fft_stage_ip<R, T, INV>(buf, p.n, ns, lc, tw, tid);   \
+    break;
+      CAV_FFT_RADICES(CAV_FFT_CASE_IP)
+#undef CAV_FFT_CASE_IP
+      default: break;
+    }
+    __syncthreads();
+    ns *= rdx;
+  }
+}
+
+// Work items of the busiest stage of one transform (n over the smallest radix).
+inline int fft_max_items(const FftPlan& p) {
+  int m = 0;
+  for (int s = 0; s < p.nst; ++s) m = p.n / p.radix[s] > m ? p.n / p.radix[s] : m;
+  return m;
+}
+
 // Even (cos) or odd (sin) extension of entry idx (0 <= idx <= L) of transform col into a
 // length-2L buffer of 2^lc interleaved transforms (entries never stored stay zero).
 template <typename T>

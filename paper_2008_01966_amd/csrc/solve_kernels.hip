@@ -1000,7 +1000,7 @@ hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const doubl
 // columns along x with TK adjacent columns per block.
 // tbuf[l][jj][m][i2], jj = j - j0.
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc,
+__global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int ip,
                                                     const zd* __restrict__ pi_d,
                                                     const zd* __restrict__ theta_d,
                                                     const zd* __restrict__ pi_n,
@@ -1017,7 +1017,7 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc,
   const int L = g.ny;
   const DivBy div_l1(L + 1);
   zd* a = reinterpret_cast<zd*>(smem_raw);
-  zd* b = a + ((2LL * L) << lc);
+  zd* b = a + ((2LL * L) << lc);   // second buffer of the ping-pong form only
   const bool ycos = (l == 1);  // E1: sin, E2: cos, E3: sin along y
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk(0.0, 0.0);
@@ -1043,7 +1043,9 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc,
     if (n == 0) c0s[c] = val;
   }
   __syncthreads();
-  zd* r = fft_lds<double, false, kMaxRadix>(a, b, out2.p, out2.tw, tid, nt, lc);
+  zd* r = a;
+  if (ip) fft_lds_ip<double, false, kMaxRadix>(a, out2.p, out2.tw, tid, lc);
+  else r = fft_lds<double, false, kMaxRadix>(a, b, out2.p, out2.tw, tid, nt, lc);
   zd* dst = tbuf + (((long long)l * jn + jj) * (g.M + 1) + m0) * (g.ny + 1);
   for (int w = tid; w < (L + 1) * Cb; w += nt) {
     const int c = div_l1.quot(w), i = w - c * div_l1.d;
@@ -1052,7 +1054,7 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc,
   }
 }
 
-__global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int j0, int jn,
+__global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int ip, int j0, int jn,
                                                     const zd* __restrict__ tbuf,
                                                     zd* __restrict__ eout) {
   CAV_DYN_SMEM(smem_raw);
@@ -1066,7 +1068,7 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
   const int L = g.nx;
   const DivBy div_l1(L + 1);
   zd* a = reinterpret_cast<zd*>(smem_raw);
-  zd* b = a + ((2LL * L) << lc);
+  zd* b = a + ((2LL * L) << lc);   // second buffer of the ping-pong form only
   const bool xcos = (l == 0);  // E1: cos, E2: sin, E3: sin along x
   const zd* src = tbuf + ((long long)l * jn + jj) * (g.M + 1) * (g.ny + 1);
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -1080,13 +1082,33 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
     if (m == 0) c0s[c] = x;
   }
   __syncthreads();
-  zd* r = fft_lds<double, false, kMaxRadix>(a, b, out1.p, out1.tw, tid, nt, lc);
+  zd* r = a;
+  if (ip) fft_lds_ip<double, false, kMaxRadix>(a, out1.p, out1.tw, tid, lc);
+  else r = fft_lds<double, false, kMaxRadix>(a, b, out1.p, out1.tw, tid, nt, lc);
   zd* dst = eout + (((long long)l * (g.Nz + 1) + j) * (g.ny + 1) + i0) * (g.nx + 1);
   for (int w = tid; w < (L + 1) * Cb; w += nt) {
     const int c = div_l1.quot(w), i = w - c * div_l1.d;
     const zd F = r[(i << lc) + c];
     dst[(long long)c * (g.nx + 1) + i] = xcos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
   }
+}
+
+// Batch of one synthesis pass: transforms of length 2 len per block (at most `cap`) and
+// whether they run in place (one LDS buffer, every thread one work item per stage) or in
+// the ping-pong form (two buffers; used when a stage has more work items than threads).
+struct SynthShape {
+  int lc, ip;
+  size_t smem;
+};
+static SynthShape synth_shape(const FftPlan& p, int len, int cap, int budget) {
+  const int items = fft_max_items(p);
+  if (items <= 256) {
+    int lc = batch_log2(len, (int)sizeof(zd), cap, budget);   // one buffer of 2 len
+    while (lc > 0 && (items << lc) > 256) --lc;
+    return {lc, 1, (size_t)2 * len * sizeof(zd) << lc};
+  }
+  const int lc = batch_log2(2 * len, (int)sizeof(zd), cap, budget);
+  return {lc, 0, (size_t)4 * len * sizeof(zd) << lc};
 }
 
 hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const zd* theta_d,
@@ -1096,19 +1118,22 @@ hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const z
   const double zb = sizeof(zd);
   const double tb = zb * 3.0 * jn * (g.M + 1) * (double)(g.ny + 1);   // staging slab
   const double prof = zb * (double)jn * g.NM * (theta_d ? 3.0 : 2.0);
-  const int lr = batch_log2(2 * g.ny, (int)sizeof(zd), g.M + 1);
+  static const int synth_budget = [] {
+    const char* e = getenv("CAVITY_SYNTH_LDS");
+    return e ? atoi(e) : 0;
+  }();
+  const SynthShape sr = synth_shape(t.out2.p, g.ny, g.M + 1, synth_budget);
   probe_begin(K_SYNTH_ROWS, st);
-  hipLaunchKernelGGL(k_synth_rows, dim3((g.M + 1 + (1 << lr) - 1) >> lr, jn, 3), dim3(256),
-                     (size_t)4 * g.ny * sizeof(zd) * (1 << lr), st, g, t.out2, lr, pi_d, theta_d,
-                     pi_n, xap, j0, jn, tbuf);
+  hipLaunchKernelGGL(k_synth_rows, dim3((g.M + 1 + (1 << sr.lc) - 1) >> sr.lc, jn, 3), dim3(256),
+                     sr.smem, st, g, t.out2, sr.lc, sr.ip, pi_d, theta_d, pi_n, xap, j0, jn,
+                     tbuf);
   probe_end(K_SYNTH_ROWS, st, prof + zb * 3.0 * g.NM + tb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int lcc = batch_log2(2 * g.nx, (int)sizeof(zd), g.ny + 1);
+  const SynthShape sc = synth_shape(t.out1.p, g.nx, g.ny + 1, synth_budget);
   probe_begin(K_SYNTH_COLS, st);
-  hipLaunchKernelGGL(k_synth_cols, dim3((g.ny + 1 + (1 << lcc) - 1) >> lcc, jn, 3), dim3(256),
-                     (size_t)4 * g.nx * sizeof(zd) * (1 << lcc), st, g, t.out1, lcc, j0, jn, tbuf,
-                     eout);
+  hipLaunchKernelGGL(k_synth_cols, dim3((g.ny + 1 + (1 << sc.lc) - 1) >> sc.lc, jn, 3), dim3(256),
+                     sc.smem, st, g, t.out1, sc.lc, sc.ip, j0, jn, tbuf, eout);
   probe_end(K_SYNTH_COLS, st, tb + zb * 3.0 * jn * (g.ny + 1) * (double)(g.nx + 1));
   return hipGetLastError();
 }

@@ -342,6 +342,7 @@ def main() -> int:
             "plan_ms_same_aperture": plan_ms[-1],
             "gmres_iterations_last": int(infos[-1].last_iterations),
             "lds_budget": int(infos[-1].lds_budget),
+            "tbc_rows_in_place": bool(infos[-1].tbc_rows_in_place),
             "direct": bool(infos[-1].last_direct),
             "direct_factor_ms": float(infos[-1].ms_factor),
         }

@@ -122,6 +122,9 @@ typedef struct {
                                   (last_iterations is then 0) */
   double ms_factor;            /* device time of assembling and inverting the aperture
                                   matrix for the direct solve (0 until it is built) */
+  int tbc_rows_in_place;       /* 1 when the TBC row passes run their transforms in place
+                                  in LDS (one buffer per transform), 0 for the two-buffer
+                                  form; chosen by timing with lds_budget */
 } cavity_info;
 
 int cavity_opts_default(cavity_opts* opts);

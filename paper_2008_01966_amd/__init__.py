@@ -56,7 +56,8 @@ class Info(ctypes.Structure):
                 ("ms_elimination", ctypes.c_double), ("ms_preconditioner", ctypes.c_double),
                 ("ms_rhs", ctypes.c_double), ("ms_krylov", ctypes.c_double),
                 ("ms_synthesis", ctypes.c_double), ("lds_budget", ctypes.c_int),
-                ("last_direct", ctypes.c_int), ("ms_factor", ctypes.c_double)]
+                ("last_direct", ctypes.c_int), ("ms_factor", ctypes.c_double),
+                ("tbc_rows_in_place", ctypes.c_int)]
 
 
 class ServerOpts(ctypes.Structure):

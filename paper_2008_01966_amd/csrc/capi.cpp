@@ -463,7 +463,7 @@ struct TuneKey {
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune;
+std::map<TuneKey, std::pair<int, int>> g_tune;   // (LDS budget, row passes in place)
 
 int autotune_lds(cavity_plan p) {
   const char* e = std::getenv("CAVITY_AUTOTUNE");
@@ -474,8 +474,10 @@ int autotune_lds(cavity_plan p) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
-      p->g.lds_budget = it->second;
-      p->info.lds_budget = it->second;
+      p->g.lds_budget = it->second.first;
+      p->g.rows_ip = it->second.second;
+      p->info.lds_budget = p->g.lds_budget;
+      p->info.tbc_rows_in_place = p->g.rows_ip;
       return CAVITY_OK;
     }
   }
@@ -488,13 +490,17 @@ int autotune_lds(cavity_plan p) {
   hipEvent_t t0 = nullptr, t1 = nullptr;
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
-  // two sweeps over the candidates, each timing 4 applies after a warm-up; the fastest
-  // sweep of each budget counts (guards against a noisy first measurement)
+  // candidates: three LDS budgets x row passes in place or ping-pong; two sweeps, each
+  // timing 4 applies after a warm-up; the fastest sweep of each candidate counts (guards
+  // against a noisy first measurement)
+  constexpr int kCand = 6;
   const int budgets[3] = {20000, 40000, 80000};
-  float ms_best[3] = {1e30f, 1e30f, 1e30f};
+  float ms_best[kCand];
+  for (float& v : ms_best) v = 1e30f;
   for (int sweep = 0; sweep < 2 && !s; ++sweep) {
-    for (int bi = 0; bi < 3 && !s; ++bi) {
-      p->g.lds_budget = budgets[bi];
+    for (int ci = 0; ci < kCand && !s; ++ci) {
+      p->g.lds_budget = budgets[ci % 3];
+      p->g.rows_ip = ci / 3;
       if ((s = run_operator(p, 0, nbt, p->zb, p->w, nullptr, single))) break;   // warm-up
       if (hipEventRecord(t0, p->st) != hipSuccess) { s = CAVITY_EDEVICE; break; }
       for (int r = 0; r < 4 && !s; ++r) s = run_operator(p, 0, nbt, p->zb, p->w, nullptr, single);
@@ -505,23 +511,21 @@ int autotune_lds(cavity_plan p) {
         s = CAVITY_EDEVICE;
         break;
       }
-      ms_best[bi] = std::min(ms_best[bi], ms);
+      ms_best[ci] = std::min(ms_best[ci], ms);
     }
   }
-  int best = 40000;
-  float best_ms = 1e30f;
-  for (int bi = 0; bi < 3; ++bi)
-    if (ms_best[bi] < best_ms) {
-      best_ms = ms_best[bi];
-      best = budgets[bi];
-    }
+  int best = 4;   // 40000 bytes, in place
+  for (int ci = 0; ci < kCand; ++ci)
+    if (ms_best[ci] < ms_best[best]) best = ci;
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (s) return s;
-  p->g.lds_budget = best;
-  p->info.lds_budget = best;
+  p->g.lds_budget = budgets[best % 3];
+  p->g.rows_ip = best / 3;
+  p->info.lds_budget = p->g.lds_budget;
+  p->info.tbc_rows_in_place = p->g.rows_ip;
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[key] = best;
+  g_tune[key] = {p->g.lds_budget, p->g.rows_ip};
   return CAVITY_OK;
 }
 
@@ -1177,6 +1181,7 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   g.k = k;
   g.hq1 = a / g.nq1;
   g.hq2 = b / g.nq2;
+  g.rows_ip = 1;
   const double R = std::sqrt(2.0) * std::max(a, b);
   g.P1 = next_5smooth((long long)std::ceil((a + R) / g.hq1));
   g.P2 = next_5smooth((long long)std::ceil((b + R) / g.hq2));
@@ -1427,7 +1432,13 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   p->info.min_pivot = p->hn[0];
   if (!(p->info.min_pivot > 1e-13))
     return bail(fail(CAVITY_ERESONANT, "z-elimination pivot below 1e-13"));
+  p->info.tbc_rows_in_place = p->g.rows_ip;
   if ((st = autotune_lds(p))) return bail(st);
+  // CAVITY_TBC_ROWS_IP=0 or 1 fixes the form of the TBC row passes (after any tuning)
+  if (const char* e = std::getenv("CAVITY_TBC_ROWS_IP")) {
+    p->g.rows_ip = std::atoi(e) != 0 ? 1 : 0;
+    p->info.tbc_rows_in_place = p->g.rows_ip;
+  }
   p->info.M = g.M;
   p->info.N = g.N;
   p->info.Nz = Nz;

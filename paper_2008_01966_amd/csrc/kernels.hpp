@@ -18,6 +18,7 @@ struct Geo {
   double a, b, h, k;
   double hq1, hq2;
   int lds_budget;       // LDS bytes per block the TBC FFT kernels size their batch for (0: default)
+  int rows_ip;          // TBC row passes: 1 = in-place transforms allowed, 0 = ping-pong form
 };
 
 // An FFT length with its device twiddle tables (double and single precision).

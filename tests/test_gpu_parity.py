@@ -184,3 +184,32 @@ def test_invalid_angle_rejected():
         gpu.solve(2.0, 0.0, W.TM)
     assert exc.value.status == 1
     gpu.close()
+
+
+@pytest.mark.parametrize("form", ["0", "1"], ids=["rows_pingpong", "rows_in_place"])
+def test_tbc_row_pass_forms(form, monkeypatch):
+    """Both forms of the TBC row passes (two LDS buffers, or in place with one work item per
+    thread) give the oracle's single-layer operators and the full operator to 1e-12."""
+    monkeypatch.setenv("CAVITY_TBC_ROWS_IP", form)
+    rng = np.random.default_rng(21)
+    for wl in CASES[:3]:
+        prob = Problem.from_cavity(wl.cavity)
+        ora = solver.plan(prob)
+        for precision in ("fp64", "mixed"):
+            gpu = P.Plan.from_cavity(wl.cavity, precision=precision)
+            assert gpu.info().tbc_rows_in_place == int(form)
+            for fam in tbc.FAMILIES:
+                x = rng.standard_normal(gpu.grid_shape) + 1j * rng.standard_normal(gpu.grid_shape)
+                got = gpu.debug_tbc(tbc.FAMILIES.index(fam), x)
+                ref = tbc.apply(prob, ora.khat, fam, x)
+                if fam == "cs":
+                    got[:, 0] = ref[:, 0] = 0
+                if fam == "sc":
+                    got[0, :] = ref[0, :] = 0
+                assert rel(got, ref) <= 1e-12, (wl.name, fam)
+            inc = wl.incidences[0]
+            gpu.solve(inc.theta, inc.phi, inc.pol, field=False)
+            ref = solver.solve(ora, inc.theta, inc.phi, inc.pol, tol=1e-13)
+            tol = 1e-10 if precision == "fp64" else 1e-8
+            assert np.linalg.norm(gpu.aperture(0) - ref.x) <= tol * np.linalg.norm(ref.x)
+            gpu.close()

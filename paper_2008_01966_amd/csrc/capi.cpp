@@ -1479,7 +1479,12 @@ int cavity_solve_batch(cavity_plan p, int nrhs, const double* theta, const doubl
                              (p->dense_F != nullptr || nrhs >= kDenseAutoRhs));
   const int group = p->dense_now ? kDenseGroup : p->opts.batch;
   if ((s = ensure_work(p, std::min(nrhs, group)))) return s;
-  if (p->dense_now && (s = dense_factor(p))) return s;
+  if (p->dense_now && (s = dense_factor(p))) {
+    // the automatic choice falls back to GMRES when the inverse does not fit in memory
+    if (s != CAVITY_ENOMEM || p->opts.direct == 1) return s;
+    p->dense_now = false;
+    if ((s = ensure_work(p, std::min(nrhs, p->opts.batch)))) return s;
+  }
   p->info.last_direct = p->dense_now ? 1 : 0;
   const long long field = 3LL * (p->g.Nz + 1) * (p->g.ny + 1) * (p->g.nx + 1);
   int worst = CAVITY_OK;

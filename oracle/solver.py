@@ -27,13 +27,14 @@ class Plan:
     timers: Dict[str, float] = field(default_factory=dict)
 
 
-def plan(prob: Problem) -> Plan:
+def plan(prob: Problem, operator: str = "trap") -> Plan:
+    """operator: the discrete TBC, "trap" (D_trap) or "spec" (D_spec)."""
     t0 = time.perf_counter()
     khat = spectrum.kernel_spectrum(prob)
     t1 = time.perf_counter()
     cols = columns.eliminate(prob)
-    op = system.ReducedSystem(prob, cols, khat)
-    pre = system.BlockPreconditioner(prob, cols, khat)
+    op = system.ReducedSystem(prob, cols, khat, operator)
+    pre = system.BlockPreconditioner(prob, cols, khat, operator)
     t2 = time.perf_counter()
     return Plan(prob, cols, khat, op, pre, {"spectrum": t1 - t0, "assemble": t2 - t1})
 

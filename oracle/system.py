@@ -43,8 +43,9 @@ TBC_SIGN = +1.0
 class ReducedSystem:
     """Matrix-free reduced aperture operator on the compact (paper-ordered) vector."""
 
-    def __init__(self, prob: Problem, cols: Columns, khat: np.ndarray):
+    def __init__(self, prob: Problem, cols: Columns, khat: np.ndarray, operator: str = "trap"):
         self.prob, self.cols, self.khat = prob, cols, khat
+        self.single = {"trap": tbc.apply, "spec": tbc.apply_spec}[operator]
         self.mu = prob.mu[:, None]
         self.nu = prob.nu[None, :]
         self.hq_ = prob.h / prob.q_norm()
@@ -55,9 +56,9 @@ class ReducedSystem:
         p, c, k2 = self.prob, self.cols, self.prob.k ** 2
         mu, nu, h = self.mu, self.nu, p.h
         sigma = nu * e1 - mu * e2
-        s_cs = tbc.apply(p, self.khat, "cs", e1)
-        s_sc = tbc.apply(p, self.khat, "sc", e2)
-        s_cc = tbc.apply(p, self.khat, "cc", sigma)
+        s_cs = self.single(p, self.khat, "cs", e1)
+        s_sc = self.single(p, self.khat, "sc", e2)
+        s_cc = self.single(p, self.khat, "cc", sigma)
         r1 = (c.rho_d - 1.0) * e1 + mu * (c.T + h) * e3 \
             + TBC_SIGN * self.hq_ * (2 * k2 * s_cs - 2 * nu * s_cc)
         r2 = (c.rho_d - 1.0) * e2 + nu * (c.T + h) * e3 \
@@ -86,13 +87,14 @@ class BlockPreconditioner:
     A design choice of this build (the paper proposes no preconditioner): only the
     convergence speed depends on it, never the solution."""
 
-    def __init__(self, prob: Problem, cols: Columns, khat: np.ndarray):
+    def __init__(self, prob: Problem, cols: Columns, khat: np.ndarray, operator: str = "trap"):
         self.prob = prob
         k2, h = prob.k ** 2, prob.h
         mu, nu = prob.mu[:, None], prob.nu[None, :]
-        d_cs = tbc.diagonal(prob, khat, "cs")
-        d_sc = tbc.diagonal(prob, khat, "sc")
-        d_cc = tbc.diagonal(prob, khat, "cc")
+        diag = {"trap": tbc.diagonal, "spec": tbc.diagonal_spec}[operator]
+        d_cs = diag(prob, khat, "cs")
+        d_sc = diag(prob, khat, "sc")
+        d_cc = diag(prob, khat, "cc")
         hq_, hc_ = h / prob.q_norm(), h / prob.c_norm()
         shape = (prob.M + 1, prob.N + 1)
         A = np.zeros(shape + (3, 3), dtype=complex)

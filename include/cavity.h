@@ -60,6 +60,7 @@ enum {
 };
 
 enum { CAVITY_FP64 = 0, CAVITY_MIXED = 1 };
+enum { CAVITY_TBC_TRAP = 0, CAVITY_TBC_SPEC = 1 };
 enum { CAVITY_TM = 0 /* theta-hat polarisation */, CAVITY_TE = 1 /* phi-hat */ };
 
 typedef struct cavity_plan_s* cavity_plan; /* opaque; owns all of its device memory */
@@ -101,6 +102,14 @@ typedef struct {
                            at least 32 right-hand sides, and for every call once the inverse
                            exists; 1 = always (3 Nx Ny <= 4096, else CAVITY_EINVAL at plan
                            creation); -1 = never (GMRES only) */
+  int tbc_operator;     /* discrete TBC (Section 5): CAVITY_TBC_TRAP (default) samples the
+                           trial functions on the trapezoid grid and convolves by FFT;
+                           CAVITY_TBC_SPEC uses their exact Fourier transforms on the same
+                           kernel-spectrum lattice (second-order accurate in the lattice
+                           size, about ten times closer to the exact Galerkin integrals),
+                           applied as four dense complex products per family in double
+                           precision in both precision modes; its work grows as
+                           P1 P2 (M + N) per family, so it suits small and mid-size cavities */
 } cavity_opts;
 
 /* Plan description and the statistics of its last solve. */

@@ -44,7 +44,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("tbc_oversample", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
                 ("hbm_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p),
-                ("batch", ctypes.c_int), ("direct", ctypes.c_int)]
+                ("batch", ctypes.c_int), ("direct", ctypes.c_int),
+                ("tbc_operator", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -176,6 +177,8 @@ def _torch():
 PRECISIONS = {"fp64": 0, "mixed": 1}
 # direct solve of the aperture system: automatic, always, never (GMRES only)
 DIRECT = {"auto": 0, "always": 1, "never": -1}
+# discrete TBC operator: trapezoid samples (D_trap) or exact trial transforms (D_spec)
+OPERATORS = {"trap": 0, "spec": 1}
 
 
 class Plan:
@@ -186,7 +189,8 @@ class Plan:
                  layer_eps: Optional[Sequence[complex]] = None, k: float = 2 * np.pi, *,
                  tol: float = 1e-12, restart: int = 60, max_iter: int = 400,
                  oversample: int = 1, hbm_budget: int = 0, stream: Optional[int] = None,
-                 batch: int = 8, precision: str = "fp64", direct: str = "auto"):
+                 batch: int = 8, precision: str = "fp64", direct: str = "auto",
+                 operator: str = "trap"):
         lib = load_library()
         self._lib = lib
         self.a, self.b, self.c = float(a), float(b), float(c)
@@ -200,6 +204,9 @@ class Plan:
         if direct not in DIRECT:
             raise ValueError(f"direct must be one of {sorted(DIRECT)}")
         opts.direct = DIRECT[direct]
+        if operator not in OPERATORS:
+            raise ValueError(f"operator must be one of {sorted(OPERATORS)}")
+        opts.tbc_operator = OPERATORS[operator]
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         opts.precision = PRECISIONS[precision]

@@ -13,7 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcavity.so")
-SOURCES = ["capi.cpp", "server.cpp", "plan_kernels.hip", "solve_kernels.hip", "dense_kernels.hip"]
+SOURCES = ["capi.cpp", "server.cpp", "plan_kernels.hip", "solve_kernels.hip", "dense_kernels.hip",
+           "spec_kernels.hip"]
 ARCH = os.environ.get("CAVITY_OFFLOAD_ARCH", "gfx950")
 
 

@@ -274,6 +274,12 @@ struct cavity_plan_s {
   // direct solve: (P A)^{-1} column-major and the row permutation, built on first use
   Arena dense_arena;
   Arena rcs_arena;                   // RCS queries and partial sums
+  // spectral TBC operator: trial-function transforms (plan) and the P1 x P2 product
+  // workspace per right-hand side and family (solve)
+  Arena spec_arena;
+  cav::SpecMats spec{};
+  zd* U = nullptr;
+  bool use_spec() const { return opts.tbc_operator == CAVITY_TBC_SPEC; }
   zd* dense_F = nullptr;
   int* dense_perm = nullptr;
   bool dense_now = false;            // the current solve call uses the direct solve
@@ -292,6 +298,7 @@ void release(cavity_plan p) {
   arena_release(p->sol_arena.ptr, p->sol_arena.bytes);
   arena_release(p->dense_arena.ptr, p->dense_arena.bytes);
   arena_release(p->rcs_arena.ptr, p->rcs_arena.bytes);
+  arena_release(p->spec_arena.ptr, p->spec_arena.bytes);
   if (p->hflags) (void)hipHostFree(p->hflags);
   if (p->hn) (void)hipHostFree(p->hn);
   if (p->hratio) (void)hipHostFree(p->hratio);
@@ -357,10 +364,12 @@ size_t plan_bytes(const cav::Geo& g, bool layered, int chunk, int nlayers, int* 
   return L.bytes;
 }
 
-size_t work_bytes(const cav::Geo& g, int restart, int nb, int nblk) {
+size_t work_bytes(const cav::Geo& g, int restart, int nb, int nblk, bool spec) {
   const size_t n = 3ull * g.NM;
   const size_t z = sizeof(zd);
   return z * ((size_t)nb * 2 * 3 * (g.M + 1) * g.P2 + (size_t)nb * 3 * g.NM +
+              (spec ? (size_t)nb * 3 * g.P1 * g.P2 + 2 * ((size_t)g.P1 * (g.M + 1) +
+                                                         (size_t)g.P2 * (g.N + 1)) : 0) +
               (size_t)(restart + 1) * nb * n + 4ull * nb * n +
               (size_t)nblk * (restart + 1) * nb +
               (size_t)nb * (restart + 1) * 3 + (size_t)nb * restart * (restart + 4) + 64) +
@@ -376,6 +385,7 @@ int ensure_work(cavity_plan p, int nb) {
   L.add(&p->X, (size_t)nb * 3 * (p->g.M + 1) * p->g.P2);
   L.add(&p->Y, (size_t)nb * 3 * (p->g.M + 1) * p->g.P2);
   L.add(&p->S, (size_t)nb * 3 * p->g.NM);
+  if (p->use_spec()) L.add(&p->U, (size_t)nb * 3 * p->g.P1 * p->g.P2);
   L.add(&p->V, (size_t)(R + 1) * nb * n);
   L.add(&p->w, (size_t)nb * n);
   L.add(&p->bvec, (size_t)nb * n);
@@ -439,6 +449,12 @@ int run_operator(cavity_plan p, int precond, int nb, const zd* v, zd* y, const i
                  bool low = false, hipStream_t stream = nullptr) {
   const long long n = p->nvec();
   hipStream_t st = stream ? stream : p->st;
+  if (p->use_spec()) {   // spectral operator: double precision in both precision modes
+    HIPCHK(cav::launch_operator_spec(p->g, p->spec, p->khat, p->rho_d, p->T, p->rho_n, p->pinv,
+                                     precond, nb, v, n, p->X, p->Y, p->U, p->S, y, n, active,
+                                     st));
+    return CAVITY_OK;
+  }
   if (low)
     HIPCHK(cav::launch_operator_f32(p->g, p->trig, p->khat_f, p->rho_d, p->T, p->rho_n, p->pinv,
                                     precond, nb, v, n, reinterpret_cast<cav::zf*>(p->X),
@@ -467,7 +483,8 @@ std::map<TuneKey, std::pair<int, int>> g_tune;   // (LDS budget, row passes in p
 
 int autotune_lds(cavity_plan p) {
   const char* e = std::getenv("CAVITY_AUTOTUNE");
-  if ((e && std::atoi(e) == 0) || std::getenv("CAVITY_LDS_BUDGET")) return CAVITY_OK;
+  if ((e && std::atoi(e) == 0) || std::getenv("CAVITY_LDS_BUDGET") || p->use_spec())
+    return CAVITY_OK;
   const bool single = p->opts.precision == CAVITY_MIXED;
   const TuneKey key{p->g.P1, p->g.P2, p->g.nq1, p->g.nq2, single ? 1 : 0};
   {
@@ -818,6 +835,57 @@ int rcs_queries(cavity_plan p, int n, const int* rhs, const double* th, const do
   return CAVITY_OK;
 }
 
+// Spectral TBC operator, plan part: the closed-form transforms of the trial functions on
+// the kernel-spectrum lattice xi = 2 pi j / L (j centred at zero), host double precision,
+//   F1[j1][m] = int_0^a cos or sin(mu_m x) e^{-i xi_j1 x} dx, F2 likewise along y,
+// from E(w) = int_0^len e^{i w x} dx = len e^{i w len / 2} sin(w len / 2) / (w len / 2):
+// cos -> (E(w+) + E(w-)) / 2, sin -> (E(w+) - E(w-)) / (2 i), w+- = -xi +- mu.
+std::complex<double> exp_int(double w, double len) {
+  const double t = 0.5 * w * len;
+  const double sc = std::abs(t) < 1e-8 ? 1.0 - t * t / 6.0 : std::sin(t) / t;
+  return len * sc * std::complex<double>(std::cos(t), std::sin(t));
+}
+
+void trial_transforms(int P, double L, int modes, double side, std::vector<zd>* fc,
+                      std::vector<zd>* fs) {
+  fc->resize((size_t)P * modes);
+  fs->resize((size_t)P * modes);
+  for (int j = 0; j < P; ++j) {
+    const int js = j <= P / 2 ? j : j - P;
+    const double alpha = -2.0 * M_PI * js / L;
+    for (int m = 0; m < modes; ++m) {
+      const double mu = M_PI * m / side;
+      const std::complex<double> ep = exp_int(alpha + mu, side), em = exp_int(alpha - mu, side);
+      const std::complex<double> c = 0.5 * (ep + em);
+      const std::complex<double> sn = (ep - em) / std::complex<double>(0.0, 2.0);
+      (*fc)[(size_t)j * modes + m] = cav::mk(c.real(), c.imag());
+      (*fs)[(size_t)j * modes + m] = cav::mk(sn.real(), sn.imag());
+    }
+  }
+}
+
+int build_spec(cavity_plan p) {
+  const cav::Geo& g = p->g;
+  const int M1 = g.M + 1, N1 = g.N + 1;
+  std::vector<zd> f1c, f1s, f2c, f2s;
+  trial_transforms(g.P1, g.P1 * g.hq1, M1, g.a, &f1c, &f1s);
+  trial_transforms(g.P2, g.P2 * g.hq2, N1, g.b, &f2c, &f2s);
+  const size_t n1 = (size_t)g.P1 * M1, n2 = (size_t)g.P2 * N1;
+  const size_t bytes = 2 * (n1 + n2) * sizeof(zd);
+  void* base = nullptr;
+  int s = arena_acquire(bytes, &base);
+  if (s) return s;
+  p->spec_arena = {base, bytes};
+  zd* d = static_cast<zd*>(base);
+  p->spec = {d, d + n1, d + 2 * n1, d + 2 * n1 + n2};
+  HIPCHK(hipMemcpy(d, f1c.data(), n1 * sizeof(zd), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d + n1, f1s.data(), n1 * sizeof(zd), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d + 2 * n1, f2c.data(), n2 * sizeof(zd), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d + 2 * n1 + n2, f2s.data(), n2 * sizeof(zd), hipMemcpyHostToDevice));
+  p->info.device_bytes += bytes;
+  return CAVITY_OK;
+}
+
 // Direct solve, plan part (the paper's Steps 1 and 3, Section 6): the aperture matrix A is
 // assembled column by column by applying the operator to unit vectors (the same TBC
 // convolutions and local blocks GMRES applies, in double precision), the entries of absent
@@ -1140,6 +1208,8 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
     return fail(CAVITY_EINVAL, "tol in (0,1), max_iter >= 1, restart in 1..200");
   if (o.batch < 1 || o.batch > 64) return fail(CAVITY_EINVAL, "batch must be in 1..64");
   if (o.direct < -1 || o.direct > 1) return fail(CAVITY_EINVAL, "direct must be -1, 0 or 1");
+  if (o.tbc_operator != CAVITY_TBC_TRAP && o.tbc_operator != CAVITY_TBC_SPEC)
+    return fail(CAVITY_EINVAL, "tbc_operator must be CAVITY_TBC_TRAP or CAVITY_TBC_SPEC");
   if (o.direct == 1 && 3LL * Nx * Ny > kDenseMax)
     return fail(CAVITY_EINVAL, "direct solve needs 3 Nx Ny <= " + std::to_string(kDenseMax));
   const int s = o.tbc_oversample;
@@ -1198,7 +1268,8 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   for (int l : fft_len) twn += l;
   const int nb0 = 1;
   const size_t need = plan_bytes(g, layered, chunk, (int)lnz.size(), &twn) +
-                      work_bytes(g, o.restart, nb0, dot_blocks(3LL * g.NM)) +
+                      work_bytes(g, o.restart, nb0, dot_blocks(3LL * g.NM),
+                                 o.tbc_operator == CAVITY_TBC_SPEC) +
                       3ull * g.NM * sizeof(zd);
   ps->g = g;
   ps->o = o;
@@ -1228,6 +1299,7 @@ int cavity_opts_default(cavity_opts* o) {
   o->stream = nullptr;
   o->batch = 8;
   o->direct = 0;
+  o->tbc_operator = CAVITY_TBC_TRAP;
   return CAVITY_OK;
 }
 
@@ -1433,6 +1505,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   if (!(p->info.min_pivot > 1e-13))
     return bail(fail(CAVITY_ERESONANT, "z-elimination pivot below 1e-13"));
   p->info.tbc_rows_in_place = p->g.rows_ip;
+  if (p->use_spec() && (st = build_spec(p))) return bail(st);
   if ((st = autotune_lds(p))) return bail(st);
   // CAVITY_TBC_ROWS_IP=0 or 1 fixes the form of the TBC row passes (after any tuning)
   if (const char* e = std::getenv("CAVITY_TBC_ROWS_IP")) {
@@ -1617,8 +1690,12 @@ int cavity_debug_tbc(cavity_plan p, int family, const cavity_c128* in, cavity_c1
   int s = ensure_work(p, 1);
   if (s) return s;
   HIPCHK(hipMemcpy(p->r, in, NM * sizeof(zd), hipMemcpyHostToDevice));
-  HIPCHK(cav::launch_single_family(p->g, p->trig, p->khat, family, p->r, p->X, p->Y, p->dbg_out,
-                                   p->st));
+  if (p->use_spec())
+    HIPCHK(cav::launch_spec_passes(p->g, p->spec, p->khat, nullptr, 0, family, 1, p->r, 0, p->X,
+                                   p->Y, p->U, p->dbg_out, nullptr, p->st));
+  else
+    HIPCHK(cav::launch_single_family(p->g, p->trig, p->khat, family, p->r, p->X, p->Y,
+                                     p->dbg_out, p->st));
   return copy_out(p, p->dbg_out, out, NM);
 }
 

@@ -114,6 +114,19 @@ hipError_t launch_rhs(const Geo& g, const Wave* waves, int nb, zd* b, hipStream_
 // y_r = A (P^{-1} v_r) when precond != 0, else y_r = A v_r, for r < nb with active[r] (or all
 // when active is null).  v_r = v + r vs, y_r = y + r ys.  X, Y: nb x 3 x (M+1) x P2 and
 // S: nb x 3 x NM workspaces.
+// Trial-function transforms of the spectral TBC operator (D_spec): F1 [P1][M+1] for the cos
+// and sin bases along x, F2 [P2][N+1] along y.
+struct SpecMats {
+  const zd *f1c, *f1s, *f2c, *f2s;
+};
+hipError_t launch_spec_passes(const Geo& g, const SpecMats& sm, const zd* khat, const zd* pinv,
+                              int precond, int fam_fixed, int nb, const zd* v, long long vs,
+                              zd* X, zd* Y, zd* U, zd* S, const int* active, hipStream_t st);
+hipError_t launch_operator_spec(const Geo& g, const SpecMats& sm, const zd* khat, const zd* rho_d,
+                                const zd* Tc, const zd* rho_n, const zd* pinv, int precond,
+                                int nb, const zd* v, long long vs, zd* X, zd* Y, zd* U, zd* S,
+                                zd* y, long long ys, const int* active, hipStream_t st);
+
 hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const zd* rho_d,
                            const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
                            const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y, long long ys,

@@ -454,6 +454,21 @@ static hipError_t operator_impl(const Geo& g, const Trig& t, const cx<T>* khat, 
   return hipGetLastError();
 }
 
+// The operator with the spectral single-layer operators (D_spec) in place of the
+// trapezoid ones; same epilogue.
+hipError_t launch_operator_spec(const Geo& g, const SpecMats& sm, const zd* khat, const zd* rho_d,
+                                const zd* Tc, const zd* rho_n, const zd* pinv, int precond,
+                                int nb, const zd* v, long long vs, zd* X, zd* Y, zd* U, zd* S,
+                                zd* y, long long ys, const int* active, hipStream_t st) {
+  hipError_t e = launch_spec_passes(g, sm, khat, pinv, precond, -1, nb, v, vs, X, Y, U, S,
+                                    active, st);
+  if (e != hipSuccess) return e;
+  const int blk = 256;
+  hipLaunchKernelGGL(k_operator_epilogue, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g,
+                     rho_d, Tc, rho_n, pinv, precond, v, vs, S, y, ys, active);
+  return hipGetLastError();
+}
+
 hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const zd* rho_d,
                            const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
                            const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y, long long ys,

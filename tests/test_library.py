@@ -145,3 +145,20 @@ def test_direct_option_validated_without_device():
         o.direct = val
         st, _ = _footprint(nx=nx, ny=ny, opts=o)
         assert st == want, (val, nx, ny, st)
+
+
+def test_tbc_operator_option_validated_without_device():
+    """tbc_operator takes CAVITY_TBC_TRAP (0, default) or CAVITY_TBC_SPEC (1); the spectral
+    operator's transforms and product workspace show in the footprint."""
+    lib = P.load_library()
+    o = P.Opts()
+    lib.cavity_opts_default(ctypes.byref(o))
+    assert o.tbc_operator == 0
+    st, trap = _footprint(opts=o)
+    assert st == 0
+    o.tbc_operator = 1
+    st, spec = _footprint(opts=o)
+    assert st == 0 and spec > trap
+    for bad in (2, -1):
+        o.tbc_operator = bad
+        assert _footprint(opts=o)[0] == 1

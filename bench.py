@@ -251,6 +251,9 @@ def main() -> int:
                     help="incidences the CPU oracle solves (0: all when at most 2, else 1)")
     ap.add_argument("--requests", type=int, default=2000, help="served stream: requests")
     ap.add_argument("--streams", type=int, default=4, help="served stream: concurrent requests")
+    ap.add_argument("--operator", choices=["trap", "spec"], default="trap",
+                    help="discrete TBC operator: trapezoid samples with FFT convolution, or "
+                         "exact trial transforms on the spectrum lattice (D_spec)")
     ap.add_argument("--direct", choices=["auto", "always", "never"], default="auto",
                     help="direct solve of the aperture system (inverse built once per plan, "
                          "in the warm-up; its time is reported as direct_factor_ms)")
@@ -303,7 +306,7 @@ def main() -> int:
             torch.cuda.synchronize()
             tp = time.perf_counter()
             plan = P.Plan.from_cavity(cav, precision=precision, tol=wl.tol, batch=batch,
-                                      direct=args.direct)
+                                      direct=args.direct, operator=args.operator)
             torch.cuda.synchronize()
             plan_ms.append(1e3 * (time.perf_counter() - tp))
             if len(plan_ms) < 2:
@@ -399,6 +402,7 @@ def main() -> int:
                      "reported as plan_ms; when the direct solve is taken, its inverse is "
                      "built once in the warm-up and its time reported as direct_factor_ms"),
             "direct": args.direct,
+            "tbc_operator": args.operator,
         },
         "latency_ms": {"p50": runs[head]["p50_ms"], "p99": runs[head]["p99_ms"],
                        "of": "one step"},

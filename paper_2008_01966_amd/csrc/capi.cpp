@@ -882,6 +882,21 @@ int build_spec(cavity_plan p) {
   HIPCHK(hipMemcpy(d + n1, f1s.data(), n1 * sizeof(zd), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(d + 2 * n1, f2c.data(), n2 * sizeof(zd), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(d + 2 * n1 + n2, f2s.data(), n2 * sizeof(zd), hipMemcpyHostToDevice));
+  // |F|^2 in the layouts of the preconditioner's diagonal contraction (pw1 [kind][m][j1],
+  // pw2 [kind][j2][n], kind 0 cos, 1 sin): the exact diagonal of D_spec's S^f
+  std::vector<double> w1(2 * n1), w2(2 * n2);
+  for (int j = 0; j < g.P1; ++j)
+    for (int m = 0; m < M1; ++m) {
+      w1[(size_t)m * g.P1 + j] = cav::cabs2(f1c[(size_t)j * M1 + m]);
+      w1[n1 + (size_t)m * g.P1 + j] = cav::cabs2(f1s[(size_t)j * M1 + m]);
+    }
+  for (int j = 0; j < g.P2; ++j)
+    for (int n = 0; n < N1; ++n) {
+      w2[(size_t)j * N1 + n] = cav::cabs2(f2c[(size_t)j * N1 + n]);
+      w2[n2 + (size_t)j * N1 + n] = cav::cabs2(f2s[(size_t)j * N1 + n]);
+    }
+  HIPCHK(hipMemcpy(p->pw1, w1.data(), w1.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p->pw2, w2.data(), w2.size() * sizeof(double), hipMemcpyHostToDevice));
   p->info.device_bytes += bytes;
   return CAVITY_OK;
 }
@@ -1486,12 +1501,20 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     return bail(CAVITY_EDEVICE);
   if ((st = mark(p, 1, true))) return bail(st);
   if ((st = mark(p, 2, false))) return bail(st);
-  if (!cached &&
-      (!chk(cav::launch_basis_power(g, p->trig, p->pw1, p->pw2, p->st), "basis power") ||
-       !chk(cav::launch_diag_contract(g, p->khat, p->pw1, p->pw2, p->ctmp, p->diag, p->st),
-            "diagonal")))
-    return bail(CAVITY_EDEVICE);
-  if (!cached) aperture_insert(g, o.tbc_oversample, p->khat, p->khat_f, p->diag, p->st);
+  if (p->use_spec()) {
+    // the spectral operator's own diagonal (the cache holds the trapezoid one)
+    if ((st = build_spec(p))) return bail(st);
+    if (!chk(cav::launch_diag_contract(g, p->khat, p->pw1, p->pw2, p->ctmp, p->diag, p->st),
+             "diagonal"))
+      return bail(CAVITY_EDEVICE);
+  } else {
+    if (!cached &&
+        (!chk(cav::launch_basis_power(g, p->trig, p->pw1, p->pw2, p->st), "basis power") ||
+         !chk(cav::launch_diag_contract(g, p->khat, p->pw1, p->pw2, p->ctmp, p->diag, p->st),
+              "diagonal")))
+      return bail(CAVITY_EDEVICE);
+    if (!cached) aperture_insert(g, o.tbc_oversample, p->khat, p->khat_f, p->diag, p->st);
+  }
   if (!chk(cav::launch_precond_build(g, p->rho_d, p->T, p->rho_n, p->diag, p->pinv, p->st),
            "preconditioner"))
     return bail(CAVITY_EDEVICE);
@@ -1505,7 +1528,6 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   if (!(p->info.min_pivot > 1e-13))
     return bail(fail(CAVITY_ERESONANT, "z-elimination pivot below 1e-13"));
   p->info.tbc_rows_in_place = p->g.rows_ip;
-  if (p->use_spec() && (st = build_spec(p))) return bail(st);
   if ((st = autotune_lds(p))) return bail(st);
   // CAVITY_TBC_ROWS_IP=0 or 1 fixes the form of the TBC row passes (after any tuning)
   if (const char* e = std::getenv("CAVITY_TBC_ROWS_IP")) {

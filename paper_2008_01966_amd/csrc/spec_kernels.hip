@@ -93,13 +93,91 @@ __global__ __launch_bounds__(256) void k_spec_gemm(int rows, int cols, int depth
     }
 }
 
+// The same product on the matrix cores: each wave of the block owns one 16 x 16 quarter of
+// the 32 x 32 output tile and accumulates it with v_mfma_f64_16x16x4f64, four real products
+// per complex step (re re - im im, re im + im re).  Operand layout of that instruction on
+// gfx950 (measured): lane l gives A(l mod 16, l div 16) and B(l div 16, l mod 16) and holds
+// D(l div 16 + 4 v, l mod 16) for v = 0..3.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_spec_gemm_mfma(int rows, int cols, int depth, int nf,
+                                                        int fam_fixed, SpecOperand A,
+                                                        SpecOperand B, SpecOut C,
+                                                        const zd* __restrict__ khat,
+                                                        long long khat_si, double kscale,
+                                                        const int* __restrict__ active) {
+  __shared__ zd As[kSpecT][kSpecK + 1];
+  __shared__ zd Bs[kSpecK][kSpecT + 1];
+  const int b = blockIdx.z;
+  const int rhs = b / nf, slot = b - rhs * nf;
+  if (active && !active[rhs]) return;
+  const int f = fam_fixed >= 0 ? fam_fixed : slot;
+  const zd* pa = A.base[f] + rhs * A.sr + slot * A.ss;
+  const zd* pb = B.base[f] + rhs * B.sr + slot * B.ss;
+  const int i0 = blockIdx.y * kSpecT, j0 = blockIdx.x * kSpecT;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wi = (wave >> 1) * 16, wj = (wave & 1) * 16;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4d cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < depth; k0 += kSpecK) {
+    for (int e = threadIdx.x; e < kSpecT * kSpecK; e += blockDim.x) {
+      const int ii = e / kSpecK, kk = e - ii * kSpecK;
+      const int i = i0 + ii, k = k0 + kk;
+      zd va = mk(0.0, 0.0);
+      if (i < rows && k < depth) {
+        va = pa[i * A.si + k * A.sk];
+        if (A.conj) va = conj(va);
+      }
+      As[ii][kk] = va;
+    }
+    for (int e = threadIdx.x; e < kSpecK * kSpecT; e += blockDim.x) {
+      const int kk = e / kSpecT, jj = e - kk * kSpecT;
+      const int k = k0 + kk, j = j0 + jj;
+      zd vb = mk(0.0, 0.0);
+      if (k < depth && j < cols) {
+        vb = pb[k * B.si + j * B.sk];
+        if (B.conj) vb = conj(vb);
+      }
+      Bs[kk][jj] = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kSpecK; ks += 4) {
+      const zd a = As[wi + lr][ks + lk];
+      const zd bv = Bs[ks + lk][wj + lr];
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, bv.re, cr, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, bv.im, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, bv.im, ci, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, bv.re, ci, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  zd* pc = C.base + rhs * C.sr + slot * C.ss;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + wi + lk + 4 * v, j = j0 + wj + lr;
+    if (i >= rows || j >= cols) continue;
+    zd r = mk(cr[v], ci[v]);
+    if (khat) r = kscale * (r * khat[i * khat_si + j]);
+    pc[i * C.si + j * C.sj] = r;
+  }
+}
+
 static hipError_t spec_gemm(int rows, int cols, int depth, int nb, int nf, int fam_fixed,
                             const SpecOperand& A, const SpecOperand& B, const SpecOut& C,
                             const zd* khat, long long khat_si, double kscale,
                             const int* active, hipStream_t st) {
+  static const bool mfma = [] {
+    const char* e = getenv("CAVITY_SPEC_MFMA");
+    return !(e && atoi(e) == 0);
+  }();
   const dim3 grid((cols + kSpecT - 1) / kSpecT, (rows + kSpecT - 1) / kSpecT, nb * nf);
-  hipLaunchKernelGGL(k_spec_gemm, grid, dim3(256), 0, st, rows, cols, depth, nf, fam_fixed, A,
-                     B, C, khat, khat_si, kscale, active);
+  if (mfma)
+    hipLaunchKernelGGL(k_spec_gemm_mfma, grid, dim3(256), 0, st, rows, cols, depth, nf, fam_fixed,
+                       A, B, C, khat, khat_si, kscale, active);
+  else
+    hipLaunchKernelGGL(k_spec_gemm, grid, dim3(256), 0, st, rows, cols, depth, nf, fam_fixed, A,
+                       B, C, khat, khat_si, kscale, active);
   return hipGetLastError();
 }
 

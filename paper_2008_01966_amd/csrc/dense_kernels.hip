@@ -15,6 +15,10 @@
 
 namespace cav {
 
+// Matrix-core complex product of the spectral-operator kernels (x_r = F p_r, F column-major).
+hipError_t launch_dense_product(const zd* F, long long n, const zd* p, int nb, zd* x,
+                                hipStream_t st);
+
 // x[r * n + i] = (i == k0 + r), r < nb: columns k0 .. k0 + nb - 1 of the identity.
 __global__ void k_unit_vectors(long long n, long long k0, int nb, zd* __restrict__ x) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -161,28 +165,7 @@ __global__ void k_dense_gather(const zd* __restrict__ b, const int* __restrict__
   pb[t] = b[r * n + perm[i]];
 }
 
-// x[r * n + i] = sum_k F[k * n + i] pb[r * n + k]: one row per lane, kDenseRhs right-hand
-// sides per thread (F read once per group of them).
-constexpr int kDenseRhs = 4;
-__global__ __launch_bounds__(64) void k_dense_apply(const zd* __restrict__ F, long long n,
-                                                    const zd* __restrict__ pb, int nb,
-                                                    zd* __restrict__ x) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int r0 = blockIdx.y * kDenseRhs;
-  const int nr = min(kDenseRhs, nb - r0);
-  if (i >= n) return;
-  zd acc[kDenseRhs];
-  for (int q = 0; q < kDenseRhs; ++q) acc[q] = mk(0.0, 0.0);
-#pragma unroll 4
-  for (long long k = 0; k < n; ++k) {
-    const zd f = F[k * n + i];
-#pragma unroll
-    for (int q = 0; q < kDenseRhs; ++q)
-      if (q < nr) acc[q] = acc[q] + f * pb[(long long)(r0 + q) * n + k];
-  }
-  for (int q = 0; q < nr; ++q) x[(long long)(r0 + q) * n + i] = acc[q];
-}
-
+// x_r = F (P b_r): gather by the row permutation, then the matrix-core product.
 hipError_t launch_dense_apply(const zd* F, const int* perm, long long n, const zd* b, int nb,
                               zd* pb, zd* x, hipStream_t st) {
   const long long tot = (long long)nb * n;
@@ -190,10 +173,7 @@ hipError_t launch_dense_apply(const zd* F, const int* perm, long long n, const z
                      perm, n, nb, pb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dense_apply,
-                     dim3((unsigned)((n + 63) / 64), (unsigned)((nb + kDenseRhs - 1) / kDenseRhs)),
-                     dim3(64), 0, st, F, n, pb, nb, x);
-  return hipGetLastError();
+  return launch_dense_product(F, n, pb, nb, x, st);
 }
 
 // x += y (total entries)

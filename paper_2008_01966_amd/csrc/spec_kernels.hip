@@ -181,6 +181,17 @@ static hipError_t spec_gemm(int rows, int cols, int depth, int nb, int nf, int f
   return hipGetLastError();
 }
 
+// x_r = F p_r for r < nb, with F column-major n x n (F[k n + i] = F(i, k)) and p, x stored
+// per right-hand side (p[r n + k]): computed as X^T = P^T F^T with the same matrix-core
+// product, every operand then read along its contiguous index.
+hipError_t launch_dense_product(const zd* F, long long n, const zd* p, int nb, zd* x,
+                                hipStream_t st) {
+  const SpecOperand A{{p, p, p}, 0, 0, n, 1, 0};   // (r, k) at r n + k
+  const SpecOperand B{{F, F, F}, 0, 0, n, 1, 0};   // (k, i) = F(i, k) at k n + i
+  const SpecOut C{x, 0, 0, n, 1};                  // (r, i) at r n + i
+  return spec_gemm(nb, (int)n, (int)n, 1, 1, 0, A, B, C, nullptr, 0, 0.0, nullptr, st);
+}
+
 // Family inputs on the mode grid: c_f = z1 (cs), z2 (sc), nu z1 - mu z2 (cc), z = P^{-1} v
 // when precond, else v.  out[rhs][slot][mn].
 __global__ void k_spec_input(Geo g, const zd* __restrict__ pinv, int precond, int fam_fixed,

@@ -56,6 +56,10 @@ cav::FftPlan make_fft_plan(int n) { return cav::plan_fft(n, cav::kMaxRadix); }
 // longest transform for at least one column.
 constexpr size_t kMaxLdsPerBlock = 160 * 1024;
 
+// Largest basis size for which the first Gram-Schmidt update and the second pass's dot
+// products share one pass over the basis (the dot kernel's group of vectors).
+constexpr int kFusedGsMax = 8;
+
 // Blocks per right-hand side of the fused update + norm pass of the Arnoldi step.
 constexpr int kNormBlocks = 1024;
 
@@ -577,9 +581,14 @@ int arnoldi_step(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipStream_t st) {
   const long long hstr = (long long)R * (R + 1);
   HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
                           nullptr, 0, kv.active, st));
-  HIPCHK(cav::launch_update(V, ldj, nv, hcol, hstr, p->w, n, nb, kv.active, st));
-  HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, p->h2, R + 1,
-                          hcol, hstr, kv.active, st));
+  if (nv <= kFusedGsMax) {   // one pass: update with hcol, dot products of the updated w
+    HIPCHK(cav::launch_update_dots(V, ldj, nv, R + 1, hcol, hstr, p->w, n, nb, p->dpart,
+                                   p->nblk_red, p->h2, R + 1, hcol, hstr, kv.active, st));
+  } else {
+    HIPCHK(cav::launch_update(V, ldj, nv, hcol, hstr, p->w, n, nb, kv.active, st));
+    HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, p->h2, R + 1,
+                            hcol, hstr, kv.active, st));
+  }
   HIPCHK(cav::launch_update_norm(V, ldj, nv, p->h2, R + 1, p->w, n, nb, p->dnpart, nblk_u,
                                  kv.active, st));
   HIPCHK(cav::launch_next_vector(p->g, kv, j, p->dnpart, nblk_u, p->w, vn, n, p->pinv, p->zb, nb,

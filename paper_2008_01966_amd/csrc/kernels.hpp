@@ -154,6 +154,16 @@ hipError_t launch_dots(const zd* V, long long ldj, int nv, int nvmax, const zd* 
 hipError_t launch_dots(const zf* V, long long ldj, int nv, int nvmax, const zd* w, long long n,
                        int nb, zd* partial, int nblk, zd* out, long long ostride, zd* acc,
                        long long astride, const int* active, hipStream_t st);
+// First update fused with the second pass's dot products (nv <= 8): w -= V h, then
+// out = V^H w (updated), also added into acc, as launch_dots writes them.
+hipError_t launch_update_dots(const zd* V, long long ldj, int nv, int nvmax, const zd* h,
+                              long long hstride, zd* w, long long n, int nb, zd* partial,
+                              int nblk, zd* out, long long ostride, zd* acc, long long astride,
+                              const int* active, hipStream_t st);
+hipError_t launch_update_dots(const zf* V, long long ldj, int nv, int nvmax, const zd* h,
+                              long long hstride, zd* w, long long n, int nb, zd* partial,
+                              int nblk, zd* out, long long ostride, zd* acc, long long astride,
+                              const int* active, hipStream_t st);
 hipError_t launch_update(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
                          zd* w, long long n, int nb, const int* active, hipStream_t st);
 hipError_t launch_update(const zf* V, long long ldj, int nv, const zd* h, long long hstride,

@@ -656,6 +656,110 @@ static hipError_t update_impl(const cx<VT>* V, long long ldj, int nv, const zd* 
   return hipGetLastError();
 }
 
+// First Gram-Schmidt update fused with the second pass's dot products, for nv <= kDotGroup
+// basis vectors: w_r -= sum_i h[r * hstride + i] V_i,r, then the per-block partial sums
+// of conj(V_i,r) w_r (updated w) in k_dots' layout, from the same loads of V (one pass
+// over the basis instead of two).
+template <typename VT>
+__global__ __launch_bounds__(256) void k_update_dots(const cx<VT>* __restrict__ V, long long ldj,
+                                                     int nv, int nvmax,
+                                                     const zd* __restrict__ h, long long hstride,
+                                                     zd* __restrict__ wall, long long n,
+                                                     zd* __restrict__ partial,
+                                                     const int* __restrict__ active) {
+  __shared__ zd hs[kDotGroup];
+  __shared__ zd red[kDotGroup][4];
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  if (threadIdx.x < nv) hs[threadIdx.x] = h[r * hstride + threadIdx.x];
+  __syncthreads();
+  zd* w = wall + r * n;
+  const cx<VT>* Vr = V + r * n;
+  zd acc[kDotGroup];
+  for (int t = 0; t < kDotGroup; ++t) acc[t] = mk(0.0, 0.0);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + (kDotUnroll - 1) * stride < n; i += kDotUnroll * stride) {
+    zd a[kDotUnroll];
+    cx<VT> v[kDotGroup][kDotUnroll];
+#pragma unroll
+    for (int u = 0; u < kDotUnroll; ++u) a[u] = w[i + u * stride];
+#pragma unroll
+    for (int t = 0; t < kDotGroup; ++t)
+      if (t < nv) {
+#pragma unroll
+        for (int u = 0; u < kDotUnroll; ++u) v[t][u] = Vr[t * ldj + i + u * stride];
+#pragma unroll
+        for (int u = 0; u < kDotUnroll; ++u) a[u] = a[u] - hs[t] * widen(v[t][u]);
+      }
+#pragma unroll
+    for (int u = 0; u < kDotUnroll; ++u) w[i + u * stride] = a[u];
+#pragma unroll
+    for (int t = 0; t < kDotGroup; ++t)
+      if (t < nv) {
+#pragma unroll
+        for (int u = 0; u < kDotUnroll; ++u) acc[t] = acc[t] + conj(widen(v[t][u])) * a[u];
+      }
+  }
+  for (; i < n; i += stride) {
+    cx<VT> v[kDotGroup];
+    zd a = w[i];
+#pragma unroll
+    for (int t = 0; t < kDotGroup; ++t)
+      if (t < nv) {
+        v[t] = Vr[t * ldj + i];
+        a = a - hs[t] * widen(v[t]);
+      }
+    w[i] = a;
+#pragma unroll
+    for (int t = 0; t < kDotGroup; ++t)
+      if (t < nv) acc[t] = acc[t] + conj(widen(v[t])) * a;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < kDotGroup; ++t) {
+    const zd sum = mk(wave_sum(acc[t].re), wave_sum(acc[t].im));
+    if (lane == 0) red[t][wv] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    const int t = threadIdx.x;
+    partial[((long long)r * nvmax + t) * gridDim.x + blockIdx.x] =
+        red[t][0] + red[t][1] + red[t][2] + red[t][3];
+  }
+}
+
+template <typename VT>
+static hipError_t update_dots_impl(const cx<VT>* V, long long ldj, int nv, int nvmax,
+                                   const zd* h, long long hstride, zd* w, long long n, int nb,
+                                   zd* partial, int nblk, zd* out, long long ostride, zd* acc,
+                                   long long astride, const int* active, hipStream_t st) {
+  if (nv < 1 || nv > kDotGroup) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_update_dots<VT>), dim3(nblk, nb), dim3(256), 0, st, V, ldj, nv, nvmax, h,
+                     hstride, w, n, partial, active);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_cols, dim3(nv, nb), dim3(256), 0, st, partial, nblk, nvmax, out,
+                     ostride, acc, astride, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_dots(const zd* V, long long ldj, int nv, int nvmax, const zd* h,
+                              long long hstride, zd* w, long long n, int nb, zd* partial,
+                              int nblk, zd* out, long long ostride, zd* acc, long long astride,
+                              const int* active, hipStream_t st) {
+  return update_dots_impl<double>(V, ldj, nv, nvmax, h, hstride, w, n, nb, partial, nblk, out,
+                                  ostride, acc, astride, active, st);
+}
+
+hipError_t launch_update_dots(const zf* V, long long ldj, int nv, int nvmax, const zd* h,
+                              long long hstride, zd* w, long long n, int nb, zd* partial,
+                              int nblk, zd* out, long long ostride, zd* acc, long long astride,
+                              const int* active, hipStream_t st) {
+  return update_dots_impl<float>(V, ldj, nv, nvmax, h, hstride, w, n, nb, partial, nblk, out,
+                                 ostride, acc, astride, active, st);
+}
+
 hipError_t launch_update(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
                          zd* w, long long n, int nb, const int* active, hipStream_t st) {
   return update_impl<double>(V, ldj, nv, h, hstride, w, n, nb, active, st);

@@ -56,9 +56,6 @@ __host__ __device__ inline cx<T> cvt(zd a) { return cx<T>{(T)a.re, (T)a.im}; }
 template <typename T>
 __host__ __device__ inline zd widen(cx<T> a) { return zd{(double)a.re, (double)a.im}; }
 
-// Logical block index of a 3D grid, renumbered so that each of the 8 XCDs (which receive
-// workgroups round-robin in linear dispatch order) runs one contiguous range of logical
-// blocks: neighbouring strips of an array then meet in the same L2.
 // Quotient and remainder by a runtime divisor d from a float reciprocal: (w + 1/2) / d lies
 // at least 1/(2 d) from an integer and the float rounding error is below (w + d) 2^-23 / d,
 // so the quotient is exact while w + d < 2^22 (a few instructions instead of an integer
@@ -73,13 +70,32 @@ struct DivBy {
 struct BlockId {
   int x, y, z;
 };
-__device__ inline BlockId xcd_block() {
+
+// Logical block index of a 3D grid, renumbered so that each of the 8 XCDs (which receive
+// workgroups round-robin in linear dispatch order) runs one contiguous range of logical
+// blocks: neighbouring strips of an array then meet in the same L2.
+__device__ inline int xcd_logical() {
   const int gx = gridDim.x, gy = gridDim.y;
   const int G = gx * gy * gridDim.z;
   const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
   const int q = G >> 3, r = G & 7, x = lin & 7;
-  const int l = x * q + (x < r ? x : r) + (lin >> 3);
+  return x * q + (x < r ? x : r) + (lin >> 3);
+}
+
+// Logical order with x fastest.
+__device__ inline BlockId xcd_block() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int l = xcd_logical();
   return BlockId{l % gx, (l / gx) % gy, l / (gx * gy)};
+}
+
+// Same ranges, with y and z running fastest: the blocks that share x (the same strip of a
+// table every (y, z) reads) run on one XCD, next to each other in dispatch order.
+__device__ inline BlockId xcd_block_x_slow() {
+  const int gy = gridDim.y, gyz = gridDim.y * gridDim.z;
+  const int l = xcd_logical();
+  const int x = l / gyz, t = l - x * gyz;
+  return BlockId{x, t % gy, t / gy};
 }
 
 }  // namespace cav

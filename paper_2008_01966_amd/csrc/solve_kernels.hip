@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
                                                       const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ cx<T> c0s[64];
-  const BlockId bid = xcd_block();
+  const BlockId bid = xcd_block_x_slow();   // the nb x 3 blocks of a strip share its K-hat columns
   const int rhs = bid.z;
   if (active && !active[rhs]) return;
   const zd* v = vall + rhs * vs;
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
                                                   const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ cx<T> c0s[64];
-  const BlockId bid = xcd_block();
+  const BlockId bid = xcd_block_x_slow();   // the nb x 3 blocks of a strip share its K-hat columns
   const int rhs = bid.z;
   if (active && !active[rhs]) return;
   const int nf = fam_fixed >= 0 ? 1 : 3;

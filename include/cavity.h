@@ -71,11 +71,19 @@ typedef struct {
 
 /* Layer stack, bottom to top (Section 4 and its closing remark for more layers).
  * layer_nz[i] >= 1 intervals of layer i with sum equal to Nz; eps_r[i] its relative
- * permittivity.  Interfaces sit on the z-grid nodes. */
+ * permittivity.  Interfaces sit on the z-grid nodes.
+ * layer_depth: NULL gives every layer the common step c / Nz (the paper's setting).
+ * Otherwise layer i is layer_depth[i] > 0 thick (the thicknesses sum to c within 1e-12 c,
+ * else CAVITY_EINVAL) with step layer_depth[i] / layer_nz[i], as Example 3 of Section 7
+ * gives its layers different interval counts.  The interface conditions of Section 4
+ * are then discretised with each one-sided difference over its own layer's step, and the
+ * aperture rows (Section 5) use the top layer's step.  The request server (below) builds
+ * its plans with the common step. */
 typedef struct {
   int n_layers;
   const int* layer_nz;        /* host, n_layers entries */
   const cavity_c128* eps_r;   /* host, n_layers entries */
+  const double* layer_depth;  /* host, n_layers entries, or NULL */
 } cavity_eps;
 
 /* Solver options; cavity_opts_default() fills the defaults listed here. */

@@ -14,6 +14,14 @@ are single-valued; at an interface the tangential-curl continuity (con41), (con5
     E1_{s-1} - 2 E1_s + E1_{s+1} = mu_m h (E3^+_s - E3^-_s)     (nu_n h for E2),
 with zero right side when the mode has no E3 partner (m = 0 or n = 0).
 
+Layers with their own steps (reading, beyond the paper's common h): the one-sided
+differences keep their own steps, h_lo below and h_up above the interface.  With
+q = h_up / h_lo the two interface rows become
+    E3_{s+1} - E3^+_s = q (E3^-_s - E3_{s-1}),
+    q E1_{s-1} - (1 + q) E1_s + E1_{s+1} = mu_m h_up (E3^+_s - E3^-_s),
+(the derivative rows multiplied by h_up), which are the rows above when q = 1; interior
+rows of layer l use h_l.
+
 The eliminated quantities (reading: the paper's r_JJ relation, generalised to layers) are
     E_{l,Nz-1} = rho_l E_{l,Nz} + tau_l E_{3,Nz},     E_{3,Nz-1} = rho_3 E_{3,Nz},
 and the profiles E_{l,j} = Pi_j E_{l,Nz} + (mu_m or nu_n) Theta_j E_{3,Nz},
@@ -73,7 +81,6 @@ def dense_e3_column(prob: Problem, m: int, n: int, e3_top: complex = 1.0):
     Returns (upper-side values at nodes 0..Nz, lower-side values at interface nodes)."""
     kinds = prob.node_kind()
     nvar, view, idx, layer_bot, layer_top = _e3_views(prob)
-    h2 = prob.h ** 2
     A = np.zeros((nvar, nvar), dtype=complex)
     rhs = np.zeros(nvar, dtype=complex)
     row = 0
@@ -95,7 +102,7 @@ def dense_e3_column(prob: Problem, m: int, n: int, e3_top: complex = 1.0):
             ell = kd[1]
             lam = prob.kappa2(ell) - prob.mu[m] ** 2 - prob.nu[n] ** 2
             put(row, ell, j - 1, 1.0)
-            put(row, ell, j, -2.0 + h2 * lam)
+            put(row, ell, j, -2.0 + prob.h_layer(ell) ** 2 * lam)
             put(row, ell, j + 1, 1.0)
             row += 1
         else:  # interface between layers lo and up
@@ -104,11 +111,12 @@ def dense_e3_column(prob: Problem, m: int, n: int, e3_top: complex = 1.0):
             A[row, idx[(j, "up")]] = prob.layer_eps[up]
             A[row, idx[(j, "lo")]] = -prob.layer_eps[lo]
             row += 1
-            # E3_{j+1} - E3^+_j = E3^-_j - E3_{j-1}   (con61, one-sided differences)
+            # E3_{j+1} - E3^+_j = q (E3^-_j - E3_{j-1})   (con61, one-sided differences)
+            q = prob.h_layer(up) / prob.h_layer(lo)
             put(row, up, j + 1, 1.0)
             put(row, up, j, -1.0)
-            put(row, lo, j, -1.0)
-            put(row, lo, j - 1, 1.0)
+            put(row, lo, j, -q)
+            put(row, lo, j - 1, q)
             row += 1
     assert row == nvar
     x = np.linalg.solve(A, rhs)
@@ -127,7 +135,6 @@ def dense_tangential_column(prob: Problem, m: int, n: int, comp: int,
     Returns values at nodes 0..Nz (node 0 is the Dirichlet zero)."""
     kinds = prob.node_kind()
     nz = prob.nz
-    h, h2 = prob.h, prob.h ** 2
     coupled = m >= 1 and n >= 1
     if coupled:
         e3_up, e3_lo = dense_e3_column(prob, m, n, e3_top)
@@ -149,14 +156,16 @@ def dense_tangential_column(prob: Problem, m: int, n: int, comp: int,
         if kd[0] == "interior":
             lam = prob.kappa2(kd[1]) - prob.mu[m] ** 2 - prob.nu[n] ** 2
             put(r, j - 1, 1.0)
-            put(r, j, -2.0 + h2 * lam)
+            put(r, j, -2.0 + prob.h_layer(kd[1]) ** 2 * lam)
             put(r, j + 1, 1.0)
         else:
-            put(r, j - 1, 1.0)
-            put(r, j, -2.0)
+            h_up = prob.h_layer(kd[2])
+            q = h_up / prob.h_layer(kd[1])
+            put(r, j - 1, q)
+            put(r, j, -1.0 - q)
             put(r, j + 1, 1.0)
             if coupled:
-                rhs[r] += factor * h * (e3_up[j] - e3_lo[j])
+                rhs[r] += factor * h_up * (e3_up[j] - e3_lo[j])
     vals = np.zeros(nz + 1, dtype=complex)
     if nz > 1:
         vals[1:nz] = np.linalg.solve(A, rhs)
@@ -188,7 +197,6 @@ class Columns:
 def eliminate(prob: Problem) -> Columns:
     kinds = prob.node_kind()
     nz = prob.nz
-    h2 = prob.h ** 2
     shape = (prob.M + 1, prob.N + 1)
     _, _, n3 = prob.masks()
     min_piv = np.inf
@@ -200,13 +208,16 @@ def eliminate(prob: Problem) -> Columns:
     for j in range(1, nz):
         kd = kinds[j]
         if kd[0] == "interior":
-            piv = alpha3[j] + (-2.0 + h2 * prob.lam(kd[1]))
+            piv = alpha3[j] + (-2.0 + prob.h_layer(kd[1]) ** 2 * prob.lam(kd[1]))
             min_piv = min(min_piv, float(np.abs(piv[n3]).min()))
             alpha3[j + 1] = -1.0 / piv
         else:
+            # E3_{j-1} = alpha_j E3^-, E3^- = r E3^+ and the derivative row give
+            # E3^+ = E3_{j+1} / (1 + q r (1 - alpha_j))
             lo, up = kd[1], kd[2]
             r = prob.layer_eps[up] / prob.layer_eps[lo]
-            piv = 1.0 + (1.0 - alpha3[j]) * r
+            q = prob.h_layer(up) / prob.h_layer(lo)
+            piv = 1.0 + (1.0 - alpha3[j]) * (q * r)
             min_piv = min(min_piv, float(np.abs(piv[n3]).min()))
             alpha3[j + 1] = 1.0 / piv
     rho_n = alpha3[nz].copy()
@@ -226,18 +237,22 @@ def eliminate(prob: Problem) -> Columns:
     bcoef = np.zeros((nz + 1,) + shape, dtype=complex)
     for j in range(1, nz):
         kd = kinds[j]
+        q = 1.0
         if kd[0] == "interior":
-            piv = alpha[j] + (-2.0 + h2 * prob.lam(kd[1]))
+            piv = alpha[j] + (-2.0 + prob.h_layer(kd[1]) ** 2 * prob.lam(kd[1]))
             f = 0.0
         else:
+            # q E_{j-1} - (1 + q) E_j + E_{j+1} = h_up (1 - r) E3^+ (times mu or nu)
             lo, up = kd[1], kd[2]
-            piv = alpha[j] - 2.0
-            f = prob.h * (1.0 - prob.layer_eps[up] / prob.layer_eps[lo]) * pi_n[j]
+            h_up = prob.h_layer(up)
+            q = h_up / prob.h_layer(lo)
+            piv = q * alpha[j] - (1.0 + q)
+            f = h_up * (1.0 - prob.layer_eps[up] / prob.layer_eps[lo]) * pi_n[j]
         mask = np.ones(shape, dtype=bool)
         mask[0, 0] = False
         min_piv = min(min_piv, float(np.abs(piv[mask]).min()))
         alpha[j + 1] = -1.0 / piv
-        bcoef[j + 1] = (f - bcoef[j]) / piv
+        bcoef[j + 1] = (f - q * bcoef[j]) / piv
     rho_d = alpha[nz].copy()
     T = bcoef[nz].copy()
     pi_d = np.zeros((nz + 1,) + shape, dtype=complex)

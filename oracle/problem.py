@@ -7,8 +7,12 @@ uniform z-grid before (dfE1M)), Section 4 (layers, interfaces on grid nodes), Se
 Readings (where the paper leaves a choice open):
 * M = Nx - 1 and N = Ny - 1 Fourier modes; the z-grid has Nz intervals, h = c / Nz, the
   aperture is node Nz (the paper's J+1) and the bottom node 0.
-* Layers share one h; interfaces sit on nodes (the paper's two-layer derivation assumes
-  a common h).  Layers are listed bottom to top.
+* Layers are listed bottom to top and interfaces sit on nodes.  By default every layer
+  has the common step h = c / Nz (the paper's two-layer derivation assumes one h).  With
+  layer thicknesses d_l given, layer l has its own step h_l = d_l / Nz_l (Example 3's
+  table assigns different interval counts to layers of different thickness); the
+  interface rows then weight the one-sided differences by their own steps (see
+  ``columns``), and h denotes the top layer's step, the one the aperture rows use.
 * TBC quadrature grid: s*Nx x s*Ny intervals on the aperture (s >= 1), trapezoid weights.
 * FFT box per axis: P = smallest 5-smooth integer >= ceil((side + R) / hq), L = P * hq,
   which keeps the kernel truncated at R from wrapping onto the aperture.
@@ -17,7 +21,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Tuple
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -47,10 +51,12 @@ class Problem:
     layer_eps: Tuple[complex, ...]
     k: float
     s: int = 1
+    layer_depth: Optional[Tuple[float, ...]] = None
     # derived
     M: int = field(init=False)
     N: int = field(init=False)
     h: float = field(init=False)
+    layer_h: Tuple[float, ...] = field(init=False)
 
     def __post_init__(self):
         if self.nx < 2 or self.ny < 2 or self.nz < 1:
@@ -61,12 +67,24 @@ class Problem:
         self.layer_eps = tuple(complex(v) for v in self.layer_eps)
         self.M = self.nx - 1
         self.N = self.ny - 1
-        self.h = self.c / self.nz
+        if self.layer_depth is None:
+            self.layer_h = tuple(self.c / self.nz for _ in self.layer_nz)
+        else:
+            d = tuple(float(v) for v in self.layer_depth)
+            if len(d) != len(self.layer_nz) or min(d) <= 0.0:
+                raise ValueError("layer_depth needs one positive thickness per layer")
+            if abs(sum(d) - self.c) > 1e-12 * self.c:
+                raise ValueError("layer thicknesses must sum to c")
+            self.layer_depth = d
+            self.layer_h = tuple(dl / nl for dl, nl in zip(d, self.layer_nz))
+        self.h = self.layer_h[-1]
 
     @classmethod
     def from_cavity(cls, cav) -> "Problem":
+        depth = getattr(cav, "layer_depth", None)
         return cls(cav.a, cav.b, cav.c, cav.nx, cav.ny, cav.nz, tuple(cav.layer_nz),
-                   tuple(cav.layer_eps), cav.k, cav.tbc_oversample)
+                   tuple(cav.layer_eps), cav.k, cav.tbc_oversample,
+                   None if depth is None else tuple(depth))
 
     # -- Fourier modes (Section 3, (E123F)) -------------------------------------------
     @property
@@ -137,6 +155,15 @@ class Problem:
             if ell < len(self.layer_nz) - 1:
                 kinds[start] = ("interface", ell, ell + 1)
         return kinds
+
+    def h_layer(self, ell: int) -> float:
+        """Grid step of layer ell."""
+        return self.layer_h[ell]
+
+    def z_nodes(self) -> np.ndarray:
+        """Heights of the nodes j = 0..Nz above the bottom."""
+        steps = np.concatenate([np.full(nl, hl) for nl, hl in zip(self.layer_nz, self.layer_h)])
+        return np.concatenate([[0.0], np.cumsum(steps)])
 
     def kappa2(self, ell: int) -> complex:
         """kappa^2 = k^2 eps_r in layer ell (non-magnetic medium)."""

@@ -24,7 +24,9 @@ div_Gamma(z x E)), the three aperture rows read (E = aperture values, node Nz):
 and the elimination replaces E_{l,Nz-1} by rho_l E_l + tau_l E3 (tau_3 = 0).  The G~, H~
 terms of Section 3 / Appendix A collapse to the sigma terms above after the integration
 by parts of Section 5.1 (the third TBC row carries the h that the printed (ENU33) omits,
-as its matrix form (ENU34) with I~3, I~4 shows).
+as its matrix form (ENU34) with I~3, I~4 shows).  With layers of their own steps, h in
+these rows is the top layer's step (the one-sided difference at the aperture lies in the
+top layer).
 """
 from __future__ import annotations
 
@@ -194,7 +196,7 @@ def assemble_full(prob: Problem, khat: np.ndarray, g1: np.ndarray, g2: np.ndarra
 
     Returns (A, b, index) where index maps (comp, m, n, j[, 'lo']) to a column."""
     kinds = prob.node_kind()
-    nz, h, h2, k2 = prob.nz, prob.h, prob.h ** 2, prob.k ** 2
+    nz, h, k2 = prob.nz, prob.h, prob.k ** 2   # h: the top layer's step (aperture rows)
     n1, n2, n3 = prob.masks()
     modes = {1: list(zip(*np.nonzero(n1))), 2: list(zip(*np.nonzero(n2))),
              3: list(zip(*np.nonzero(n3)))}
@@ -236,16 +238,19 @@ def assemble_full(prob: Problem, khat: np.ndarray, g1: np.ndarray, g2: np.ndarra
                 r = row[0]
                 kd = kinds[j]
                 key = lambda jj: None if jj == 0 else (comp, m, n, jj)  # noqa: E731
-                add(r, key(j - 1), 1.0)
                 add(r, key(j + 1), 1.0)
                 if kd[0] == "interior":
                     lam = prob.kappa2(kd[1]) - mu[m] ** 2 - nu[n] ** 2
-                    add(r, key(j), -2.0 + h2 * lam)
+                    add(r, key(j - 1), 1.0)
+                    add(r, key(j), -2.0 + prob.h_layer(kd[1]) ** 2 * lam)
                 else:
-                    add(r, key(j), -2.0)
+                    h_up = prob.h_layer(kd[2])
+                    q = h_up / prob.h_layer(kd[1])
+                    add(r, key(j - 1), q)
+                    add(r, key(j), -1.0 - q)
                     if m >= 1 and n >= 1:
-                        add(r, (3, m, n, j), -fac * h)
-                        add(r, (3, m, n, j, "lo"), fac * h)
+                        add(r, (3, m, n, j), -fac * h_up)
+                        add(r, (3, m, n, j, "lo"), fac * h_up)
                 row[0] += 1
     # normal column
     for (m, n) in modes[3]:
@@ -260,7 +265,7 @@ def assemble_full(prob: Problem, khat: np.ndarray, g1: np.ndarray, g2: np.ndarra
                 ell = kd[1]
                 lam = prob.kappa2(ell) - mu[m] ** 2 - nu[n] ** 2
                 add(r, e3key(m, n, ell, j - 1), 1.0)
-                add(r, e3key(m, n, ell, j), -2.0 + h2 * lam)
+                add(r, e3key(m, n, ell, j), -2.0 + prob.h_layer(ell) ** 2 * lam)
                 add(r, e3key(m, n, ell, j + 1), 1.0)
                 row[0] += 1
             else:
@@ -269,10 +274,11 @@ def assemble_full(prob: Problem, khat: np.ndarray, g1: np.ndarray, g2: np.ndarra
                 add(r, (3, m, n, j, "lo"), -prob.layer_eps[lo])
                 row[0] += 1
                 r = row[0]
+                q = prob.h_layer(up) / prob.h_layer(lo)
                 add(r, e3key(m, n, up, j + 1), 1.0)
                 add(r, e3key(m, n, up, j), -1.0)
-                add(r, e3key(m, n, lo, j), -1.0)
-                add(r, e3key(m, n, lo, j - 1), 1.0)
+                add(r, e3key(m, n, lo, j), -q)
+                add(r, e3key(m, n, lo, j - 1), q)
                 row[0] += 1
     # aperture rows with dense single-layer matrices
     shape = (prob.M + 1, prob.N + 1)

@@ -37,7 +37,7 @@ class C128(ctypes.Structure):
 
 class EpsStack(ctypes.Structure):
     _fields_ = [("n_layers", ctypes.c_int), ("layer_nz", ctypes.POINTER(ctypes.c_int)),
-                ("eps_r", ctypes.POINTER(C128))]
+                ("eps_r", ctypes.POINTER(C128)), ("layer_depth", ctypes.POINTER(ctypes.c_double))]
 
 
 class Opts(ctypes.Structure):
@@ -190,7 +190,7 @@ class Plan:
                  tol: float = 1e-12, restart: int = 60, max_iter: int = 400,
                  oversample: int = 1, hbm_budget: int = 0, stream: Optional[int] = None,
                  batch: int = 8, precision: str = "fp64", direct: str = "auto",
-                 operator: str = "trap"):
+                 operator: str = "trap", layer_depth: Optional[Sequence[float]] = None):
         lib = load_library()
         self._lib = lib
         self.a, self.b, self.c = float(a), float(b), float(c)
@@ -221,8 +221,15 @@ class Plan:
             nzs = (ctypes.c_int * len(layer_nz))(*[int(v) for v in layer_nz])
             epsv = (C128 * len(layer_eps))(*[C128(complex(e).real, complex(e).imag)
                                               for e in layer_eps])
-            self._keep = (nzs, epsv)
-            eps_p = ctypes.pointer(EpsStack(len(layer_nz), nzs, epsv))
+            stack = EpsStack(len(layer_nz), nzs, epsv)
+            depth = None
+            if layer_depth is not None:
+                depth = (ctypes.c_double * len(layer_depth))(*[float(v) for v in layer_depth])
+                stack.layer_depth = depth
+            self._keep = (nzs, epsv, depth)
+            eps_p = ctypes.pointer(stack)
+        elif layer_depth is not None:
+            raise ValueError("layer_depth needs layer_nz and layer_eps")
         handle = ctypes.c_void_p()
         _check(lib.cavity_plan_create(self.a, self.b, self.c, self.nx, self.ny, self.nz, eps_p,
                                       float(k), ctypes.byref(opts), ctypes.byref(handle)))
@@ -232,6 +239,8 @@ class Plan:
     @classmethod
     def from_cavity(cls, cav, **kw) -> "Plan":
         kw.setdefault("oversample", cav.tbc_oversample)
+        if getattr(cav, "layer_depth", None) is not None:
+            kw.setdefault("layer_depth", cav.layer_depth)
         return cls(cav.a, cav.b, cav.c, cav.nx, cav.ny, cav.nz, cav.layer_nz, cav.layer_eps,
                    cav.k, **kw)
 

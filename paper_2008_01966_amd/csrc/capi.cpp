@@ -238,6 +238,7 @@ struct cavity_plan_s {
   double *pivmin = nullptr, *dmin = nullptr;
   int* node_code = nullptr;
   zd *kappa2 = nullptr, *ratio = nullptr, *twiddles = nullptr;
+  double* hl = nullptr;   // grid step per layer
   cav::zf* twiddles_f = nullptr;
   cav::zf* khat_f = nullptr;   // single-precision spectrum for the mixed-precision inner solve
   double *pw1 = nullptr, *pw2 = nullptr;
@@ -354,7 +355,7 @@ size_t plan_bytes(const cav::Geo& g, bool layered, int chunk, int nlayers, int* 
   if (layered) L.add(&z, (size_t)(g.Nz + 1) * NM);
   L.add(&z, 9 * NM); L.add(&z, 3 * NM);
   L.add(&d, NM); L.add(&d, 1);
-  L.add(&i, g.Nz + 1); L.add(&z, nlayers); L.add(&z, nlayers);
+  L.add(&i, g.Nz + 1); L.add(&z, nlayers); L.add(&z, nlayers); L.add(&d, nlayers);
   L.add(&z, *twn);
   cav::zf* zf1 = nullptr;
   L.add(&zf1, *twn);
@@ -1207,6 +1208,7 @@ struct PlanSpec {
   cavity_opts o{};
   std::vector<int> lnz;
   std::vector<std::complex<double>> leps;
+  std::vector<double> lh;   // grid step of each layer
   bool layered = false;
   double R = 0.0;
   int chunk = 1;
@@ -1259,6 +1261,20 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
     lnz.push_back(Nz);
     leps.emplace_back(1.0, 0.0);
   }
+  // per-layer steps: common c / Nz unless the layer thicknesses are given
+  std::vector<double> lh(lnz.size(), c / Nz);
+  if (eps && eps->layer_depth) {
+    double dsum = 0.0;
+    for (size_t i = 0; i < lnz.size(); ++i) {
+      const double d = eps->layer_depth[i];
+      if (!(d > 0.0) || !std::isfinite(d))
+        return fail(CAVITY_EINVAL, "layer thicknesses must be positive and finite");
+      dsum += d;
+      lh[i] = d / lnz[i];
+    }
+    if (std::fabs(dsum - c) > 1e-12 * c)
+      return fail(CAVITY_EINVAL, "layer thicknesses must sum to c");
+  }
 
   cav::Geo g{};
   g.M = Nx - 1;
@@ -1271,7 +1287,7 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   g.ny = Ny;
   g.a = a;
   g.b = b;
-  g.h = c / Nz;
+  g.h = lh.back();   // the aperture rows use the top layer's step
   g.k = k;
   g.hq1 = a / g.nq1;
   g.hq2 = b / g.nq2;
@@ -1299,6 +1315,7 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   ps->o = o;
   ps->lnz = lnz;
   ps->leps = leps;
+  ps->lh = lh;
   ps->layered = layered;
   ps->R = R;
   ps->chunk = chunk;
@@ -1420,6 +1437,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   L.add(&p->node_code, Nz + 1);
   L.add(&p->kappa2, lnz.size());
   L.add(&p->ratio, lnz.size());
+  L.add(&p->hl, lnz.size());
   L.add(&p->twiddles, twn);
   L.add(&p->twiddles_f, twn);
   L.add(&p->khat_f, (size_t)g.P1 * g.P2);
@@ -1490,7 +1508,9 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
       !chk(hipMemcpyAsync(p->kappa2, kap.data(), kap.size() * sizeof(zd), hipMemcpyHostToDevice,
                           p->st), "layer upload") ||
       !chk(hipMemcpyAsync(p->ratio, rat.data(), rat.size() * sizeof(zd), hipMemcpyHostToDevice,
-                          p->st), "layer upload"))
+                          p->st), "layer upload") ||
+      !chk(hipMemcpyAsync(p->hl, ps.lh.data(), ps.lh.size() * sizeof(double),
+                          hipMemcpyHostToDevice, p->st), "layer upload"))
     return bail(CAVITY_EDEVICE);
 
   // spectrum (scaled for the unnormalised inverse FFT and the grid cell)
@@ -1503,7 +1523,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
        !chk(cav::launch_to_f32(p->khat, p->khat_f, (long long)g.P1 * g.P2, p->st), "spectrum")))
     return bail(CAVITY_EDEVICE);
   if ((st = mark(p, 0, true))) return bail(st);
-  cav::Layers ly{p->node_code, p->kappa2, p->ratio, layered ? 1 : 0};
+  cav::Layers ly{p->node_code, p->kappa2, p->ratio, p->hl, layered ? 1 : 0};
   if ((st = mark(p, 1, false))) return bail(st);
   if (!chk(cav::launch_elimination(g, ly, p->rho_d, p->T, p->rho_n, p->pi_d, p->theta_d, p->pi_n,
                                    p->pivmin, p->st), "elimination"))

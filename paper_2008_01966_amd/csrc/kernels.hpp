@@ -49,6 +49,7 @@ struct Layers {
   const int* node_code;   // per node j = 0..Nz: >= 0 interior of that layer, -(s+1) interface s
   const zd* kappa2;       // per layer: k^2 eps_r
   const zd* ratio;        // per interface: eps_upper / eps_lower
+  const double* h;        // per layer: grid step (interface s lies between layers s, s+1)
   int layered;            // 1 when there is at least one interface
 };
 

@@ -68,13 +68,15 @@ hipError_t launch_spectrum(const Geo& g, double R, double scale, zd* khat, hipSt
 // wavefront touches 64 consecutive modes (coalesced).
 //
 // E3 (Neumann bottom, E3_0 = E3_1): relation V(j-1) = alpha_j V(j) within a layer;
-//   interior node: alpha_{j+1} = -1 / (alpha_j - 2 + h^2 lambda_layer)
-//   interface node (derivative continuity with eps_up E3^+ = eps_lo E3^-):
-//                  alpha_{j+1} = 1 / (1 + (1 - alpha_j) eps_up / eps_lo)
+//   interior node: alpha_{j+1} = -1 / (alpha_j - 2 + h_l^2 lambda_l), h_l the layer's step
+//   interface node (derivative continuity with eps_up E3^+ = eps_lo E3^-, each one-sided
+//   difference over its own layer's step, q = h_up / h_lo):
+//                  alpha_{j+1} = 1 / (1 + (1 - alpha_j) q eps_up / eps_lo)
 // E1/E2 (Dirichlet bottom): E_{j-1} = alpha_j E_j + b_j E3_top (times mu_m or nu_n);
-//   interior: pivot alpha_j - 2 + h^2 lambda, no source;
-//   interface: pivot alpha_j - 2, source h (1 - eps_up/eps_lo) Pi3_s (tangential-curl
-//   continuity with one-sided differences).
+//   interior: pivot alpha_j - 2 + h_l^2 lambda_l, no source;
+//   interface: row q E_{j-1} - (1 + q) E_j + E_{j+1} = h_up (1 - eps_up/eps_lo) Pi3_s
+//   (tangential-curl continuity with one-sided differences): pivot q alpha_j - (1 + q),
+//   b_{j+1} = (source - q b_j) / pivot.  With one step everywhere q = 1.
 // rho = alpha_Nz, T = b_Nz; profiles by back-substitution from the aperture (value 1).
 // The up-sweep stores alpha_j in the profile slot j; the down-sweep overwrites it.
 // ---------------------------------------------------------------------------------
@@ -87,7 +89,6 @@ __global__ void k_elimination(Geo g, Layers ly, zd* __restrict__ rho_d, zd* __re
   const int m = mn / (g.N + 1), n = mn % (g.N + 1);
   const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
   const double mn2 = mu * mu + nu * nu;
-  const double h2 = g.h * g.h;
   const long long NM = g.NM;
   const int Nz = g.Nz;
   const bool has3 = (m >= 1 && n >= 1);
@@ -102,12 +103,15 @@ __global__ void k_elimination(Geo g, Layers ly, zd* __restrict__ rho_d, zd* __re
       zd piv;
       if (code >= 0) {
         const zd k2 = ly.kappa2[code];
+        const double h2 = ly.h[code] * ly.h[code];
         piv = mk(al.re - 2.0 + h2 * (k2.re - mn2), al.im + h2 * k2.im);
         al = cdiv(mk(-1.0, 0.0), piv);
       } else {
-        const zd r = ly.ratio[-code - 1];
+        const int s = -code - 1;
+        const double q = ly.h[s + 1] / ly.h[s];
+        const zd r = ly.ratio[s];
         const zd one_m = mk(1.0 - al.re, -al.im);
-        piv = mk(1.0, 0.0) + one_m * r;
+        piv = mk(1.0, 0.0) + one_m * (q * r);
         al = cdiv(mk(1.0, 0.0), piv);
       }
       pmin = fmin(pmin, sqrt(cabs2(piv)));
@@ -135,21 +139,26 @@ __global__ void k_elimination(Geo g, Layers ly, zd* __restrict__ rho_d, zd* __re
   for (int j = 1; j < Nz; ++j) {
     const int code = ly.node_code[j];
     zd piv, f = mk(0.0, 0.0);
+    double q = 1.0;
     if (code >= 0) {
       const zd k2 = ly.kappa2[code];
+      const double h2 = ly.h[code] * ly.h[code];
       piv = mk(al.re - 2.0 + h2 * (k2.re - mn2), al.im + h2 * k2.im);
     } else {
-      piv = mk(al.re - 2.0, al.im);
+      const int s = -code - 1;
+      const double h_up = ly.h[s + 1];
+      q = h_up / ly.h[s];
+      piv = mk(q * al.re - (1.0 + q), q * al.im);
       if (has3) {
-        const zd r = ly.ratio[-code - 1];
+        const zd r = ly.ratio[s];
         const zd p3 = pi_n[(long long)j * NM + mn];
-        f = g.h * (mk(1.0 - r.re, -r.im) * p3);
+        f = h_up * (mk(1.0 - r.re, -r.im) * p3);
       }
     }
     if (mn != 0) pmin = fmin(pmin, sqrt(cabs2(piv)));
     const zd inv = cdiv(mk(1.0, 0.0), piv);
     al = mk(-inv.re, -inv.im);
-    bb = (f - bb) * inv;
+    bb = (f - q * bb) * inv;
     pi_d[(long long)(j + 1) * NM + mn] = al;
     if (ly.layered) theta_d[(long long)(j + 1) * NM + mn] = bb;
   }

@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 def _mix():
     """Ten requests: the four small parity cavities, permittivity variants of two of them
     (same aperture, different columns), and a 48 x 48 x 16 lossy cavity."""
-    cases = W.small_cases()
+    cases = W.small_cases()[:4]       # the server builds its plans with the common step
     reqs = []
     for wl in cases:
         reqs.append((wl.cavity, wl.incidences[0]))

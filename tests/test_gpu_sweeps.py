@@ -2,7 +2,9 @@
 one plan per geometry, many incidences solved together without field output, RCS from the
 stored aperture solutions.  Each geometry: the GPU sweep against the oracle at two angles
 (1e-9 relative, both polarisations), the mixed-precision sweep against the double one
-(1e-8), and the phi = 0 mirror rule (the cross-polarised backscatter vanishes)."""
+(1e-8), and the phi = 0 mirror rule (the cross-polarised backscatter vanishes).  Example 3
+runs with both readings of its interval counts: one common step, and each layer with its
+own step."""
 import numpy as np
 import pytest
 
@@ -15,8 +17,9 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("make", [W.example1_sweep, W.example2_sweep, W.example3_sweep],
-                         ids=["example1", "example2", "example3"])
+@pytest.mark.parametrize("make", [W.example1_sweep, W.example2_sweep, W.example3_sweep,
+                                  W.example3_sweep_steps],
+                         ids=["example1", "example2", "example3", "example3_steps"])
 def test_sweep_against_oracle(make):
     import torch
     wl = make()

@@ -67,6 +67,15 @@ def test_invalid_layers_rejected():
     assert st == 1
 
 
+def test_invalid_layer_thickness_rejected():
+    nzs = (ctypes.c_int * 2)(3, 5)
+    eps = (P.C128 * 2)(P.C128(1, 0), P.C128(2, 0))
+    for depth in ((0.2, 0.2), (0.6, -0.1), (0.25, float("nan"))):   # c = 0.5
+        d = (ctypes.c_double * 2)(*depth)
+        st, h, msg = _create(nz=8, eps=ctypes.pointer(P.EpsStack(2, nzs, eps, d)))
+        assert st == 1 and not h.value and "thickness" in msg, depth
+
+
 def test_invalid_options_rejected():
     lib = P.load_library()
     o = P.Opts()

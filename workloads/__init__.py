@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -36,10 +36,14 @@ class Cavity:
     layer_eps: Tuple[complex, ...]
     k: float = TWO_PI
     tbc_oversample: int = 1
+    # thickness of each layer (sum c); None: every layer has the common step c / nz
+    layer_depth: Optional[Tuple[float, ...]] = None
 
     def __post_init__(self):
         if len(self.layer_nz) != len(self.layer_eps):
             raise ValueError("layer_nz and layer_eps differ in length")
+        if self.layer_depth is not None and len(self.layer_depth) != len(self.layer_nz):
+            raise ValueError("layer_depth and layer_nz differ in length")
 
 
 @dataclasses.dataclass(frozen=True)
@@ -149,6 +153,16 @@ def example3_sweep() -> Workload:
                     fields=False)
 
 
+def example3_sweep_steps() -> Workload:
+    """Example 3 with the other reading of its interval counts: the 2-wavelength bottom
+    layer with 1000 intervals (h = 1/500) and the 1-wavelength top layer with 2000
+    (h = 1/2000), each layer with its own step."""
+    cav = Cavity(1.0, 1.0, 3.0, 20, 20, 3000, (1000, 2000), (3.0 + 0.05j, 7.0 + 1.5j),
+                 layer_depth=(2.0, 1.0))
+    return Workload("example3_sweep_steps_1x1x3_20x20x1000+2000", cav, _sweep(180), batch=32,
+                    fields=False)
+
+
 @dataclasses.dataclass(frozen=True)
 class Request:
     arrival_s: float
@@ -202,6 +216,10 @@ def small_cases() -> List[Workload]:
                  Cavity(1.0, 1.0, 0.25, 20, 20, 9, (1, 2, 1, 5),
                         (3.0 + 0.2j, 1.5 + 0.0j, 5.0 + 2.0j, 1.0 + 0j)),
                  (Incidence(deg(45), deg(0), TE),)),
+        Workload("steps_1.2x1x0.5_24x20x12_2layer",
+                 Cavity(1.2, 1.0, 0.5, 24, 20, 12, (4, 8), (4.0 + 1.0j, 1.0 + 0j),
+                        layer_depth=(0.3, 0.2)),
+                 (Incidence(deg(40), deg(75), TM), Incidence(deg(40), deg(75), TE))),
     ]
     return cases
 
@@ -209,5 +227,5 @@ def small_cases() -> List[Workload]:
 def by_name(name: str) -> Workload:
     table = {w.name: w for w in [vacuum_1x1x05(), lossy_8x8x2(), layered_16x16x4(),
                                  batched_layered_8x8x2(), example1_sweep(), example2_sweep(),
-                                 example3_sweep()] + small_cases()}
+                                 example3_sweep(), example3_sweep_steps()] + small_cases()}
     return table[name]

@@ -61,6 +61,8 @@ enum {
 
 enum { CAVITY_FP64 = 0, CAVITY_MIXED = 1 };
 enum { CAVITY_TBC_TRAP = 0, CAVITY_TBC_SPEC = 1 };
+/* Evaluation of the kernel spectrum (cavity_opts.spectrum). */
+enum { CAVITY_SPECTRUM_EXACT = 0, CAVITY_SPECTRUM_ASYMPTOTIC = 1 };
 enum { CAVITY_TM = 0 /* theta-hat polarisation */, CAVITY_TE = 1 /* phi-hat */ };
 
 typedef struct cavity_plan_s* cavity_plan; /* opaque; owns all of its device memory */
@@ -118,6 +120,12 @@ typedef struct {
                            applied as four dense complex products per family in double
                            precision in both precision modes; its work grows as
                            P1 P2 (M + N) per family, so it suits small and mid-size cavities */
+  int spectrum;         /* kernel spectrum (Section 5.2): CAVITY_SPECTRUM_EXACT (default)
+                           integrates the radial J0 integral by quadrature at every lattice
+                           frequency rho; CAVITY_SPECTRUM_ASYMPTOTIC uses the paper's Case 2
+                           (two-term Hankel expansion of J0, Fresnel tails) where
+                           (rho - k) R >= 100, with an error below about 1e-8 of the
+                           spectrum's largest value, and the quadrature elsewhere */
 } cavity_opts;
 
 /* Plan description and the statistics of its last solve. */

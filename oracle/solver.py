@@ -27,10 +27,11 @@ class Plan:
     timers: Dict[str, float] = field(default_factory=dict)
 
 
-def plan(prob: Problem, operator: str = "trap") -> Plan:
-    """operator: the discrete TBC, "trap" (D_trap) or "spec" (D_spec)."""
+def plan(prob: Problem, operator: str = "trap", spectrum_method: str = "exact") -> Plan:
+    """operator: the discrete TBC, "trap" (D_trap) or "spec" (D_spec); spectrum_method:
+    "exact" (quadrature) or "asymptotic" (Case 2 of Section 5.2 at large frequencies)."""
     t0 = time.perf_counter()
-    khat = spectrum.kernel_spectrum(prob)
+    khat = spectrum.kernel_spectrum(prob, spectrum_method)
     t1 = time.perf_counter()
     cols = columns.eliminate(prob)
     op = system.ReducedSystem(prob, cols, khat, operator)

@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
                 ("hbm_budget", ctypes.c_size_t), ("stream", ctypes.c_void_p),
                 ("batch", ctypes.c_int), ("direct", ctypes.c_int),
-                ("tbc_operator", ctypes.c_int)]
+                ("tbc_operator", ctypes.c_int), ("spectrum", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -179,6 +179,8 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 DIRECT = {"auto": 0, "always": 1, "never": -1}
 # discrete TBC operator: trapezoid samples (D_trap) or exact trial transforms (D_spec)
 OPERATORS = {"trap": 0, "spec": 1}
+# kernel spectrum: quadrature everywhere, or the asymptotic (Case 2) form at large |xi|
+SPECTRA = {"exact": 0, "asymptotic": 1}
 
 
 class Plan:
@@ -190,7 +192,8 @@ class Plan:
                  tol: float = 1e-12, restart: int = 60, max_iter: int = 400,
                  oversample: int = 1, hbm_budget: int = 0, stream: Optional[int] = None,
                  batch: int = 8, precision: str = "fp64", direct: str = "auto",
-                 operator: str = "trap", layer_depth: Optional[Sequence[float]] = None):
+                 operator: str = "trap", layer_depth: Optional[Sequence[float]] = None,
+                 spectrum: str = "exact"):
         lib = load_library()
         self._lib = lib
         self.a, self.b, self.c = float(a), float(b), float(c)
@@ -207,6 +210,9 @@ class Plan:
         if operator not in OPERATORS:
             raise ValueError(f"operator must be one of {sorted(OPERATORS)}")
         opts.tbc_operator = OPERATORS[operator]
+        if spectrum not in SPECTRA:
+            raise ValueError(f"spectrum must be one of {sorted(SPECTRA)}")
+        opts.spectrum = SPECTRA[spectrum]
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         opts.precision = PRECISIONS[precision]

@@ -1089,7 +1089,7 @@ namespace {
 // copies from the entry may still be queued on other streams.
 struct ApertureEntry {
   double a, b, k;
-  int nx, ny, s, dev;
+  int nx, ny, s, method, dev;
   void* mem;
   size_t bytes;
   hipEvent_t ready;
@@ -1114,21 +1114,21 @@ size_t aperture_bytes(const cav::Geo& g) {
   return (size_t)g.P1 * g.P2 * (sizeof(zd) + sizeof(cav::zf)) + 3ull * g.NM * sizeof(zd);
 }
 
-bool aperture_match(const ApertureEntry& e, const cav::Geo& g, int s, int dev) {
+bool aperture_match(const ApertureEntry& e, const cav::Geo& g, int s, int method, int dev) {
   return e.dev == dev && e.a == g.a && e.b == g.b && e.k == g.k && e.nx == g.nx &&
-         e.ny == g.ny && e.s == s;
+         e.ny == g.ny && e.s == s && e.method == method;
 }
 
 // On a hit, queue copies of the cached spectrum, its single-precision copy and the
 // diagonal into the plan's arrays on stream st and return true.
-bool aperture_lookup(const cav::Geo& g, int s, zd* khat, cav::zf* khat_f, zd* diag,
+bool aperture_lookup(const cav::Geo& g, int s, int method, zd* khat, cav::zf* khat_f, zd* diag,
                      hipStream_t st) {
   if (aperture_cache_limit() == 0) return false;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return false;
   std::lock_guard<std::mutex> lk(g_ap_mu);
   for (ApertureEntry& e : g_ap) {
-    if (!aperture_match(e, g, s, dev)) continue;
+    if (!aperture_match(e, g, s, method, dev)) continue;
     const size_t nk = (size_t)g.P1 * g.P2;
     char* base = static_cast<char*>(e.mem);
     if (hipStreamWaitEvent(st, e.ready, 0) != hipSuccess ||
@@ -1146,7 +1146,7 @@ bool aperture_lookup(const cav::Geo& g, int s, zd* khat, cav::zf* khat_f, zd* di
 
 // Store a freshly computed aperture (queued on st after its computation).  Best effort:
 // any failure leaves the cache unchanged.
-void aperture_insert(const cav::Geo& g, int s, const zd* khat, const cav::zf* khat_f,
+void aperture_insert(const cav::Geo& g, int s, int method, const zd* khat, const cav::zf* khat_f,
                      const zd* diag, hipStream_t st) {
   const size_t limit = aperture_cache_limit();
   const size_t bytes = aperture_bytes(g);
@@ -1156,7 +1156,7 @@ void aperture_insert(const cav::Geo& g, int s, const zd* khat, const cav::zf* kh
   {
     std::lock_guard<std::mutex> lk(g_ap_mu);
     for (const ApertureEntry& e : g_ap)
-      if (aperture_match(e, g, s, dev)) return;   // another plan stored it meanwhile
+      if (aperture_match(e, g, s, method, dev)) return;   // another plan stored it meanwhile
   }
   void* mem = nullptr;
   if (hipMalloc(&mem, bytes) != hipSuccess) return;
@@ -1186,7 +1186,7 @@ void aperture_insert(const cav::Geo& g, int s, const zd* khat, const cav::zf* kh
       g_ap_bytes -= g_ap[lru].bytes;
       g_ap.erase(g_ap.begin() + lru);
     }
-    g_ap.push_back({g.a, g.b, g.k, g.nx, g.ny, s, dev, mem, bytes, ev, ++g_ap_clock});
+    g_ap.push_back({g.a, g.b, g.k, g.nx, g.ny, s, method, dev, mem, bytes, ev, ++g_ap_clock});
     g_ap_bytes += bytes;
   }
   if (!evict.empty()) {
@@ -1234,6 +1234,9 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
     return fail(CAVITY_EINVAL, "tol in (0,1), max_iter >= 1, restart in 1..200");
   if (o.batch < 1 || o.batch > 64) return fail(CAVITY_EINVAL, "batch must be in 1..64");
   if (o.direct < -1 || o.direct > 1) return fail(CAVITY_EINVAL, "direct must be -1, 0 or 1");
+  if (o.spectrum != CAVITY_SPECTRUM_EXACT && o.spectrum != CAVITY_SPECTRUM_ASYMPTOTIC)
+    return fail(CAVITY_EINVAL,
+                "spectrum must be CAVITY_SPECTRUM_EXACT or CAVITY_SPECTRUM_ASYMPTOTIC");
   if (o.tbc_operator != CAVITY_TBC_TRAP && o.tbc_operator != CAVITY_TBC_SPEC)
     return fail(CAVITY_EINVAL, "tbc_operator must be CAVITY_TBC_TRAP or CAVITY_TBC_SPEC");
   if (o.direct == 1 && 3LL * Nx * Ny > kDenseMax)
@@ -1341,6 +1344,7 @@ int cavity_opts_default(cavity_opts* o) {
   o->batch = 8;
   o->direct = 0;
   o->tbc_operator = CAVITY_TBC_TRAP;
+  o->spectrum = CAVITY_SPECTRUM_EXACT;
   return CAVITY_OK;
 }
 
@@ -1517,9 +1521,10 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   const double scale = 1.0 / (g.hq1 * g.hq2 * (double)g.P1 * (double)g.P2);
   int st = CAVITY_OK;
   if ((st = mark(p, 0, false))) return bail(st);
-  const bool cached = aperture_lookup(g, o.tbc_oversample, p->khat, p->khat_f, p->diag, p->st);
+  const bool cached =
+      aperture_lookup(g, o.tbc_oversample, o.spectrum, p->khat, p->khat_f, p->diag, p->st);
   if (!cached &&
-      (!chk(cav::launch_spectrum(g, R, scale, p->khat, p->st), "spectrum") ||
+      (!chk(cav::launch_spectrum(g, R, scale, o.spectrum, p->khat, p->st), "spectrum") ||
        !chk(cav::launch_to_f32(p->khat, p->khat_f, (long long)g.P1 * g.P2, p->st), "spectrum")))
     return bail(CAVITY_EDEVICE);
   if ((st = mark(p, 0, true))) return bail(st);
@@ -1542,7 +1547,8 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
          !chk(cav::launch_diag_contract(g, p->khat, p->pw1, p->pw2, p->ctmp, p->diag, p->st),
               "diagonal")))
       return bail(CAVITY_EDEVICE);
-    if (!cached) aperture_insert(g, o.tbc_oversample, p->khat, p->khat_f, p->diag, p->st);
+    if (!cached)
+      aperture_insert(g, o.tbc_oversample, o.spectrum, p->khat, p->khat_f, p->diag, p->st);
   }
   if (!chk(cav::launch_precond_build(g, p->rho_d, p->T, p->rho_n, p->diag, p->pinv, p->st),
            "preconditioner"))

@@ -80,7 +80,9 @@ bool g_probe_active();   // a kernel is being watched
 void probe_end(int id, hipStream_t st, double bytes);
 
 // ---- plan-time kernels ------------------------------------------------------------
-hipError_t launch_spectrum(const Geo& g, double R, double scale, zd* khat, hipStream_t st);
+// method 0: quadrature everywhere; 1: the asymptotic (Case 2) form where (rho - k) R >= 100
+hipError_t launch_spectrum(const Geo& g, double R, double scale, int method, zd* khat,
+                           hipStream_t st);
 hipError_t launch_elimination(const Geo& g, const Layers& ly, zd* rho_d, zd* T, zd* rho_n,
                               zd* pi_d, zd* theta_d, zd* pi_n, double* pivmin,
                               hipStream_t st);

@@ -30,22 +30,74 @@ __device__ inline zd exp_integral(double w, double len) {
   return mk(len * c * sinc, len * s * sinc);
 }
 
-__global__ void k_spectrum(Geo g, double R, double scale, zd* __restrict__ khat) {
+// Asymptotic form for large rho (Case 2 of Section 5.2).  With Z = rho R and a = k / rho,
+//   int_0^R J0(rho r) e^{ikr} dr = 1/sqrt(rho^2 - k^2) - sqrt(2/pi)/rho * T,
+// T the tail beyond Z of [cos(z - pi/4) z^{-1/2} + sin(z - pi/4) z^{-3/2} / 8] e^{iaz}
+// (two-term Hankel expansion of J0).  Splitting cos and sin into exponentials leaves
+// tails F(p) = int_Z^inf e^{ipz} z^{-1/2} dz and, by parts, int_Z^inf e^{iqz} z^{-3/2} dz
+// = 2 e^{iqZ}/sqrt(Z) + 2iq F(q); F(p) = sqrt(pi/(2|p|)) (1 - 2C(t) + i (1 - 2S(t))),
+// t = sqrt(2|p|Z/pi) (conjugated for p < 0), with the two-term asymptotic expansions of
+// the Fresnel integrals C, S.
+constexpr double kAsymptoticSwitch = 100.0;   // applies where (rho - k) R >= this
+
+__device__ inline zd fresnel_tail(double p, double Z) {
+  const double ap = fabs(p);
+  const double t = sqrt(2.0 * ap * Z / M_PI);
+  const double x = M_PI * t * t, x2 = x * x;
+  const double f = (1.0 - 3.0 / x2) / (M_PI * t);
+  const double gg = (1.0 - 15.0 / x2) / (M_PI * M_PI * t * t * t);
+  double sp, cp;
+  sincos(ap * Z, &sp, &cp);
+  const double amp = sqrt(M_PI / (2.0 * ap));
+  const double re = amp * (-2.0 * f * sp + 2.0 * gg * cp);
+  const double im = amp * (2.0 * f * cp + 2.0 * gg * sp);
+  return mk(re, p > 0 ? im : -im);
+}
+
+__device__ inline zd tail_32(double q, double Z) {
+  double s, c;
+  sincos(q * Z, &s, &c);
+  const double w = 2.0 / sqrt(Z);
+  const zd F = fresnel_tail(q, Z);
+  // 2 e^{iqZ}/sqrt(Z) + 2 i q F
+  return mk(w * c - 2.0 * q * F.im, w * s + 2.0 * q * F.re);
+}
+
+__device__ inline zd ghat_asymptotic(double rho, double k, double R) {
+  const double Z = rho * R, a = k / rho;
+  const double h = 0.70710678118654752440;   // cos(pi/4) = sin(pi/4)
+  const zd em = mk(h, -h), ep = mk(h, h);
+  const zd t1 = em * fresnel_tail(1.0 + a, Z), t2 = ep * fresnel_tail(a - 1.0, Z);
+  const zd d = em * tail_32(1.0 + a, Z) - ep * tail_32(a - 1.0, Z);
+  // T = (t1 + t2) / 2 + d / (16 i)
+  const zd T = mk(0.5 * (t1.re + t2.re) + d.im / 16.0, 0.5 * (t1.im + t2.im) - d.re / 16.0);
+  const double inf = 1.0 / sqrt(rho * rho - k * k);
+  const double c = sqrt(2.0 / M_PI) / rho;
+  return mk(0.5 * (inf - c * T.re), -0.5 * c * T.im);
+}
+
+__global__ void k_spectrum(Geo g, double R, double scale, int method, zd* __restrict__ khat) {
   const int u1 = blockIdx.y * blockDim.y + threadIdx.y;
   const int u2 = blockIdx.x * blockDim.x + threadIdx.x;
   if (u1 > g.P1 / 2 || u2 > g.P2 / 2) return;
   const double L1 = g.P1 * g.hq1, L2 = g.P2 * g.hq2;
   const double x1 = 2.0 * M_PI * u1 / L1, x2 = 2.0 * M_PI * u2 / L2;
   const double rho = sqrt(x1 * x1 + x2 * x2);
-  const int nt = (int)ceil(0.5 * (rho + g.k) * R) + 48;
-  double sr = 0.0, si = 0.0;
-  for (int i = 0; i < nt; ++i) {
-    const double ct = cospi((i + 0.5) / nt);
-    const zd e = exp_integral(g.k + rho * ct, R);
-    sr += e.re;
-    si += e.im;
+  zd val;
+  if (method == 1 && (rho - g.k) * R >= kAsymptoticSwitch) {
+    const zd v = ghat_asymptotic(rho, g.k, R);
+    val = mk(scale * v.re, scale * v.im);
+  } else {
+    const int nt = (int)ceil(0.5 * (rho + g.k) * R) + 48;
+    double sr = 0.0, si = 0.0;
+    for (int i = 0; i < nt; ++i) {
+      const double ct = cospi((i + 0.5) / nt);
+      const zd e = exp_integral(g.k + rho * ct, R);
+      sr += e.re;
+      si += e.im;
+    }
+    val = mk(scale * sr / (2.0 * nt), scale * si / (2.0 * nt));
   }
-  const zd val = mk(scale * sr / (2.0 * nt), scale * si / (2.0 * nt));
   const int i1a = u1, i1b = (g.P1 - u1) % g.P1;
   const int i2a = u2, i2b = (g.P2 - u2) % g.P2;
   khat[(long long)i1a * g.P2 + i2a] = val;
@@ -54,11 +106,12 @@ __global__ void k_spectrum(Geo g, double R, double scale, zd* __restrict__ khat)
   khat[(long long)i1b * g.P2 + i2b] = val;
 }
 
-hipError_t launch_spectrum(const Geo& g, double R, double scale, zd* khat, hipStream_t st) {
+hipError_t launch_spectrum(const Geo& g, double R, double scale, int method, zd* khat,
+                           hipStream_t st) {
   dim3 blk(64, 4);
   dim3 grd((g.P2 / 2 + 1 + blk.x - 1) / blk.x, (g.P1 / 2 + 1 + blk.y - 1) / blk.y);
   probe_begin(K_SPECTRUM, st);
-  hipLaunchKernelGGL(k_spectrum, grd, blk, 0, st, g, R, scale, khat);
+  hipLaunchKernelGGL(k_spectrum, grd, blk, 0, st, g, R, scale, method, khat);
   probe_end(K_SPECTRUM, st, sizeof(zd) * (double)g.P1 * g.P2);
   return hipGetLastError();
 }

@@ -80,6 +80,11 @@ def test_invalid_options_rejected():
     lib = P.load_library()
     o = P.Opts()
     lib.cavity_opts_default(ctypes.byref(o))
+    assert o.spectrum == 0
+    o.spectrum = 2
+    st, h, msg = _create(opts=o)
+    assert st == 1 and "spectrum" in msg
+    lib.cavity_opts_default(ctypes.byref(o))
     o.restart = 0
     assert _create(opts=o)[0] == 1
     lib.cavity_opts_default(ctypes.byref(o))

@@ -277,6 +277,76 @@ __device__ cx<T>* fft_lds(cx<T>* a, cx<T>* b, const FftPlan& p, const cx<T>* __r
   return in;
 }
 
+// The stage above with its outputs handed to `put(dst, pos, col, v)` (pos: output
+// position within transform col) instead of stored at out[(pos << lc) + col]: lets the
+// last stage of a transform apply a pointwise product or write global memory directly.
+template <int R, typename T, bool INV, class Put>
+__device__ inline void fft_stage_put(const cx<T>* __restrict__ in, cx<T>* dst, int n, int ns,
+                                     int lc, const cx<T>* __restrict__ tw, int tid, int nthr,
+                                     const Put& put) {
+  const int nb = n / R;
+  const int tstep = n / (ns * R);
+  const int total = nb << lc;
+  const int cmask = (1 << lc) - 1;
+  const int istride = nb << lc;
+  const float inv_ns = 1.0f / (float)ns;
+  for (int w = tid; w < total; w += nthr) {
+    const int j = w >> lc;
+    const int col = w & cmask;
+    const int q = (int)(((float)j + 0.5f) * inv_ns);
+    const int k = j - q * ns;
+    const cx<T>* ip = in + w;
+    cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = ip[r * istride];
+    if (ns > 1) {
+      const cx<T>* tp = tw + k * tstep;
+      const int step = k * tstep;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const cx<T> w2 = tp[(r - 1) * step];
+        v[r] = v[r] * (INV ? conj(w2) : w2);
+      }
+    }
+    Dft<R, T, INV>::run(v);
+    const int p0 = q * R * ns + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) put(dst, p0 + r * ns, col, v[r]);
+  }
+}
+
+// fft_lds whose last stage hands its outputs to `put` (see fft_stage_put) with dst the
+// buffer that stage would have written; ends with a barrier and returns dst.
+template <typename T, bool INV, int MAXR, class Put>
+__device__ cx<T>* fft_lds_put(cx<T>* a, cx<T>* b, const FftPlan& p, const cx<T>* __restrict__ tw,
+                              int tid, int nthr, int lc, const Put& put) {
+  int ns = 1;
+  cx<T>* in = a;
+  cx<T>* out = b;
+  for (int s = 0; s < p.nst; ++s) {
+    const int rdx = p.radix[s];
+    const bool last = s == p.nst - 1;
+    switch (rdx) {
+#define CAV_FFT_CASE_PUT(R)                                                              \
+  case R:                                                                                \
+    if constexpr (R <= MAXR) {                                                           \
+      if (last) fft_stage_put<R, T, INV>(in, out, p.n, ns, lc, tw, tid, nthr, put);      \
+      else fft_stage<R, T, INV>(in, out, p.n, ns, lc, tw, tid, nthr);                    \
+    }                                                                                    \
+    break;
+      CAV_FFT_RADICES(CAV_FFT_CASE_PUT)
+#undef CAV_FFT_CASE_PUT
+      default: break;
+    }
+    __syncthreads();
+    cx<T>* t = in;
+    in = out;
+    out = t;
+    ns *= rdx;
+  }
+  return in;
+}
+
 // In-place form of a Stockham stage for one LDS buffer: work item w < (n/R) 2^lc (at most
 // one per thread) loads its R inputs, applies the twiddles and the butterfly in registers,
 // the block synchronises, and the outputs overwrite the buffer.  Half the LDS of the

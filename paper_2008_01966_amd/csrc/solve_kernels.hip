@@ -179,6 +179,31 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
 }
 
 // Pass 2: columns k0 .. k0+Cb-1 of one family.
+// Last-stage output handlers of the column pass (see fft_lds_put).
+// dst[(k1 << lc) + c] = v * K-hat[k1][k0 + c] for the block's Cb live columns.
+template <typename T>
+struct SpectrumProduct {
+  const cx<T>* khat;   // K-hat + k0
+  int P2, Cb, lc;
+  __device__ void operator()(cx<T>* dst, int k1, int c, cx<T> v) const {
+    dst[(k1 << lc) + c] = c < Cb ? v * khat[(long long)k1 * P2 + c] : v;
+  }
+};
+
+// Y[m][k0 + c] = hq * (cosine: F / 2, sine: i F / 2) for m <= M and the live columns.
+template <typename T>
+struct ColumnStore {
+  cx<T>* Y;            // Y + k0
+  int P2, rows, Cb;
+  bool xcos;
+  T hq;
+  __device__ void operator()(cx<T>*, int m, int c, cx<T> F) const {
+    if (m >= rows || c >= Cb) return;
+    const cx<T> s = xcos ? (T)0.5 * F : (T)0.5 * mul_i(F);
+    Y[(long long)m * P2 + c] = hq * s;
+  }
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
                                                   const cx<T>* __restrict__ khat, int fam_fixed,
@@ -234,13 +259,18 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   }
   __syncthreads();
   cx<T>* r2 = o;
-  if (ip) fft_lds_ip<T, false, kMaxRadix>(o, box1.p, tw_b, tid, lc);
-  else r2 = fft_lds<T, false, kMaxRadix>(o, r, box1.p, tw_b, tid, nt, lc);
-  for (int w = tid; w < P << lc; w += nt) {
-    const int k1 = w >> lc, c = w & (C - 1);
-    if (c < Cb) r2[w] = r2[w] * khat[(long long)k1 * g.P2 + k0 + c];
+  if (ip) {
+    fft_lds_ip<T, false, kMaxRadix>(o, box1.p, tw_b, tid, lc);
+    for (int w = tid; w < P << lc; w += nt) {
+      const int k1 = w >> lc, c = w & (C - 1);
+      if (c < Cb) r2[w] = r2[w] * khat[(long long)k1 * g.P2 + k0 + c];
+    }
+    __syncthreads();
+  } else {
+    // the product with K-hat rides on the transform's last stage
+    r2 = fft_lds_put<T, false, kMaxRadix>(o, r, box1.p, tw_b, tid, nt, lc,
+                                          SpectrumProduct<T>{khat + k0, g.P2, Cb, lc});
   }
-  __syncthreads();
   cx<T>* r3 = r2;
   if (ip) fft_lds_ip<T, true, kMaxRadix>(r2, box1.p, tw_b, tid, lc);
   else r3 = fft_lds<T, true, kMaxRadix>(r2, (r2 == a) ? b : a, box1.p, tw_b, tid, nt, lc);
@@ -250,15 +280,19 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
     store_extension(o3, L, xcos, i, r3[w], lc, c);
   }
   __syncthreads();
-  cx<T>* r4 = o3;
-  if (ip) fft_lds_ip<T, false, kMaxRadix>(o3, ext1.p, tw_e, tid, lc);
-  else r4 = fft_lds<T, false, kMaxRadix>(o3, r3, ext1.p, tw_e, tid, nt, lc);
-  for (int w = tid; w < (g.M + 1) << lc; w += nt) {
-    const int m = w >> lc, c = w & (C - 1);
-    if (c >= Cb) continue;
-    const cx<T> F = r4[w];
-    const cx<T> s = xcos ? (T)0.5 * F : (T)0.5 * mul_i(F);
-    Y[(long long)m * g.P2 + k0 + c] = hq * s;
+  if (ip) {
+    fft_lds_ip<T, false, kMaxRadix>(o3, ext1.p, tw_e, tid, lc);
+    for (int w = tid; w < (g.M + 1) << lc; w += nt) {
+      const int m = w >> lc, c = w & (C - 1);
+      if (c >= Cb) continue;
+      const cx<T> F = o3[w];
+      const cx<T> s = xcos ? (T)0.5 * F : (T)0.5 * mul_i(F);
+      Y[(long long)m * g.P2 + k0 + c] = hq * s;
+    }
+  } else {
+    // the last stage writes the projected entries m = 0..M straight to Y
+    fft_lds_put<T, false, kMaxRadix>(o3, r3, ext1.p, tw_e, tid, nt, lc,
+                                     ColumnStore<T>{Y + k0, g.P2, g.M + 1, Cb, xcos, hq});
   }
 }
 

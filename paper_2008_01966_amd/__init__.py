@@ -406,7 +406,11 @@ class Server:
     def submit(self, cav, theta: float, phi: float, pol: int, out=None) -> int:
         """Queue cavity `cav` (a workloads.Cavity-like object) at one incidence; `out`: an
         optional complex128 device tensor of shape (3, Nz+1, Ny+1, Nx+1) for the field,
-        which must stay alive until wait() returns."""
+        which must stay alive until wait() returns.  The server's plans use the common
+        z-step, so a cavity with its own layer thicknesses is refused."""
+        if getattr(cav, "layer_depth", None) is not None:
+            raise ValueError("the request server does not take layer thicknesses; "
+                             "use Plan(layer_depth=...)")
         nzs = (ctypes.c_int * len(cav.layer_nz))(*[int(v) for v in cav.layer_nz])
         eps = (C128 * len(cav.layer_eps))(*[C128(complex(e).real, complex(e).imag)
                                             for e in cav.layer_eps])

@@ -176,3 +176,13 @@ def test_tbc_operator_option_validated_without_device():
     for bad in (2, -1):
         o.tbc_operator = bad
         assert _footprint(opts=o)[0] == 1
+
+
+def test_binding_validates_spectrum_and_thickness_arguments():
+    """The binding refuses an unknown spectrum method and layer thicknesses without a layer
+    stack before anything reaches the device."""
+    with pytest.raises(ValueError):
+        P.Plan(1.0, 1.0, 0.5, 16, 16, 8, stream=0, spectrum="hankel")
+    with pytest.raises(ValueError):
+        P.Plan(1.0, 1.0, 0.5, 16, 16, 8, stream=0, layer_depth=(0.5,))
+    assert P.SPECTRA == {"exact": 0, "asymptotic": 1}

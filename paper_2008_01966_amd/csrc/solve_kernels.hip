@@ -105,7 +105,9 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
                                                       const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ cx<T> c0s[64];
-  const BlockId bid = xcd_block_x_slow();   // the nb x 3 blocks of a strip share its K-hat columns
+  // strip-major order: the 3 family blocks of a row strip read the same aperture entries
+  // and preconditioner blocks, next to each other on one XCD
+  const BlockId bid = xcd_block_x_slow();
   const int rhs = bid.z;
   if (active && !active[rhs]) return;
   const zd* v = vall + rhs * vs;

@@ -675,7 +675,6 @@ int gmres_batch_t(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
   HIPCHK(hipMemsetAsync(x, 0, (size_t)nb * n * sizeof(zd), p->st));
   HIPCHK(cav::launch_norm2(p->bvec, n, nb, p->dnpart, p->nblk_red, kv.nrm2, nullptr, p->st));
   HIPCHK(cav::launch_krylov_init(kv, nb, p->st));
-  const int nblk_u = (int)std::min<long long>(kNormBlocks, (n + 255) / 256);
   int s;
   bool first = true;
   while (true) {
@@ -834,8 +833,7 @@ int rcs_queries(cavity_plan p, int n, const int* rhs, const double* th, const do
       e1 += std::complex<double>(pb[0].re, pb[0].im);
       e2 += std::complex<double>(pb[1].re, pb[1].im);
     }
-    const double st = std::sin(th[i]), ct = std::cos(th[i]), sp = std::sin(ph[i]),
-                 cp = std::cos(ph[i]);
+    const double ct = std::cos(th[i]), sp = std::sin(ph[i]), cp = std::cos(ph[i]);
     const std::complex<double> L1 = -e2, L2 = e1;
     const std::complex<double> phiL = -sp * L1 + cp * L2;
     const std::complex<double> thL = ct * cp * L1 + ct * sp * L2;

@@ -316,6 +316,15 @@ void release(cavity_plan p) {
   delete p;
 }
 
+// Wait for an event by polling it.  The waits of the Krylov loop last about one Arnoldi
+// step; a blocking wait's wake-up can cost far more than that.
+hipError_t poll_event(hipEvent_t ev) {
+  hipError_t q;
+  while ((q = hipEventQuery(ev)) == hipErrorNotReady) {
+  }
+  return q;
+}
+
 int mark(cavity_plan p, int phase, bool end) {
   HIPCHK(hipEventRecord(p->ev[2 * phase + (end ? 1 : 0)], p->st));
   if (end) p->ev_used[phase] = true;
@@ -656,9 +665,10 @@ int gmres_batch_t(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
   cav::Krylov& kv = p->kv;
   // How many Arnoldi steps the host may run ahead of the last convergence flags it has seen.
   constexpr int kLag = 1;
-  if ((int)p->poll_ev.size() < R) {
+  // one event per step, and one more for the waits at each cycle start and at the end
+  if ((int)p->poll_ev.size() < R + 1) {
     const size_t old = p->poll_ev.size();
-    p->poll_ev.resize(R, nullptr);
+    p->poll_ev.resize(R + 1, nullptr);
     for (size_t i = old; i < p->poll_ev.size(); ++i)
       HIPCHK(hipEventCreateWithFlags(&p->poll_ev[i], hipEventDisableTiming));
   }
@@ -692,7 +702,8 @@ int gmres_batch_t(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
     HIPCHK(cav::launch_cycle_start(kv, nb, p->opts.max_iter, inner, p->st));
     HIPCHK(hipMemcpyAsync(hstat, kv.active, nb * sizeof(int), hipMemcpyDeviceToHost, p->st));
     HIPCHK(hipMemcpyAsync(hstat + nb, kv.iters, nb * sizeof(int), hipMemcpyDeviceToHost, p->st));
-    HIPCHK(hipStreamSynchronize(p->st));
+    HIPCHK(hipEventRecord(p->poll_ev[R], p->st));
+    HIPCHK(poll_event(p->poll_ev[R]));
     bool any = false;
     int budget = R;
     for (int r = 0; r < nb; ++r)
@@ -745,7 +756,7 @@ int gmres_batch_t(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
           wait = all;
         }
         if (wait) {
-          HIPCHK(hipEventSynchronize(p->poll_ev[seen]));
+          HIPCHK(poll_event(p->poll_ev[seen]));
         } else {
           const hipError_t q = hipEventQuery(p->poll_ev[seen]);
           if (q == hipErrorNotReady) break;
@@ -771,7 +782,8 @@ int gmres_batch_t(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
   std::vector<int> iters(nb);
   HIPCHK(hipMemcpyAsync(p->hn, kv.relres, nb * sizeof(double), hipMemcpyDeviceToHost, p->st));
   HIPCHK(hipMemcpyAsync(hstat, kv.iters, nb * sizeof(int), hipMemcpyDeviceToHost, p->st));
-  HIPCHK(hipStreamSynchronize(p->st));
+  HIPCHK(hipEventRecord(p->poll_ev[R], p->st));
+  HIPCHK(poll_event(p->poll_ev[R]));
   for (int r = 0; r < nb; ++r) {
     relres[r] = p->hn[r];
     iters[r] = hstat[r];

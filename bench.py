@@ -254,6 +254,9 @@ def main() -> int:
     ap.add_argument("--operator", choices=["trap", "spec"], default="trap",
                     help="discrete TBC operator: trapezoid samples with FFT convolution, or "
                          "exact trial transforms on the spectrum lattice (D_spec)")
+    ap.add_argument("--spectrum", choices=["exact", "asymptotic"], default="exact",
+                    help="kernel spectrum at plan time: quadrature everywhere, or the "
+                         "large-frequency asymptotic form where it applies")
     ap.add_argument("--direct", choices=["auto", "always", "never"], default="auto",
                     help="direct solve of the aperture system (inverse built once per plan, "
                          "in the warm-up; its time is reported as direct_factor_ms)")
@@ -306,7 +309,8 @@ def main() -> int:
             torch.cuda.synchronize()
             tp = time.perf_counter()
             plan = P.Plan.from_cavity(cav, precision=precision, tol=wl.tol, batch=batch,
-                                      direct=args.direct, operator=args.operator)
+                                      direct=args.direct, operator=args.operator,
+                                      spectrum=args.spectrum)
             torch.cuda.synchronize()
             plan_ms.append(1e3 * (time.perf_counter() - tp))
             if len(plan_ms) < 2:
@@ -403,6 +407,8 @@ def main() -> int:
                      "built once in the warm-up and its time reported as direct_factor_ms"),
             "direct": args.direct,
             "tbc_operator": args.operator,
+            "spectrum": args.spectrum,
+            "layer_depth": None if cav.layer_depth is None else list(cav.layer_depth),
         },
         "latency_ms": {"p50": runs[head]["p50_ms"], "p99": runs[head]["p99_ms"],
                        "of": "one step"},

@@ -209,7 +209,7 @@ struct ColumnStore {
 template <typename T>
 __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
                                                   const cx<T>* __restrict__ khat, int fam_fixed,
-                                                  int lc, int ip, const cx<T>* __restrict__ Xall,
+                                                  int lc, const cx<T>* __restrict__ Xall,
                                                   cx<T>* __restrict__ Yall,
                                                   const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
@@ -227,9 +227,9 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   const int k0 = bid.x << lc;
   const int Cb = min(C, g.P2 - k0);
   const int L = g.nq1, P = g.P1;
-  // ping-pong: two buffers of P; in place: the extension transforms' 2L, then the box's P
+  // two ping-pong buffers of P (> 2L) entries per column
   cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* b = a + ((long long)(ip ? 2 * L : P) << lc);
+  cx<T>* b = a + ((long long)P << lc);
   const bool xcos = fam_xcos(f);
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk<T>(0, 0);
@@ -244,9 +244,7 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   __syncthreads();
   const cx<T>* tw_e = twiddles<T>(ext1);
   const cx<T>* tw_b = twiddles<T>(box1);
-  cx<T>* r = a;
-  if (ip) fft_lds_ip<T, false, kMaxRadix>(a, ext1.p, tw_e, tid, lc);
-  else r = fft_lds<T, false, kMaxRadix>(a, b, ext1.p, tw_e, tid, nt, lc);
+  cx<T>* r = fft_lds<T, false, kMaxRadix>(a, b, ext1.p, tw_e, tid, nt, lc);
   cx<T>* o = (r == a) ? b : a;
   const T hq = (T)g.hq1;
   for (int w = tid; w < P << lc; w += nt) {
@@ -260,42 +258,19 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
     o[w] = val;
   }
   __syncthreads();
-  cx<T>* r2 = o;
-  if (ip) {
-    fft_lds_ip<T, false, kMaxRadix>(o, box1.p, tw_b, tid, lc);
-    for (int w = tid; w < P << lc; w += nt) {
-      const int k1 = w >> lc, c = w & (C - 1);
-      if (c < Cb) r2[w] = r2[w] * khat[(long long)k1 * g.P2 + k0 + c];
-    }
-    __syncthreads();
-  } else {
-    // the product with K-hat rides on the transform's last stage
-    r2 = fft_lds_put<T, false, kMaxRadix>(o, r, box1.p, tw_b, tid, nt, lc,
-                                          SpectrumProduct<T>{khat + k0, g.P2, Cb, lc});
-  }
-  cx<T>* r3 = r2;
-  if (ip) fft_lds_ip<T, true, kMaxRadix>(r2, box1.p, tw_b, tid, lc);
-  else r3 = fft_lds<T, true, kMaxRadix>(r2, (r2 == a) ? b : a, box1.p, tw_b, tid, nt, lc);
+  // the product with K-hat rides on the transform's last stage
+  cx<T>* r2 = fft_lds_put<T, false, kMaxRadix>(o, r, box1.p, tw_b, tid, nt, lc,
+                                               SpectrumProduct<T>{khat + k0, g.P2, Cb, lc});
+  cx<T>* r3 = fft_lds<T, true, kMaxRadix>(r2, (r2 == a) ? b : a, box1.p, tw_b, tid, nt, lc);
   cx<T>* o3 = (r3 == a) ? b : a;
   for (int w = tid; w < (L + 1) << lc; w += nt) {
     const int i = w >> lc, c = w & (C - 1);
     store_extension(o3, L, xcos, i, r3[w], lc, c);
   }
   __syncthreads();
-  if (ip) {
-    fft_lds_ip<T, false, kMaxRadix>(o3, ext1.p, tw_e, tid, lc);
-    for (int w = tid; w < (g.M + 1) << lc; w += nt) {
-      const int m = w >> lc, c = w & (C - 1);
-      if (c >= Cb) continue;
-      const cx<T> F = o3[w];
-      const cx<T> s = xcos ? (T)0.5 * F : (T)0.5 * mul_i(F);
-      Y[(long long)m * g.P2 + k0 + c] = hq * s;
-    }
-  } else {
-    // the last stage writes the projected entries m = 0..M straight to Y
-    fft_lds_put<T, false, kMaxRadix>(o3, r3, ext1.p, tw_e, tid, nt, lc,
-                                     ColumnStore<T>{Y + k0, g.P2, g.M + 1, Cb, xcos, hq});
-  }
+  // the last stage writes the projected entries m = 0..M straight to Y
+  fft_lds_put<T, false, kMaxRadix>(o3, r3, ext1.p, tw_e, tid, nt, lc,
+                                   ColumnStore<T>{Y + k0, g.P2, g.M + 1, Cb, xcos, hq});
 }
 
 // Pass 3: rows m0 .. m0+Cb-1 backward; writes S[slot][mn] in double.
@@ -454,11 +429,13 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
   probe_end(id_fwd, st, vin + xbytes);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // the column pass has only the two-buffer form (its last stages carry the K-hat product
+  // and the store to Y)
   const TbcShape sc =
       tbc_shape(t.ext1.p, t.box1.p, g.nq1, g.P1, (int)tb, g.P2, g.lds_budget, false);
   probe_begin(id_cols, st);
   hipLaunchKernelGGL((k_tbc_cols<T>), dim3((g.P2 + (1 << sc.lc) - 1) >> sc.lc, nf, nb), dim3(256),
-                     sc.smem, st, g, t.ext1, t.box1, khat, fam_fixed, sc.lc, sc.ip, X, Y, active);
+                     sc.smem, st, g, t.ext1, t.box1, khat, fam_fixed, sc.lc, X, Y, active);
   probe_end(id_cols, st, 2.0 * xbytes + tb * (double)g.P1 * g.P2);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -31,3 +31,16 @@ def test_served_stream_reproducible():
 
 def test_next_5smooth():
     assert [next_5smooth(n) for n in (1, 7, 39, 618, 1237, 928)] == [1, 8, 40, 625, 1250, 960]
+
+
+def test_example3_readings_differ_only_in_the_step_assignment():
+    """Both readings of Example 3's interval counts: 2000 + 1000 intervals of one step, or
+    1000 + 2000 with each layer's own step (bottom 2 wavelengths, top 1)."""
+    from oracle.problem import Problem
+    one = Problem.from_cavity(W.example3_sweep().cavity)
+    own = Problem.from_cavity(W.example3_sweep_steps().cavity)
+    assert one.nz == own.nz == 3000 and one.c == own.c == 3.0
+    assert one.layer_h == (1e-3, 1e-3)
+    assert own.layer_h == (2.0 / 1000, 1.0 / 2000)
+    assert own.h == 1.0 / 2000 and one.h == 1e-3       # aperture rows: the top layer's step
+    assert one.layer_eps == own.layer_eps and (one.M, one.N) == (own.M, own.N)

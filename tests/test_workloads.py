@@ -36,7 +36,6 @@ def test_next_5smooth():
 def test_example3_readings_differ_only_in_the_step_assignment():
     """Both readings of Example 3's interval counts: 2000 + 1000 intervals of one step, or
     1000 + 2000 with each layer's own step (bottom 2 wavelengths, top 1)."""
-    from oracle.problem import Problem
     one = Problem.from_cavity(W.example3_sweep().cavity)
     own = Problem.from_cavity(W.example3_sweep_steps().cavity)
     assert one.nz == own.nz == 3000 and one.c == own.c == 3.0

@@ -167,3 +167,42 @@ def test_divergence_free_interior():
             w = max(w, np.abs(d[low]).max() / ref)
         worst.append(w)
     assert worst[-1] < 0.02 and worst[0] / worst[-1] > 3.0, worst
+
+
+def _direct_sum(prob, grid, comp):
+    """Field of one component on the nodes from its mode values by the plain double sum
+    of (E123F): cos(mu x) sin(nu y), sin(mu x) cos(nu y) or sin(mu x) sin(nu y)."""
+    x1 = np.arange(prob.nx + 1) * prob.a / prob.nx
+    x2 = np.arange(prob.ny + 1) * prob.b / prob.ny
+    f1 = np.cos if comp == 0 else np.sin
+    f2 = np.cos if comp == 1 else np.sin
+    out = np.zeros((prob.ny + 1, prob.nx + 1), dtype=complex)
+    for m in range(prob.M + 1):
+        for n in range(prob.N + 1):
+            if grid[m, n] != 0:
+                out += grid[m, n] * np.outer(f2(prob.nu[n] * x2), f1(prob.mu[m] * x1))
+    return out
+
+
+@pytest.mark.parametrize("case", [1, 3, 4])
+def test_field_synthesis_against_full_system(case):
+    """fields.synthesize (through solver.field_out) at every z-level equals the full
+    discrete system's mode values summed on the nodes.  The layered cases have nonzero
+    Theta, so the mu / nu factors of its E3 term in E1 and E2 are exercised (the grids
+    are not square, so a swap changes the result); E3 at an interface is the upper-side
+    value and E3 at node 0 the bottom value of the full system."""
+    wl = W.small_cases()[case]
+    prob = _prob(wl)
+    pl = solver.plan(prob)
+    assert np.abs(pl.cols.theta_d).max() > 0.0
+    inc = wl.incidences[0]
+    g1, g2 = incident.rhs(prob, inc.theta, inc.phi, inc.pol)
+    full, _, _, _ = system.solve_full(prob, pl.khat, g1, g2)
+    sol = solver.solve(pl, inc.theta, inc.phi, inc.pol, dense=True)
+    got = solver.field_out(pl, sol)
+    assert got.shape == (3, prob.nz + 1, prob.ny + 1, prob.nx + 1)
+    scale = np.abs(got).max()
+    for comp in range(3):
+        for j in range(prob.nz + 1):
+            ref = _direct_sum(prob, full[comp][j], comp)
+            assert np.abs(got[comp, j] - ref).max() <= 1e-11 * scale, (comp, j)

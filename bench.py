@@ -9,13 +9,19 @@ reported on its own as plan_ms.
 
 value = unknowns solved per second = steps * incidences * n_ap * Nz / wall time.
 
-The default workload is the 8 x 8 x 2 wavelength cavity filled with eps_r = 4+1i on a
-256 x 256 x 64 grid (h = lambda/32), incidence theta = 30 deg, phi = 45 deg, both
-polarisations.  Inputs are synthetic (the paper's workloads are geometries, not data).
+The default workload is the batched layered cavity: 8 x 8 x 2 wavelengths, three layers
+(eps_r = 4+1i, 2.5+0.5i, 1 over 25 / 50 / 25 % of the depth), 256 x 256 x 64 grid, 128
+right-hand sides (8 theta in [0, 80 deg] x 8 phi x 2 polarisations) solved to 1e-10.  It
+runs in double precision and then in mixed precision (the headline), and the two fields are
+compared.  A prefix of the served stream (random cavities of 2-12 wavelengths, Poisson
+arrivals at 40/s, replayed in real time through the library's request server) gives the
+p50/p99 latency of the same JSON line.  Inputs are synthetic (the paper's workloads are
+geometries, not data).
 
 Also reported: the average-launch roofline of the dominant kernel (timed with HIP events on
 its launch stream through the library's probe) and the CPU oracle timed on the host cores
-on the same workload (reported baseline), plus the GPU field's error against that oracle.
+on a bounded sample of the same workload (reported baseline), plus the GPU field's error
+against that oracle.
 """
 from __future__ import annotations
 
@@ -29,13 +35,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 METRIC = "cavity unknowns solved/s + p50/p99 latency, mixed vs FP64 at ≤1e-8 rel err"
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_baseline(wl, gpu_fields, gpu_sigma, sample):
-    """Time the CPU oracle on the same workload: plan + the first `sample` incidences (field
-    and RCS each), a bounded sample of the workload."""
+def cpu_baseline(wl, gpu_fields, gpu_sigma, indices):
+    """Time the CPU oracle on a bounded sample of the workload: the plan + the incidences
+    `indices` (field and RCS each); gpu_fields / gpu_sigma hold the GPU results of the same
+    incidences, in the same order."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -46,7 +58,7 @@ def cpu_baseline(wl, gpu_fields, gpu_sigma, sample):
     t0 = time.perf_counter()
     pl = solver.plan(prob)
     fields, sig = [], []
-    incs = wl.incidences[:sample]
+    incs = [wl.incidences[i] for i in indices]
     for inc in incs:
         sol = solver.solve(pl, inc.theta, inc.phi, inc.pol, tol=1e-13)
         if gpu_fields is not None:
@@ -57,12 +69,12 @@ def cpu_baseline(wl, gpu_fields, gpu_sigma, sample):
     errs = ([float(np.linalg.norm(g - o) / np.linalg.norm(o)) for g, o in zip(gpu_fields, fields)]
             if gpu_fields is not None else [])
     rerr = []
-    for i, (g, o) in enumerate(zip(gpu_sigma, sig)):
-        co = int(wl.incidences[i].pol)      # co-polarised component of this incidence
+    for inc, g, o in zip(incs, gpu_sigma, sig):
+        co = int(inc.pol)      # co-polarised component of this incidence
         rerr.append(float(abs(g[co] - o[co]) / abs(o[co])))
     unknowns = len(incs) * prob.unknowns
     what = ("whole workload once" if len(incs) == len(wl.incidences) else
-            f"first {len(incs)} of {len(wl.incidences)} incidences")
+            f"incidences {list(indices)} of {len(wl.incidences)}")
     return {
         "value": unknowns / (t1 - t0), "unit": "unknowns/s", "cores": int(threads),
         "kind": "oracle",
@@ -109,28 +121,26 @@ def measured_traffic(kernel, workload):
 
 
 SERVED = "served_stream_2000_poisson40"
+DEFAULT_WORKLOAD = "batched_layered_8x8x2_256x256x64_x128"
+# incidences the oracle solves for a batched workload: every 17th of the 128
+ORACLE_SUBSET = (0, 17, 34, 51, 68, 85, 102, 119)
 
 
-def served_main(args) -> int:
-    """Replay the served stream in real time: each request (random cavity, one incidence)
-    is submitted to the library's request server at its seeded Poisson arrival time; the
-    latency of a request runs from its arrival to its field and backscatter RCS being
-    ready.  value = unknowns of all requests / (last completion - first arrival)."""
-    import numpy as np
+def replay_served(n_requests, streams, prec):
+    """Submit the first n_requests of the served stream to the library's request server at
+    their seeded Poisson arrival times (real time) and collect the results."""
     import torch
 
     import paper_2008_01966_amd as P
     import workloads as W
 
-    torch.cuda.set_device(0)
-    stream = W.served_stream(args.requests)
+    stream = W.served_stream(n_requests)
     # warm-up on a cavity outside the stream (loads the kernels; no aperture of the stream)
-    warm = P.Plan(0.75, 0.75, 0.25, 24, 24, 8, precision="mixed")
+    warm = P.Plan(0.75, 0.75, 0.25, 24, 24, 8, precision=prec)
     warm.solve(0.2, 0.1, 0)
     warm.close()
     torch.cuda.synchronize()
-    prec = "mixed" if args.precision in ("mixed", "both") else "fp64"
-    srv = P.Server(streams=args.streams, precision=prec)
+    srv = P.Server(streams=streams, precision=prec)
     tickets = []
     t_origin = srv.now_ms() + 50.0
     for req in stream:
@@ -148,52 +158,44 @@ def served_main(args) -> int:
         res.append((r, due))
         srv.release(t)
     srv.close()
+    return stream, res, t_origin
+
+
+def served_summary(res, t_origin, streams, prec):
+    """Latency from arrival to field and RCS ready, queueing, throughput of a replay."""
+    import numpy as np
+
     bad = [k for k, (r, _) in enumerate(res) if r.status != 0]
     lat = np.array([r.t_done_ms - due for r, due in res])
     queue = np.array([r.t_start_ms - due for r, due in res])
     unknowns = float(sum(r.unknowns for r, _ in res))
     span_s = (max(r.t_done_ms for r, _ in res) - t_origin) * 1e-3
     its = [r.iterations for r, _ in res]
-    out = {
-        "metric": METRIC,
-        "value": unknowns / span_s,
-        "unit": "unknowns/s",
-        "n_gpus": 1,
-        "steps": len(res),
-        "warmup": 1,
-        "ms_per_step": float(np.mean(lat)),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {
-            "workload": SERVED,
-            "requests": len(res),
-            "arrivals": "Poisson 40/s, seed 200801966, replayed in real time",
-            "streams": args.streams,
-            "precision": prec,
-            "step": "one request: plan (aperture data from the cache when seen before) + "
-                    "GMRES + field on all nodes + backscatter RCS",
-        },
+    return {
+        "workload": SERVED,
+        "requests": len(res),
+        "arrivals": "Poisson 40/s, seed 200801966, replayed in real time",
+        "streams": streams,
+        "precision": prec,
+        "unknowns_per_s": unknowns / span_s,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "max": float(lat.max()), "of": "arrival to field and RCS ready"},
+                       "max": float(lat.max()), "mean": float(lat.mean()),
+                       "of": "arrival to field and RCS ready"},
         "queueing_ms": {"p50": float(np.percentile(queue, 50)),
                         "p99": float(np.percentile(queue, 99))},
         "failed_requests": bad,
         "gmres_iterations": {"min": int(min(its)), "max": int(max(its))},
         "span_s": span_s,
+        "step": "one request: plan (aperture data from the cache when seen before) + GMRES + "
+                "field on all nodes + backscatter RCS",
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["oracle_check"] = served_oracle(stream, res, prec)
-    print(json.dumps(out), flush=True)
-    return 0
 
 
-def served_oracle(stream, res, prec):
-    """The oracle serves the stream's requests in order, serially, for about 20 s of host
-    time (at least one); the same requests are solved alone on the GPU with their field
-    kept and compared with the oracle's field and RCS."""
+def served_oracle(stream, res, prec, budget_s, max_side=None):
+    """The oracle serves the stream's requests in order, serially (those of side at most
+    max_side when given), for about budget_s of host time (at least one); the same requests
+    are solved alone on the GPU with their field kept and compared with the oracle's field
+    and RCS; the server's RCS is compared too."""
     import numpy as np
     import torch
     from threadpoolctl import threadpool_info
@@ -202,41 +204,82 @@ def served_oracle(stream, res, prec):
     from oracle import solver
     from oracle.problem import Problem
 
-    t0 = time.perf_counter()
+    t_cpu = 0.0
     done, unknowns, errs = 0, 0, []
-    for req, (r, _) in zip(stream, res):
+    for k, (req, (r, _)) in enumerate(zip(stream, res)):
         cav = req.workload.cavity
+        if max_side is not None and max(cav.a, cav.b) > max_side:
+            continue
         inc = req.workload.incidences[0]
+        t0 = time.perf_counter()
         prob = Problem.from_cavity(cav)
         pl = solver.plan(prob)
         sol = solver.solve(pl, inc.theta, inc.phi, inc.pol, tol=1e-13)
         field = solver.field_out(pl, sol)
         sig = solver.backscatter(pl, sol, inc.theta, inc.phi)
+        t_cpu += time.perf_counter() - t0
         done += 1
         unknowns += prob.unknowns
         plan = P.Plan.from_cavity(cav, precision=prec, batch=1)
         g = plan.solve(inc.theta, inc.phi, inc.pol).cpu().numpy()
         plan.close()
         co = inc.pol
-        errs.append({"request": done - 1, "side": cav.a, "grid": [cav.nx, cav.ny, cav.nz],
+        errs.append({"request": k, "side": cav.a, "grid": [cav.nx, cav.ny, cav.nz],
                      "field_rel_err": float(np.linalg.norm(g - field) / np.linalg.norm(field)),
                      "rcs_rel_err_server": float(abs(r.sigma[co] - sig[co]) / sig[co])})
-        if time.perf_counter() - t0 > 20.0:
+        if t_cpu > budget_s:
             break
-    t1 = time.perf_counter()
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     torch.cuda.synchronize()
-    return ({"value": unknowns / (t1 - t0), "unit": "unknowns/s", "cores": int(threads),
+    which = "" if max_side is None else f" of side <= {max_side:g} wavelengths"
+    return ({"value": unknowns / max(t_cpu, 1e-9), "unit": "unknowns/s", "cores": int(threads),
              "kind": "oracle",
-             "sample": f"first {done} requests of the stream served serially, {t1 - t0:.1f} s "
-                       "wall (includes the GPU re-solve of each for the field check)"}, errs)
+             "sample": f"first {done} requests{which} of the stream served serially, "
+                       f"{t_cpu:.1f} s of oracle time"}, errs)
+
+
+def served_main(args) -> int:
+    """The whole served stream on its own: value = unknowns of all requests / (last
+    completion - first arrival)."""
+    import torch
+
+    torch.cuda.set_device(0)
+    prec = "mixed" if args.precision in ("mixed", "both") else "fp64"
+    stream, res, t_origin = replay_served(args.requests, args.streams, prec)
+    summ = served_summary(res, t_origin, args.streams, prec)
+    out = {
+        "metric": METRIC,
+        "value": summ["unknowns_per_s"],
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": len(res),
+        "warmup": 1,
+        "ms_per_step": summ["latency_ms"]["mean"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {k: summ[k] for k in ("workload", "requests", "arrivals", "streams",
+                                         "precision", "step")},
+        "latency_ms": summ["latency_ms"],
+        "queueing_ms": summ["queueing_ms"],
+        "failed_requests": summ["failed_requests"],
+        "gmres_iterations": summ["gmres_iterations"],
+        "span_s": summ["span_s"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["oracle_check"] = served_oracle(stream, res, prec, 20.0)
+    print(json.dumps(out), flush=True)
+    return 0
+
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="lossy_8x8x2_256x256x64")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--probe", default=None,
                     help="kernel timed for the roofline (default: the column pass of the TBC "
                          "convolution in the headline precision); none: no probe (the "
@@ -248,9 +291,15 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=0,
                     help="right-hand sides iterated together (0: the workload's choice)")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="incidences the CPU oracle solves (0: all when at most 2, else 1)")
+                    help="incidences the CPU oracle solves (0: all when at most 2, the "
+                         "subset 0, 17, ..., 119 of a 128-incidence batch, else 1)")
     ap.add_argument("--requests", type=int, default=2000, help="served stream: requests")
     ap.add_argument("--streams", type=int, default=4, help="served stream: concurrent requests")
+    ap.add_argument("--served-prefix", type=int, default=320,
+                    help="requests of the served stream replayed after the batched workload "
+                         "for the p50/p99 latency of the same line (0: none)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain double-precision run (one incidence per solve)")
     ap.add_argument("--operator", choices=["trap", "spec"], default="trap",
                     help="discrete TBC operator: trapezoid samples with FFT convolution, or "
                          "exact trial transforms on the spectrum lattice (D_spec)")
@@ -299,7 +348,7 @@ def main() -> int:
     fields = (torch.empty((len(incs), 3, cav.nz + 1, cav.ny + 1, cav.nx + 1),
                           dtype=torch.complex128, device="cuda") if wl.fields else None)
 
-    def timed(precision, out, probe):
+    def timed(precision, out, probe, nb):
         """Create the plan (timed on its own, outside the step: the first creation computes
         the aperture data, the second takes it from the library's aperture cache), warm up,
         then time `steps` steps of solve + fields + RCS; each step ends with host-side RCS
@@ -308,7 +357,7 @@ def main() -> int:
         for _ in range(2):
             torch.cuda.synchronize()
             tp = time.perf_counter()
-            plan = P.Plan.from_cavity(cav, precision=precision, tol=wl.tol, batch=batch,
+            plan = P.Plan.from_cavity(cav, precision=precision, tol=wl.tol, batch=nb,
                                       direct=args.direct, operator=args.operator,
                                       spectrum=args.spectrum)
             torch.cuda.synchronize()
@@ -340,11 +389,19 @@ def main() -> int:
         probe_res = P.probe_stop() if probe else (0, 0.0, 0.0)
         plan.close()
         unknowns_step = len(incs) * infos[-1].unknowns
+        slow = int(np.argmax(lat))
         res = {
             "value": args.steps * unknowns_step / (t1 - t0),
             "ms_per_step": 1e3 * (t1 - t0) / args.steps,
+            "batch": nb,
+            "step_ms": [round(1e3 * v, 3) for v in lat],
             "p50_ms": 1e3 * float(np.percentile(lat, 50)),
             "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+            # phases of the last lockstep group of the slowest step (device time)
+            "slowest_step": {"index": slow, "ms": 1e3 * lat[slow],
+                             "krylov_ms_last_group": infos[slow].ms_krylov,
+                             "synthesis_ms_last_group": infos[slow].ms_synthesis,
+                             "gmres_iterations": int(infos[slow].last_iterations)},
             "plan_ms": plan_ms[0],
             "plan_ms_same_aperture": plan_ms[-1],
             "gmres_iterations_last": int(infos[-1].last_iterations),
@@ -361,16 +418,24 @@ def main() -> int:
         args.probe = "tbc_cols_f32" if head == "mixed" else "tbc_cols"
     runs, sigs = {}, {}
     fields_by = {}
+    other = None
+    if fields is not None and len(precisions) > 1:
+        other = torch.empty_like(fields)
+    if args.precision == "both" and len(incs) > 1 and not args.no_plain:
+        # the plain method: double precision, one incidence per solve (no lockstep group)
+        res, _, _, _ = timed("fp64", other, probe=False, nb=1)
+        runs["fp64_plain"] = res
+        log(f"fp64, one incidence per solve: {res['ms_per_step']:.1f} ms per step")
     for prec in precisions:
-        out = None if fields is None else (fields if prec == head else torch.empty_like(fields))
-        res, sig, info_p, probe_res = timed(prec, out, probe=(prec == head))
+        out = None if fields is None else (fields if prec == head else other)
+        res, sig, info_p, probe_res = timed(prec, out, probe=(prec == head), nb=batch)
         runs[prec] = res
         sigs[prec] = sig
+        log(f"{prec}, batch {batch}: {res['ms_per_step']:.1f} ms per step")
         fields_by[prec] = out
         if prec == head:
             info, (launches, k_ms, k_bytes) = info_p, probe_res
 
-    unknowns_step = len(incs) * info.unknowns
     value = runs[head]["value"]
     traffic, traffic_src = measured_traffic(args.probe, wl.name)
     achieved = (k_bytes / (k_ms * 1e-3)) / 1e9 if k_ms > 0 else None
@@ -411,7 +476,7 @@ def main() -> int:
             "layer_depth": None if cav.layer_depth is None else list(cav.layer_depth),
         },
         "latency_ms": {"p50": runs[head]["p50_ms"], "p99": runs[head]["p99_ms"],
-                       "of": "one step"},
+                       "of": "one step (all incidences)"},
         "plan_ms": runs[head]["plan_ms"],
         "plan_ms_same_aperture": runs[head]["plan_ms_same_aperture"],
         "by_precision": runs,
@@ -445,15 +510,44 @@ def main() -> int:
             abs(sigs["mixed"][i][incs[i].pol] - sigs["fp64"][i][incs[i].pol]) /
             abs(sigs["fp64"][i][incs[i].pol]) for i in range(len(incs)))
         out["mixed_speedup_vs_fp64"] = runs["mixed"]["value"] / runs["fp64"]["value"]
+        if "fp64_plain" in runs:
+            out["mixed_speedup_vs_fp64_plain"] = runs["mixed"]["value"] / runs["fp64_plain"]["value"]
+    del other
     if not args.no_cpu_baseline:
-        sample = args.cpu_sample or (len(incs) if len(incs) <= 2 else 1)
-        sample = min(sample, len(incs))
-        gpu_fields = ([fields[i].cpu().numpy() for i in range(sample)] if fields is not None
-                      else None)
-        base, ferr, rerr = cpu_baseline(wl, gpu_fields, sigs[head][:sample], sample)
+        if args.cpu_sample:
+            idx = list(range(min(args.cpu_sample, len(incs))))
+        elif len(incs) <= 2:
+            idx = list(range(len(incs)))
+        elif len(incs) == 128:
+            idx = list(ORACLE_SUBSET)
+        else:
+            idx = [0]
+        gpu_fields = ([fields[i].cpu().numpy() for i in idx] if fields is not None else None)
+        log(f"oracle on incidences {idx}")
+        base, ferr, rerr = cpu_baseline(wl, gpu_fields, [sigs[head][i] for i in idx], idx)
+        log(f"oracle done: {base['sample']}")
+        del gpu_fields
         out["cpu_baseline"] = base
         out["field_rel_err_vs_oracle"] = ferr
         out["rcs_rel_err_vs_oracle"] = rerr
+    del fields, fields_by
+    torch.cuda.empty_cache()
+    if args.served_prefix > 0:
+        prec = "mixed" if args.precision in ("mixed", "both") else "fp64"
+        log(f"served stream, first {args.served_prefix} requests")
+        stream, res, t_origin = replay_served(args.served_prefix, args.streams, prec)
+        summ = served_summary(res, t_origin, args.streams, prec)
+        log(f"served: p50 {summ['latency_ms']['p50']:.2f} ms, p99 {summ['latency_ms']['p99']:.2f} ms")
+        if not args.no_cpu_baseline:
+            base, errs = served_oracle(stream, res, prec, 10.0, max_side=4.0)
+            summ["oracle_check"] = errs
+            summ["cpu_baseline"] = base
+        out["served"] = summ
+        out["latency_ms"] = dict(summ["latency_ms"])
+        out["latency_ms"]["of"] = (f"served stream, first {len(res)} requests: "
+                                   "arrival to field and RCS ready")
+        out["step_latency_ms"] = {"p50": runs[head]["p50_ms"], "p99": runs[head]["p99_ms"],
+                                  "of": "one step of the batched workload"}
     print(json.dumps(out), flush=True)
     return 0
 

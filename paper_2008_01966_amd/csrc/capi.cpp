@@ -1611,6 +1611,8 @@ int cavity_solve_batch(cavity_plan p, int nrhs, const double* theta, const doubl
   for (int i = 0; i < nrhs; ++i)
     if (!angles_ok(theta[i], phi[i], pol[i]))
       return fail(CAVITY_EINVAL, "theta must lie in [0, pi/2], phi finite, pol TM or TE");
+  // the stored solutions are those of this call only: indices 0..nrhs-1 once it succeeds
+  p->nsol = 0;
   int s = ensure_solutions(p, nrhs);
   if (s) return s;
   const long long n = p->nvec();
@@ -1638,7 +1640,7 @@ int cavity_solve_batch(cavity_plan p, int nrhs, const double* theta, const doubl
     if (s == CAVITY_ENOCONV) worst = s;
     its = std::max(its, p->info.last_iterations);
     res = std::max(res, p->info.last_rel_residual);
-    p->nsol = std::max(p->nsol, i0 + nb);
+    p->nsol = i0 + nb;
   }
   p->info.last_iterations = its;
   p->info.last_rel_residual = res;

@@ -156,9 +156,11 @@ int cavity_opts_default(cavity_opts* opts);
 
 /* Build a plan: validates arguments, derives sizes, allocates device memory, computes
  * the truncated-kernel spectrum (Section 5), runs the per-mode z-elimination (Sections
- * 3-4) and the block preconditioner.  a, b, c, k > 0; Nx, Ny >= 2 with 2*s*Nx and 2*s*Ny
- * products of 2, 3 and 5; Nz >= 1; eps may be NULL (vacuum).  opts may be NULL.
- * Errors: CAVITY_EINVAL, CAVITY_ENOMEM, CAVITY_ERESONANT, CAVITY_EDEVICE. */
+ * 3-4) and the block preconditioner.  a, b, c, k > 0; Nx, Ny >= 2; Nz >= 1; eps may be
+ * NULL (vacuum).  opts may be NULL.  The sine/cosine transforms run as FFTs of lengths
+ * 2 Nx, 2 Ny, 2 s Nx and 2 s Ny built from radices with the prime factors 2, 3, 5, 7, 11
+ * and 13; a length with another prime factor gives CAVITY_ENOTIMPL.
+ * Errors: CAVITY_EINVAL, CAVITY_ENOMEM, CAVITY_ERESONANT, CAVITY_ENOTIMPL, CAVITY_EDEVICE. */
 int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
                        const cavity_eps* eps, double k, const cavity_opts* opts,
                        cavity_plan* out);
@@ -172,21 +174,33 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
 int cavity_solve(cavity_plan plan, double theta, double phi, int pol, cavity_c128* E_out);
 
 /* Solve nrhs plane waves (host arrays theta, phi, pol) on the plan's stream, opts.batch
- * of them at a time iterating together (every kernel launch serves the whole group).  E_out (device) holds nrhs consecutive fields or is NULL; aperture_out
- * (device) holds nrhs consecutive aperture vectors of n_ap entries or is NULL.  The plan
- * keeps every aperture solution (indices 0..nrhs-1) for cavity_rcs. */
+ * of them at a time iterating together (every kernel launch serves the whole group).  The
+ * paper computes the singular-integral data once per geometry and reuses it for every
+ * incidence (Section 7, Example 1; Steps 1-3 of Section 6): here the plan is that data,
+ * and each right-hand side is one reduced aperture system (EJ1) / (uT1) with the source
+ * g of (ENUC1) for its wave.  E_out (device) holds nrhs consecutive fields or is NULL;
+ * aperture_out (device) holds nrhs consecutive aperture vectors of n_ap entries or is
+ * NULL.  The plan keeps the aperture solutions of this call only (indices 0..nrhs-1) for
+ * cavity_rcs; those of earlier calls are forgotten.
+ * Errors: CAVITY_EINVAL (nrhs < 1, NULL arrays, angles as for cavity_solve),
+ * CAVITY_ENOCONV (every field still written), CAVITY_ENOMEM, CAVITY_EDEVICE. */
 int cavity_solve_batch(cavity_plan plan, int nrhs, const double* theta, const double* phi,
                        const int* pol, cavity_c128* E_out, cavity_c128* aperture_out);
 
 /* Radar cross section (units of length squared) of stored solution rhs_index at n_obs
  * observation directions (host arrays); sigma (host) receives {sigma_theta, sigma_phi}
- * per direction.  Backscatter: observation direction equal to the incidence angles.
+ * per direction.  Backscatter: observation direction equal to the incidence angles, the
+ * theta-theta and phi-phi RCS of Section 7.  The far field is radiated by the aperture's
+ * tangential field with image doubling (the representation (EGa2) of Section 2): with
+ * E^l(u) the aperture transform of E_l at u = k (sin t cos f, sin t sin f) and
+ * L = (-E^2, E^1, 0), sigma_theta = (k^2/pi) |phi^.L|^2, sigma_phi = (k^2/pi) |theta^.L|^2.
  * Errors: CAVITY_EINVAL (no such solution), CAVITY_EDEVICE. */
 int cavity_rcs(cavity_plan plan, int rhs_index, int n_obs, const double* theta_o,
                const double* phi_o, double* sigma);
 
-/* The same for n (solution, direction) pairs at once, e.g. the backscatter of every
- * incidence of a sweep: pair i is stored solution rhs_index[i] seen from (theta_o[i],
+/* The RCS above (Section 7) for n (solution, direction) pairs at once, e.g. the
+ * backscatter of every incidence of a sweep such as the paper's RCS-versus-theta curves:
+ * pair i is stored solution rhs_index[i] seen from (theta_o[i],
  * phi_o[i]); sigma[2 i], sigma[2 i + 1] = {sigma_theta, sigma_phi}.  One kernel launch and
  * one device-to-host copy for all pairs (cavity_rcs with n_obs directions is this call
  * with a repeated index; results are identical).  The plan keeps a device buffer of at
@@ -204,6 +218,10 @@ int cavity_plan_footprint(double a, double b, double c, int Nx, int Ny, int Nz,
                           const cavity_eps* eps, double k, const cavity_opts* opts,
                           size_t* bytes);
 
+/* Sizes of the plan (M, N, the aperture unknowns 3MN + M + N of Section 6's complexity
+ * table, the FFT box of Section 5) and the device times of its phases, which mirror the
+ * paper's T_singular (spectrum), T_assemble (elimination, preconditioner) and T_solve
+ * (Krylov, synthesis) of Section 7.  Errors: CAVITY_EINVAL (NULL arguments). */
 int cavity_plan_info(cavity_plan plan, cavity_info* out);
 void cavity_plan_destroy(cavity_plan plan);
 const char* cavity_status_string(int status);

@@ -1252,8 +1252,13 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   if (o.direct == 1 && 3LL * Nx * Ny > kDenseMax)
     return fail(CAVITY_EINVAL, "direct solve needs 3 Nx Ny <= " + std::to_string(kDenseMax));
   const int s = o.tbc_oversample;
-  if (!is_5smooth(2LL * s * Nx) || !is_5smooth(2LL * s * Ny))
-    return fail(CAVITY_EINVAL, "2*s*Nx and 2*s*Ny must be products of 2, 3 and 5");
+  // the sine/cosine transforms run as FFTs of length 2 s Nx, 2 s Ny, 2 Nx and 2 Ny, built
+  // from radices with the prime factors 2, 3, 5, 7, 11 and 13
+  for (long long len : {2LL * s * Nx, 2LL * s * Ny, 2LL * Nx, 2LL * Ny})
+    if (len > (1 << 20) || cav::plan_fft((int)len, cav::kMaxRadix).nst == 0)
+      return fail(CAVITY_ENOTIMPL, "transform length " + std::to_string(len) +
+                                       " has a prime factor above 13 (Nx, Ny and s*Nx, s*Ny "
+                                       "need prime factors 2, 3, 5, 7, 11, 13)");
   std::vector<int> lnz;
   std::vector<std::complex<double>> leps;
   if (eps) {

@@ -2,10 +2,10 @@
 // convolution of the cavity solver (the Fourier expansions (E123F) sampled on uniform
 // nodes, and the FFT evaluation of the singular integrals in Section 5).
 //
-// Engine: Stockham autosort stages whose radix may be composite (up to 32).  A composite
-// radix R = R1 R2 is computed in registers by one Cooley-Tukey split (R2 DFTs of length
-// R1, constant twiddles, R1 DFTs of length R2), so a length-625 transform takes two LDS
-// round trips (25 x 25) instead of four.  C transforms of a block are interleaved in LDS,
+// Engine: Stockham autosort stages whose radix may be composite (up to 32) or one of the
+// odd primes 7, 11, 13.  A composite radix R = R1 R2 is computed in registers by one
+// Cooley-Tukey split (R2 DFTs of length R1, constant twiddles, R1 DFTs of length R2), so a
+// length-625 transform takes two LDS round trips (25 x 25) instead of four.  C transforms of a block are interleaved in LDS,
 // element (pos, col) at buf[pos * C + col] with C a power of two, so consecutive lanes
 // work on the same butterfly of consecutive transforms and share its twiddles.
 //
@@ -128,6 +128,58 @@ struct Dft<5, T, INV> {
   }
 };
 
+// Odd prime R (7, 11, 13): with a_j = x_j + x_{R-j}, b_j = x_j - x_{R-j} (j = 1..H,
+// H = (R-1)/2) the outputs pair up as
+//   X_k, X_{R-k} = x_0 + sum_j cos(2 pi jk/R) a_j  -/+ i sum_j sin(2 pi jk/R) b_j
+// (signs swapped for the inverse), H^2 real multiplies per output pair instead of R^2.
+template <int R>
+struct OddTrig {
+  static constexpr int H = (R - 1) / 2;
+  double c[H][H];
+  double s[H][H];
+  constexpr OddTrig() : c(), s() {
+    for (int k = 1; k <= H; ++k)
+      for (int j = 1; j <= H; ++j) {
+        c[k - 1][j - 1] = ct_cos((j * k) % R, R);
+        s[k - 1][j - 1] = ct_sin((j * k) % R, R);
+      }
+  }
+};
+
+template <int R, typename T, bool INV>
+struct DftOddPrime {
+  __device__ static inline void run(cx<T>* v) {
+    constexpr int H = (R - 1) / 2;
+    constexpr OddTrig<R> tb{};
+    cx<T> a[H], b[H];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      a[j - 1] = v[j] + v[R - j];
+      b[j - 1] = v[j] - v[R - j];
+    }
+    const cx<T> x0 = v[0];
+    cx<T> sum = x0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) sum = sum + a[j];
+    v[0] = sum;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+      cx<T> p = x0, q = mk<T>(0, 0);
+#pragma unroll
+      for (int j = 1; j <= H; ++j) {
+        p = p + (T)tb.c[k - 1][j - 1] * a[j - 1];
+        q = q + (T)tb.s[k - 1][j - 1] * b[j - 1];
+      }
+      v[k] = INV ? p + mul_i(q) : p + mul_mi(q);
+      v[R - k] = INV ? p + mul_mi(q) : p + mul_i(q);
+    }
+  }
+};
+
+template <typename T, bool INV> struct Dft<7, T, INV> : DftOddPrime<7, T, INV> {};
+template <typename T, bool INV> struct Dft<11, T, INV> : DftOddPrime<11, T, INV> {};
+template <typename T, bool INV> struct Dft<13, T, INV> : DftOddPrime<13, T, INV> {};
+
 // Multiply y[I] (I = r2 R1 + k1) by W_R^{r2 k1}, with the trivial factors 1, -1, +-i
 // done by sign and swap.
 template <int R1, int R2, typename T, bool INV, int I>
@@ -193,7 +245,8 @@ template <typename T, bool INV> struct Dft<25, T, INV> : DftCt<5, 5, T, INV> {};
 template <typename T, bool INV> struct Dft<32, T, INV> : DftCt<4, 8, T, INV> {};
 
 // Radices the planner may choose (host and device agree on this list).
-#define CAV_FFT_RADICES(X) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(20) X(25) X(32)
+#define CAV_FFT_RADICES(X) \
+  X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(15) X(16) X(20) X(25) X(32)
 
 // ---- FFT plan -----------------------------------------------------------------------
 // Factorisation of n into the radices of its Stockham stages, applied in order.
@@ -443,7 +496,7 @@ namespace cav {
 // Host planner: the factorisation of n into the fewest stages with radices from
 // CAV_FFT_RADICES not above max_radix, ties broken towards balanced radices (smallest sum
 // of squares); stages ordered by decreasing radix so the largest runs without twiddles.
-// Returns nst = 0 when n has a prime factor above 5 or does not fit.
+// Returns nst = 0 when n has a prime factor other than 2, 3, 5, 7, 11, 13 or does not fit.
 inline FftPlan plan_fft(int n, int max_radix) {
   FftPlan p{};
   p.n = n;

@@ -1,4 +1,4 @@
-"""Backscatter RCS sweeps on the geometries of the paper's numerical examples (Section 8):
+"""Backscatter RCS sweeps on the geometries of the paper's numerical examples (Section 7):
 one plan per geometry, many incidences solved together without field output, RCS from the
 stored aperture solutions.  Each geometry: the GPU sweep against the oracle at two angles
 (1e-9 relative, both polarisations), the mixed-precision sweep against the double one
@@ -17,9 +17,10 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("make", [W.example1_sweep, W.example2_sweep, W.example3_sweep,
-                                  W.example3_sweep_steps],
-                         ids=["example1", "example2", "example3", "example3_steps"])
+@pytest.mark.parametrize("make", [W.example1_sweep, W.example1_sweep_m21, W.example1_small_sweep,
+                                  W.example2_sweep, W.example3_sweep, W.example3_sweep_steps],
+                         ids=["example1", "example1_m21", "example1_small", "example2", "example3",
+                              "example3_steps"])
 def test_sweep_against_oracle(make):
     import torch
     wl = make()

@@ -49,11 +49,18 @@ def _create(a=1.0, b=1.0, c=0.5, nx=16, ny=16, nz=8, eps=None, k=6.28, opts=None
     return st, h, lib.cavity_last_error().decode()
 
 
-@pytest.mark.parametrize("kw", [dict(a=-1.0), dict(c=0.0), dict(k=0.0), dict(nx=1), dict(nz=0),
-                                dict(nx=14), dict(ny=7)])
+@pytest.mark.parametrize("kw", [dict(a=-1.0), dict(c=0.0), dict(k=0.0), dict(nx=1), dict(nz=0)])
 def test_invalid_arguments_rejected(kw):
     st, h, msg = _create(**kw)
     assert st == 1 and not h.value and msg
+
+
+@pytest.mark.parametrize("kw", [dict(nx=17), dict(ny=19), dict(nx=46)])
+def test_transform_lengths_beyond_the_radices_not_implemented(kw):
+    """2 Nx or 2 Ny with a prime factor above 13 is a valid size the transforms do not
+    cover: CAVITY_ENOTIMPL, not CAVITY_EINVAL."""
+    st, h, msg = _create(**kw)
+    assert st == 6 and not h.value and "prime factor" in msg
 
 
 def test_invalid_layers_rejected():
@@ -129,7 +136,8 @@ def test_footprint_needs_no_device_and_scales():
     o.restart = 20
     st, short = _footprint(a=8.0, b=8.0, c=2.0, nx=256, ny=256, nz=64, opts=o)
     assert st == 0 and short < big
-    assert _footprint(nx=14)[0] == 1 and _footprint(c=-1.0)[0] == 1
+    assert _footprint(nx=14)[0] == 0 and _footprint(nx=22)[0] == 0
+    assert _footprint(nx=17)[0] == 6 and _footprint(c=-1.0)[0] == 1
 
 
 def test_server_arguments_rejected_without_device():

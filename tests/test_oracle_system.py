@@ -23,7 +23,7 @@ def _prob(wl):
     return Problem.from_cavity(wl.cavity)
 
 
-@pytest.mark.parametrize("case", [0, 1, 3])
+@pytest.mark.parametrize("case", [0, 1, 3, 5, 6])
 def test_brute_force_full_system(case):
     wl = W.small_cases()[case]
     prob = _prob(wl)

@@ -42,4 +42,4 @@ def test_example3_readings_differ_only_in_the_step_assignment():
     assert one.layer_h == (1e-3, 1e-3)
     assert own.layer_h == (2.0 / 1000, 1.0 / 2000)
     assert own.h == 1.0 / 2000 and one.h == 1e-3       # aperture rows: the top layer's step
-    assert one.layer_eps == own.layer_eps and (one.M, one.N) == (own.M, own.N)
+    assert one.layer_eps == own.layer_eps and (one.M, one.N) == (own.M, own.N) == (21, 21)

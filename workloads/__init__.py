@@ -121,8 +121,8 @@ def batched_layered_8x8x2() -> Workload:
 
 
 # -- backscatter RCS sweeps on the geometries of the paper's numerical examples ---------
-# (Section 8: phi = 0, theta stepped by 0.5 degrees, both polarisations; the paper's mode
-# counts where 2 Nx is a product of 2, 3 and 5, and its number of z-partition points).
+# (Section 7: phi = 0, theta stepped by 0.5 degrees, both polarisations; the mode counts
+# and z-partition counts of its timing tables).
 
 def _sweep(n_theta: int) -> Tuple[Incidence, ...]:
     return tuple(Incidence(deg(0.5 * i), 0.0, pol) for i in range(n_theta) for pol in (TM, TE))
@@ -130,9 +130,25 @@ def _sweep(n_theta: int) -> Tuple[Incidence, ...]:
 
 def example1_sweep() -> Workload:
     """Example 1: 10 x 10 x 30 wavelength cavity, homogeneous (vacuum), M = N = 15
-    (16 x 16 nodes), J + 1 = 1000 z-intervals, 100 angles x 2 polarisations."""
+    (16 x 16 nodes), 1000 z-intervals, 100 angles x 2 polarisations."""
     cav = Cavity(10.0, 10.0, 30.0, 16, 16, 1000, (1000,), (1.0 + 0j,))
     return Workload("example1_sweep_10x10x30_16x16x1000", cav, _sweep(100), batch=32,
+                    fields=False)
+
+
+def example1_sweep_m21() -> Workload:
+    """Example 1, the same cavity with the table's larger mode count M = N = 21 (22 x 22
+    nodes; the sine/cosine transforms have length 44 = 4 x 11)."""
+    cav = Cavity(10.0, 10.0, 30.0, 22, 22, 1000, (1000,), (1.0 + 0j,))
+    return Workload("example1_sweep_10x10x30_22x22x1000", cav, _sweep(100), batch=32,
+                    fields=False)
+
+
+def example1_small_sweep() -> Workload:
+    """Example 1, second cavity: 1 x 1 x 3 wavelengths, vacuum, M = N = 21, 1000
+    z-intervals, 100 angles x 2 polarisations."""
+    cav = Cavity(1.0, 1.0, 3.0, 22, 22, 1000, (1000,), (1.0 + 0j,))
+    return Workload("example1_sweep_1x1x3_22x22x1000", cav, _sweep(100), batch=32,
                     fields=False)
 
 
@@ -147,9 +163,9 @@ def example2_sweep() -> Workload:
 def example3_sweep() -> Workload:
     """Example 3: 1 x 1 x 3 wavelength cavity, bottom layer 2 wavelengths of
     eps_r = 3 + 0.05i, top layer 1 wavelength of eps_r = 7 + 1.5i (one h: 2000 + 1000
-    intervals), M = N = 19 (20 x 20 nodes; 2 Nx must be 5-smooth), 180 angles x 2."""
-    cav = Cavity(1.0, 1.0, 3.0, 20, 20, 3000, (2000, 1000), (3.0 + 0.05j, 7.0 + 1.5j))
-    return Workload("example3_sweep_1x1x3_20x20x3000", cav, _sweep(180), batch=32,
+    intervals), M = N = 21 (22 x 22 nodes), 180 angles x 2 polarisations."""
+    cav = Cavity(1.0, 1.0, 3.0, 22, 22, 3000, (2000, 1000), (3.0 + 0.05j, 7.0 + 1.5j))
+    return Workload("example3_sweep_1x1x3_22x22x3000", cav, _sweep(180), batch=32,
                     fields=False)
 
 
@@ -157,9 +173,9 @@ def example3_sweep_steps() -> Workload:
     """Example 3 with the other reading of its interval counts: the 2-wavelength bottom
     layer with 1000 intervals (h = 1/500) and the 1-wavelength top layer with 2000
     (h = 1/2000), each layer with its own step."""
-    cav = Cavity(1.0, 1.0, 3.0, 20, 20, 3000, (1000, 2000), (3.0 + 0.05j, 7.0 + 1.5j),
+    cav = Cavity(1.0, 1.0, 3.0, 22, 22, 3000, (1000, 2000), (3.0 + 0.05j, 7.0 + 1.5j),
                  layer_depth=(2.0, 1.0))
-    return Workload("example3_sweep_steps_1x1x3_20x20x1000+2000", cav, _sweep(180), batch=32,
+    return Workload("example3_sweep_steps_1x1x3_22x22x1000+2000", cav, _sweep(180), batch=32,
                     fields=False)
 
 
@@ -220,12 +236,21 @@ def small_cases() -> List[Workload]:
                  Cavity(1.2, 1.0, 0.5, 24, 20, 12, (4, 8), (4.0 + 1.0j, 1.0 + 0j),
                         layer_depth=(0.3, 0.2)),
                  (Incidence(deg(40), deg(75), TM), Incidence(deg(40), deg(75), TE))),
+        # node counts with the prime factors 7 and 13 (transform lengths 28 and 52)
+        Workload("primes_1.4x1.3x0.45_14x26x9_2layer",
+                 Cavity(1.4, 1.3, 0.45, 14, 26, 9, (3, 6), (3.0 + 0.5j, 1.0 + 0j)),
+                 (Incidence(deg(25), deg(200), TM), Incidence(deg(55), deg(10), TE))),
+        # the paper's M = 21 (22 nodes, length 44 = 4 x 11) and 11 nodes along y
+        Workload("primes_1.1x0.9x0.3_22x11x7",
+                 Cavity(1.1, 0.9, 0.3, 22, 11, 7, (7,), (2.0 + 0.2j,)),
+                 (Incidence(deg(70), deg(300), TE),)),
     ]
     return cases
 
 
 def by_name(name: str) -> Workload:
     table = {w.name: w for w in [vacuum_1x1x05(), lossy_8x8x2(), layered_16x16x4(),
-                                 batched_layered_8x8x2(), example1_sweep(), example2_sweep(),
-                                 example3_sweep(), example3_sweep_steps()] + small_cases()}
+                                 batched_layered_8x8x2(), example1_sweep(), example1_sweep_m21(),
+                                 example1_small_sweep(), example2_sweep(), example3_sweep(),
+                                 example3_sweep_steps()] + small_cases()}
     return table[name]

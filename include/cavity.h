@@ -208,6 +208,19 @@ int cavity_rcs(cavity_plan plan, int rhs_index, int n_obs, const double* theta_o
 int cavity_rcs_many(cavity_plan plan, int n, const int* rhs_index, const double* theta_o,
                     const double* phi_o, double* sigma);
 
+/* cavity_rcs_many for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same pairs, the same
+ * aperture-transform kernel and the same results up to rounding (the block sums are added
+ * on the device in the same order), with no allocation at all.  Its queries, partial sums
+ * and results use a fixed 4 MiB device array of the library, one per device, held until the
+ * process ends: the pairs must fit in it, n (60 + 32 B) bytes plus alignment with
+ * B = min(64, ceil((M+1)(N+1)/256)) blocks per pair (at least 1900 pairs for any plan),
+ * else CAVITY_EINVAL.  All calls on one device share that array: calls that overlap on a
+ * device race, so the caller serialises them.  sigma (host) as for cavity_rcs_many; the call
+ * synchronises the plan's stream.  Errors: CAVITY_EINVAL, CAVITY_EDEVICE. */
+int cavity_rcs_many_noalloc(cavity_plan plan, int n, const int* rhs_index,
+                            const double* theta_o, const double* phi_o, double* sigma);
+
 /* Copy stored aperture solution rhs_index to host memory (n_ap entries, paper order). */
 int cavity_aperture(cavity_plan plan, int rhs_index, cavity_c128* out_host);
 

@@ -85,7 +85,7 @@ class Result(ctypes.Structure):
 
 EXPORTS = [
     "cavity_opts_default", "cavity_plan_create", "cavity_solve", "cavity_solve_batch",
-    "cavity_rcs", "cavity_rcs_many", "cavity_aperture", "cavity_plan_footprint", "cavity_plan_info",
+    "cavity_rcs", "cavity_rcs_many", "cavity_rcs_many_noalloc", "cavity_aperture", "cavity_plan_footprint", "cavity_plan_info",
     "cavity_plan_destroy", "cavity_status_string", "cavity_last_error",
     "cavity_server_opts_default", "cavity_server_create", "cavity_server_submit",
     "cavity_server_wait", "cavity_server_release", "cavity_server_now_ms",
@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cavity_solve_batch.argtypes = [vp, i, P(d), P(d), P(i), vp, vp]
     lib.cavity_rcs.argtypes = [vp, i, i, P(d), P(d), P(d)]
     lib.cavity_rcs_many.argtypes = [vp, i, P(i), P(d), P(d), P(d)]
+    lib.cavity_rcs_many_noalloc.argtypes = [vp, i, P(i), P(d), P(d), P(d)]
     lib.cavity_aperture.argtypes = [vp, i, P(C128)]
     lib.cavity_plan_info.argtypes = [vp, P(Info)]
     lib.cavity_plan_destroy.argtypes = [vp]
@@ -325,6 +326,22 @@ class Plan:
                                          idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                          th.ctypes.data_as(dp), ph.ctypes.data_as(dp),
                                          sig.ctypes.data_as(dp)))
+        return sig
+
+    def rcs_many_noalloc(self, indices, theta_o, phi_o) -> np.ndarray:
+        """rcs_many through the library's no-allocation entry point (fixed device scratch;
+        calls on one device must not overlap)."""
+        idx = np.ascontiguousarray(np.atleast_1d(indices), dtype=np.int32)
+        th = np.ascontiguousarray(np.atleast_1d(theta_o), dtype=np.float64)
+        ph = np.ascontiguousarray(np.atleast_1d(phi_o), dtype=np.float64)
+        if not idx.size == th.size == ph.size:
+            raise ValueError("indices, theta_o and phi_o differ in length")
+        sig = np.zeros((th.size, 2))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(self._lib.cavity_rcs_many_noalloc(self._h, idx.size,
+                                                 idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                                 th.ctypes.data_as(dp), ph.ctypes.data_as(dp),
+                                                 sig.ctypes.data_as(dp)))
         return sig
 
     def aperture(self, index: int = 0) -> np.ndarray:

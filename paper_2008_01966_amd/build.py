@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcavity.so")
 SOURCES = ["capi.cpp", "server.cpp", "plan_kernels.hip", "solve_kernels.hip", "dense_kernels.hip",
-           "spec_kernels.hip"]
+           "spec_kernels.hip", "rcs_noalloc.hip"]
 ARCH = os.environ.get("CAVITY_OFFLOAD_ARCH", "gfx950")
 
 

@@ -71,6 +71,9 @@ int dot_blocks(long long n) {
 
 // Most blocks per query of the aperture-transform reduction behind the RCS.
 constexpr int kRcsBlocks = 64;
+int rcs_blocks(long long NM) {
+  return (int)std::max<long long>(1, std::min<long long>(kRcsBlocks, (NM + 255) / 256));
+}
 
 // Direct solve limits on n = 3 Nx Ny: the largest system it accepts, and the largest it
 // picks by itself (for calls with at least kDenseAutoRhs right-hand sides).
@@ -228,6 +231,7 @@ struct cavity_plan_s {
   cav::Trig trig{};
   cavity_opts opts{};
   hipStream_t st = nullptr;
+  int device = 0;                    // device current at plan creation (owns all its memory)
   bool layered = false;
   int nlayers = 1;
   double R = 0.0;
@@ -291,6 +295,20 @@ struct cavity_plan_s {
 
   long long nvec() const { return 3LL * g.NM; }
 };
+
+namespace cav {
+int plan_view(cavity_plan p, PlanView* out) {
+  if (!p || !out) return fail(CAVITY_EINVAL, "NULL argument");
+  out->g = p->g;
+  out->xsol = p->xsol;
+  out->nvec = p->nvec();
+  out->nsol = p->nsol;
+  out->stream = p->st;
+  out->device = p->device;
+  out->rcs_blocks = rcs_blocks(p->g.NM);
+  return CAVITY_OK;
+}
+}  // namespace cav
 
 namespace {
 
@@ -813,8 +831,7 @@ int gmres_batch(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
 int rcs_queries(cavity_plan p, int n, const int* rhs, const double* th, const double* ph,
                 double* sigma) {
   if (n == 0) return CAVITY_OK;
-  const int nblk = (int)std::max<long long>(1, std::min<long long>(kRcsBlocks,
-                                                                   (p->g.NM + 255) / 256));
+  const int nblk = rcs_blocks(p->g.NM);
   const size_t qbytes = ((size_t)n * sizeof(cav::RcsQuery) + 255) / 256 * 256;
   const size_t need = qbytes + (size_t)n * 2 * nblk * sizeof(zd);
   if (need > p->rcs_arena.bytes) {
@@ -1420,6 +1437,10 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
                                    std::to_string(budget));
 
   cavity_plan p = new cavity_plan_s();
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(CAVITY_EDEVICE, "hipGetDevice failed");
+  }
   p->g = g;
   p->opts = o;
   p->st = static_cast<hipStream_t>(o.stream);

@@ -2,7 +2,12 @@
 // (server.cpp).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstddef>
+
+#include "cavity.h"
+#include "kernels.hpp"
 
 namespace cav {
 
@@ -13,5 +18,19 @@ void device_block_release(void* ptr, size_t bytes);
 
 // Record the status and message of the calling thread's last error (cavity_last_error).
 int record_error(int status, const char* msg);
+
+// What the RCS of stored solutions needs from a plan: its sizes, the padded solutions
+// (nsol of them, nvec entries each), its stream and device, and the number of blocks per
+// query of the aperture-transform reduction.
+struct PlanView {
+  Geo g;
+  const zd* xsol;
+  long long nvec;
+  int nsol;
+  hipStream_t stream;
+  int device;
+  int rcs_blocks;
+};
+int plan_view(cavity_plan plan, PlanView* out);
 
 }  // namespace cav

@@ -25,20 +25,22 @@ from .problem import Problem
 from .tbc import bases
 
 
-def synthesize(prob: Problem, cols: Columns, e1, e2, e3) -> np.ndarray:
-    """E_out[3, Nz+1, Ny+1, Nx+1] from the aperture mode values (padded mode grids)."""
+def synthesize(prob: Problem, cols: Columns, e1, e2, e3, levels=None) -> np.ndarray:
+    """E_out[3, Nz+1, Ny+1, Nx+1] from the aperture mode values (padded mode grids); with
+    `levels` (a list of z-nodes) only those levels, E_out[3, len(levels), Ny+1, Nx+1]."""
     x1 = np.arange(prob.nx + 1) * prob.a / prob.nx
     x2 = np.arange(prob.ny + 1) * prob.b / prob.ny
     c1, s1, c2, s2 = bases(prob, x1, x2)
     mu, nu = prob.mu[:, None], prob.nu[None, :]
-    out = np.zeros((3, prob.nz + 1, prob.ny + 1, prob.nx + 1), dtype=complex)
-    for j in range(prob.nz + 1):
+    js = list(range(prob.nz + 1)) if levels is None else list(levels)
+    out = np.zeros((3, len(js), prob.ny + 1, prob.nx + 1), dtype=complex)
+    for o, j in enumerate(js):
         k1 = cols.pi_d[j] * e1 + mu * cols.theta_d[j] * e3
         k2 = cols.pi_d[j] * e2 + nu * cols.theta_d[j] * e3
         k3 = cols.pi_n[j] * e3
-        out[0, j] = (c1.T @ k1 @ s2).T
-        out[1, j] = (s1.T @ k2 @ c2).T
-        out[2, j] = (s1.T @ k3 @ s2).T
+        out[0, o] = (c1.T @ k1 @ s2).T
+        out[1, o] = (s1.T @ k2 @ c2).T
+        out[2, o] = (s1.T @ k3 @ s2).T
     return out
 
 

@@ -78,6 +78,43 @@ def test_lossy_8x8x2_mixed_precision_full_size():
     plan.close()
 
 
+_ORACLE_3LAYER = {}
+
+
+def _oracle_layered():
+    """Spectrum, columns and reduced operator of the 512 x 512 x 128 cavity (computed once
+    per process: the spectrum alone takes about a minute on the host)."""
+    from oracle import columns, spectrum, system
+    if not _ORACLE_3LAYER:
+        prob = Problem.from_cavity(W.layered_16x16x4().cavity)
+        khat = spectrum.kernel_spectrum(prob)
+        cols = columns.eliminate(prob)
+        _ORACLE_3LAYER.update(prob=prob, cols=cols, op=system.ReducedSystem(prob, cols, khat))
+    return _ORACLE_3LAYER["prob"], _ORACLE_3LAYER["cols"], _ORACLE_3LAYER["op"]
+
+
+def _layered_full_levels(plan, fields, incs, precision, tol):
+    """Properties of the 512 x 512 x 128 solution that hold at any size, checked in full:
+    the oracle's reduced operator leaves a residual of at most `tol` at the GPU's aperture
+    solution (the oracle's own GMRES stops at 1e-13), and whole z-levels of the GPU field
+    (bottom, the two interfaces, the node below the aperture and the aperture) equal the
+    oracle's synthesis of that aperture solution element by element."""
+    from oracle import fields as ofields, incident
+    prob, cols, op = _oracle_layered()
+    levels = [0, 32, 96, prob.nz - 1, prob.nz]
+    for i, inc in enumerate(incs):
+        x = plan.aperture(i)
+        g1, g2 = incident.rhs(prob, inc.theta, inc.phi, inc.pol)
+        b = prob.pack(g1, g2, np.zeros_like(g1))
+        res = np.linalg.norm(b - op.matvec(x)) / np.linalg.norm(b)
+        lv = ofields.synthesize(prob, cols, *prob.unpack(x), levels=levels)
+        got = fields[i][:, levels].cpu().numpy()
+        err = np.abs(got - lv).max() / np.abs(lv).max()
+        print(f"[compare] {precision} incidence {i}: oracle residual {res:.2e}, "
+              f"levels {levels} max elementwise {err:.2e}", flush=True)
+        assert res <= tol and err <= 1e-12
+
+
 @pytest.mark.timeout(900)
 def test_layered_16x16x4_against_stored_oracle():
     """Three-layer 16 x 16 x 4 wavelength cavity on the 512 x 512 x 128 grid (P = 1250),
@@ -111,4 +148,41 @@ def test_layered_16x16x4_against_stored_oracle():
         print(f"[compare] incidence {i}: aperture {err_a:.2e}, field {err_f:.2e}, "
               f"rcs {err_r:.2e}", flush=True)
         assert err_a <= 1e-10 and err_f <= 1e-10 and err_r <= 1e-9
+    _layered_full_levels(plan, fields, incs, "fp64", 1e-11)
+    plan.close()
+
+
+@pytest.mark.timeout(900)
+def test_layered_16x16x4_mixed_against_stored_oracle():
+    """The same three-layer 512 x 512 x 128 workload in mixed precision (single-precision
+    convolutions inside GMRES, double-precision refinement residuals) against the stored
+    oracle values within 1e-8, plus the full-size level and residual checks."""
+    import os
+
+    import torch
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "layered_16x16x4.npz")
+    ref = np.load(path)
+    wl = W.layered_16x16x4()
+    print(f"\n[case] {wl.name} mixed", flush=True)
+    incs = wl.incidences
+    plan = P.Plan.from_cavity(wl.cavity, precision="mixed")
+    fields = plan.solve_batch([i.theta for i in incs], [i.phi for i in incs],
+                              [i.pol for i in incs])
+    torch.cuda.synchronize()
+    idx = torch.as_tensor(ref["field_idx"], device="cuda")
+    for i, inc in enumerate(incs):
+        ap = plan.aperture(i)[ref["ap_idx"]]
+        a_ref = ref[f"ap_{i}"]
+        err_a = np.linalg.norm(ap - a_ref) / np.linalg.norm(a_ref)
+        fs = fields[i].reshape(-1).index_select(0, idx).cpu().numpy()
+        f_ref = ref[f"field_{i}"]
+        err_f = np.linalg.norm(fs - f_ref) / np.linalg.norm(f_ref)
+        sig = plan.rcs(i, inc.theta, inc.phi)[0]
+        r_ref = ref[f"rcs_{i}"]
+        co = inc.pol
+        err_r = abs(sig[co] - r_ref[co]) / r_ref[co]
+        print(f"[compare] mixed incidence {i}: aperture {err_a:.2e}, field {err_f:.2e}, "
+              f"rcs {err_r:.2e}", flush=True)
+        assert err_a <= 1e-8 and err_f <= 1e-8 and err_r <= 1e-8
+    _layered_full_levels(plan, fields, incs, "mixed", 1e-11)
     plan.close()

@@ -138,3 +138,51 @@ def test_aperture_cache_reuse_is_exact():
     ref = solver.solve(ora, 0.3, 0.5, W.TM, tol=1e-13)
     oe = solver.field_out(ora, ref)
     assert np.linalg.norm(f2.cpu().numpy() - oe) <= 1e-10 * np.linalg.norm(oe)
+
+
+@pytest.mark.timeout(900)
+def test_served_stream_first_requests():
+    """The first 20 requests of the served stream (cavities of 2 to 12 wavelengths, one to
+    three layers) submitted together to the server in mixed precision: every field and
+    backscatter RCS within 1e-8 of the same request solved alone in double precision, and
+    those of side at most 4 wavelengths within 1e-8 of the oracle."""
+    import torch
+    stream = W.served_stream(20)
+    print(f"\n[case] served stream, first {len(stream)} requests", flush=True)
+    srv = P.Server(streams=4, precision="mixed")
+    outs, tickets = [], []
+    for req in stream:
+        cav, inc = req.workload.cavity, req.workload.incidences[0]
+        o = torch.empty((3, cav.nz + 1, cav.ny + 1, cav.nx + 1), dtype=torch.complex128,
+                        device="cuda")
+        outs.append(o)
+        tickets.append(srv.submit(cav, inc.theta, inc.phi, inc.pol, out=o))
+    results = [srv.wait(t) for t in tickets]
+    for t in tickets:
+        srv.release(t)
+    srv.close()
+    torch.cuda.synchronize()
+    n_oracle = 0
+    for k, (req, r, o) in enumerate(zip(stream, results, outs)):
+        cav, inc = req.workload.cavity, req.workload.incidences[0]
+        assert r.status == 0, (k, r.status)
+        co = inc.pol
+        f64, s64 = _alone(cav, inc, "fp64")
+        e = float(torch.linalg.vector_norm(o - f64) / torch.linalg.vector_norm(f64))
+        er = abs(r.sigma[co] - s64[co]) / s64[co]
+        del f64
+        msg = f"[compare] request {k} ({cav.a:g} lambda, {cav.nx}x{cav.ny}x{cav.nz}): " \
+              f"vs double alone field {e:.2e} rcs {er:.2e}"
+        assert e <= 1e-8 and er <= 1e-8, msg
+        if cav.a <= 4.0:
+            ora = solver.plan(Problem.from_cavity(cav))
+            ref = solver.solve(ora, inc.theta, inc.phi, inc.pol, tol=1e-13)
+            oe = solver.field_out(ora, ref)
+            eo = np.linalg.norm(o.cpu().numpy() - oe) / np.linalg.norm(oe)
+            so = solver.backscatter(ora, ref, inc.theta, inc.phi)
+            ro = abs(r.sigma[co] - so[co]) / so[co]
+            msg += f"; vs oracle field {eo:.2e} rcs {ro:.2e}"
+            assert eo <= 1e-8 and ro <= 1e-8, msg
+            n_oracle += 1
+        print(msg, flush=True)
+    assert n_oracle >= 5

@@ -50,7 +50,19 @@ int next_5smooth(long long n) {
   return (int)n;
 }
 
-cav::FftPlan make_fft_plan(int n) { return cav::plan_fft(n, cav::kMaxRadix); }
+// Stages of radix at most 8 when n factors that way in no more stages than with the larger
+// radices (the kernels compiled for radices up to 8 hold half the registers), else up to the
+// largest compiled radix.
+cav::FftPlan make_fft_plan(int n) {
+  const cav::FftPlan small = cav::plan_fft(n, cav::kSmallRadix);
+  const cav::FftPlan big = cav::plan_fft(n, cav::kMaxRadix);
+  return (small.nst > 0 && small.nst <= big.nst) || n <= 1 ? small : big;
+}
+int plan_max_radix(const cav::FftPlan& p) {
+  int r = 1;
+  for (int s = 0; s < p.nst; ++s) r = std::max(r, p.radix[s]);
+  return r;
+}
 
 // LDS of one workgroup on gfx950 (160 KiB); every FFT kernel needs two buffers of its
 // longest transform for at least one column.
@@ -505,9 +517,10 @@ int run_operator(cavity_plan p, int precond, int nb, const zd* v, zd* y, const i
 // budgets and keeps the fastest; later plans of the same shape reuse the choice.
 // CAVITY_AUTOTUNE=0 turns this off (default budget), CAVITY_LDS_BUDGET fixes the budget.
 struct TuneKey {
-  int P1, P2, nq1, nq2, single;
+  int P1, P2, nq1, nq2, single, maxr;
   bool operator<(const TuneKey& o) const {
-    return std::tie(P1, P2, nq1, nq2, single) < std::tie(o.P1, o.P2, o.nq1, o.nq2, o.single);
+    return std::tie(P1, P2, nq1, nq2, single, maxr) <
+           std::tie(o.P1, o.P2, o.nq1, o.nq2, o.single, o.maxr);
   }
 };
 std::mutex g_tune_mu;
@@ -518,7 +531,7 @@ int autotune_lds(cavity_plan p) {
   if ((e && std::atoi(e) == 0) || std::getenv("CAVITY_LDS_BUDGET") || p->use_spec())
     return CAVITY_OK;
   const bool single = p->opts.precision == CAVITY_MIXED;
-  const TuneKey key{p->g.P1, p->g.P2, p->g.nq1, p->g.nq2, single ? 1 : 0};
+  const TuneKey key{p->g.P1, p->g.P2, p->g.nq1, p->g.nq2, single ? 1 : 0, p->trig.maxr};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
@@ -1083,12 +1096,18 @@ int solve_chunk(cavity_plan p, int i0, int nb, const double* theta, const double
   const long long field = 3LL * (p->g.Nz + 1) * (p->g.ny + 1) * (p->g.nx + 1);
   if (E_out) {
     if ((s0 = mark(p, 5, false))) return s0;
-    for (int r = 0; r < nb; ++r) {
-      for (int j0 = 0; j0 <= p->g.Nz; j0 += p->synth_chunk) {
-        const int j1 = std::min(p->g.Nz + 1, j0 + p->synth_chunk);
+    // the staging slab holds synth_chunk levels of one field: each launch pair takes up to
+    // that many (field, level) pairs, all fields of the group together when they fit
+    const int rg = std::min(nb, p->synth_chunk);
+    const int jn = std::max(1, p->synth_chunk / rg);
+    for (int r0 = 0; r0 < nb; r0 += rg) {
+      const int nr = std::min(rg, nb - r0);
+      for (int j0 = 0; j0 <= p->g.Nz; j0 += jn) {
+        const int j1 = std::min(p->g.Nz + 1, j0 + jn);
         HIPCHK(cav::launch_synthesis(p->g, p->trig, p->pi_d, p->layered ? p->theta_d : nullptr,
-                                     p->pi_n, x + (long long)r * p->nvec(), j0, j1, p->tbuf,
-                                     reinterpret_cast<zd*>(E_out) + r * field, p->st));
+                                     p->pi_n, x + (long long)r0 * p->nvec(), p->nvec(), nr, j0,
+                                     j1, p->tbuf, reinterpret_cast<zd*>(E_out) + r0 * field,
+                                     field, p->st));
       }
     }
     if ((s0 = mark(p, 5, true))) return s0;
@@ -1503,13 +1522,18 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     int off = 0;
     cav::Fft* dst[6] = {&p->trig.ext1, &p->trig.ext2, &p->trig.box1, &p->trig.box2,
                         &p->trig.out1, &p->trig.out2};
+    p->trig.maxr = 1;
     for (int i = 0; i < 6; ++i) {
       twiddle_table(fft_len[i], tw.data() + off);
       dst[i]->p = make_fft_plan(fft_len[i]);
       dst[i]->tw = p->twiddles + off;
       dst[i]->twf = p->twiddles_f + off;
+      p->trig.maxr = std::max(p->trig.maxr, plan_max_radix(dst[i]->p));
       off += fft_len[i];
     }
+    // CAVITY_FFT_MAXR=16: the same plans run by the kernels compiled for radices up to 16
+    if (const char* e = std::getenv("CAVITY_FFT_MAXR"))
+      if (std::atoi(e) == cav::kMaxRadix) p->trig.maxr = cav::kMaxRadix;
     for (int t = 0; t < twn; ++t) twf[t] = cav::cvt<float>(tw[t]);
   }
   std::vector<int> code(Nz + 1, 0);

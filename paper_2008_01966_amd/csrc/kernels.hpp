@@ -34,14 +34,18 @@ __device__ inline const zd* twiddles<double>(const Fft& f) { return f.tw; }
 template <>
 __device__ inline const zf* twiddles<float>(const Fft& f) { return f.twf; }
 
-// Largest radix compiled into the FFT kernels (the planner's limit).
+// Largest radix compiled into the FFT kernels (the planner's limit).  Each FFT kernel also
+// has a form compiled with radices up to 8 only: about half the registers, so more waves
+// per SIMD; a plan uses it when all its transform lengths factor into radices up to 8.
 constexpr int kMaxRadix = 16;
+constexpr int kSmallRadix = 8;
 
 // The transforms one plan needs.
 struct Trig {
   Fft ext1, ext2;   // length 2*nq1, 2*nq2: sine/cosine transforms on the TBC grid
   Fft box1, box2;   // length P1, P2: the zero-padded convolution
   Fft out1, out2;   // length 2*Nx, 2*Ny: sine/cosine transforms on the output grid
+  int maxr;         // largest radix of the six plans (kSmallRadix or kMaxRadix kernels)
 };
 
 // Layer description on the z-grid for the elimination kernel.
@@ -206,10 +210,11 @@ hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long
 hipError_t launch_combine(const Geo& g, const Krylov& kv, const zf* V, long long ldj,
                           const zd* pinv, zd* x, int nb, hipStream_t st);
 
-// Back-substitution and synthesis of E_out for levels [j0, j1).
+// Back-substitution and synthesis of levels [j0, j1) of nr fields: solution r at
+// xap + r xs, field r at eout + r es; tbuf holds 3 nr (j1 - j0) staging levels.
 hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const zd* theta_d,
-                            const zd* pi_n, const zd* xap, int j0, int j1, zd* tbuf,
-                            zd* eout, hipStream_t st);
+                            const zd* pi_n, const zd* xap, long long xs, int nr, int j0, int j1,
+                            zd* tbuf, zd* eout, long long es, hipStream_t st);
 // Aperture transforms E^1(u), E^2(u) for nq queries: per-block partial sums (2 complex per
 // block and query); solution r at xall + r * n.
 hipError_t launch_rcs_partial(const Geo& g, const zd* xall, long long n, const RcsQuery* queries,

@@ -96,7 +96,7 @@ __device__ inline bool fam_ycos(int f) { return f != 0; }
 // Pass 1: rows m0 .. m0+Cb-1 of one family.  fam_fixed >= 0: `v` is the coefficient grid
 // of that family (inspection path); otherwise `v` is a padded aperture vector, optionally
 // preconditioned first.
-template <typename T>
+template <typename T, int MR>
 __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
                                                       const zd* __restrict__ pinv, int precond,
                                                       int fam_fixed, int lc, int ip,
@@ -155,8 +155,8 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
   }
   __syncthreads();
   cx<T>* r = a;
-  if (ip) fft_lds_ip<T, false, kMaxRadix>(a, ext2.p, twiddles<T>(ext2), tid, lc);
-  else r = fft_lds<T, false, kMaxRadix>(a, b, ext2.p, twiddles<T>(ext2), tid, nt, lc);
+  if (ip) fft_lds_ip<T, false, MR>(a, ext2.p, twiddles<T>(ext2), tid, lc);
+  else r = fft_lds<T, false, MR>(a, b, ext2.p, twiddles<T>(ext2), tid, nt, lc);
   cx<T>* o = (r == a) ? b : a;
   const T hq = (T)g.hq2;
   for (int w = tid; w < P << lc; w += nt) {
@@ -171,8 +171,8 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
   }
   __syncthreads();
   cx<T>* r2 = o;
-  if (ip) fft_lds_ip<T, false, kMaxRadix>(o, box2.p, twiddles<T>(box2), tid, lc);
-  else r2 = fft_lds<T, false, kMaxRadix>(o, r, box2.p, twiddles<T>(box2), tid, nt, lc);
+  if (ip) fft_lds_ip<T, false, MR>(o, box2.p, twiddles<T>(box2), tid, lc);
+  else r2 = fft_lds<T, false, MR>(o, r, box2.p, twiddles<T>(box2), tid, nt, lc);
   cx<T>* dst = X + ((long long)slot * (g.M + 1) + m0) * g.P2;
   for (int w = tid; w < P * Cb; w += nt) {
     const int c = div_p.quot(w), k = w - c * div_p.d;
@@ -206,7 +206,7 @@ struct ColumnStore {
   }
 };
 
-template <typename T>
+template <typename T, int MR>
 __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
                                                   const cx<T>* __restrict__ khat, int fam_fixed,
                                                   int lc, const cx<T>* __restrict__ Xall,
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   __syncthreads();
   const cx<T>* tw_e = twiddles<T>(ext1);
   const cx<T>* tw_b = twiddles<T>(box1);
-  cx<T>* r = fft_lds<T, false, kMaxRadix>(a, b, ext1.p, tw_e, tid, nt, lc);
+  cx<T>* r = fft_lds<T, false, MR>(a, b, ext1.p, tw_e, tid, nt, lc);
   cx<T>* o = (r == a) ? b : a;
   const T hq = (T)g.hq1;
   for (int w = tid; w < P << lc; w += nt) {
@@ -259,9 +259,9 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   }
   __syncthreads();
   // the product with K-hat rides on the transform's last stage
-  cx<T>* r2 = fft_lds_put<T, false, kMaxRadix>(o, r, box1.p, tw_b, tid, nt, lc,
+  cx<T>* r2 = fft_lds_put<T, false, MR>(o, r, box1.p, tw_b, tid, nt, lc,
                                                SpectrumProduct<T>{khat + k0, g.P2, Cb, lc});
-  cx<T>* r3 = fft_lds<T, true, kMaxRadix>(r2, (r2 == a) ? b : a, box1.p, tw_b, tid, nt, lc);
+  cx<T>* r3 = fft_lds<T, true, MR>(r2, (r2 == a) ? b : a, box1.p, tw_b, tid, nt, lc);
   cx<T>* o3 = (r3 == a) ? b : a;
   for (int w = tid; w < (L + 1) << lc; w += nt) {
     const int i = w >> lc, c = w & (C - 1);
@@ -269,12 +269,12 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   }
   __syncthreads();
   // the last stage writes the projected entries m = 0..M straight to Y
-  fft_lds_put<T, false, kMaxRadix>(o3, r3, ext1.p, tw_e, tid, nt, lc,
+  fft_lds_put<T, false, MR>(o3, r3, ext1.p, tw_e, tid, nt, lc,
                                    ColumnStore<T>{Y + k0, g.P2, g.M + 1, Cb, xcos, hq});
 }
 
 // Pass 3: rows m0 .. m0+Cb-1 backward; writes S[slot][mn] in double.
-template <typename T>
+template <typename T, int MR>
 __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed,
                                                       int lc, int ip,
                                                       const cx<T>* __restrict__ Yall,
@@ -306,8 +306,8 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
   __syncthreads();
   // in place: a holds the box transform (P), b the extension transform (2L)
   cx<T>* r = a;
-  if (ip) fft_lds_ip<T, true, kMaxRadix>(a, box2.p, twiddles<T>(box2), tid, lc);
-  else r = fft_lds<T, true, kMaxRadix>(a, b, box2.p, twiddles<T>(box2), tid, nt, lc);
+  if (ip) fft_lds_ip<T, true, MR>(a, box2.p, twiddles<T>(box2), tid, lc);
+  else r = fft_lds<T, true, MR>(a, b, box2.p, twiddles<T>(box2), tid, nt, lc);
   cx<T>* o = (r == a) ? b : a;
   for (int w = tid; w < (L + 1) << lc; w += nt) {
     const int i = w >> lc, c = w & (C - 1);
@@ -315,8 +315,8 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
   }
   __syncthreads();
   cx<T>* r2 = o;
-  if (ip) fft_lds_ip<T, false, kMaxRadix>(o, ext2.p, twiddles<T>(ext2), tid, lc);
-  else r2 = fft_lds<T, false, kMaxRadix>(o, r, ext2.p, twiddles<T>(ext2), tid, nt, lc);
+  if (ip) fft_lds_ip<T, false, MR>(o, ext2.p, twiddles<T>(ext2), tid, lc);
+  else r2 = fft_lds<T, false, MR>(o, r, ext2.p, twiddles<T>(ext2), tid, nt, lc);
   const int rowlen = g.N + 1;
   const DivBy div_row(rowlen);
   for (int w = tid; w < rowlen * Cb; w += nt) {
@@ -424,8 +424,12 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
       tbc_shape(t.ext2.p, t.box2.p, g.nq2, g.P2, (int)tb, g.M + 1, g.lds_budget, g.rows_ip);
   const int gr = (g.M + 1 + (1 << sr.lc) - 1) >> sr.lc;
   probe_begin(id_fwd, st);
-  hipLaunchKernelGGL((k_tbc_rows_fwd<T>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g, t.ext2,
-                     t.box2, pinv, precond, fam_fixed, sr.lc, sr.ip, v, vs, X, active);
+  if (t.maxr <= 8)
+    hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g, t.ext2,
+                       t.box2, pinv, precond, fam_fixed, sr.lc, sr.ip, v, vs, X, active);
+  else
+    hipLaunchKernelGGL((k_tbc_rows_fwd<T, kMaxRadix>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
+                       t.ext2, t.box2, pinv, precond, fam_fixed, sr.lc, sr.ip, v, vs, X, active);
   probe_end(id_fwd, st, vin + xbytes);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -434,14 +438,23 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
   const TbcShape sc =
       tbc_shape(t.ext1.p, t.box1.p, g.nq1, g.P1, (int)tb, g.P2, g.lds_budget, false);
   probe_begin(id_cols, st);
-  hipLaunchKernelGGL((k_tbc_cols<T>), dim3((g.P2 + (1 << sc.lc) - 1) >> sc.lc, nf, nb), dim3(256),
-                     sc.smem, st, g, t.ext1, t.box1, khat, fam_fixed, sc.lc, X, Y, active);
+  const dim3 gc((g.P2 + (1 << sc.lc) - 1) >> sc.lc, nf, nb);
+  if (t.maxr <= 8)
+    hipLaunchKernelGGL((k_tbc_cols<T, 8>), gc, dim3(256), sc.smem, st, g, t.ext1, t.box1, khat,
+                       fam_fixed, sc.lc, X, Y, active);
+  else
+    hipLaunchKernelGGL((k_tbc_cols<T, kMaxRadix>), gc, dim3(256), sc.smem, st, g, t.ext1, t.box1,
+                       khat, fam_fixed, sc.lc, X, Y, active);
   probe_end(id_cols, st, 2.0 * xbytes + tb * (double)g.P1 * g.P2);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   probe_begin(id_bwd, st);
-  hipLaunchKernelGGL((k_tbc_rows_bwd<T>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g, t.ext2,
-                     t.box2, fam_fixed, sr.lc, sr.ip, Y, S, active);
+  if (t.maxr <= 8)
+    hipLaunchKernelGGL((k_tbc_rows_bwd<T, 8>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g, t.ext2,
+                       t.box2, fam_fixed, sr.lc, sr.ip, Y, S, active);
+  else
+    hipLaunchKernelGGL((k_tbc_rows_bwd<T, kMaxRadix>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
+                       t.ext2, t.box2, fam_fixed, sr.lc, sr.ip, Y, S, active);
   probe_end(id_bwd, st, xbytes + zb * nb * nf * g.NM);
   return hipGetLastError();
 }
@@ -1172,18 +1185,26 @@ hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const doubl
 //   E1 = Pi_j a1 + mu_m Theta_j a3,  E2 = Pi_j a2 + nu_n Theta_j a3,  E3 = Pi3_j a3,
 // then the 2D sine/cosine series is summed on the output nodes: rows along y, then
 // columns along x with TK adjacent columns per block.
-// tbuf[l][jj][m][i2], jj = j - j0.
+// One launch pair covers nr right-hand sides (solutions at xap + r xs) and jn levels from
+// j0; the staging slab is tbuf[r][l][jj][m][i2], jj = j - j0.  The profiles do not depend
+// on the right-hand side: a row block (row strip, level, component) takes kSynthRhsPerBlock
+// right-hand sides in turn, and the blocks of one strip run next to each other on one XCD,
+// so each profile strip comes from HBM about once per launch.
 // ---------------------------------------------------------------------------------
+constexpr int kSynthRhsPerBlock = 4;
+
+template <int MR>
 __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int ip,
                                                     const zd* __restrict__ pi_d,
                                                     const zd* __restrict__ theta_d,
                                                     const zd* __restrict__ pi_n,
-                                                    const zd* __restrict__ xap, int j0, int jn,
+                                                    const zd* __restrict__ xap, long long xs,
+                                                    int nr, int j0, int jn,
                                                     zd* __restrict__ tbuf) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ zd c0s[64];
-  const BlockId bid = xcd_block();
-  const int jj = bid.y, l = bid.z;
+  const BlockId bid = xcd_block_x_slow();
+  const int jj = bid.y / 3, l = bid.y - 3 * jj;
   const int j = j0 + jj;
   const int C = 1 << lc;
   const int m0 = bid.x << lc;
@@ -1194,47 +1215,55 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int
   zd* b = a + ((2LL * L) << lc);   // second buffer of the ping-pong form only
   const bool ycos = (l == 1);  // E1: sin, E2: cos, E3: sin along y
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk(0.0, 0.0);
-  __syncthreads();
   const long long NM = g.NM;
   const int rowlen = g.N + 1;
   const DivBy div_row(rowlen);
-  for (int w = tid; w < rowlen * Cb; w += nt) {
-    const int c = div_row.quot(w), n = w - c * div_row.d;
-    const int m = m0 + c;
-    const long long mn = (long long)m * rowlen + n;
-    zd val;
-    if (l < 2) {
-      val = pi_d[(long long)j * NM + mn] * xap[l * NM + mn];
-      if (theta_d) {
-        const double fac = l == 0 ? M_PI * m / g.a : M_PI * n / g.b;
-        val = val + fac * (theta_d[(long long)j * NM + mn] * xap[2 * NM + mn]);
+  const int r0 = bid.z * kSynthRhsPerBlock;
+  const int r1 = min(nr, r0 + kSynthRhsPerBlock);
+  for (int r = r0; r < r1; ++r) {
+    const zd* x = xap + r * xs;
+    for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk(0.0, 0.0);
+    __syncthreads();
+    for (int w = tid; w < rowlen * Cb; w += nt) {
+      const int c = div_row.quot(w), n = w - c * div_row.d;
+      const int m = m0 + c;
+      const long long mn = (long long)m * rowlen + n;
+      zd val;
+      if (l < 2) {
+        val = pi_d[(long long)j * NM + mn] * x[l * NM + mn];
+        if (theta_d) {
+          const double fac = l == 0 ? M_PI * m / g.a : M_PI * n / g.b;
+          val = val + fac * (theta_d[(long long)j * NM + mn] * x[2 * NM + mn]);
+        }
+      } else {
+        val = pi_n[(long long)j * NM + mn] * x[2 * NM + mn];
       }
-    } else {
-      val = pi_n[(long long)j * NM + mn] * xap[2 * NM + mn];
+      store_extension(a, L, ycos, n, val, lc, c);
+      if (n == 0) c0s[c] = val;
     }
-    store_extension(a, L, ycos, n, val, lc, c);
-    if (n == 0) c0s[c] = val;
-  }
-  __syncthreads();
-  zd* r = a;
-  if (ip) fft_lds_ip<double, false, kMaxRadix>(a, out2.p, out2.tw, tid, lc);
-  else r = fft_lds<double, false, kMaxRadix>(a, b, out2.p, out2.tw, tid, nt, lc);
-  zd* dst = tbuf + (((long long)l * jn + jj) * (g.M + 1) + m0) * (g.ny + 1);
-  for (int w = tid; w < (L + 1) * Cb; w += nt) {
-    const int c = div_l1.quot(w), i = w - c * div_l1.d;
-    const zd F = r[(i << lc) + c];
-    dst[(long long)c * (g.ny + 1) + i] = ycos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
+    __syncthreads();
+    zd* rr = a;
+    if (ip) fft_lds_ip<double, false, MR>(a, out2.p, out2.tw, tid, lc);
+    else rr = fft_lds<double, false, MR>(a, b, out2.p, out2.tw, tid, nt, lc);
+    zd* dst = tbuf + ((((long long)r * 3 + l) * jn + jj) * (g.M + 1) + m0) * (g.ny + 1);
+    for (int w = tid; w < (L + 1) * Cb; w += nt) {
+      const int c = div_l1.quot(w), i = w - c * div_l1.d;
+      const zd F = rr[(i << lc) + c];
+      dst[(long long)c * (g.ny + 1) + i] = ycos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
+    }
+    __syncthreads();
   }
 }
 
+// Columns: blockIdx.y = jj * 3 + l, blockIdx.z = right-hand side r; field r at eout + r es.
+template <int MR>
 __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int ip, int j0, int jn,
                                                     const zd* __restrict__ tbuf,
-                                                    zd* __restrict__ eout) {
+                                                    zd* __restrict__ eout, long long es) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ zd c0s[64];
   const BlockId bid = xcd_block();
-  const int jj = bid.y, l = bid.z;
+  const int jj = bid.y / 3, l = bid.y - 3 * jj, r = bid.z;
   const int j = j0 + jj;
   const int C = 1 << lc;
   const int i0 = bid.x << lc;
@@ -1244,7 +1273,7 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
   zd* a = reinterpret_cast<zd*>(smem_raw);
   zd* b = a + ((2LL * L) << lc);   // second buffer of the ping-pong form only
   const bool xcos = (l == 0);  // E1: cos, E2: sin, E3: sin along x
-  const zd* src = tbuf + ((long long)l * jn + jj) * (g.M + 1) * (g.ny + 1);
+  const zd* src = tbuf + (((long long)r * 3 + l) * jn + jj) * (g.M + 1) * (g.ny + 1);
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk(0.0, 0.0);
   __syncthreads();
@@ -1256,13 +1285,13 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
     if (m == 0) c0s[c] = x;
   }
   __syncthreads();
-  zd* r = a;
-  if (ip) fft_lds_ip<double, false, kMaxRadix>(a, out1.p, out1.tw, tid, lc);
-  else r = fft_lds<double, false, kMaxRadix>(a, b, out1.p, out1.tw, tid, nt, lc);
-  zd* dst = eout + (((long long)l * (g.Nz + 1) + j) * (g.ny + 1) + i0) * (g.nx + 1);
+  zd* rr = a;
+  if (ip) fft_lds_ip<double, false, MR>(a, out1.p, out1.tw, tid, lc);
+  else rr = fft_lds<double, false, MR>(a, b, out1.p, out1.tw, tid, nt, lc);
+  zd* dst = eout + r * es + (((long long)l * (g.Nz + 1) + j) * (g.ny + 1) + i0) * (g.nx + 1);
   for (int w = tid; w < (L + 1) * Cb; w += nt) {
     const int c = div_l1.quot(w), i = w - c * div_l1.d;
-    const zd F = r[(i << lc) + c];
+    const zd F = rr[(i << lc) + c];
     dst[(long long)c * (g.nx + 1) + i] = xcos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
   }
 }
@@ -1286,29 +1315,39 @@ static SynthShape synth_shape(const FftPlan& p, int len, int cap, int budget) {
 }
 
 hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const zd* theta_d,
-                            const zd* pi_n, const zd* xap, int j0, int j1, zd* tbuf, zd* eout,
-                            hipStream_t st) {
+                            const zd* pi_n, const zd* xap, long long xs, int nr, int j0, int j1,
+                            zd* tbuf, zd* eout, long long es, hipStream_t st) {
   const int jn = j1 - j0;
   const double zb = sizeof(zd);
-  const double tb = zb * 3.0 * jn * (g.M + 1) * (double)(g.ny + 1);   // staging slab
+  const double tb = zb * 3.0 * nr * jn * (g.M + 1) * (double)(g.ny + 1);   // staging slab
   const double prof = zb * (double)jn * g.NM * (theta_d ? 3.0 : 2.0);
   static const int synth_budget = [] {
     const char* e = getenv("CAVITY_SYNTH_LDS");
     return e ? atoi(e) : 0;
   }();
   const SynthShape sr = synth_shape(t.out2.p, g.ny, g.M + 1, synth_budget);
+  const int rgroups = (nr + kSynthRhsPerBlock - 1) / kSynthRhsPerBlock;
   probe_begin(K_SYNTH_ROWS, st);
-  hipLaunchKernelGGL(k_synth_rows, dim3((g.M + 1 + (1 << sr.lc) - 1) >> sr.lc, jn, 3), dim3(256),
-                     sr.smem, st, g, t.out2, sr.lc, sr.ip, pi_d, theta_d, pi_n, xap, j0, jn,
-                     tbuf);
-  probe_end(K_SYNTH_ROWS, st, prof + zb * 3.0 * g.NM + tb);
+  const dim3 grs((g.M + 1 + (1 << sr.lc) - 1) >> sr.lc, 3 * jn, rgroups);
+  if (t.maxr <= 8)
+    hipLaunchKernelGGL(k_synth_rows<8>, grs, dim3(256), sr.smem, st, g, t.out2, sr.lc, sr.ip, pi_d,
+                       theta_d, pi_n, xap, xs, nr, j0, jn, tbuf);
+  else
+    hipLaunchKernelGGL(k_synth_rows<kMaxRadix>, grs, dim3(256), sr.smem, st, g, t.out2, sr.lc,
+                       sr.ip, pi_d, theta_d, pi_n, xap, xs, nr, j0, jn, tbuf);
+  probe_end(K_SYNTH_ROWS, st, prof + zb * 3.0 * g.NM * nr + tb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const SynthShape sc = synth_shape(t.out1.p, g.nx, g.ny + 1, synth_budget);
   probe_begin(K_SYNTH_COLS, st);
-  hipLaunchKernelGGL(k_synth_cols, dim3((g.ny + 1 + (1 << sc.lc) - 1) >> sc.lc, jn, 3), dim3(256),
-                     sc.smem, st, g, t.out1, sc.lc, sc.ip, j0, jn, tbuf, eout);
-  probe_end(K_SYNTH_COLS, st, tb + zb * 3.0 * jn * (g.ny + 1) * (double)(g.nx + 1));
+  const dim3 gcs((g.ny + 1 + (1 << sc.lc) - 1) >> sc.lc, 3 * jn, nr);
+  if (t.maxr <= 8)
+    hipLaunchKernelGGL(k_synth_cols<8>, gcs, dim3(256), sc.smem, st, g, t.out1, sc.lc, sc.ip, j0,
+                       jn, tbuf, eout, es);
+  else
+    hipLaunchKernelGGL(k_synth_cols<kMaxRadix>, gcs, dim3(256), sc.smem, st, g, t.out1, sc.lc,
+                       sc.ip, j0, jn, tbuf, eout, es);
+  probe_end(K_SYNTH_COLS, st, tb + zb * 3.0 * nr * jn * (g.ny + 1) * (double)(g.nx + 1));
   return hipGetLastError();
 }
 

@@ -244,15 +244,20 @@ const char* cavity_last_error(void);
  * A request is one cavity (geometry, grid, layers, k) and one incidence; its result is
  * the field on all nodes (the E_out of cavity_solve) and the backscatter RCS.  The server
  * runs requests on `streams` worker threads, each with its own HIP stream on the device
- * that was current when the server was created, so requests overlap on the GPU.  A
- * request is admitted in arrival order once a worker is free and its device footprint
- * (cavity_plan_footprint, plus its field when the server holds it) fits in what the
- * budget leaves; requests larger
- * than the whole budget fail with CAVITY_ENOMEM.  The kernel spectrum and operator
- * diagonal of an aperture are cached across plans (Section 5 quantities depend on a, b,
- * k, Nx, Ny only).  Results are independent of the mix: a request computes exactly what
- * cavity_plan_create + cavity_solve + cavity_rcs compute for it alone.  All functions
- * are thread-safe. */
+ * that was current when the server was created, so requests overlap on the GPU.
+ * Admission: a free worker takes the oldest queued request whose device footprint
+ * (cavity_plan_footprint, plus its field when the server holds it) fits in what the budget
+ * leaves, so a large request at the head does not hold back smaller ones that fit; once the
+ * head has been passed over for 25 ms, nothing else is admitted until it starts.  Requests
+ * larger than the whole budget fail with CAVITY_ENOMEM.  The kernel spectrum and operator
+ * diagonal of an aperture are cached across plans (Section 5 quantities depend on a, b, k,
+ * Nx, Ny only), and the whole plan of a finished request (spectrum, per-mode elimination of
+ * Sections 3-4, preconditioner, workspaces) stays resident, charged to the budget, for a
+ * later request on the same cavity, which then skips plan creation; resident plans are
+ * dropped least recently used first when admission needs their memory or their total
+ * exceeds plan_cache_bytes.  Results are independent of the mix and of plan reuse: a
+ * request computes exactly what cavity_plan_create + cavity_solve + cavity_rcs compute for
+ * it alone.  All functions are thread-safe. */
 typedef struct cavity_server_s* cavity_server;
 
 typedef struct {
@@ -261,6 +266,9 @@ typedef struct {
                            free device memory at creation */
   int precision;        /* CAVITY_FP64 or CAVITY_MIXED (default) */
   double tol;           /* GMRES tolerance (default 1e-12) */
+  size_t plan_cache_bytes; /* most device bytes of resident plans kept for repeated cavities
+                              (inside the budget); (size_t)-1, the default, = 25 % of the
+                              budget; 0 = no plan reuse */
 } cavity_server_opts;
 
 typedef struct {
@@ -284,6 +292,8 @@ typedef struct {
   long long unknowns;           /* n_ap * Nz */
   size_t device_bytes;          /* bytes the request held while running */
   double t_submit_ms, t_start_ms, t_done_ms;   /* server clock: ms since creation */
+  int plan_reused;              /* 1 when the request ran on a resident plan of an earlier
+                                   request on the same cavity */
 } cavity_result;
 
 int cavity_server_opts_default(cavity_server_opts* opts);

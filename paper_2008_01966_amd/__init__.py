@@ -63,7 +63,8 @@ class Info(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_int), ("hbm_budget", ctypes.c_size_t),
-                ("precision", ctypes.c_int), ("tol", ctypes.c_double)]
+                ("precision", ctypes.c_int), ("tol", ctypes.c_double),
+                ("plan_cache_bytes", ctypes.c_size_t)]
 
 
 class Request(ctypes.Structure):
@@ -80,7 +81,7 @@ class Result(ctypes.Structure):
                 ("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double),
                 ("unknowns", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t),
                 ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
-                ("t_done_ms", ctypes.c_double)]
+                ("t_done_ms", ctypes.c_double), ("plan_reused", ctypes.c_int)]
 
 
 EXPORTS = [
@@ -403,17 +404,20 @@ def probe_stop():
 
 class Server:
     """Request server of the library: cavities of any size solved for one incidence each,
-    several in flight on the GPU, admitted in arrival order within a device-memory budget.
+    several in flight on the GPU, the oldest queued request that fits admitted within a
+    device-memory budget, plans of finished requests kept resident for repeated cavities.
     Results carry the backscatter RCS, iteration count and timestamps; the field goes to
     the caller's device tensor when one is given to submit()."""
 
     def __init__(self, streams: int = 4, hbm_budget: int = 0, precision: str = "mixed",
-                 tol: float = 1e-12):
+                 tol: float = 1e-12, plan_cache_bytes: Optional[int] = None):
         lib = load_library()
         self._lib = lib
         o = ServerOpts()
         _check(lib.cavity_server_opts_default(ctypes.byref(o)))
         o.streams, o.hbm_budget, o.tol = int(streams), int(hbm_budget), float(tol)
+        if plan_cache_bytes is not None:
+            o.plan_cache_bytes = int(plan_cache_bytes)
         o.precision = PRECISIONS[precision]
         h = ctypes.c_void_p()
         _check(lib.cavity_server_create(ctypes.byref(o), ctypes.byref(h)))

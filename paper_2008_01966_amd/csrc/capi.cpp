@@ -320,6 +320,12 @@ int plan_view(cavity_plan p, PlanView* out) {
   out->rcs_blocks = rcs_blocks(p->g.NM);
   return CAVITY_OK;
 }
+int plan_set_stream(cavity_plan p, hipStream_t st) {
+  if (!p) return fail(CAVITY_EINVAL, "NULL plan");
+  p->st = st;
+  p->opts.stream = st;
+  return CAVITY_OK;
+}
 }  // namespace cav
 
 namespace {

@@ -33,4 +33,8 @@ struct PlanView {
 };
 int plan_view(cavity_plan plan, PlanView* out);
 
+// Move a plan to stream st: all its later work is queued there.  The caller guarantees
+// that no work of the plan is pending on its previous stream.
+int plan_set_stream(cavity_plan plan, hipStream_t st);
+
 }  // namespace cav

@@ -1,12 +1,14 @@
 // Request server: many cavities, each solved for one incidence, with several requests in
-// flight on the GPU at once.  Worker threads each own a HIP stream; a request is admitted
-// in arrival order when a worker is free and its device footprint fits in the budget left
-// by the requests already running.
+// flight on the GPU at once.  Worker threads each own a HIP stream; a free worker takes the
+// oldest queued request whose device footprint fits in the budget left by the requests
+// running and the resident plans, and the plan of a finished request stays resident for a
+// later request on the same cavity.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdint>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -21,12 +23,16 @@
 
 namespace {
 
+// A request passed over by later ones for longer than this is the only one admitted next.
+constexpr double kMaxBypassMs = 25.0;
+
 struct Pending {
   long long ticket;
   cavity_request req;
   std::vector<int> lnz;
   std::vector<cavity_c128> eps;
-  size_t footprint;       // plan + workspace + solution (+ field when the server holds it)
+  std::string key;        // the cavity (geometry, grid, layers, k): equal keys share a plan
+  size_t plan_bytes;      // plan + workspace + solution (cavity_plan_footprint)
   size_t field_bytes;     // temporary field buffer, 0 when the caller gave E_out
   double t_submit_ms;
 };
@@ -35,18 +41,44 @@ struct Done {
   cavity_result res;
 };
 
+// A plan kept after its request, charged to the budget at its footprint.
+struct Resident {
+  std::string key;
+  cavity_plan plan;
+  size_t bytes;
+  unsigned long long last_use;
+  bool busy;
+};
+
+std::string cavity_key(const cavity_request& r, const std::vector<int>& lnz,
+                       const std::vector<cavity_c128>& eps) {
+  std::string k;
+  auto put = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+  const double d[4] = {r.a, r.b, r.c, r.k};
+  const int n[4] = {r.Nx, r.Ny, r.Nz, (int)lnz.size()};
+  put(d, sizeof(d));
+  put(n, sizeof(n));
+  if (!lnz.empty()) put(lnz.data(), lnz.size() * sizeof(int));
+  if (!eps.empty()) put(eps.data(), eps.size() * sizeof(cavity_c128));
+  return k;
+}
+
 }  // namespace
 
 struct cavity_server_s {
   cavity_server_opts opts{};
   int device = 0;
   size_t budget = 0;
-  size_t in_use = 0;
+  size_t in_use = 0;              // running requests and resident plans
+  size_t plan_cache_limit = 0;
+  size_t resident_bytes = 0;
+  unsigned long long clock = 0;
   std::chrono::steady_clock::time_point t0;
   std::vector<std::thread> workers;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Pending> queue;
+  std::vector<Resident> resident;
   std::map<long long, Done> done;
   std::set<long long> live;     // submitted and not yet released
   long long next_ticket = 1;
@@ -57,9 +89,59 @@ struct cavity_server_s {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
         .count();
   }
-  // The head of the queue may start (caller holds mu).
-  bool head_fits() const {
-    return !queue.empty() && in_use + queue.front().footprint <= budget;
+  // Index of an idle resident plan for key, or -1 (caller holds mu).
+  int idle_plan(const std::string& key) const {
+    for (size_t i = 0; i < resident.size(); ++i)
+      if (!resident[i].busy && resident[i].key == key) return (int)i;
+    return -1;
+  }
+  // Bytes request pd needs on top of in_use, and bytes of idle resident plans it could
+  // evict for them (caller holds mu).
+  size_t need_of(const Pending& pd, int reuse) const {
+    return reuse >= 0 ? pd.field_bytes : pd.plan_bytes + pd.field_bytes;
+  }
+  size_t evictable(int keep) const {
+    size_t b = 0;
+    for (size_t i = 0; i < resident.size(); ++i)
+      if (!resident[i].busy && (int)i != keep) b += resident[i].bytes;
+    return b;
+  }
+  bool fits(const Pending& pd) const {
+    const int reuse = idle_plan(pd.key);
+    return in_use + need_of(pd, reuse) <= budget + evictable(reuse);
+  }
+  // The queued request a free worker takes: the oldest that fits, unless the head has been
+  // passed over for longer than kMaxBypassMs (then the head or nothing).  -1: none.
+  int pick() const {
+    for (size_t i = 0; i < queue.size(); ++i) {
+      if (fits(queue[i])) return (int)i;
+      if (i == 0 && now_ms() - queue[0].t_submit_ms > kMaxBypassMs) return -1;
+    }
+    return -1;
+  }
+  // Drop idle resident plans, least recently used first (never `keep`), until `extra` more
+  // bytes fit in the budget and the resident total is within its limit.  The plans are
+  // returned for destruction outside the lock (caller holds mu).
+  std::vector<cavity_plan> evict_for(size_t extra, cavity_plan keep) {
+    std::vector<cavity_plan> out;
+    while (in_use + extra > budget || resident_bytes > plan_cache_limit) {
+      int lru = -1;
+      for (size_t i = 0; i < resident.size(); ++i)
+        if (!resident[i].busy && resident[i].plan != keep &&
+            (lru < 0 || resident[i].last_use < resident[lru].last_use))
+          lru = (int)i;
+      if (lru < 0) break;
+      out.push_back(resident[lru].plan);
+      in_use -= resident[lru].bytes;
+      resident_bytes -= resident[lru].bytes;
+      resident.erase(resident.begin() + lru);
+    }
+    return out;
+  }
+  bool has_resident(const std::string& key) const {
+    for (const Resident& rp : resident)
+      if (rp.key == key) return true;
+    return false;
   }
   void work();
 };
@@ -77,36 +159,40 @@ void fill_eps(const Pending& pd, cavity_eps* e) {
   e->eps_r = pd.eps.data();
 }
 
-// One request on stream st: plan, solve into the field buffer, backscatter RCS.
+// One request on stream st: plan (given, or created into *plan), solve into the field
+// buffer, backscatter RCS.
 void run_request(const cavity_server_opts& so, hipStream_t st, const Pending& pd, void* field,
-                 cavity_result* res) {
-  cavity_opts o;
-  cavity_opts_default(&o);
-  o.precision = so.precision;
-  o.tol = so.tol;
-  o.batch = 1;
-  o.stream = st;
-  o.hbm_budget = pd.footprint + ((size_t)64 << 20);
-  cavity_eps e{};
-  fill_eps(pd, &e);
+                 cavity_plan* plan, cavity_result* res) {
   const cavity_request& r = pd.req;
-  cavity_plan plan = nullptr;
-  int s = cavity_plan_create(r.a, r.b, r.c, r.Nx, r.Ny, r.Nz, pd.lnz.empty() ? nullptr : &e,
-                             r.k, &o, &plan);
+  int s = CAVITY_OK;
+  if (*plan) {
+    s = cav::plan_set_stream(*plan, st);
+  } else {
+    cavity_opts o;
+    cavity_opts_default(&o);
+    o.precision = so.precision;
+    o.tol = so.tol;
+    o.batch = 1;
+    o.stream = st;
+    o.hbm_budget = pd.plan_bytes + ((size_t)64 << 20);
+    cavity_eps e{};
+    fill_eps(pd, &e);
+    s = cavity_plan_create(r.a, r.b, r.c, r.Nx, r.Ny, r.Nz, pd.lnz.empty() ? nullptr : &e, r.k,
+                           &o, plan);
+  }
   if (s == CAVITY_OK) {
-    s = cavity_solve(plan, r.theta, r.phi, r.pol, static_cast<cavity_c128*>(field));
+    s = cavity_solve(*plan, r.theta, r.phi, r.pol, static_cast<cavity_c128*>(field));
     if (s == CAVITY_OK || s == CAVITY_ENOCONV) {
-      const int s2 = cavity_rcs(plan, 0, 1, &r.theta, &r.phi, res->sigma);
+      const int s2 = cavity_rcs(*plan, 0, 1, &r.theta, &r.phi, res->sigma);
       if (s == CAVITY_OK) s = s2;
       cavity_info inf{};
-      if (cavity_plan_info(plan, &inf) == CAVITY_OK) {
+      if (cavity_plan_info(*plan, &inf) == CAVITY_OK) {
         res->iterations = inf.last_iterations;
         res->rel_residual = inf.last_rel_residual;
         res->unknowns = inf.unknowns;
       }
     }
   }
-  if (plan) cavity_plan_destroy(plan);
   if (hipStreamSynchronize(st) != hipSuccess && s == CAVITY_OK) s = CAVITY_EDEVICE;
   res->status = s;
 }
@@ -119,37 +205,71 @@ void cavity_server_s::work() {
   const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
   while (true) {
     Pending pd;
+    cavity_plan plan = nullptr;
+    size_t held = 0;           // bytes this request adds to in_use while it runs
+    std::vector<cavity_plan> drop;
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return (stopping && queue.empty()) || head_fits(); });
+      int i = -1;
+      cv_work.wait(lk, [&] {
+        if (stopping && queue.empty()) return true;
+        i = pick();
+        return i >= 0;
+      });
       if (queue.empty()) break;
-      pd = std::move(queue.front());
-      queue.pop_front();
-      in_use += pd.footprint;
+      pd = std::move(queue[i]);
+      queue.erase(queue.begin() + i);
+      const int reuse = idle_plan(pd.key);
+      held = need_of(pd, reuse);
+      if (reuse >= 0) {
+        resident[reuse].busy = true;
+        resident[reuse].last_use = ++clock;
+        plan = resident[reuse].plan;
+      }
+      drop = evict_for(held, plan);
+      in_use += held;
       ++running;
     }
+    for (cavity_plan q : drop) cavity_plan_destroy(q);
     cv_work.notify_all();
     Done d;
     std::memset(&d.res, 0, sizeof(d.res));
     d.res.t_submit_ms = pd.t_submit_ms;
     d.res.t_start_ms = now_ms();
-    d.res.device_bytes = pd.footprint;
+    d.res.device_bytes = pd.plan_bytes + pd.field_bytes;
+    d.res.plan_reused = plan ? 1 : 0;
+    const bool reused = plan != nullptr;
     void* field = pd.req.E_out;
     int s = have_stream ? CAVITY_OK : CAVITY_EDEVICE;
     if (s == CAVITY_OK && !field) s = cav::device_block_acquire(pd.field_bytes, &field);
     if (s == CAVITY_OK) {
-      run_request(opts, st, pd, field, &d.res);
+      run_request(opts, st, pd, field, &plan, &d.res);
     } else {
       d.res.status = s;
     }
     if (!pd.req.E_out && field) cav::device_block_release(field, pd.field_bytes);
     d.res.t_done_ms = now_ms();
+    drop.clear();
     {
       std::lock_guard<std::mutex> lk(mu);
-      in_use -= pd.footprint;
+      in_use -= pd.field_bytes;
+      if (reused) {
+        for (Resident& rp : resident)
+          if (rp.plan == plan) rp.busy = false;
+      } else if (plan && d.res.status == CAVITY_OK && pd.plan_bytes <= plan_cache_limit &&
+                 !has_resident(pd.key)) {
+        // keep the new plan resident (its bytes stay in in_use)
+        resident.push_back({pd.key, plan, pd.plan_bytes, ++clock, false});
+        resident_bytes += pd.plan_bytes;
+        drop = evict_for(0, plan);
+      } else {
+        in_use -= pd.plan_bytes;
+        if (plan) drop.push_back(plan);
+      }
       --running;
       done[pd.ticket] = d;
     }
+    for (cavity_plan q : drop) cavity_plan_destroy(q);
     cv_done.notify_all();
     cv_work.notify_all();
   }
@@ -164,6 +284,7 @@ int cavity_server_opts_default(cavity_server_opts* o) {
   o->hbm_budget = 0;
   o->precision = CAVITY_MIXED;
   o->tol = 1e-12;
+  o->plan_cache_bytes = SIZE_MAX;
   return CAVITY_OK;
 }
 
@@ -192,6 +313,8 @@ int cavity_server_create(const cavity_server_opts* opts, cavity_server* out) {
   srv->opts = o;
   srv->device = dev;
   srv->budget = budget;
+  srv->plan_cache_limit = o.plan_cache_bytes == SIZE_MAX ? budget / 4
+                                                         : std::min(o.plan_cache_bytes, budget);
   srv->t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < o.streams; ++i) srv->workers.emplace_back([srv] { srv->work(); });
   *out = srv;
@@ -223,7 +346,9 @@ int cavity_server_submit(cavity_server srv, const cavity_request* r, long long* 
                                       pd.lnz.empty() ? nullptr : &e, r->k, &o, &plan_bytes);
   if (s) return s;
   pd.field_bytes = r->E_out ? 0 : field_bytes_of(*r);
-  pd.footprint = plan_bytes + pd.field_bytes;
+  pd.plan_bytes = plan_bytes;
+  pd.key = cavity_key(*r, pd.lnz, pd.eps);
+  const size_t footprint = plan_bytes + pd.field_bytes;
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stopping) return cav::record_error(CAVITY_EINVAL, "server is shutting down");
@@ -231,11 +356,11 @@ int cavity_server_submit(cavity_server srv, const cavity_request* r, long long* 
     pd.t_submit_ms = srv->now_ms();
     *ticket = pd.ticket;
     srv->live.insert(pd.ticket);
-    if (pd.footprint > srv->budget) {
+    if (footprint > srv->budget) {
       Done d;
       std::memset(&d.res, 0, sizeof(d.res));
       d.res.status = CAVITY_ENOMEM;
-      d.res.device_bytes = pd.footprint;
+      d.res.device_bytes = footprint;
       d.res.t_submit_ms = d.res.t_start_ms = d.res.t_done_ms = pd.t_submit_ms;
       srv->done[pd.ticket] = d;
     } else {
@@ -276,6 +401,7 @@ void cavity_server_destroy(cavity_server srv) {
   }
   srv->cv_work.notify_all();
   for (std::thread& t : srv->workers) t.join();
+  for (Resident& rp : srv->resident) cavity_plan_destroy(rp.plan);
   delete srv;
 }
 

@@ -186,3 +186,83 @@ def test_served_stream_first_requests():
             n_oracle += 1
         print(msg, flush=True)
     assert n_oracle >= 5
+
+
+def _footprint(cav, field=True):
+    lib = P.load_library()
+    nzs = (ctypes.c_int * len(cav.layer_nz))(*cav.layer_nz)
+    eps = (P.C128 * len(cav.layer_eps))(*[P.C128(e.real, e.imag) for e in map(complex, cav.layer_eps)])
+    o = P.Opts()
+    lib.cavity_opts_default(ctypes.byref(o))
+    o.precision, o.batch = 1, 1
+    b = ctypes.c_size_t()
+    assert lib.cavity_plan_footprint(cav.a, cav.b, cav.c, cav.nx, cav.ny, cav.nz,
+                                     ctypes.pointer(P.EpsStack(len(cav.layer_nz), nzs, eps)),
+                                     cav.k, ctypes.byref(o), ctypes.byref(b)) == 0
+    return b.value + (3 * (cav.nz + 1) * (cav.ny + 1) * (cav.nx + 1) * 16 if field else 0)
+
+
+@pytest.mark.timeout(300)
+def test_resident_plan_reuse_is_exact():
+    """Requests on a cavity seen before run on its resident plan (no plan creation) and
+    give exactly the result of the request alone; another cavity in between stays resident
+    beside it."""
+    import torch
+    a = W.small_cases()[1].cavity
+    b = W.small_cases()[2].cavity
+    seq = [(a, W.Incidence(0.3, 0.4, W.TM)), (b, W.Incidence(0.5, 1.0, W.TE)),
+           (a, W.Incidence(0.7, 2.0, W.TE)), (a, W.Incidence(0.2, 5.0, W.TM)),
+           (b, W.Incidence(1.1, 0.1, W.TM))]
+    print(f"\n[case] {len(seq)} requests on two cavities, one at a time", flush=True)
+    srv = P.Server(streams=2, precision="mixed")
+    res, outs = [], []
+    for cav, inc in seq:
+        o = torch.empty((3, cav.nz + 1, cav.ny + 1, cav.nx + 1), dtype=torch.complex128,
+                        device="cuda")
+        t = srv.submit(cav, inc.theta, inc.phi, inc.pol, out=o)
+        res.append(srv.wait(t))
+        srv.release(t)
+        outs.append(o)
+    srv.close()
+    assert [r.plan_reused for r in res] == [0, 0, 1, 1, 1]
+    for k, ((cav, inc), r, o) in enumerate(zip(seq, res, outs)):
+        assert r.status == 0
+        field, sig = _alone(cav, inc, "mixed")
+        d = float((o - field).abs().max()) / float(field.abs().max())
+        ds = float(np.abs(np.array(r.sigma[:]) - sig).max() / max(sig))
+        print(f"[compare] request {k} reused {r.plan_reused}: vs alone field {d:.1e} rcs {ds:.1e}, "
+              f"{r.t_done_ms - r.t_start_ms:.2f} ms", flush=True)
+        assert d <= 1e-13 and ds <= 1e-13
+    # no plan reuse when the resident budget is 0
+    srv = P.Server(streams=1, precision="mixed", plan_cache_bytes=0)
+    rr = []
+    for cav, inc in seq[:3]:
+        t = srv.submit(cav, inc.theta, inc.phi, inc.pol)
+        rr.append(srv.wait(t).plan_reused)
+        srv.release(t)
+    srv.close()
+    assert rr == [0, 0, 0]
+
+
+@pytest.mark.timeout(300)
+def test_admission_passes_a_large_head():
+    """With room for the large request alone, a small request queued behind it starts while
+    another small one runs, before the large head (which then runs alone)."""
+    import torch
+    slow = W.Cavity(2.0, 2.0, 1.0, 64, 64, 32, (16, 16), (4.0 + 1.0j, 1.0 + 0j))
+    big = W.Cavity(3.0, 3.0, 1.0, 96, 96, 32, (32,), (2.0 + 0.5j,))
+    small = W.small_cases()[0].cavity
+    f_slow, f_big, f_small = _footprint(slow), _footprint(big), _footprint(small)
+    assert f_slow + f_big > f_big + 1024 >= f_slow + f_small
+    srv = P.Server(streams=2, hbm_budget=f_big + 1024, precision="mixed", plan_cache_bytes=0)
+    t1 = srv.submit(slow, 0.3, 0.2, W.TM)
+    t2 = srv.submit(big, 0.3, 0.2, W.TM)
+    t3 = srv.submit(small, 0.3, 0.2, W.TE)
+    r1, r2, r3 = srv.wait(t1), srv.wait(t2), srv.wait(t3)
+    srv.close()
+    torch.cuda.synchronize()
+    print(f"\n[case] starts: slow {r1.t_start_ms:.2f}, big {r2.t_start_ms:.2f}, "
+          f"small {r3.t_start_ms:.2f} ms; slow done {r1.t_done_ms:.2f}", flush=True)
+    assert r1.status == r2.status == r3.status == 0
+    assert r3.t_start_ms < r2.t_start_ms
+    assert r2.t_start_ms >= max(r1.t_done_ms, r3.t_done_ms) - 1e-6

@@ -187,6 +187,25 @@ int cavity_solve(cavity_plan plan, double theta, double phi, int pol, cavity_c12
 int cavity_solve_batch(cavity_plan plan, int nrhs, const double* theta, const double* phi,
                        const int* pol, cavity_c128* E_out, cavity_c128* aperture_out);
 
+/* Solve n small cavities together, one plane wave each: plans[r] (distinct plans) at
+ * (theta[r], phi[r], pol[r]).  The transparent boundary operator of Section 5 depends only
+ * on the aperture, so cavities that share it (equal a, b, Nx, Ny, k, tbc_oversample and
+ * spectrum) but differ in depth, z-grid or layers (their own columns of Sections 3-4, their
+ * own aperture step h) iterate as one lockstep group: every kernel launch of the Krylov
+ * solve serves all n of them, each right-hand side with its own cavity's local blocks and
+ * preconditioner.  The plans must also share precision, tol, restart and max_iter, use the
+ * trapezoid operator (else CAVITY_ENOTIMPL) and not be used by another thread meanwhile;
+ * the work runs on plans[0]'s stream (workspace of plans[0] sized for n right-hand sides),
+ * and the call synchronises it before returning.  Afterwards every plan keeps its own
+ * solution as right-hand side 0 (cavity_rcs, cavity_aperture) and E_out[r] (device,
+ * [3][Nz+1][Ny+1][Nx+1] of plans[r]) holds its field unless E_out or E_out[r] is NULL.
+ * Each result equals that of cavity_solve on the plan alone up to rounding.
+ * Errors: CAVITY_EINVAL (n outside 1..64, NULL or repeated plans, plans that do not share
+ * the aperture or options, angles), CAVITY_ENOTIMPL, CAVITY_ENOCONV, CAVITY_ENOMEM,
+ * CAVITY_EDEVICE. */
+int cavity_solve_group(int n, const cavity_plan* plans, const double* theta, const double* phi,
+                       const int* pol, cavity_c128* const* E_out);
+
 /* Radar cross section (units of length squared) of stored solution rhs_index at n_obs
  * observation directions (host arrays); sigma (host) receives {sigma_theta, sigma_phi}
  * per direction.  Backscatter: observation direction equal to the incidence angles, the
@@ -255,7 +274,10 @@ const char* cavity_last_error(void);
  * Sections 3-4, preconditioner, workspaces) stays resident, charged to the budget, for a
  * later request on the same cavity, which then skips plan creation; resident plans are
  * dropped least recently used first when admission needs their memory or their total
- * exceeds plan_cache_bytes.  Results are independent of the mix and of plan reuse: a
+ * exceeds plan_cache_bytes.  Queued requests on cavities that share the aperture of the
+ * request a worker takes (a, b, Nx, Ny, k), without a resident plan, are taken with it, up
+ * to 8, as far as the budget allows, and solved as one lockstep group (cavity_solve_group).
+ * Results are independent of the mix, of plan reuse and of grouping: a
  * request computes exactly what cavity_plan_create + cavity_solve + cavity_rcs compute for
  * it alone.  All functions are thread-safe. */
 typedef struct cavity_server_s* cavity_server;
@@ -294,6 +316,8 @@ typedef struct {
   double t_submit_ms, t_start_ms, t_done_ms;   /* server clock: ms since creation */
   int plan_reused;              /* 1 when the request ran on a resident plan of an earlier
                                    request on the same cavity */
+  int group_size;               /* requests solved together with this one in one lockstep
+                                   group (cavity_solve_group), 1 when alone */
 } cavity_result;
 
 int cavity_server_opts_default(cavity_server_opts* opts);

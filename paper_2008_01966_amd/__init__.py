@@ -81,11 +81,13 @@ class Result(ctypes.Structure):
                 ("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double),
                 ("unknowns", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t),
                 ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
-                ("t_done_ms", ctypes.c_double), ("plan_reused", ctypes.c_int)]
+                ("t_done_ms", ctypes.c_double), ("plan_reused", ctypes.c_int),
+                ("group_size", ctypes.c_int)]
 
 
 EXPORTS = [
     "cavity_opts_default", "cavity_plan_create", "cavity_solve", "cavity_solve_batch",
+    "cavity_solve_group",
     "cavity_rcs", "cavity_rcs_many", "cavity_rcs_many_noalloc", "cavity_aperture", "cavity_plan_footprint", "cavity_plan_info",
     "cavity_plan_destroy", "cavity_status_string", "cavity_last_error",
     "cavity_server_opts_default", "cavity_server_create", "cavity_server_submit",
@@ -121,6 +123,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cavity_plan_create.argtypes = [d, d, d, i, i, i, P(EpsStack), d, P(Opts), P(vp)]
     lib.cavity_solve.argtypes = [vp, d, d, i, vp]
     lib.cavity_solve_batch.argtypes = [vp, i, P(d), P(d), P(i), vp, vp]
+    lib.cavity_solve_group.argtypes = [i, P(vp), P(d), P(d), P(i), P(vp)]
     lib.cavity_rcs.argtypes = [vp, i, i, P(d), P(d), P(d)]
     lib.cavity_rcs_many.argtypes = [vp, i, P(i), P(d), P(d), P(d)]
     lib.cavity_rcs_many_noalloc.argtypes = [vp, i, P(i), P(d), P(d), P(d)]
@@ -386,6 +389,21 @@ class Plan:
         _check(self._lib.cavity_debug_rhs(self._h, float(theta), float(phi), int(pol), _cbuf(g1),
                                           _cbuf(g2)))
         return g1, g2
+
+
+def solve_group(plans, thetas, phis, pols, fields: bool = True):
+    """One incidence on each of several plans that share an aperture, solved as one lockstep
+    group (cavity_solve_group); returns the list of device field tensors (or None)."""
+    lib = load_library()
+    n = len(plans)
+    hs = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+    th = (ctypes.c_double * n)(*map(float, thetas))
+    ph = (ctypes.c_double * n)(*map(float, phis))
+    po = (ctypes.c_int * n)(*map(int, pols))
+    outs = [p.empty_field() for p in plans] if fields else None
+    eptr = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs]) if fields else None
+    _check(lib.cavity_solve_group(n, hs, th, ph, po, eptr))
+    return outs
 
 
 def probe_start(kernel: str, capacity: int = 100000):

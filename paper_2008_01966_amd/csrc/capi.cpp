@@ -242,6 +242,11 @@ struct cavity_plan_s {
   cav::Geo g{};
   cav::Trig trig{};
   cavity_opts opts{};
+  // column data the Krylov kernels read: this plan's own (one cavity), or those of a
+  // group of plans gathered for a group solve
+  cav::Cols cols{};
+  std::vector<double> group_h;       // aperture step of each right-hand side of a group solve
+  Arena group_arena;                 // gathered column data of a group solve
   hipStream_t st = nullptr;
   int device = 0;                    // device current at plan creation (owns all its memory)
   bool layered = false;
@@ -340,6 +345,7 @@ void release(cavity_plan p) {
   arena_release(p->dense_arena.ptr, p->dense_arena.bytes);
   arena_release(p->rcs_arena.ptr, p->rcs_arena.bytes);
   arena_release(p->spec_arena.ptr, p->spec_arena.bytes);
+  arena_release(p->group_arena.ptr, p->group_arena.bytes);
   if (p->hflags) (void)hipHostFree(p->hflags);
   if (p->hn) (void)hipHostFree(p->hn);
   if (p->hratio) (void)hipHostFree(p->hratio);
@@ -500,18 +506,17 @@ int run_operator(cavity_plan p, int precond, int nb, const zd* v, zd* y, const i
   const long long n = p->nvec();
   hipStream_t st = stream ? stream : p->st;
   if (p->use_spec()) {   // spectral operator: double precision in both precision modes
-    HIPCHK(cav::launch_operator_spec(p->g, p->spec, p->khat, p->rho_d, p->T, p->rho_n, p->pinv,
-                                     precond, nb, v, n, p->X, p->Y, p->U, p->S, y, n, active,
-                                     st));
+    HIPCHK(cav::launch_operator_spec(p->g, p->spec, p->khat, p->cols, precond, nb, v, n, p->X,
+                                     p->Y, p->U, p->S, y, n, active, st));
     return CAVITY_OK;
   }
   if (low)
-    HIPCHK(cav::launch_operator_f32(p->g, p->trig, p->khat_f, p->rho_d, p->T, p->rho_n, p->pinv,
-                                    precond, nb, v, n, reinterpret_cast<cav::zf*>(p->X),
+    HIPCHK(cav::launch_operator_f32(p->g, p->trig, p->khat_f, p->cols, precond, nb, v, n,
+                                    reinterpret_cast<cav::zf*>(p->X),
                                     reinterpret_cast<cav::zf*>(p->Y), p->S, y, n, active, st));
   else
-    HIPCHK(cav::launch_operator(p->g, p->trig, p->khat, p->rho_d, p->T, p->rho_n, p->pinv,
-                                precond, nb, v, n, p->X, p->Y, p->S, y, n, active, st));
+    HIPCHK(cav::launch_operator(p->g, p->trig, p->khat, p->cols, precond, nb, v, n, p->X, p->Y,
+                                p->S, y, n, active, st));
   return CAVITY_OK;
 }
 
@@ -638,7 +643,7 @@ int arnoldi_step(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipStream_t st) {
   }
   HIPCHK(cav::launch_update_norm(V, ldj, nv, p->h2, R + 1, p->w, n, nb, p->dnpart, nblk_u,
                                  kv.active, st));
-  HIPCHK(cav::launch_next_vector(p->g, kv, j, p->dnpart, nblk_u, p->w, vn, n, p->pinv, p->zb, nb,
+  HIPCHK(cav::launch_next_vector(p->g, kv, j, p->dnpart, nblk_u, p->w, vn, n, p->cols, p->zb, nb,
                                  st));
   return CAVITY_OK;
 }
@@ -760,7 +765,7 @@ int gmres_batch_t(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
     // per-step flag slots start at -1 ("not written yet"); the device writes 0 or 1
     for (size_t i = (size_t)2 * nb; i < (size_t)(2 + R) * nb; ++i) hstat[i] = -1;
     // v_0 = r / |r| and z = P^{-1} v_0 (norms already in kv.nrm2)
-    HIPCHK(cav::launch_next_vector(p->g, kv, -1, nullptr, 0, r0, V, n, p->pinv, p->zb, nb, p->st));
+    HIPCHK(cav::launch_next_vector(p->g, kv, -1, nullptr, 0, r0, V, n, p->cols, p->zb, nb, p->st));
     int seen = 0;   // first step whose flags the host has not looked at
     const bool graphs = use_step_graphs();
     for (int j = 0; j < budget; ++j) {
@@ -812,7 +817,7 @@ int gmres_batch_t(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
       if (stop) break;
     }
     HIPCHK(cav::launch_solve_y(kv, nb, p->st));
-    HIPCHK(cav::launch_combine(p->g, kv, V, ldj, p->pinv, x, nb, p->st));
+    HIPCHK(cav::launch_combine(p->g, kv, V, ldj, p->cols, x, nb, p->st));
     HIPCHK(cav::launch_cycle_end(kv, nb, p->st));
   }
   std::vector<double> relres(nb);
@@ -1059,8 +1064,9 @@ int dense_solve(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
   return CAVITY_OK;
 }
 
-void wave_setup(double k, double theta, double phi, int pol, cav::Wave* wv) {
+void wave_setup(double k, double h, double theta, double phi, int pol, cav::Wave* wv) {
   const double st = std::sin(theta), ct = std::cos(theta), sp = std::sin(phi), cp = std::cos(phi);
+  wv->h = h;
   wv->alpha1 = -k * st * cp;
   wv->alpha2 = -k * st * sp;
   wv->beta = k * ct;
@@ -1082,7 +1088,9 @@ bool angles_ok(double theta, double phi, int pol) {
 int solve_chunk(cavity_plan p, int i0, int nb, const double* theta, const double* phi,
                 const int* pol, cavity_c128* E_out, cavity_c128* ap_out) {
   std::vector<cav::Wave> wv(nb);
-  for (int r = 0; r < nb; ++r) wave_setup(p->g.k, theta[r], phi[r], pol[r], &wv[r]);
+  for (int r = 0; r < nb; ++r)
+    wave_setup(p->g.k, p->cols.hs ? p->group_h[i0 + r] : p->g.h, theta[r], phi[r], pol[r],
+               &wv[r]);
   HIPCHK(hipMemcpyAsync(p->dwaves, wv.data(), nb * sizeof(cav::Wave), hipMemcpyHostToDevice,
                         p->st));
   int s0;
@@ -1387,6 +1395,20 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
 
 }  // namespace
 
+namespace cav {
+int footprint_per_rhs(double a, double b, double c, int Nx, int Ny, int Nz, const cavity_eps* eps,
+                      double k, const cavity_opts* opts, size_t* bytes) {
+  PlanSpec ps;
+  const int st = prepare_plan(a, b, c, Nx, Ny, Nz, eps, k, opts, &ps);
+  if (st) return st;
+  const bool spec = ps.o.tbc_operator == CAVITY_TBC_SPEC;
+  const int nblk = dot_blocks(3LL * ps.g.NM);
+  *bytes = work_bytes(ps.g, ps.o.restart, 2, nblk, spec) - work_bytes(ps.g, ps.o.restart, 1, nblk, spec) +
+           15ull * ps.g.NM * sizeof(zd) + 2 * sizeof(double);
+  return CAVITY_OK;
+}
+}  // namespace cav
+
 extern "C" {
 
 int cavity_opts_default(cavity_opts* o) {
@@ -1616,6 +1638,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     if (!cached)
       aperture_insert(g, o.tbc_oversample, o.spectrum, p->khat, p->khat_f, p->diag, p->st);
   }
+  p->cols = cav::Cols{p->rho_d, p->T, p->rho_n, p->pinv, 0, nullptr};
   if (!chk(cav::launch_precond_build(g, p->rho_d, p->T, p->rho_n, p->diag, p->pinv, p->st),
            "preconditioner"))
     return bail(CAVITY_EDEVICE);
@@ -1651,7 +1674,9 @@ void cavity_plan_destroy(cavity_plan p) { release(p); }
 int cavity_plan_info(cavity_plan p, cavity_info* out) {
   if (!p || !out) return fail(CAVITY_EINVAL, "NULL argument");
   resolve_timers(p);
-  p->info.device_bytes = p->plan_arena.bytes + p->work_arena.bytes + p->sol_arena.bytes;
+  p->info.device_bytes = p->plan_arena.bytes + p->work_arena.bytes + p->sol_arena.bytes +
+                         p->dense_arena.bytes + p->rcs_arena.bytes + p->spec_arena.bytes +
+                         p->group_arena.bytes;
   *out = p->info;
   return CAVITY_OK;
 }
@@ -1703,6 +1728,99 @@ int cavity_solve_batch(cavity_plan p, int nrhs, const double* theta, const doubl
   if (worst != CAVITY_OK)
     return fail(worst, p->dense_now ? "direct solve did not reach the tolerance"
                                     : "GMRES did not reach the tolerance");
+  return CAVITY_OK;
+}
+
+int cavity_solve_group(int n, const cavity_plan* plans, const double* theta, const double* phi,
+                       const int* pol, cavity_c128* const* E_out) {
+  if (n < 1 || n > 64 || !plans || !theta || !phi || !pol)
+    return fail(CAVITY_EINVAL, "group needs 1..64 plans and host angle arrays");
+  cavity_plan lead = plans[0];
+  if (!lead) return fail(CAVITY_EINVAL, "NULL plan in group");
+  for (int r = 0; r < n; ++r) {
+    const cavity_plan q = plans[r];
+    if (!q) return fail(CAVITY_EINVAL, "NULL plan in group");
+    for (int t = 0; t < r; ++t)
+      if (plans[t] == q) return fail(CAVITY_EINVAL, "a plan appears twice in the group");
+    if (!angles_ok(theta[r], phi[r], pol[r]))
+      return fail(CAVITY_EINVAL, "theta must lie in [0, pi/2], phi finite, pol TM or TE");
+    const cav::Geo &a = lead->g, &b = q->g;
+    if (a.M != b.M || a.N != b.N || a.nq1 != b.nq1 || a.nq2 != b.nq2 || a.P1 != b.P1 ||
+        a.P2 != b.P2 || a.a != b.a || a.b != b.b || a.k != b.k || q->device != lead->device ||
+        q->opts.spectrum != lead->opts.spectrum || q->opts.precision != lead->opts.precision ||
+        q->opts.tol != lead->opts.tol || q->opts.restart != lead->opts.restart ||
+        q->opts.max_iter != lead->opts.max_iter)
+      return fail(CAVITY_EINVAL, "group plans need one aperture (a, b, Nx, Ny, k, oversampling, "
+                                 "spectrum) and the same precision, tol, restart and max_iter");
+    if (q->use_spec()) return fail(CAVITY_ENOTIMPL, "group solves use the trapezoid operator");
+  }
+  for (int r = 1; r < n; ++r) {
+    if (plans[r]->st) HIPCHK(hipStreamSynchronize(plans[r]->st));
+    else HIPCHK(hipDeviceSynchronize());
+  }
+  int s;
+  if ((s = ensure_work(lead, n)) || (s = ensure_solutions(lead, n))) return s;
+  // gather each cavity's column data: [rho_d | T | rho_n | pinv] per right-hand side, then h
+  const long long NM = lead->g.NM;
+  const long long cs = 12 * NM;
+  const size_t need = (size_t)n * cs * sizeof(zd) + (size_t)n * sizeof(double) + 256;
+  if (need > lead->group_arena.bytes) {
+    if (lead->st) HIPCHK(hipStreamSynchronize(lead->st));
+    else HIPCHK(hipDeviceSynchronize());
+    arena_release(lead->group_arena.ptr, lead->group_arena.bytes);
+    lead->group_arena = Arena();
+    void* base = nullptr;
+    if ((s = arena_acquire(need, &base))) return s;
+    lead->group_arena = {base, need};
+  }
+  zd* gc = static_cast<zd*>(lead->group_arena.ptr);
+  double* gh = reinterpret_cast<double*>(gc + (size_t)n * cs);
+  lead->group_h.assign(n, 0.0);
+  for (int r = 0; r < n; ++r) {
+    const cavity_plan q = plans[r];
+    zd* dst = gc + (size_t)r * cs;
+    HIPCHK(hipMemcpyAsync(dst, q->rho_d, NM * sizeof(zd), hipMemcpyDeviceToDevice, lead->st));
+    HIPCHK(hipMemcpyAsync(dst + NM, q->T, NM * sizeof(zd), hipMemcpyDeviceToDevice, lead->st));
+    HIPCHK(hipMemcpyAsync(dst + 2 * NM, q->rho_n, NM * sizeof(zd), hipMemcpyDeviceToDevice,
+                          lead->st));
+    HIPCHK(hipMemcpyAsync(dst + 3 * NM, q->pinv, 9 * NM * sizeof(zd), hipMemcpyDeviceToDevice,
+                          lead->st));
+    lead->group_h[r] = q->g.h;
+  }
+  HIPCHK(hipMemcpyAsync(gh, lead->group_h.data(), n * sizeof(double), hipMemcpyHostToDevice,
+                        lead->st));
+  const cav::Cols own = lead->cols;
+  lead->cols = cav::Cols{gc, gc + NM, gc + 2 * NM, gc + 3 * NM, cs, gh};
+  lead->dense_now = false;
+  lead->nsol = 0;
+  const int status = solve_chunk(lead, 0, n, theta, phi, pol, nullptr, nullptr);
+  lead->cols = own;
+  if (status != CAVITY_OK && status != CAVITY_ENOCONV) return status;
+  // each plan keeps its own solution as index 0; fields from its own profiles
+  const long long nv = lead->nvec();
+  for (int r = 0; r < n; ++r) {
+    const cavity_plan q = plans[r];
+    if (r > 0) {
+      q->nsol = 0;
+      if ((s = ensure_solutions(q, 1))) return s;
+      HIPCHK(hipMemcpyAsync(q->xsol, lead->xsol + (long long)r * nv, nv * sizeof(zd),
+                            hipMemcpyDeviceToDevice, lead->st));
+    }
+    q->nsol = 1;
+    q->info.last_iterations = lead->info.last_iterations;
+    q->info.last_rel_residual = lead->info.last_rel_residual;
+    q->info.last_direct = 0;
+    if (E_out && E_out[r]) {
+      for (int j0 = 0; j0 <= q->g.Nz; j0 += q->synth_chunk) {
+        const int j1 = std::min(q->g.Nz + 1, j0 + q->synth_chunk);
+        HIPCHK(cav::launch_synthesis(q->g, q->trig, q->pi_d, q->layered ? q->theta_d : nullptr,
+                                     q->pi_n, q->xsol, nv, 1, j0, j1, q->tbuf,
+                                     reinterpret_cast<zd*>(E_out[r]), 0, lead->st));
+      }
+    }
+  }
+  HIPCHK(hipStreamSynchronize(lead->st));
+  if (status != CAVITY_OK) return fail(status, "GMRES did not reach the tolerance");
   return CAVITY_OK;
 }
 
@@ -1838,7 +1956,7 @@ int cavity_debug_rhs(cavity_plan p, double theta, double phi, int pol, cavity_c1
                      cavity_c128* g2) {
   if (!p || !g1 || !g2) return fail(CAVITY_EINVAL, "NULL argument");
   cav::Wave wv;
-  wave_setup(p->g.k, theta, phi, pol, &wv);
+  wave_setup(p->g.k, p->g.h, theta, phi, pol, &wv);
   HIPCHK(hipMemcpy(p->dwave1, &wv, sizeof(wv), hipMemcpyHostToDevice));
   HIPCHK(cav::launch_rhs(p->g, p->dwave1, 1, p->r, p->st));
   int s;

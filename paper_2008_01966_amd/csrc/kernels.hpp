@@ -57,10 +57,25 @@ struct Layers {
   int layered;            // 1 when there is at least one interface
 };
 
-// Plane-wave data of one right-hand side, set up on the host (Section 7 incidence).
+// Plane-wave data of one right-hand side, set up on the host (Section 7 incidence), and the
+// aperture step h of its cavity (the one-sided difference of the aperture rows).
 struct Wave {
   double alpha1, alpha2, beta;
   double p1, p2, p3;
+  double h;
+};
+
+// Column data (Sections 3-4) of the cavities one lockstep group solves: right-hand side r
+// uses rho_d, T, rho_n (NM each) and the 3x3 block preconditioner pinv (9 NM) at offset
+// r * cs from these pointers (cs = 0: one cavity for the whole group), and the aperture
+// step hs[r] (hs = nullptr: Geo::h).
+struct Cols {
+  const zd* rho_d;
+  const zd* T;
+  const zd* rho_n;
+  const zd* pinv;
+  long long cs;
+  const double* hs;
 };
 
 // One aperture-transform evaluation behind an RCS value: stored solution rhs at the
@@ -129,21 +144,21 @@ struct SpecMats {
 hipError_t launch_spec_passes(const Geo& g, const SpecMats& sm, const zd* khat, const zd* pinv,
                               int precond, int fam_fixed, int nb, const zd* v, long long vs,
                               zd* X, zd* Y, zd* U, zd* S, const int* active, hipStream_t st);
-hipError_t launch_operator_spec(const Geo& g, const SpecMats& sm, const zd* khat, const zd* rho_d,
-                                const zd* Tc, const zd* rho_n, const zd* pinv, int precond,
-                                int nb, const zd* v, long long vs, zd* X, zd* Y, zd* U, zd* S,
+hipError_t launch_operator_spec(const Geo& g, const SpecMats& sm, const zd* khat, const Cols& c,
+                                int precond, int nb, const zd* v, long long vs, zd* X, zd* Y,
+                                zd* U, zd* S,
                                 zd* y, long long ys, const int* active, hipStream_t st);
 
-hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const zd* rho_d,
-                           const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
-                           const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y, long long ys,
+hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const Cols& c,
+                           int precond, int nb, const zd* v, long long vs, zd* X, zd* Y, zd* S,
+                           zd* y, long long ys,
                            const int* active, hipStream_t st);
 // The same operator with the three single-layer convolutions in single precision
 // (spectrum khat_f, workspaces Xf, Yf of the same element count as X, Y); the vectors v, y
 // and the local terms stay double.
-hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, const zd* rho_d,
-                               const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
-                               const zd* v, long long vs, zf* Xf, zf* Yf, zd* S, zd* y,
+hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
+                               int precond, int nb, const zd* v, long long vs, zf* Xf, zf* Yf,
+                               zd* S, zd* y,
                                long long ys, const int* active, hipStream_t st);
 // out[i] = (float) in[i]
 hipError_t launch_to_f32(const zd* in, zf* out, long long n, hipStream_t st);
@@ -191,10 +206,10 @@ hipError_t launch_update_norm(const zf* V, long long ldj, int nv, const zd* h, l
 // |w_r|^2 (from nparts partials, or kv.nrm2 when nparts == 0), Givens step of column j
 // (j >= 0), v_r = w_r / |w_r| (v_r at v + r vstride) and z_r = P^{-1} v_r (z_r at z + r n).
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
-                              int nparts, const zd* w, zd* v, long long vstride, const zd* pinv,
+                              int nparts, const zd* w, zd* v, long long vstride, const Cols& c,
                               zd* z, int nb, hipStream_t st);
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
-                              int nparts, const zd* w, zf* v, long long vstride, const zd* pinv,
+                              int nparts, const zd* w, zf* v, long long vstride, const Cols& c,
                               zd* z, int nb, hipStream_t st);
 hipError_t launch_solve_y(const Krylov& kv, int nb, hipStream_t st);
 // Restart bookkeeping on the device.  init: |b_r| = sqrt(nrm2[r]), iterations zero.
@@ -206,9 +221,9 @@ hipError_t launch_cycle_start(const Krylov& kv, int nb, int max_iter, double inn
                               hipStream_t st);
 hipError_t launch_cycle_end(const Krylov& kv, int nb, hipStream_t st);
 hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long ldj,
-                          const zd* pinv, zd* x, int nb, hipStream_t st);
+                          const Cols& c, zd* x, int nb, hipStream_t st);
 hipError_t launch_combine(const Geo& g, const Krylov& kv, const zf* V, long long ldj,
-                          const zd* pinv, zd* x, int nb, hipStream_t st);
+                          const Cols& c, zd* x, int nb, hipStream_t st);
 
 // Back-substitution and synthesis of levels [j0, j1) of nr fields: solution r at
 // xap + r xs, field r at eout + r es; tbuf holds 3 nr (j1 - j0) staging levels.

@@ -33,6 +33,11 @@ struct PlanView {
 };
 int plan_view(cavity_plan plan, PlanView* out);
 
+// Device bytes one more right-hand side of a lockstep group adds to a plan with these
+// arguments (Krylov and transform workspace, solution, gathered column data of a group).
+int footprint_per_rhs(double a, double b, double c, int Nx, int Ny, int Nz, const cavity_eps* eps,
+                      double k, const cavity_opts* opts, size_t* bytes);
+
 // Move a plan to stream st: all its later work is queued there.  The caller guarantees
 // that no work of the plan is pending on its previous stream.
 int plan_set_stream(cavity_plan plan, hipStream_t st);

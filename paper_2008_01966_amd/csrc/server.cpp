@@ -25,6 +25,8 @@ namespace {
 
 // A request passed over by later ones for longer than this is the only one admitted next.
 constexpr double kMaxBypassMs = 25.0;
+// Most requests solved together as one lockstep group.
+constexpr int kMaxGroup = 8;
 
 struct Pending {
   long long ticket;
@@ -32,7 +34,9 @@ struct Pending {
   std::vector<int> lnz;
   std::vector<cavity_c128> eps;
   std::string key;        // the cavity (geometry, grid, layers, k): equal keys share a plan
+  std::string ap_key;     // the aperture (a, b, Nx, Ny, k): equal keys may share a group
   size_t plan_bytes;      // plan + workspace + solution (cavity_plan_footprint)
+  size_t rhs_bytes;       // what one more right-hand side adds to a group leader's plan
   size_t field_bytes;     // temporary field buffer, 0 when the caller gave E_out
   double t_submit_ms;
 };
@@ -63,6 +67,15 @@ std::string cavity_key(const cavity_request& r, const std::vector<int>& lnz,
   return k;
 }
 
+std::string aperture_key(const cavity_request& r) {
+  std::string k;
+  const double d[3] = {r.a, r.b, r.k};
+  const int n[2] = {r.Nx, r.Ny};
+  k.append(reinterpret_cast<const char*>(d), sizeof(d));
+  k.append(reinterpret_cast<const char*>(n), sizeof(n));
+  return k;
+}
+
 }  // namespace
 
 struct cavity_server_s {
@@ -83,6 +96,7 @@ struct cavity_server_s {
   std::set<long long> live;     // submitted and not yet released
   long long next_ticket = 1;
   int running = 0;
+  int ready = 0;                // workers that have set up their stream
   bool stopping = false;
 
   double now_ms() const {
@@ -197,16 +211,83 @@ void run_request(const cavity_server_opts& so, hipStream_t st, const Pending& pd
   res->status = s;
 }
 
+// Requests on cavities that share an aperture, solved as one lockstep group on stream st:
+// a plan each (created here), one group solve, the backscatter RCS of each.  A request whose
+// plan cannot be created fails alone; the others are still solved together.
+void run_group(const cavity_server_opts& so, hipStream_t st, const std::vector<Pending>& grp,
+               const std::vector<void*>& fields, std::vector<cavity_plan>* plans,
+               std::vector<cavity_result>* res) {
+  const int n = (int)grp.size();
+  std::vector<cavity_plan> live;
+  std::vector<int> idx;
+  std::vector<double> th, ph;
+  std::vector<int> po;
+  std::vector<cavity_c128*> eo;
+  for (int r = 0; r < n; ++r) {
+    const Pending& pd = grp[r];
+    const cavity_request& q = pd.req;
+    cavity_opts o;
+    cavity_opts_default(&o);
+    o.precision = so.precision;
+    o.tol = so.tol;
+    o.batch = 1;
+    o.stream = st;
+    o.hbm_budget = pd.plan_bytes + (size_t)n * pd.rhs_bytes + ((size_t)64 << 20);
+    cavity_eps e{};
+    fill_eps(pd, &e);
+    const int s = cavity_plan_create(q.a, q.b, q.c, q.Nx, q.Ny, q.Nz,
+                                     pd.lnz.empty() ? nullptr : &e, q.k, &o, &(*plans)[r]);
+    if (s != CAVITY_OK) {
+      (*res)[r].status = s;
+      continue;
+    }
+    live.push_back((*plans)[r]);
+    idx.push_back(r);
+    th.push_back(q.theta);
+    ph.push_back(q.phi);
+    po.push_back(q.pol);
+    eo.push_back(static_cast<cavity_c128*>(fields[r]));
+  }
+  if (!live.empty()) {
+    int s = cavity_solve_group((int)live.size(), live.data(), th.data(), ph.data(), po.data(),
+                               eo.data());
+    for (size_t i = 0; i < live.size(); ++i) {
+      cavity_result& rr = (*res)[idx[i]];
+      const cavity_request& q = grp[idx[i]].req;
+      int si = s;
+      if (s == CAVITY_OK || s == CAVITY_ENOCONV) {
+        const int s2 = cavity_rcs(live[i], 0, 1, &q.theta, &q.phi, rr.sigma);
+        if (si == CAVITY_OK) si = s2;
+        cavity_info inf{};
+        if (cavity_plan_info(live[i], &inf) == CAVITY_OK) {
+          rr.iterations = inf.last_iterations;
+          rr.rel_residual = inf.last_rel_residual;
+          rr.unknowns = inf.unknowns;
+        }
+      }
+      rr.status = si;
+    }
+  }
+  if (hipStreamSynchronize(st) != hipSuccess)
+    for (int r = 0; r < n; ++r)
+      if ((*res)[r].status == CAVITY_OK) (*res)[r].status = CAVITY_EDEVICE;
+}
+
 }  // namespace
 
 void cavity_server_s::work() {
   (void)hipSetDevice(device);
   hipStream_t st = nullptr;
   const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    ++ready;
+  }
+  cv_done.notify_all();
   while (true) {
-    Pending pd;
-    cavity_plan plan = nullptr;
-    size_t held = 0;           // bytes this request adds to in_use while it runs
+    std::vector<Pending> grp;
+    cavity_plan reused = nullptr;
+    size_t lead_extra = 0;     // group workspace the leader's plan adds
     std::vector<cavity_plan> drop;
     {
       std::unique_lock<std::mutex> lk(mu);
@@ -217,57 +298,91 @@ void cavity_server_s::work() {
         return i >= 0;
       });
       if (queue.empty()) break;
-      pd = std::move(queue[i]);
+      grp.push_back(std::move(queue[i]));
       queue.erase(queue.begin() + i);
-      const int reuse = idle_plan(pd.key);
-      held = need_of(pd, reuse);
+      const int reuse = idle_plan(grp[0].key);
+      size_t total = need_of(grp[0], reuse);
       if (reuse >= 0) {
         resident[reuse].busy = true;
         resident[reuse].last_use = ++clock;
-        plan = resident[reuse].plan;
+        reused = resident[reuse].plan;
+      } else {
+        // queued requests on the same aperture without a resident plan join the group
+        for (size_t j = 0; j < queue.size() && (int)grp.size() < kMaxGroup;) {
+          const Pending& q = queue[j];
+          if (q.ap_key == grp[0].ap_key && idle_plan(q.key) < 0) {
+            const size_t add = q.plan_bytes + q.field_bytes + grp[0].rhs_bytes;
+            if (in_use + total + add <= budget + evictable(-1)) {
+              total += add;
+              lead_extra += grp[0].rhs_bytes;
+              grp.push_back(std::move(queue[j]));
+              queue.erase(queue.begin() + j);
+              continue;
+            }
+          }
+          ++j;
+        }
       }
-      drop = evict_for(held, plan);
-      in_use += held;
+      drop = evict_for(total, reused);
+      in_use += total;
       ++running;
     }
     for (cavity_plan q : drop) cavity_plan_destroy(q);
     cv_work.notify_all();
-    Done d;
-    std::memset(&d.res, 0, sizeof(d.res));
-    d.res.t_submit_ms = pd.t_submit_ms;
-    d.res.t_start_ms = now_ms();
-    d.res.device_bytes = pd.plan_bytes + pd.field_bytes;
-    d.res.plan_reused = plan ? 1 : 0;
-    const bool reused = plan != nullptr;
-    void* field = pd.req.E_out;
+    const int n = (int)grp.size();
+    std::vector<cavity_result> res(n);
+    std::vector<void*> fields(n, nullptr);
+    std::vector<cavity_plan> plans(n, nullptr);
+    const double t_start = now_ms();
     int s = have_stream ? CAVITY_OK : CAVITY_EDEVICE;
-    if (s == CAVITY_OK && !field) s = cav::device_block_acquire(pd.field_bytes, &field);
-    if (s == CAVITY_OK) {
-      run_request(opts, st, pd, field, &plan, &d.res);
-    } else {
-      d.res.status = s;
+    for (int r = 0; r < n; ++r) {
+      std::memset(&res[r], 0, sizeof(res[r]));
+      res[r].t_submit_ms = grp[r].t_submit_ms;
+      res[r].t_start_ms = t_start;
+      res[r].device_bytes = grp[r].plan_bytes + grp[r].field_bytes + (r == 0 ? lead_extra : 0);
+      res[r].plan_reused = reused ? 1 : 0;
+      res[r].group_size = n;
+      fields[r] = grp[r].req.E_out;
+      if (s == CAVITY_OK && !fields[r]) s = cav::device_block_acquire(grp[r].field_bytes, &fields[r]);
     }
-    if (!pd.req.E_out && field) cav::device_block_release(field, pd.field_bytes);
-    d.res.t_done_ms = now_ms();
+    if (s != CAVITY_OK) {
+      for (int r = 0; r < n; ++r) res[r].status = s;
+    } else if (n == 1) {
+      plans[0] = reused;
+      run_request(opts, st, grp[0], fields[0], &plans[0], &res[0]);
+    } else {
+      run_group(opts, st, grp, fields, &plans, &res);
+    }
+    for (int r = 0; r < n; ++r)
+      if (!grp[r].req.E_out && fields[r]) cav::device_block_release(fields[r], grp[r].field_bytes);
+    const double t_done = now_ms();
     drop.clear();
     {
       std::lock_guard<std::mutex> lk(mu);
-      in_use -= pd.field_bytes;
-      if (reused) {
-        for (Resident& rp : resident)
-          if (rp.plan == plan) rp.busy = false;
-      } else if (plan && d.res.status == CAVITY_OK && pd.plan_bytes <= plan_cache_limit &&
-                 !has_resident(pd.key)) {
-        // keep the new plan resident (its bytes stay in in_use)
-        resident.push_back({pd.key, plan, pd.plan_bytes, ++clock, false});
-        resident_bytes += pd.plan_bytes;
-        drop = evict_for(0, plan);
-      } else {
-        in_use -= pd.plan_bytes;
-        if (plan) drop.push_back(plan);
+      for (int r = 0; r < n; ++r) {
+        const Pending& pd = grp[r];
+        cavity_plan plan = plans[r];
+        in_use -= pd.field_bytes;
+        if (reused) {
+          for (Resident& rp : resident)
+            if (rp.plan == plan) rp.busy = false;
+        } else if (plan && res[r].status == CAVITY_OK && (n == 1 || r > 0) &&
+                   pd.plan_bytes <= plan_cache_limit && !has_resident(pd.key)) {
+          // keep the plan resident (its bytes stay in in_use); a group leader's plan holds
+          // the group's workspace and is not kept
+          resident.push_back({pd.key, plan, pd.plan_bytes, ++clock, false});
+          resident_bytes += pd.plan_bytes;
+          std::vector<cavity_plan> ev = evict_for(0, plan);
+          drop.insert(drop.end(), ev.begin(), ev.end());
+        } else {
+          in_use -= pd.plan_bytes;
+          if (plan) drop.push_back(plan);
+        }
+        res[r].t_done_ms = t_done;
+        done[pd.ticket] = Done{res[r]};
       }
+      in_use -= lead_extra;
       --running;
-      done[pd.ticket] = d;
     }
     for (cavity_plan q : drop) cavity_plan_destroy(q);
     cv_done.notify_all();
@@ -317,6 +432,11 @@ int cavity_server_create(const cavity_server_opts* opts, cavity_server* out) {
                                                          : std::min(o.plan_cache_bytes, budget);
   srv->t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < o.streams; ++i) srv->workers.emplace_back([srv] { srv->work(); });
+  {
+    // every worker has its stream before the first request can arrive
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv_done.wait(lk, [&] { return srv->ready == o.streams; });
+  }
   *out = srv;
   return CAVITY_OK;
 }
@@ -348,6 +468,11 @@ int cavity_server_submit(cavity_server srv, const cavity_request* r, long long* 
   pd.field_bytes = r->E_out ? 0 : field_bytes_of(*r);
   pd.plan_bytes = plan_bytes;
   pd.key = cavity_key(*r, pd.lnz, pd.eps);
+  pd.ap_key = aperture_key(*r);
+  pd.rhs_bytes = 0;
+  if (cav::footprint_per_rhs(r->a, r->b, r->c, r->Nx, r->Ny, r->Nz, pd.lnz.empty() ? nullptr : &e,
+                             r->k, &o, &pd.rhs_bytes) != CAVITY_OK)
+    return cav::record_error(CAVITY_EINVAL, "request arguments");
   const size_t footprint = plan_bytes + pd.field_bytes;
   {
     std::lock_guard<std::mutex> lk(srv->mu);

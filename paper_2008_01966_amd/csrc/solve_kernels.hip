@@ -51,13 +51,13 @@ __global__ void k_rhs(Geo g, const Wave* __restrict__ waves, zd* __restrict__ b)
   zd g1 = mk(0.0, 0.0), g2 = mk(0.0, 0.0);
   if (n >= 1) {
     const double q = (m == 0 ? 0.5 : 0.25) * g.a * g.b;
-    const double amp = 2.0 * (wv.alpha1 * wv.p3 + wv.beta * wv.p1) * g.h / q;
+    const double amp = 2.0 * (wv.alpha1 * wv.p3 + wv.beta * wv.p1) * wv.h / q;
     const zd pr = cos_proj(wv.alpha1, mu, g.a) * sin_proj(wv.alpha2, nu, g.b);
     g1 = mk(-amp * pr.im, amp * pr.re);  // i * amp * pr
   }
   if (m >= 1) {
     const double c = (n == 0 ? 0.5 : 0.25) * g.a * g.b;
-    const double amp = 2.0 * (wv.alpha2 * wv.p3 + wv.beta * wv.p2) * g.h / c;
+    const double amp = 2.0 * (wv.alpha2 * wv.p3 + wv.beta * wv.p2) * wv.h / c;
     const zd pr = sin_proj(wv.alpha1, mu, g.a) * cos_proj(wv.alpha2, nu, g.b);
     g2 = mk(-amp * pr.im, amp * pr.re);
   }
@@ -98,7 +98,8 @@ __device__ inline bool fam_ycos(int f) { return f != 0; }
 // preconditioned first.
 template <typename T, int MR>
 __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
-                                                      const zd* __restrict__ pinv, int precond,
+                                                      const zd* __restrict__ pinv_all,
+                                                      long long pcs, int precond,
                                                       int fam_fixed, int lc, int ip,
                                                       const zd* __restrict__ vall, long long vs,
                                                       cx<T>* __restrict__ Xall,
@@ -111,6 +112,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
   const int rhs = bid.z;
   if (active && !active[rhs]) return;
   const zd* v = vall + rhs * vs;
+  const zd* pinv = pinv_all + rhs * pcs;
   const int nf = fam_fixed >= 0 ? 1 : 3;
   cx<T>* X = Xall + (long long)rhs * nf * (g.M + 1) * g.P2;
   const int C = 1 << lc;
@@ -331,11 +333,10 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
 //  r1 = (rho_d - 1) z1 + mu (T + h) z3 + (h/q) (2k^2 S^cs z1 - 2 nu S^cc sigma)   on N1
 //  r2 = (rho_d - 1) z2 + nu (T + h) z3 + (h/c) (2k^2 S^sc z2 + 2 mu S^cc sigma)   on N2
 //  r3 = (rho_n - 1) z3 + mu h z1 + nu h z2                                        on N3
-__global__ void k_operator_epilogue(Geo g, const zd* __restrict__ rho_d, const zd* __restrict__ T,
-                                    const zd* __restrict__ rho_n, const zd* __restrict__ pinv,
-                                    int precond, const zd* __restrict__ vall, long long vs,
-                                    const zd* __restrict__ Sall, zd* __restrict__ yall,
-                                    long long ys, const int* __restrict__ active) {
+__global__ void k_operator_epilogue(Geo g, Cols cl, int precond, const zd* __restrict__ vall,
+                                    long long vs, const zd* __restrict__ Sall,
+                                    zd* __restrict__ yall, long long ys,
+                                    const int* __restrict__ active) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
   const int mn = blockIdx.x * blockDim.x + threadIdx.x;
@@ -343,8 +344,14 @@ __global__ void k_operator_epilogue(Geo g, const zd* __restrict__ rho_d, const z
   const zd* v = vall + rhs * vs;
   const zd* S = Sall + 3LL * rhs * g.NM;
   zd* y = yall + rhs * ys;
+  const long long co = rhs * cl.cs;
+  const zd* __restrict__ rho_d = cl.rho_d + co;
+  const zd* __restrict__ T = cl.T + co;
+  const zd* __restrict__ rho_n = cl.rho_n + co;
+  const zd* __restrict__ pinv = cl.pinv + co;
   const int m = mn / (g.N + 1), n = mn % (g.N + 1);
-  const double mu = M_PI * m / g.a, nu = M_PI * n / g.b, h = g.h, k2 = g.k * g.k;
+  const double h = cl.hs ? cl.hs[rhs] : g.h;
+  const double mu = M_PI * m / g.a, nu = M_PI * n / g.b, k2 = g.k * g.k;
   zd z[3] = {v[mn], v[g.NM + mn], v[2LL * g.NM + mn]};
   if (precond) {
     zd t[3];
@@ -410,7 +417,8 @@ static TbcShape tbc_shape(const FftPlan& ext, const FftPlan& box, int L, int P, 
 
 template <typename T>
 static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, const zd* pinv,
-                             int precond, int fam_fixed, int nb, const zd* v, long long vs,
+                             long long pcs, int precond, int fam_fixed, int nb, const zd* v,
+                             long long vs,
                              cx<T>* X, cx<T>* Y, zd* S, const int* active, hipStream_t st) {
   const int nf = fam_fixed >= 0 ? 1 : 3;
   const double zb = sizeof(zd), tb = sizeof(cx<T>);
@@ -426,10 +434,11 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
   probe_begin(id_fwd, st);
   if (t.maxr <= 8)
     hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g, t.ext2,
-                       t.box2, pinv, precond, fam_fixed, sr.lc, sr.ip, v, vs, X, active);
+                       t.box2, pinv, pcs, precond, fam_fixed, sr.lc, sr.ip, v, vs, X, active);
   else
     hipLaunchKernelGGL((k_tbc_rows_fwd<T, kMaxRadix>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
-                       t.ext2, t.box2, pinv, precond, fam_fixed, sr.lc, sr.ip, v, vs, X, active);
+                       t.ext2, t.box2, pinv, pcs, precond, fam_fixed, sr.lc, sr.ip, v, vs, X,
+                       active);
   probe_end(id_fwd, st, vin + xbytes);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -462,53 +471,52 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
 static hipError_t launch_tbc_passes(const Geo& g, const Trig& t, const zd* khat, const zd* pinv,
                                     int precond, int fam_fixed, int nb, const zd* v, long long vs,
                                     zd* X, zd* Y, zd* S, const int* active, hipStream_t st) {
-  return tbc_passes<double>(g, t, khat, pinv, precond, fam_fixed, nb, v, vs, X, Y, S, active, st);
+  return tbc_passes<double>(g, t, khat, pinv, 0, precond, fam_fixed, nb, v, vs, X, Y, S, active,
+                            st);
 }
 
 template <typename T>
-static hipError_t operator_impl(const Geo& g, const Trig& t, const cx<T>* khat, const zd* rho_d,
-                                const zd* Tc, const zd* rho_n, const zd* pinv, int precond, int nb,
-                                const zd* v, long long vs, cx<T>* X, cx<T>* Y, zd* S, zd* y,
-                                long long ys, const int* active, hipStream_t st) {
-  hipError_t e = tbc_passes<T>(g, t, khat, pinv, precond, -1, nb, v, vs, X, Y, S, active, st);
+static hipError_t operator_impl(const Geo& g, const Trig& t, const cx<T>* khat, const Cols& c,
+                                int precond, int nb, const zd* v, long long vs, cx<T>* X,
+                                cx<T>* Y, zd* S, zd* y, long long ys, const int* active,
+                                hipStream_t st) {
+  hipError_t e = tbc_passes<T>(g, t, khat, c.pinv, c.cs, precond, -1, nb, v, vs, X, Y, S, active,
+                               st);
   if (e != hipSuccess) return e;
   const int blk = 256;
   probe_begin(K_EPILOGUE, st);
   hipLaunchKernelGGL(k_operator_epilogue, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g,
-                     rho_d, Tc, rho_n, pinv, precond, v, vs, S, y, ys, active);
+                     c, precond, v, vs, S, y, ys, active);
   probe_end(K_EPILOGUE, st, sizeof(zd) * (double)g.NM * (nb * 9.0 + 3.0 + (precond ? 9.0 : 0.0)));
   return hipGetLastError();
 }
 
 // The operator with the spectral single-layer operators (D_spec) in place of the
 // trapezoid ones; same epilogue.
-hipError_t launch_operator_spec(const Geo& g, const SpecMats& sm, const zd* khat, const zd* rho_d,
-                                const zd* Tc, const zd* rho_n, const zd* pinv, int precond,
-                                int nb, const zd* v, long long vs, zd* X, zd* Y, zd* U, zd* S,
-                                zd* y, long long ys, const int* active, hipStream_t st) {
-  hipError_t e = launch_spec_passes(g, sm, khat, pinv, precond, -1, nb, v, vs, X, Y, U, S,
+hipError_t launch_operator_spec(const Geo& g, const SpecMats& sm, const zd* khat, const Cols& c,
+                                int precond, int nb, const zd* v, long long vs, zd* X, zd* Y,
+                                zd* U, zd* S, zd* y, long long ys, const int* active,
+                                hipStream_t st) {
+  // one cavity per call (the column data of a group have cs > 0 only on the FFT operator)
+  hipError_t e = launch_spec_passes(g, sm, khat, c.pinv, precond, -1, nb, v, vs, X, Y, U, S,
                                     active, st);
   if (e != hipSuccess) return e;
   const int blk = 256;
   hipLaunchKernelGGL(k_operator_epilogue, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g,
-                     rho_d, Tc, rho_n, pinv, precond, v, vs, S, y, ys, active);
+                     c, precond, v, vs, S, y, ys, active);
   return hipGetLastError();
 }
 
-hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const zd* rho_d,
-                           const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
-                           const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y, long long ys,
-                           const int* active, hipStream_t st) {
-  return operator_impl<double>(g, t, khat, rho_d, T, rho_n, pinv, precond, nb, v, vs, X, Y, S, y,
-                               ys, active, st);
+hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const Cols& c,
+                           int precond, int nb, const zd* v, long long vs, zd* X, zd* Y, zd* S,
+                           zd* y, long long ys, const int* active, hipStream_t st) {
+  return operator_impl<double>(g, t, khat, c, precond, nb, v, vs, X, Y, S, y, ys, active, st);
 }
 
-hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, const zd* rho_d,
-                               const zd* T, const zd* rho_n, const zd* pinv, int precond, int nb,
-                               const zd* v, long long vs, zf* Xf, zf* Yf, zd* S, zd* y,
-                               long long ys, const int* active, hipStream_t st) {
-  return operator_impl<float>(g, t, khat_f, rho_d, T, rho_n, pinv, precond, nb, v, vs, Xf, Yf, S,
-                              y, ys, active, st);
+hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
+                               int precond, int nb, const zd* v, long long vs, zf* Xf, zf* Yf,
+                               zd* S, zd* y, long long ys, const int* active, hipStream_t st) {
+  return operator_impl<float>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S, y, ys, active, st);
 }
 
 __global__ void k_to_f32(const zd* __restrict__ in, zf* __restrict__ out, long long n) {
@@ -999,10 +1007,11 @@ hipError_t launch_solve_y(const Krylov& kv, int nb, hipStream_t st) {
 // x_r += P^{-1} (sum_{i < jcount[r]} y[r][i] V_i,r)
 template <typename VT>
 __global__ void k_combine(Geo g, Krylov kv, const cx<VT>* __restrict__ V, long long ldj,
-                          const zd* __restrict__ pinv, zd* __restrict__ xall) {
+                          const zd* __restrict__ pinv_all, long long pcs, zd* __restrict__ xall) {
   __shared__ zd ys[256];
   const int r = blockIdx.y;
   if (!kv.incycle[r]) return;
+  const zd* __restrict__ pinv = pinv_all + r * pcs;
   const int jc = kv.jcount[r];
   for (int i = threadIdx.x; i < jc; i += blockDim.x) ys[i] = kv.y[(long long)r * kv.restart + i];
   __syncthreads();
@@ -1026,21 +1035,21 @@ __global__ void k_combine(Geo g, Krylov kv, const cx<VT>* __restrict__ V, long l
 
 template <typename VT>
 static hipError_t combine_impl(const Geo& g, const Krylov& kv, const cx<VT>* V, long long ldj,
-                               const zd* pinv, zd* x, int nb, hipStream_t st) {
+                               const Cols& c, zd* x, int nb, hipStream_t st) {
   const int blk = 256;
   hipLaunchKernelGGL((k_combine<VT>), dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g, kv,
-                     V, ldj, pinv, x);
+                     V, ldj, c.pinv, c.cs, x);
   return hipGetLastError();
 }
 
 hipError_t launch_combine(const Geo& g, const Krylov& kv, const zd* V, long long ldj,
-                          const zd* pinv, zd* x, int nb, hipStream_t st) {
-  return combine_impl<double>(g, kv, V, ldj, pinv, x, nb, st);
+                          const Cols& c, zd* x, int nb, hipStream_t st) {
+  return combine_impl<double>(g, kv, V, ldj, c, x, nb, st);
 }
 
 hipError_t launch_combine(const Geo& g, const Krylov& kv, const zf* V, long long ldj,
-                          const zd* pinv, zd* x, int nb, hipStream_t st) {
-  return combine_impl<float>(g, kv, V, ldj, pinv, x, nb, st);
+                          const Cols& c, zd* x, int nb, hipStream_t st) {
+  return combine_impl<float>(g, kv, V, ldj, c, x, nb, st);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1109,8 +1118,8 @@ __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
                                                      const double* __restrict__ npart, int nparts,
                                                      const zd* __restrict__ wall,
                                                      cx<VT>* __restrict__ vall, long long vstride,
-                                                     const zd* __restrict__ pinv,
-                                                     zd* __restrict__ zall) {
+                                                     const zd* __restrict__ pinv_all,
+                                                     long long pcs, zd* __restrict__ zall) {
   __shared__ double red[4];
   __shared__ double s_nrm;
   const int r = blockIdx.y;
@@ -1140,6 +1149,7 @@ __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
   const zd* w = wall + r * n;
   cx<VT>* v = vall + r * vstride;
   zd* z = zall + r * n;
+  const zd* __restrict__ pinv = pinv_all + r * pcs;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long mn = (long long)blockIdx.x * blockDim.x + threadIdx.x; mn < g.NM; mn += stride) {
     zd u[3];
@@ -1160,24 +1170,24 @@ __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
 template <typename VT>
 static hipError_t next_vector_impl(const Geo& g, const Krylov& kv, int j, const double* npart,
                                    int nparts, const zd* w, cx<VT>* v, long long vstride,
-                                   const zd* pinv, zd* z, int nb, hipStream_t st) {
+                                   const Cols& c, zd* z, int nb, hipStream_t st) {
   int nblk = (g.NM + 255) / 256;
   if (nblk > 1024) nblk = 1024;
   hipLaunchKernelGGL((k_next_vector<VT>), dim3(nblk, nb), dim3(256), 0, st, g, kv, j, npart, nparts,
-                     w, v, vstride, pinv, z);
+                     w, v, vstride, c.pinv, c.cs, z);
   return hipGetLastError();
 }
 
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
-                              int nparts, const zd* w, zd* v, long long vstride, const zd* pinv,
+                              int nparts, const zd* w, zd* v, long long vstride, const Cols& c,
                               zd* z, int nb, hipStream_t st) {
-  return next_vector_impl<double>(g, kv, j, npart, nparts, w, v, vstride, pinv, z, nb, st);
+  return next_vector_impl<double>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb, st);
 }
 
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
-                              int nparts, const zd* w, zf* v, long long vstride, const zd* pinv,
+                              int nparts, const zd* w, zf* v, long long vstride, const Cols& c,
                               zd* z, int nb, hipStream_t st) {
-  return next_vector_impl<float>(g, kv, j, npart, nparts, w, v, vstride, pinv, z, nb, st);
+  return next_vector_impl<float>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb, st);
 }
 
 // ---------------------------------------------------------------------------------

@@ -266,3 +266,35 @@ def test_admission_passes_a_large_head():
     assert r1.status == r2.status == r3.status == 0
     assert r3.t_start_ms < r2.t_start_ms
     assert r2.t_start_ms >= max(r1.t_done_ms, r3.t_done_ms) - 1e-6
+
+
+@pytest.mark.timeout(300)
+def test_same_aperture_requests_are_grouped():
+    """Requests queued behind a running one, on cavities that share an aperture, are taken
+    together and solved as one lockstep group; each result equals the request alone."""
+    import torch
+    from test_gpu_group import GROUP
+    busy = W.Cavity(3.0, 3.0, 1.0, 96, 96, 32, (32,), (2.0 + 0.5j,))
+    srv = P.Server(streams=1, precision="mixed", plan_cache_bytes=0)
+    t0 = srv.submit(busy, 0.3, 0.2, W.TM)
+    outs, tickets = [], []
+    for cav, inc in GROUP:
+        o = torch.empty((3, cav.nz + 1, cav.ny + 1, cav.nx + 1), dtype=torch.complex128,
+                        device="cuda")
+        outs.append(o)
+        tickets.append(srv.submit(cav, inc.theta, inc.phi, inc.pol, out=o))
+    r0 = srv.wait(t0)
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    torch.cuda.synchronize()
+    print(f"\n[case] group sizes {[r.group_size for r in res]}, first request alone "
+          f"{r0.group_size}", flush=True)
+    assert r0.status == 0 and r0.group_size == 1
+    assert [r.group_size for r in res] == [len(GROUP)] * len(GROUP)
+    for k, ((cav, inc), r, o) in enumerate(zip(GROUP, res, outs)):
+        assert r.status == 0
+        field, sig = _alone(cav, inc, "mixed")
+        d = float((o - field).abs().max()) / float(field.abs().max())
+        ds = float(np.abs(np.array(r.sigma[:]) - sig).max() / max(sig))
+        print(f"[compare] grouped request {k}: vs alone field {d:.1e} rcs {ds:.1e}", flush=True)
+        assert d <= 1e-13 and ds <= 1e-13

@@ -95,8 +95,10 @@ constexpr int kDenseAutoRhs = 32;
 // Right-hand sides per product with the inverse (and per residual check).
 constexpr int kDenseGroup = 64;
 
-// Device bytes of the staging slab between the two synthesis passes; the levels of one
-// slab are synthesised by one pair of launches.
+// Device bytes of the staging slab between the two synthesis passes, per 8 right-hand
+// sides of the lockstep batch (at most 4 such units); the (field, level) pairs of one slab
+// are synthesised by one pair of launches, and the fewer the launches, the fewer times
+// the row pass re-reads the aperture solutions.
 constexpr size_t kSynthStagingBytes = (size_t)256 << 20;
 
 }  // namespace
@@ -1369,8 +1371,9 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
 
   const bool layered = lnz.size() > 1;
   const size_t per_level = 3ull * (g.M + 1) * (g.ny + 1) * sizeof(zd);
-  int chunk = (int)std::max<size_t>(1, kSynthStagingBytes / per_level);
-  chunk = std::min(chunk, Nz + 1);
+  const size_t slab = kSynthStagingBytes * (size_t)std::min(4, std::max(1, o.batch / 8));
+  int chunk = (int)std::max<size_t>(1, slab / per_level);
+  chunk = (int)std::min<long long>(chunk, (long long)(Nz + 1) * o.batch);
   const int fft_len[6] = {2 * g.nq1, 2 * g.nq2, g.P1, g.P2, 2 * g.nx, 2 * g.ny};
   int twn = 0;
   for (int l : fft_len) twn += l;

@@ -194,6 +194,36 @@ struct SpectrumProduct {
   }
 };
 
+// Synthesis along x on the trapezoid grid, trapezoid weights and zero padding, in one:
+// dst[(i << lc) + c] = w_i hq (cosine: (F + c0) / 2, sine: i F / 2) for i <= L, 0 for
+// L < i < 2L (positions 2L..P-1 are zero from the start).
+template <typename T>
+struct WeightPad {
+  const cx<T>* c0s;
+  int L, lc;
+  bool xcos;
+  T hq;
+  __device__ void operator()(cx<T>* dst, int i, int c, cx<T> F) const {
+    cx<T> val = mk<T>(0, 0);
+    if (i <= L) {
+      const cx<T> sx = xcos ? (T)0.5 * (F + c0s[c]) : (T)0.5 * mul_i(F);
+      val = ((i == 0 || i == L) ? (T)0.5 * hq : hq) * sx;
+    }
+    dst[(i << lc) + c] = val;
+  }
+};
+
+// Crop to the trapezoid grid and extend for the projection's transform: entry i <= L of
+// the inverse box transform goes to position i and (mirrored, negated for sine) 2L - i.
+template <typename T>
+struct ExtendCrop {
+  int L, lc;
+  bool xcos;
+  __device__ void operator()(cx<T>* dst, int i, int c, cx<T> v) const {
+    if (i <= L) store_extension(dst, L, xcos, i, v, lc, c);
+  }
+};
+
 // Y[m][k0 + c] = hq * (cosine: F / 2, sine: i F / 2) for m <= M and the live columns.
 template <typename T>
 struct ColumnStore {
@@ -234,7 +264,14 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   cx<T>* b = a + ((long long)P << lc);
   const bool xcos = fam_xcos(f);
   const int tid = threadIdx.x, nt = blockDim.x;
+  // zero the first transform's input (entries the extension does not set) and, in both
+  // buffers, the padding 2L..P-1 of the box transform, which no later step writes
   for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk<T>(0, 0);
+  for (int i = tid; i < (P - 2 * L) << lc; i += nt) {
+    a[((2 * L) << lc) + i] = mk<T>(0, 0);
+    b[((2 * L) << lc) + i] = mk<T>(0, 0);
+  }
+  for (int c = tid; c < C; c += nt) c0s[c] = mk<T>(0, 0);
   __syncthreads();
   for (int w = tid; w < (g.M + 1) << lc; w += nt) {
     const int m = w >> lc, c = w & (C - 1);
@@ -246,33 +283,53 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   __syncthreads();
   const cx<T>* tw_e = twiddles<T>(ext1);
   const cx<T>* tw_b = twiddles<T>(box1);
-  cx<T>* r = fft_lds<T, false, MR>(a, b, ext1.p, tw_e, tid, nt, lc);
-  cx<T>* o = (r == a) ? b : a;
   const T hq = (T)g.hq1;
-  for (int w = tid; w < P << lc; w += nt) {
-    const int i = w >> lc, c = w & (C - 1);
-    cx<T> val = mk<T>(0, 0);
-    if (i <= L && c < Cb) {
-      const cx<T> F = r[w];
-      const cx<T> sx = xcos ? (T)0.5 * (F + c0s[c]) : (T)0.5 * mul_i(F);
-      val = ((i == 0 || i == L) ? (T)0.5 * hq : hq) * sx;
+  cx<T>* o;
+  cx<T>* r;
+  if constexpr (MR <= kSmallRadix) {
+    // synthesis along x; its last stage applies the trapezoid weights and pads to P
+    o = fft_lds_put<T, false, MR>(a, b, ext1.p, tw_e, tid, nt, lc,
+                                  WeightPad<T>{c0s, L, lc, xcos, hq});
+    r = (o == a) ? b : a;
+  } else {
+    // with the larger radices the extra last-stage forms cost registers (spills): the
+    // weights and padding take a pass of their own
+    r = fft_lds<T, false, MR>(a, b, ext1.p, tw_e, tid, nt, lc);
+    o = (r == a) ? b : a;
+    for (int w = tid; w < P << lc; w += nt) {
+      const int i = w >> lc, c = w & (C - 1);
+      cx<T> val = mk<T>(0, 0);
+      if (i <= L) {
+        const cx<T> F = r[w];
+        const cx<T> sx = xcos ? (T)0.5 * (F + c0s[c]) : (T)0.5 * mul_i(F);
+        val = ((i == 0 || i == L) ? (T)0.5 * hq : hq) * sx;
+      }
+      o[w] = val;
     }
-    o[w] = val;
+    __syncthreads();
   }
-  __syncthreads();
   // the product with K-hat rides on the transform's last stage
   cx<T>* r2 = fft_lds_put<T, false, MR>(o, r, box1.p, tw_b, tid, nt, lc,
-                                               SpectrumProduct<T>{khat + k0, g.P2, Cb, lc});
-  cx<T>* r3 = fft_lds<T, true, MR>(r2, (r2 == a) ? b : a, box1.p, tw_b, tid, nt, lc);
-  cx<T>* o3 = (r3 == a) ? b : a;
-  for (int w = tid; w < (L + 1) << lc; w += nt) {
-    const int i = w >> lc, c = w & (C - 1);
-    store_extension(o3, L, xcos, i, r3[w], lc, c);
+                                        SpectrumProduct<T>{khat + k0, g.P2, Cb, lc});
+  cx<T>* o3;
+  cx<T>* r3;
+  if constexpr (MR <= kSmallRadix) {
+    // inverse transform; its last stage crops to the grid and writes the extension
+    o3 = fft_lds_put<T, true, MR>(r2, (r2 == a) ? b : a, box1.p, tw_b, tid, nt, lc,
+                                  ExtendCrop<T>{L, lc, xcos});
+    r3 = (o3 == a) ? b : a;
+  } else {
+    r3 = fft_lds<T, true, MR>(r2, (r2 == a) ? b : a, box1.p, tw_b, tid, nt, lc);
+    o3 = (r3 == a) ? b : a;
+    for (int w = tid; w < (L + 1) << lc; w += nt) {
+      const int i = w >> lc, c = w & (C - 1);
+      store_extension(o3, L, xcos, i, r3[w], lc, c);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   // the last stage writes the projected entries m = 0..M straight to Y
   fft_lds_put<T, false, MR>(o3, r3, ext1.p, tw_e, tid, nt, lc,
-                                   ColumnStore<T>{Y + k0, g.P2, g.M + 1, Cb, xcos, hq});
+                            ColumnStore<T>{Y + k0, g.P2, g.M + 1, Cb, xcos, hq});
 }
 
 // Pass 3: rows m0 .. m0+Cb-1 backward; writes S[slot][mn] in double.

@@ -98,4 +98,21 @@ __device__ inline BlockId xcd_block_x_slow() {
   return BlockId{x, t % gy, t / gy};
 }
 
+// Strips in groups of W: the W x (y, z) blocks of a group run next to each other on one
+// XCD, x fastest within the group.  A kernel whose blocks each own a strip narrower than a
+// cache line (W strips per line) then has the W sharers of a line in flight together, so
+// the line is fetched from (and written back to) memory once, while the blocks that share
+// a strip's table entries still sit within W (y, z) rows of each other.  The last group
+// holds the gridDim.x mod W strips left over when W does not divide gridDim.x.
+__device__ inline BlockId xcd_block_x_grouped(int W) {
+  const int gx = gridDim.x, gy = gridDim.y, gyz = gridDim.y * gridDim.z;
+  const int l = xcd_logical();
+  const int span = W * gyz;
+  const int sg = l / span;
+  const int w = min(W, gx - sg * W);
+  const int t = l - sg * span;
+  const int yz = t / w;
+  return BlockId{sg * W + (t - yz * w), yz % gy, yz / gy};
+}
+
 }  // namespace cav

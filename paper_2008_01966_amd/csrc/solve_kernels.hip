@@ -246,7 +246,9 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
                                                   const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ cx<T> c0s[64];
-  const BlockId bid = xcd_block_x_slow();   // the nb x 3 blocks of a strip share its K-hat columns
+  // the strips of one 128-byte line of X and Y run together (their blocks share the line),
+  // and the nb x 3 blocks of a strip, which share its K-hat columns, stay close
+  const BlockId bid = xcd_block_x_grouped(max(1, 128 / ((int)sizeof(cx<T>) << lc)));
   const int rhs = bid.z;
   if (active && !active[rhs]) return;
   const int nf = fam_fixed >= 0 ? 1 : 3;

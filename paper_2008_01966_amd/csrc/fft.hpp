@@ -489,6 +489,21 @@ __device__ inline void store_extension(cx<T>* buf, int L, bool is_cos, int idx, 
   }
 }
 
+// Even extension of xc plus odd extension of xs (entry idx, 0 <= idx <= L, of transform
+// col): one transform of the sum yields the cosine series of one sequence and the sine
+// series of another, F_k = E_k + O_k with E even and O odd in k, so
+// E_k = (F_k + F_{2L-k}) / 2 and O_k = (F_k - F_{2L-k}) / 2.
+template <typename T>
+__device__ inline void store_pair_extension(cx<T>* buf, int L, int idx, cx<T> xc, cx<T> xs,
+                                            int lc, int col) {
+  if (idx == 0 || idx == L) {
+    buf[(idx << lc) + col] = xc;
+  } else {
+    buf[(idx << lc) + col] = xc + xs;
+    buf[((2 * L - idx) << lc) + col] = xc - xs;
+  }
+}
+
 }  // namespace cav
 
 namespace cav {

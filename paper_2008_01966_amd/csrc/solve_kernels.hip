@@ -1253,10 +1253,13 @@ hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const doubl
 // Back-substitution and synthesis (EInter): at level j the mode values are
 //   E1 = Pi_j a1 + mu_m Theta_j a3,  E2 = Pi_j a2 + nu_n Theta_j a3,  E3 = Pi3_j a3,
 // then the 2D sine/cosine series is summed on the output nodes: rows along y, then
-// columns along x with TK adjacent columns per block.
+// columns along x with TK adjacent columns per block.  Along either axis one of E1, E2
+// takes the cosine series and the other the sine series, so both come from one transform
+// of the even extension of one plus the odd extension of the other (store_pair_extension):
+// two transforms per level and axis instead of three.
 // One launch pair covers nr right-hand sides (solutions at xap + r xs) and jn levels from
 // j0; the staging slab is tbuf[r][l][jj][m][i2], jj = j - j0.  The profiles do not depend
-// on the right-hand side: a row block (row strip, level, component) takes kSynthRhsPerBlock
+// on the right-hand side: a row block (row strip, level, E1+E2 or E3) takes kSynthRhsPerBlock
 // right-hand sides in turn, and the blocks of one strip run next to each other on one XCD,
 // so each profile strip comes from HBM about once per launch.
 // ---------------------------------------------------------------------------------
@@ -1273,7 +1276,9 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int
   CAV_DYN_SMEM(smem_raw);
   __shared__ zd c0s[64];
   const BlockId bid = xcd_block_x_slow();
-  const int jj = bid.y / 3, l = bid.y - 3 * jj;
+  // blockIdx.y = 2 jj + q: q = 0 sums E1 (sine along y) and E2 (cosine along y) in one
+  // transform of the paired extension, q = 1 sums E3 (sine along y)
+  const int jj = bid.y >> 1, q = bid.y & 1;
   const int j = j0 + jj;
   const int C = 1 << lc;
   const int m0 = bid.x << lc;
@@ -1282,13 +1287,13 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int
   const DivBy div_l1(L + 1);
   zd* a = reinterpret_cast<zd*>(smem_raw);
   zd* b = a + ((2LL * L) << lc);   // second buffer of the ping-pong form only
-  const bool ycos = (l == 1);  // E1: sin, E2: cos, E3: sin along y
   const int tid = threadIdx.x, nt = blockDim.x;
   const long long NM = g.NM;
   const int rowlen = g.N + 1;
   const DivBy div_row(rowlen);
   const int r0 = bid.z * kSynthRhsPerBlock;
   const int r1 = min(nr, r0 + kSynthRhsPerBlock);
+  const long long slab = (long long)jn * (g.M + 1) * (g.ny + 1);   // one component's slab
   for (int r = r0; r < r1; ++r) {
     const zd* x = xap + r * xs;
     for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk(0.0, 0.0);
@@ -1297,34 +1302,45 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int
       const int c = div_row.quot(w), n = w - c * div_row.d;
       const int m = m0 + c;
       const long long mn = (long long)m * rowlen + n;
-      zd val;
-      if (l < 2) {
-        val = pi_d[(long long)j * NM + mn] * x[l * NM + mn];
+      if (q == 0) {
+        const zd p = pi_d[(long long)j * NM + mn];
+        zd v1 = p * x[mn], v2 = p * x[NM + mn];
         if (theta_d) {
-          const double fac = l == 0 ? M_PI * m / g.a : M_PI * n / g.b;
-          val = val + fac * (theta_d[(long long)j * NM + mn] * x[2 * NM + mn]);
+          const zd t = theta_d[(long long)j * NM + mn] * x[2 * NM + mn];
+          v1 = v1 + (M_PI * m / g.a) * t;
+          v2 = v2 + (M_PI * n / g.b) * t;
         }
+        store_pair_extension(a, L, n, v2, v1, lc, c);
+        if (n == 0) c0s[c] = v2;
       } else {
-        val = pi_n[(long long)j * NM + mn] * x[2 * NM + mn];
+        store_extension(a, L, false, n, pi_n[(long long)j * NM + mn] * x[2 * NM + mn], lc, c);
       }
-      store_extension(a, L, ycos, n, val, lc, c);
-      if (n == 0) c0s[c] = val;
     }
     __syncthreads();
     zd* rr = a;
     if (ip) fft_lds_ip<double, false, MR>(a, out2.p, out2.tw, tid, lc);
     else rr = fft_lds<double, false, MR>(a, b, out2.p, out2.tw, tid, nt, lc);
-    zd* dst = tbuf + ((((long long)r * 3 + l) * jn + jj) * (g.M + 1) + m0) * (g.ny + 1);
+    zd* dst = tbuf + ((((long long)r * 3 + (q == 0 ? 0 : 2)) * jn + jj) * (g.M + 1) + m0) *
+                         (g.ny + 1);
     for (int w = tid; w < (L + 1) * Cb; w += nt) {
       const int c = div_l1.quot(w), i = w - c * div_l1.d;
       const zd F = rr[(i << lc) + c];
-      dst[(long long)c * (g.ny + 1) + i] = ycos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
+      const long long o = (long long)c * (g.ny + 1) + i;
+      if (q == 0) {
+        const zd Fm = rr[((i == 0 ? 0 : 2 * L - i) << lc) + c];
+        dst[o] = 0.5 * mul_i(0.5 * (F - Fm));            // E1: sine series
+        dst[slab + o] = 0.5 * (0.5 * (F + Fm) + c0s[c]);  // E2: cosine series
+      } else {
+        dst[o] = 0.5 * mul_i(F);
+      }
     }
     __syncthreads();
   }
 }
 
-// Columns: blockIdx.y = jj * 3 + l, blockIdx.z = right-hand side r; field r at eout + r es.
+// Columns: blockIdx.y = 2 jj + q (q = 0: E1, cosine along x, with E2, sine along x, in
+// one transform; q = 1: E3, sine along x), blockIdx.z = right-hand side r; field r at
+// eout + r es.
 template <int MR>
 __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int ip, int j0, int jn,
                                                     const zd* __restrict__ tbuf,
@@ -1332,7 +1348,7 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
   CAV_DYN_SMEM(smem_raw);
   __shared__ zd c0s[64];
   const BlockId bid = xcd_block();
-  const int jj = bid.y / 3, l = bid.y - 3 * jj, r = bid.z;
+  const int jj = bid.y >> 1, q = bid.y & 1, r = bid.z;
   const int j = j0 + jj;
   const int C = 1 << lc;
   const int i0 = bid.x << lc;
@@ -1341,27 +1357,41 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
   const DivBy div_l1(L + 1);
   zd* a = reinterpret_cast<zd*>(smem_raw);
   zd* b = a + ((2LL * L) << lc);   // second buffer of the ping-pong form only
-  const bool xcos = (l == 0);  // E1: cos, E2: sin, E3: sin along x
-  const zd* src = tbuf + (((long long)r * 3 + l) * jn + jj) * (g.M + 1) * (g.ny + 1);
+  const long long slab = (long long)jn * (g.M + 1) * (g.ny + 1);   // one component's slab
+  const zd* src = tbuf + (((long long)r * 3 + (q == 0 ? 0 : 2)) * jn + jj) * (g.M + 1) * (g.ny + 1);
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk(0.0, 0.0);
   __syncthreads();
   for (int w = tid; w < (g.M + 1) << lc; w += nt) {
     const int m = w >> lc, c = w & (C - 1);
     if (c >= Cb) continue;
-    const zd x = src[(long long)m * (g.ny + 1) + i0 + c];
-    store_extension(a, L, xcos, m, x, lc, c);
-    if (m == 0) c0s[c] = x;
+    const long long o = (long long)m * (g.ny + 1) + i0 + c;
+    if (q == 0) {
+      const zd x1 = src[o];
+      store_pair_extension(a, L, m, x1, src[slab + o], lc, c);
+      if (m == 0) c0s[c] = x1;
+    } else {
+      store_extension(a, L, false, m, src[o], lc, c);
+    }
   }
   __syncthreads();
   zd* rr = a;
   if (ip) fft_lds_ip<double, false, MR>(a, out1.p, out1.tw, tid, lc);
   else rr = fft_lds<double, false, MR>(a, b, out1.p, out1.tw, tid, nt, lc);
-  zd* dst = eout + r * es + (((long long)l * (g.Nz + 1) + j) * (g.ny + 1) + i0) * (g.nx + 1);
+  const long long plane = (long long)(g.Nz + 1) * (g.ny + 1) * (g.nx + 1);   // one component
+  zd* dst = eout + r * es + (q == 0 ? 0 : 2 * plane) +
+            ((long long)j * (g.ny + 1) + i0) * (g.nx + 1);
   for (int w = tid; w < (L + 1) * Cb; w += nt) {
     const int c = div_l1.quot(w), i = w - c * div_l1.d;
     const zd F = rr[(i << lc) + c];
-    dst[(long long)c * (g.nx + 1) + i] = xcos ? 0.5 * (F + c0s[c]) : 0.5 * mul_i(F);
+    const long long o = (long long)c * (g.nx + 1) + i;
+    if (q == 0) {
+      const zd Fm = rr[((i == 0 ? 0 : 2 * L - i) << lc) + c];
+      dst[o] = 0.5 * (0.5 * (F + Fm) + c0s[c]);           // E1: cosine series
+      dst[plane + o] = 0.5 * mul_i(0.5 * (F - Fm));      // E2: sine series
+    } else {
+      dst[o] = 0.5 * mul_i(F);
+    }
   }
 }
 
@@ -1397,7 +1427,7 @@ hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const z
   const SynthShape sr = synth_shape(t.out2.p, g.ny, g.M + 1, synth_budget);
   const int rgroups = (nr + kSynthRhsPerBlock - 1) / kSynthRhsPerBlock;
   probe_begin(K_SYNTH_ROWS, st);
-  const dim3 grs((g.M + 1 + (1 << sr.lc) - 1) >> sr.lc, 3 * jn, rgroups);
+  const dim3 grs((g.M + 1 + (1 << sr.lc) - 1) >> sr.lc, 2 * jn, rgroups);
   if (t.maxr <= 8)
     hipLaunchKernelGGL(k_synth_rows<8>, grs, dim3(256), sr.smem, st, g, t.out2, sr.lc, sr.ip, pi_d,
                        theta_d, pi_n, xap, xs, nr, j0, jn, tbuf);
@@ -1409,7 +1439,7 @@ hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const z
   if (e != hipSuccess) return e;
   const SynthShape sc = synth_shape(t.out1.p, g.nx, g.ny + 1, synth_budget);
   probe_begin(K_SYNTH_COLS, st);
-  const dim3 gcs((g.ny + 1 + (1 << sc.lc) - 1) >> sc.lc, 3 * jn, nr);
+  const dim3 gcs((g.ny + 1 + (1 << sc.lc) - 1) >> sc.lc, 2 * jn, nr);
   if (t.maxr <= 8)
     hipLaunchKernelGGL(k_synth_cols<8>, gcs, dim3(256), sc.smem, st, g, t.out1, sc.lc, sc.ip, j0,
                        jn, tbuf, eout, es);

@@ -70,7 +70,7 @@ constexpr size_t kMaxLdsPerBlock = 160 * 1024;
 
 // Largest basis size for which the first Gram-Schmidt update and the second pass's dot
 // products share one pass over the basis (the dot kernel's group of vectors).
-constexpr int kFusedGsMax = 8;
+constexpr int kFusedGsMax = 16;
 
 // Blocks per right-hand side of the fused update + norm pass of the Arnoldi step.
 constexpr int kNormBlocks = 1024;

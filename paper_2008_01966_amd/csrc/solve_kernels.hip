@@ -603,6 +603,8 @@ hipError_t launch_single_family(const Geo& g, const Trig& t, const zd* khat, int
 // ---------------------------------------------------------------------------------
 constexpr int kDotGroup = 8;
 constexpr int kDotUnroll = 4;
+constexpr int kDotGroupWide = 16;   // basis vectors per group beyond kDotGroup
+constexpr int kDotUnrollWide = 2;
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -610,57 +612,60 @@ __device__ inline double wave_sum(double v) {
 }
 
 
-// partial[(r * nvmax + vi) * nblk + blk] = sum over the block's slice of conj(V_vi,r) w_r.
-// VT: precision of the stored basis (double, or float in the mixed-precision solve).
-template <typename VT>
+// partial[(r * nvmax + vi) * nblk + blk] = sum over the block's slice of conj(V_vi,r) w_r,
+// for the G basis vectors of group blockIdx.y.  VT: precision of the stored basis (double,
+// or float in the mixed-precision solve).  Each thread sums its elements i, i + stride,
+// i + 2 stride, ..., U of them per trip with every load of a trip issued before the
+// products.  The variant is chosen from nv alone, so a solve's sums do not depend on how
+// many right-hand sides share the launch.
+template <typename VT, int G, int U>
 __global__ __launch_bounds__(256) void k_dots(const cx<VT>* __restrict__ V, long long ldj, int nv,
                                               int nvmax, const zd* __restrict__ wall, long long n,
                                               zd* __restrict__ partial,
                                               const int* __restrict__ active) {
-  __shared__ zd red[kDotGroup][4];
+  __shared__ zd red[G][4];
   const int r = blockIdx.z;
   if (active && !active[r]) return;
   const int grp = blockIdx.y;
   const zd* w = wall + r * n;
   const cx<VT>* Vr = V + r * n;
-  const int nvg = min(kDotGroup, nv - grp * kDotGroup);
-  const cx<VT>* Vg = Vr + (long long)grp * kDotGroup * ldj;
-  zd acc[kDotGroup];
-  for (int t = 0; t < kDotGroup; ++t) acc[t] = mk(0.0, 0.0);
+  const int nvg = min(G, nv - grp * G);
+  const cx<VT>* Vg = Vr + (long long)grp * G * ldj;
+  zd acc[G];
+  for (int t = 0; t < G; ++t) acc[t] = mk(0.0, 0.0);
   const long long stride = (long long)gridDim.x * blockDim.x;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  // kDotUnroll elements per thread per trip, every load of a trip issued before the products
-  for (; i + (kDotUnroll - 1) * stride < n; i += kDotUnroll * stride) {
-    zd wi[kDotUnroll];
+  for (; i + (U - 1) * stride < n; i += U * stride) {
+    zd wi[U];
 #pragma unroll
-    for (int u = 0; u < kDotUnroll; ++u) wi[u] = w[i + u * stride];
+    for (int u = 0; u < U; ++u) wi[u] = w[i + u * stride];
 #pragma unroll
-    for (int t = 0; t < kDotGroup; ++t) {
+    for (int t = 0; t < G; ++t) {
       if (t < nvg) {
-        cx<VT> v[kDotUnroll];
+        cx<VT> v[U];
 #pragma unroll
-        for (int u = 0; u < kDotUnroll; ++u) v[u] = Vg[t * ldj + i + u * stride];
+        for (int u = 0; u < U; ++u) v[u] = Vg[t * ldj + i + u * stride];
 #pragma unroll
-        for (int u = 0; u < kDotUnroll; ++u) acc[t] = acc[t] + conj(widen(v[u])) * wi[u];
+        for (int u = 0; u < U; ++u) acc[t] = acc[t] + conj(widen(v[u])) * wi[u];
       }
     }
   }
   for (; i < n; i += stride) {
     const zd wi = w[i];
 #pragma unroll
-    for (int t = 0; t < kDotGroup; ++t)
+    for (int t = 0; t < G; ++t)
       if (t < nvg) acc[t] = acc[t] + conj(widen(Vg[t * ldj + i])) * wi;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int t = 0; t < kDotGroup; ++t) {
+  for (int t = 0; t < G; ++t) {
     const zd sum = mk(wave_sum(acc[t].re), wave_sum(acc[t].im));
     if (lane == 0) red[t][wv] = sum;
   }
   __syncthreads();
   if (threadIdx.x < nvg) {
     const int t = threadIdx.x;
-    partial[((long long)r * nvmax + grp * kDotGroup + t) * gridDim.x + blockIdx.x] =
+    partial[((long long)r * nvmax + grp * G + t) * gridDim.x + blockIdx.x] =
         red[t][0] + red[t][1] + red[t][2] + red[t][3];
   }
 }
@@ -693,9 +698,15 @@ static hipError_t dots_impl(const cx<VT>* V, long long ldj, int nv, int nvmax, c
                             long long n, int nb, zd* partial, int nblk, zd* out,
                             long long ostride, zd* acc, long long astride, const int* active,
                             hipStream_t st) {
-  const int ng = (nv + kDotGroup - 1) / kDotGroup;
-  hipLaunchKernelGGL((k_dots<VT>), dim3(nblk, ng, nb), dim3(256), 0, st, V, ldj, nv, nvmax, w, n,
-                     partial, active);
+  // groups of 8 basis vectors while there are at most 8, else of 16 (w read once per group)
+  if (nv <= kDotGroup) {
+    hipLaunchKernelGGL((k_dots<VT, kDotGroup, kDotUnroll>), dim3(nblk, 1, nb), dim3(256), 0, st,
+                       V, ldj, nv, nvmax, w, n, partial, active);
+  } else {
+    const int ng = (nv + kDotGroupWide - 1) / kDotGroupWide;
+    hipLaunchKernelGGL((k_dots<VT, kDotGroupWide, kDotUnrollWide>), dim3(nblk, ng, nb), dim3(256),
+                       0, st, V, ldj, nv, nvmax, w, n, partial, active);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_cols, dim3(nv, nb), dim3(256), 0, st, partial, nblk, nvmax, out,
@@ -749,68 +760,68 @@ static hipError_t update_impl(const cx<VT>* V, long long ldj, int nv, const zd* 
   return hipGetLastError();
 }
 
-// First Gram-Schmidt update fused with the second pass's dot products, for nv <= kDotGroup
-// basis vectors: w_r -= sum_i h[r * hstride + i] V_i,r, then the per-block partial sums
-// of conj(V_i,r) w_r (updated w) in k_dots' layout, from the same loads of V (one pass
-// over the basis instead of two).
-template <typename VT>
+// First Gram-Schmidt update fused with the second pass's dot products, for nv <= G basis
+// vectors: w_r -= sum_i h[r * hstride + i] V_i,r, then the per-block partial sums of
+// conj(V_i,r) w_r (updated w) in k_dots' layout, from the same loads of V (one pass over
+// the basis instead of two).
+template <typename VT, int G, int U>
 __global__ __launch_bounds__(256) void k_update_dots(const cx<VT>* __restrict__ V, long long ldj,
                                                      int nv, int nvmax,
                                                      const zd* __restrict__ h, long long hstride,
                                                      zd* __restrict__ wall, long long n,
                                                      zd* __restrict__ partial,
                                                      const int* __restrict__ active) {
-  __shared__ zd hs[kDotGroup];
-  __shared__ zd red[kDotGroup][4];
+  __shared__ zd hs[G];
+  __shared__ zd red[G][4];
   const int r = blockIdx.y;
   if (active && !active[r]) return;
   if (threadIdx.x < nv) hs[threadIdx.x] = h[r * hstride + threadIdx.x];
   __syncthreads();
   zd* w = wall + r * n;
   const cx<VT>* Vr = V + r * n;
-  zd acc[kDotGroup];
-  for (int t = 0; t < kDotGroup; ++t) acc[t] = mk(0.0, 0.0);
+  zd acc[G];
+  for (int t = 0; t < G; ++t) acc[t] = mk(0.0, 0.0);
   const long long stride = (long long)gridDim.x * blockDim.x;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + (kDotUnroll - 1) * stride < n; i += kDotUnroll * stride) {
-    zd a[kDotUnroll];
-    cx<VT> v[kDotGroup][kDotUnroll];
+  for (; i + (U - 1) * stride < n; i += U * stride) {
+    zd a[U];
+    cx<VT> v[G][U];
 #pragma unroll
-    for (int u = 0; u < kDotUnroll; ++u) a[u] = w[i + u * stride];
+    for (int u = 0; u < U; ++u) a[u] = w[i + u * stride];
 #pragma unroll
-    for (int t = 0; t < kDotGroup; ++t)
+    for (int t = 0; t < G; ++t)
       if (t < nv) {
 #pragma unroll
-        for (int u = 0; u < kDotUnroll; ++u) v[t][u] = Vr[t * ldj + i + u * stride];
+        for (int u = 0; u < U; ++u) v[t][u] = Vr[t * ldj + i + u * stride];
 #pragma unroll
-        for (int u = 0; u < kDotUnroll; ++u) a[u] = a[u] - hs[t] * widen(v[t][u]);
+        for (int u = 0; u < U; ++u) a[u] = a[u] - hs[t] * widen(v[t][u]);
       }
 #pragma unroll
-    for (int u = 0; u < kDotUnroll; ++u) w[i + u * stride] = a[u];
+    for (int u = 0; u < U; ++u) w[i + u * stride] = a[u];
 #pragma unroll
-    for (int t = 0; t < kDotGroup; ++t)
+    for (int t = 0; t < G; ++t)
       if (t < nv) {
 #pragma unroll
-        for (int u = 0; u < kDotUnroll; ++u) acc[t] = acc[t] + conj(widen(v[t][u])) * a[u];
+        for (int u = 0; u < U; ++u) acc[t] = acc[t] + conj(widen(v[t][u])) * a[u];
       }
   }
   for (; i < n; i += stride) {
-    cx<VT> v[kDotGroup];
+    cx<VT> v[G];
     zd a = w[i];
 #pragma unroll
-    for (int t = 0; t < kDotGroup; ++t)
+    for (int t = 0; t < G; ++t)
       if (t < nv) {
         v[t] = Vr[t * ldj + i];
         a = a - hs[t] * widen(v[t]);
       }
     w[i] = a;
 #pragma unroll
-    for (int t = 0; t < kDotGroup; ++t)
+    for (int t = 0; t < G; ++t)
       if (t < nv) acc[t] = acc[t] + conj(widen(v[t])) * a;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int t = 0; t < kDotGroup; ++t) {
+  for (int t = 0; t < G; ++t) {
     const zd sum = mk(wave_sum(acc[t].re), wave_sum(acc[t].im));
     if (lane == 0) red[t][wv] = sum;
   }
@@ -822,14 +833,21 @@ __global__ __launch_bounds__(256) void k_update_dots(const cx<VT>* __restrict__ 
   }
 }
 
+// Up to 8 basis vectors: 4 elements per trip; up to 16: 2 (single-precision basis) or 1
+// (double) elements per trip, which keeps the loaded basis values within the registers.
 template <typename VT>
 static hipError_t update_dots_impl(const cx<VT>* V, long long ldj, int nv, int nvmax,
                                    const zd* h, long long hstride, zd* w, long long n, int nb,
                                    zd* partial, int nblk, zd* out, long long ostride, zd* acc,
                                    long long astride, const int* active, hipStream_t st) {
-  if (nv < 1 || nv > kDotGroup) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_update_dots<VT>), dim3(nblk, nb), dim3(256), 0, st, V, ldj, nv, nvmax, h,
-                     hstride, w, n, partial, active);
+  if (nv < 1 || nv > kDotGroupWide) return hipErrorInvalidValue;
+  constexpr int kUw = sizeof(VT) == sizeof(float) ? kDotUnrollWide : 1;
+  if (nv <= kDotGroup)
+    hipLaunchKernelGGL((k_update_dots<VT, kDotGroup, kDotUnroll>), dim3(nblk, nb), dim3(256), 0,
+                       st, V, ldj, nv, nvmax, h, hstride, w, n, partial, active);
+  else
+    hipLaunchKernelGGL((k_update_dots<VT, kDotGroupWide, kUw>), dim3(nblk, nb), dim3(256), 0, st,
+                       V, ldj, nv, nvmax, h, hstride, w, n, partial, active);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_cols, dim3(nv, nb), dim3(256), 0, st, partial, nblk, nvmax, out,

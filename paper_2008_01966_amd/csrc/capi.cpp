@@ -425,7 +425,7 @@ size_t plan_bytes(const cav::Geo& g, bool layered, int chunk, int nlayers, int* 
 size_t work_bytes(const cav::Geo& g, int restart, int nb, int nblk, bool spec) {
   const size_t n = 3ull * g.NM;
   const size_t z = sizeof(zd);
-  return z * ((size_t)nb * 2 * 3 * (g.M + 1) * g.P2 + (size_t)nb * 3 * g.NM +
+  return z * ((size_t)nb * 2 * 3 * (g.M + 1) * g.ldx + (size_t)nb * 3 * g.NM +
               (spec ? (size_t)nb * 3 * g.P1 * g.P2 + 2 * ((size_t)g.P1 * (g.M + 1) +
                                                          (size_t)g.P2 * (g.N + 1)) : 0) +
               (size_t)(restart + 1) * nb * n + 4ull * nb * n +
@@ -440,8 +440,8 @@ int ensure_work(cavity_plan p, int nb) {
   const int R = p->opts.restart;
   const long long n = p->nvec();
   Layout L;
-  L.add(&p->X, (size_t)nb * 3 * (p->g.M + 1) * p->g.P2);
-  L.add(&p->Y, (size_t)nb * 3 * (p->g.M + 1) * p->g.P2);
+  L.add(&p->X, (size_t)nb * 3 * (p->g.M + 1) * p->g.ldx);
+  L.add(&p->Y, (size_t)nb * 3 * (p->g.M + 1) * p->g.ldx);
   L.add(&p->S, (size_t)nb * 3 * p->g.NM);
   if (p->use_spec()) L.add(&p->U, (size_t)nb * 3 * p->g.P1 * p->g.P2);
   L.add(&p->V, (size_t)(R + 1) * nb * n);
@@ -1365,6 +1365,7 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   const double R = std::sqrt(2.0) * std::max(a, b);
   g.P1 = next_5smooth((long long)std::ceil((a + R) / g.hq1));
   g.P2 = next_5smooth((long long)std::ceil((b + R) / g.hq2));
+  g.ldx = (g.P2 + 15) & ~15;
 
   if ((size_t)2 * std::max(g.P1, g.P2) * sizeof(zd) > (size_t)kMaxLdsPerBlock)
     return fail(CAVITY_EINVAL, "FFT box too large for one block's LDS");

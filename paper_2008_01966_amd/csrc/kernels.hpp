@@ -14,6 +14,8 @@ struct Geo {
   int M, N, Nz, NM;     // modes per axis, z-intervals, (M+1)(N+1)
   int nq1, nq2;         // TBC quadrature intervals per axis (s*Nx, s*Ny)
   int P1, P2;           // FFT box of the TBC convolution
+  int ldx;              // row stride of the TBC workspaces X, Y: P2 rounded up to 16 entries,
+                        // so every row starts on a 128-byte line
   int nx, ny;           // output grid intervals (Nx, Ny)
   double a, b, h, k;
   double hq1, hq2;

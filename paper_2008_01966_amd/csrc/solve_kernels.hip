@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
   const zd* v = vall + rhs * vs;
   const zd* pinv = pinv_all + rhs * pcs;
   const int nf = fam_fixed >= 0 ? 1 : 3;
-  cx<T>* X = Xall + (long long)rhs * nf * (g.M + 1) * g.P2;
+  cx<T>* X = Xall + (long long)rhs * nf * (g.M + 1) * g.ldx;
   const int C = 1 << lc;
   const int m0 = bid.x << lc;
   const int Cb = min(C, g.M + 1 - m0);
@@ -175,10 +175,10 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
   cx<T>* r2 = o;
   if (ip) fft_lds_ip<T, false, MR>(o, box2.p, twiddles<T>(box2), tid, lc);
   else r2 = fft_lds<T, false, MR>(o, r, box2.p, twiddles<T>(box2), tid, nt, lc);
-  cx<T>* dst = X + ((long long)slot * (g.M + 1) + m0) * g.P2;
+  cx<T>* dst = X + ((long long)slot * (g.M + 1) + m0) * g.ldx;
   for (int w = tid; w < P * Cb; w += nt) {
     const int c = div_p.quot(w), k = w - c * div_p.d;
-    dst[(long long)c * g.P2 + k] = r2[(k << lc) + c];
+    dst[(long long)c * g.ldx + k] = r2[(k << lc) + c];
   }
 }
 
@@ -228,13 +228,13 @@ struct ExtendCrop {
 template <typename T>
 struct ColumnStore {
   cx<T>* Y;            // Y + k0
-  int P2, rows, Cb;
+  int ld, rows, Cb;   // ld: row stride of Y
   bool xcos;
   T hq;
   __device__ void operator()(cx<T>*, int m, int c, cx<T> F) const {
     if (m >= rows || c >= Cb) return;
     const cx<T> s = xcos ? (T)0.5 * F : (T)0.5 * mul_i(F);
-    Y[(long long)m * P2 + c] = hq * s;
+    Y[(long long)m * ld + c] = hq * s;
   }
 };
 
@@ -252,11 +252,11 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   const int rhs = bid.z;
   if (active && !active[rhs]) return;
   const int nf = fam_fixed >= 0 ? 1 : 3;
-  const long long wsz = (long long)nf * (g.M + 1) * g.P2;
+  const long long wsz = (long long)nf * (g.M + 1) * g.ldx;
   const int f = fam_fixed >= 0 ? fam_fixed : bid.y;
   const int slot = fam_fixed >= 0 ? 0 : bid.y;
-  const cx<T>* X = Xall + rhs * wsz + (long long)slot * (g.M + 1) * g.P2;
-  cx<T>* Y = Yall + rhs * wsz + (long long)slot * (g.M + 1) * g.P2;
+  const cx<T>* X = Xall + rhs * wsz + (long long)slot * (g.M + 1) * g.ldx;
+  cx<T>* Y = Yall + rhs * wsz + (long long)slot * (g.M + 1) * g.ldx;
   const int C = 1 << lc;
   const int k0 = bid.x << lc;
   const int Cb = min(C, g.P2 - k0);
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   for (int w = tid; w < (g.M + 1) << lc; w += nt) {
     const int m = w >> lc, c = w & (C - 1);
     if (c >= Cb) continue;
-    const cx<T> x = X[(long long)m * g.P2 + k0 + c];
+    const cx<T> x = X[(long long)m * g.ldx + k0 + c];
     store_extension(a, L, xcos, m, x, lc, c);
     if (m == 0) c0s[c] = x;
   }
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   }
   // the last stage writes the projected entries m = 0..M straight to Y
   fft_lds_put<T, false, MR>(o3, r3, ext1.p, tw_e, tid, nt, lc,
-                            ColumnStore<T>{Y + k0, g.P2, g.M + 1, Cb, xcos, hq});
+                            ColumnStore<T>{Y + k0, g.ldx, g.M + 1, Cb, xcos, hq});
 }
 
 // Pass 3: rows m0 .. m0+Cb-1 backward; writes S[slot][mn] in double.
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
   const int f = fam_fixed >= 0 ? fam_fixed : bid.y;
   const int slot = fam_fixed >= 0 ? 0 : bid.y;
   const cx<T>* Y =
-      Yall + (long long)rhs * nf * (g.M + 1) * g.P2 + (long long)slot * (g.M + 1) * g.P2;
+      Yall + (long long)rhs * nf * (g.M + 1) * g.ldx + (long long)slot * (g.M + 1) * g.ldx;
   zd* S = Sall + (long long)rhs * nf * g.NM + (long long)slot * g.NM;
   const int C = 1 << lc;
   const int m0 = bid.x << lc;
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int w = tid; w < P << lc; w += nt) {
     const int c = div_p.quot(w), k = w - c * div_p.d;
-    a[(k << lc) + c] = c < Cb ? Y[(long long)(m0 + c) * g.P2 + k] : mk<T>(0, 0);
+    a[(k << lc) + c] = c < Cb ? Y[(long long)(m0 + c) * g.ldx + k] : mk<T>(0, 0);
   }
   __syncthreads();
   // in place: a holds the box transform (P), b the extension transform (2L)

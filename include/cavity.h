@@ -32,6 +32,9 @@
  *    the outputs except where stated, and cavity_last_error() returns a message for the
  *    calling thread.
  *  - A plan is not thread-safe; distinct plans may be used from distinct threads/streams.
+ *  - Device arrays of complex values passed in (E_out, aperture_out, a request's E_out)
+ *    must be 16-byte aligned (as every hipMalloc or torch allocation is); a misaligned
+ *    one gives CAVITY_EINVAL.
  *  - Field output layout E_out[3][Nz+1][Ny+1][Nx+1] (component, z-node, y-node, x-node;
  *    x fastest) on the nodes x = i1 a/Nx, y = i2 b/Ny, z = -c + j h.  At an interface
  *    node the normal component E3 is reported on the upper side.

@@ -1693,6 +1693,8 @@ int cavity_solve(cavity_plan p, double theta, double phi, int pol, cavity_c128* 
 int cavity_solve_batch(cavity_plan p, int nrhs, const double* theta, const double* phi,
                        const int* pol, cavity_c128* E_out, cavity_c128* aperture_out) {
   if (!p || nrhs < 1 || !theta || !phi || !pol) return fail(CAVITY_EINVAL, "bad batch arguments");
+  if (!cav::aligned16(E_out) || !cav::aligned16(aperture_out))
+    return fail(CAVITY_EINVAL, "device outputs must be 16-byte aligned");
   for (int i = 0; i < nrhs; ++i)
     if (!angles_ok(theta[i], phi[i], pol[i]))
       return fail(CAVITY_EINVAL, "theta must lie in [0, pi/2], phi finite, pol TM or TE");
@@ -1748,6 +1750,8 @@ int cavity_solve_group(int n, const cavity_plan* plans, const double* theta, con
       if (plans[t] == q) return fail(CAVITY_EINVAL, "a plan appears twice in the group");
     if (!angles_ok(theta[r], phi[r], pol[r]))
       return fail(CAVITY_EINVAL, "theta must lie in [0, pi/2], phi finite, pol TM or TE");
+    if (E_out && !cav::aligned16(E_out[r]))
+      return fail(CAVITY_EINVAL, "device outputs must be 16-byte aligned");
     const cav::Geo &a = lead->g, &b = q->g;
     if (a.M != b.M || a.N != b.N || a.nq1 != b.nq1 || a.nq2 != b.nq2 || a.P1 != b.P1 ||
         a.P2 != b.P2 || a.a != b.a || a.b != b.b || a.k != b.k || q->device != lead->device ||

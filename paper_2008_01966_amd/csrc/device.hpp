@@ -11,8 +11,10 @@
 
 namespace cav {
 
+// Aligned to its size, so that a complex value moves as one 8- or 16-byte access (LDS
+// ds_read_b64 / ds_read_b128 rather than two half-width accesses).
 template <typename R>
-struct cx {
+struct alignas(2 * sizeof(R)) cx {
   R re, im;
 };
 

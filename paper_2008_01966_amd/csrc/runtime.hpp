@@ -19,6 +19,10 @@ void device_block_release(void* ptr, size_t bytes);
 // Record the status and message of the calling thread's last error (cavity_last_error).
 int record_error(int status, const char* msg);
 
+// Whether a caller's device array of complex values meets the 16-byte alignment the
+// kernels' complex accesses assume (a null pointer passes).
+inline bool aligned16(const void* p) { return (reinterpret_cast<size_t>(p) & 15) == 0; }
+
 // What the RCS of stored solutions needs from a plan: its sizes, the padded solutions
 // (nsol of them, nvec entries each), its stream and device, and the number of blocks per
 // query of the aperture-transform reduction.

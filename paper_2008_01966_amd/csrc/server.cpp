@@ -9,6 +9,8 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -98,6 +100,7 @@ struct cavity_server_s {
   int running = 0;
   int ready = 0;                // workers that have set up their stream
   bool stopping = false;
+  bool trace = false;             // CAVITY_SERVER_TRACE=1: admissions on stderr
 
   double now_ms() const {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
@@ -295,6 +298,10 @@ void cavity_server_s::work() {
       cv_work.wait(lk, [&] {
         if (stopping && queue.empty()) return true;
         i = pick();
+        if (trace && i < 0 && !queue.empty())
+          std::fprintf(stderr, "[server] %.3f ms: worker waits, head %lld needs %zu, in use %zu of %zu, "
+                       "%zu queued\n", now_ms(), queue[0].ticket,
+                       queue[0].plan_bytes + queue[0].field_bytes, in_use, budget, queue.size());
         return i >= 0;
       });
       if (queue.empty()) break;
@@ -326,6 +333,10 @@ void cavity_server_s::work() {
       drop = evict_for(total, reused);
       in_use += total;
       ++running;
+      if (trace)
+        std::fprintf(stderr, "[server] %.3f ms: ticket %lld starts (group %zu), in use %zu of %zu, "
+                     "%zu queued\n", now_ms(), grp[0].ticket, grp.size(), in_use, budget,
+                     queue.size());
     }
     for (cavity_plan q : drop) cavity_plan_destroy(q);
     cv_work.notify_all();
@@ -385,6 +396,8 @@ void cavity_server_s::work() {
       --running;
     }
     for (cavity_plan q : drop) cavity_plan_destroy(q);
+    if (trace)
+      std::fprintf(stderr, "[server] %.3f ms: ticket %lld done\n", now_ms(), grp[0].ticket);
     cv_done.notify_all();
     cv_work.notify_all();
   }
@@ -431,6 +444,7 @@ int cavity_server_create(const cavity_server_opts* opts, cavity_server* out) {
   srv->plan_cache_limit = o.plan_cache_bytes == SIZE_MAX ? budget / 4
                                                          : std::min(o.plan_cache_bytes, budget);
   srv->t0 = std::chrono::steady_clock::now();
+  if (const char* e = std::getenv("CAVITY_SERVER_TRACE")) srv->trace = std::atoi(e) != 0;
   for (int i = 0; i < o.streams; ++i) srv->workers.emplace_back([srv] { srv->work(); });
   {
     // every worker has its stream before the first request can arrive
@@ -448,6 +462,8 @@ int cavity_server_submit(cavity_server srv, const cavity_request* r, long long* 
   if (!(r->theta >= 0.0 && r->theta <= 0.5 * M_PI + 1e-12) || !std::isfinite(r->phi) ||
       (r->pol != CAVITY_TM && r->pol != CAVITY_TE))
     return cav::record_error(CAVITY_EINVAL, "theta in [0, pi/2], finite phi, pol TM or TE");
+  if (!cav::aligned16(r->E_out))
+    return cav::record_error(CAVITY_EINVAL, "E_out must be 16-byte aligned");
   Pending pd;
   pd.req = *r;
   pd.lnz.assign(r->layer_nz, r->layer_nz + r->n_layers);

@@ -5,6 +5,7 @@ match the oracle within 1e-8, admission must respect the device-memory budget, a
 that share an aperture (spectrum and diagonal taken from the library's cache) must equal a
 plan computed from scratch."""
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -247,23 +248,47 @@ def test_resident_plan_reuse_is_exact():
 @pytest.mark.timeout(300)
 def test_admission_passes_a_large_head():
     """With room for the large request alone, a small request queued behind it starts while
-    another small one runs, before the large head (which then runs alone)."""
+    another small one runs, before the large head (which then runs alone).  An attempt in
+    which the small request could not start while the first one ran (it was queued after
+    the first one ended, or a worker thread was not scheduled in time) says nothing about
+    the admission rule and is repeated, at most five times; the rule itself would fail
+    every attempt."""
+    import time
+
     import torch
-    slow = W.Cavity(2.0, 2.0, 1.0, 64, 64, 32, (16, 16), (4.0 + 1.0j, 1.0 + 0j))
+    # 64 z-levels make the first request last a few ms while its footprint stays below the
+    # large one's
+    slow = W.Cavity(2.0, 2.0, 1.0, 64, 64, 64, (32, 32), (4.0 + 1.0j, 1.0 + 0j))
     big = W.Cavity(3.0, 3.0, 1.0, 96, 96, 32, (32,), (2.0 + 0.5j,))
     small = W.small_cases()[0].cavity
     f_slow, f_big, f_small = _footprint(slow), _footprint(big), _footprint(small)
     assert f_slow + f_big > f_big + 1024 >= f_slow + f_small
-    srv = P.Server(streams=2, hbm_budget=f_big + 1024, precision="mixed", plan_cache_bytes=0)
-    t1 = srv.submit(slow, 0.3, 0.2, W.TM)
-    t2 = srv.submit(big, 0.3, 0.2, W.TM)
-    t3 = srv.submit(small, 0.3, 0.2, W.TE)
-    r1, r2, r3 = srv.wait(t1), srv.wait(t2), srv.wait(t3)
-    srv.close()
-    torch.cuda.synchronize()
-    print(f"\n[case] starts: slow {r1.t_start_ms:.2f}, big {r2.t_start_ms:.2f}, "
-          f"small {r3.t_start_ms:.2f} ms; slow done {r1.t_done_ms:.2f}", flush=True)
-    assert r1.status == r2.status == r3.status == 0
+    for attempt in range(5):
+        # the server's admission trace (stderr) goes into the captured output of a failure
+        os.environ["CAVITY_SERVER_TRACE"] = "1"
+        try:
+            srv = P.Server(streams=2, hbm_budget=f_big + 1024, precision="mixed",
+                           plan_cache_bytes=0)
+        finally:
+            del os.environ["CAVITY_SERVER_TRACE"]
+        c0 = time.perf_counter()
+        t1 = srv.submit(slow, 0.3, 0.2, W.TM)
+        t2 = srv.submit(big, 0.3, 0.2, W.TM)
+        t3 = srv.submit(small, 0.3, 0.2, W.TE)
+        c1 = time.perf_counter()
+        r1, r2, r3 = srv.wait(t1), srv.wait(t2), srv.wait(t3)
+        srv.close()
+        torch.cuda.synchronize()
+        print(f"\n[case] attempt {attempt}: starts slow {r1.t_start_ms:.2f}, big "
+              f"{r2.t_start_ms:.2f}, small {r3.t_start_ms:.2f} ms; slow done {r1.t_done_ms:.2f}; "
+              f"queued at {r1.t_submit_ms:.2f}, {r2.t_submit_ms:.2f}, {r3.t_submit_ms:.2f} "
+              f"(three submits {1e3 * (c1 - c0):.2f} ms)", flush=True)
+        assert r1.status == r2.status == r3.status == 0
+        # the budget holds the large head alone: it never starts while the first one runs
+        assert r2.t_start_ms >= r1.t_done_ms - 1e-6
+        if r3.t_start_ms < r1.t_done_ms:
+            break
+    assert r3.t_start_ms < r1.t_done_ms, "the small request never started beside the first"
     assert r3.t_start_ms < r2.t_start_ms
     assert r2.t_start_ms >= max(r1.t_done_ms, r3.t_done_ms) - 1e-6
 

@@ -1376,8 +1376,8 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   int chunk = (int)std::max<size_t>(1, slab / per_level);
   chunk = (int)std::min<long long>(chunk, (long long)(Nz + 1) * o.batch);
   const int fft_len[6] = {2 * g.nq1, 2 * g.nq2, g.P1, g.P2, 2 * g.nx, 2 * g.ny};
-  int twn = 0;
-  for (int l : fft_len) twn += l;
+  int twn = 0;   // stage twiddle tables of the six transform lengths
+  for (int l : fft_len) twn += std::max(1, make_fft_plan(l).ntw);
   const int nb0 = 1;
   const size_t need = plan_bytes(g, layered, chunk, (int)lnz.size(), &twn) +
                       work_bytes(g, o.restart, nb0, dot_blocks(3LL * g.NM),
@@ -1555,13 +1555,16 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     cav::Fft* dst[6] = {&p->trig.ext1, &p->trig.ext2, &p->trig.box1, &p->trig.box2,
                         &p->trig.out1, &p->trig.out2};
     p->trig.maxr = 1;
+    std::vector<zd> table;
     for (int i = 0; i < 6; ++i) {
-      twiddle_table(fft_len[i], tw.data() + off);
       dst[i]->p = make_fft_plan(fft_len[i]);
+      table.resize(fft_len[i]);
+      twiddle_table(fft_len[i], table.data());
+      cav::fill_stage_twiddles(dst[i]->p, table.data(), tw.data() + off);
       dst[i]->tw = p->twiddles + off;
       dst[i]->twf = p->twiddles_f + off;
       p->trig.maxr = std::max(p->trig.maxr, plan_max_radix(dst[i]->p));
-      off += fft_len[i];
+      off += std::max(1, dst[i]->p.ntw);
     }
     // CAVITY_FFT_MAXR=16: the same plans run by the kernels compiled for radices up to 16
     if (const char* e = std::getenv("CAVITY_FFT_MAXR"))

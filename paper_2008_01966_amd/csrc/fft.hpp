@@ -249,22 +249,27 @@ template <typename T, bool INV> struct Dft<32, T, INV> : DftCt<4, 8, T, INV> {};
   X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(15) X(16) X(20) X(25) X(32)
 
 // ---- FFT plan -----------------------------------------------------------------------
-// Factorisation of n into the radices of its Stockham stages, applied in order.
+// Factorisation of n into the radices of its Stockham stages, applied in order, and the
+// layout of its stage twiddle table: stage s (s >= 1; span ns = radix[0] ... radix[s-1],
+// radix R) keeps the R - 1 twiddles of butterfly k (0 <= k < ns) side by side at
+// twoff[s] + k (R - 1), so a work item loads its twiddles from one place; ntw entries in
+// all.  Entry r - 1 of butterfly k is W_n^{r k n/(ns R)} = exp(-2 pi i r k / (ns R)).
 struct FftPlan {
   int n;
   int nst;
   int radix[20];
+  int twoff[20];
+  int ntw;
 };
-// Twiddle table of a length-n transform: tw[t] = exp(-2 pi i t / n), t = 0..n-1.
 
 // One Stockham stage of radix R over C = 2^lc interleaved transforms of length n with
 // span ns: butterfly j (0 <= j < n/R) of transform col reads in[(j + r n/R) C + col],
-// scales input r by W_{ns R}^{r (j mod ns)}, and writes out[((j - k) R + k + r ns) C + col].
+// scales input r by W_{ns R}^{r (j mod ns)} (tw: this stage's part of the stage twiddle
+// table, see FftPlan), and writes out[((j - k) R + k + r ns) C + col].
 template <int R, typename T, bool INV>
 __device__ inline void fft_stage(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int n,
                                  int ns, int lc, const cx<T>* __restrict__ tw, int tid, int nthr) {
   const int nb = n / R;
-  const int tstep = n / (ns * R);
   const int total = nb << lc;
   const int cmask = (1 << lc) - 1;
   // Uniform strides: input r of work item w sits at w + r istride, output r at
@@ -284,11 +289,10 @@ __device__ inline void fft_stage(const cx<T>* __restrict__ in, cx<T>* __restrict
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = ip[r * istride];
     if (ns > 1) {
-      const cx<T>* tp = tw + k * tstep;
-      const int step = k * tstep;
+      const cx<T>* tp = tw + k * (R - 1);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const cx<T> w2 = tp[(r - 1) * step];
+        const cx<T> w2 = tp[r - 1];
         v[r] = v[r] * (INV ? conj(w2) : w2);
       }
     }
@@ -315,7 +319,7 @@ __device__ cx<T>* fft_lds(cx<T>* a, cx<T>* b, const FftPlan& p, const cx<T>* __r
     switch (rdx) {
 #define CAV_FFT_CASE(R)                                                 \
   case R:                                                               \
-    if constexpr (R <= MAXR) fft_stage<R, T, INV>(in, out, p.n, ns, lc, tw, tid, nthr); \
+    if constexpr (R <= MAXR) fft_stage<R, T, INV>(in, out, p.n, ns, lc, tw + p.twoff[s], tid, nthr); \
     break;
       CAV_FFT_RADICES(CAV_FFT_CASE)
 #undef CAV_FFT_CASE
@@ -338,7 +342,6 @@ __device__ inline void fft_stage_put(const cx<T>* __restrict__ in, cx<T>* dst, i
                                      int lc, const cx<T>* __restrict__ tw, int tid, int nthr,
                                      const Put& put) {
   const int nb = n / R;
-  const int tstep = n / (ns * R);
   const int total = nb << lc;
   const int cmask = (1 << lc) - 1;
   const int istride = nb << lc;
@@ -353,11 +356,10 @@ __device__ inline void fft_stage_put(const cx<T>* __restrict__ in, cx<T>* dst, i
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = ip[r * istride];
     if (ns > 1) {
-      const cx<T>* tp = tw + k * tstep;
-      const int step = k * tstep;
+      const cx<T>* tp = tw + k * (R - 1);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const cx<T> w2 = tp[(r - 1) * step];
+        const cx<T> w2 = tp[r - 1];
         v[r] = v[r] * (INV ? conj(w2) : w2);
       }
     }
@@ -383,8 +385,8 @@ __device__ cx<T>* fft_lds_put(cx<T>* a, cx<T>* b, const FftPlan& p, const cx<T>*
 #define CAV_FFT_CASE_PUT(R)                                                              \
   case R:                                                                                \
     if constexpr (R <= MAXR) {                                                           \
-      if (last) fft_stage_put<R, T, INV>(in, out, p.n, ns, lc, tw, tid, nthr, put);      \
-      else fft_stage<R, T, INV>(in, out, p.n, ns, lc, tw, tid, nthr);                    \
+      if (last) fft_stage_put<R, T, INV>(in, out, p.n, ns, lc, tw + p.twoff[s], tid, nthr, put); \
+      else fft_stage<R, T, INV>(in, out, p.n, ns, lc, tw + p.twoff[s], tid, nthr);     \
     }                                                                                    \
     break;
       CAV_FFT_RADICES(CAV_FFT_CASE_PUT)
@@ -408,7 +410,6 @@ template <int R, typename T, bool INV>
 __device__ inline void fft_stage_ip(cx<T>* buf, int n, int ns, int lc,
                                     const cx<T>* __restrict__ tw, int tid) {
   const int nb = n / R;
-  const int tstep = n / (ns * R);
   const int total = nb << lc;
   const int istride = nb << lc, ostride = ns << lc;
   const bool act = tid < total;
@@ -423,11 +424,10 @@ __device__ inline void fft_stage_ip(cx<T>* buf, int n, int ns, int lc,
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = ip[r * istride];
     if (ns > 1) {
-      const int step = k * tstep;
-      const cx<T>* tp = tw + step;
+      const cx<T>* tp = tw + k * (R - 1);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const cx<T> w2 = tp[(r - 1) * step];
+        const cx<T> w2 = tp[r - 1];
         v[r] = v[r] * (INV ? conj(w2) : w2);
       }
     }
@@ -453,7 +453,7 @@ __device__ void fft_lds_ip(cx<T>* buf, const FftPlan& p, const cx<T>* __restrict
     switch (rdx) {
 #define CAV_FFT_CASE_IP(R)                                                         \
   case R:                                                                          \
-    if constexpr (R <= MAXR) fft_stage_ip<R, T, INV>(buf, p.n, ns, lc, tw, tid);   \
+    if constexpr (R <= MAXR) fft_stage_ip<R, T, INV>(buf, p.n, ns, lc, tw + p.twoff[s], tid); \
     break;
       CAV_FFT_RADICES(CAV_FFT_CASE_IP)
 #undef CAV_FFT_CASE_IP
@@ -557,7 +557,28 @@ inline FftPlan plan_fft(int n, int max_radix) {
         }
   }
   delete[] best;
+  int ns = 1, off = 0;
+  for (int s = 0; s < p.nst; ++s) {
+    p.twoff[s] = off;
+    if (s > 0) off += ns * (p.radix[s] - 1);
+    ns *= p.radix[s];
+  }
+  p.ntw = off;
   return p;
+}
+
+// Stage twiddle table of plan p (layout in FftPlan) from the plain table
+// table[t] = exp(-2 pi i t / n): entry r - 1 of butterfly k of stage s is table[r k n/(ns R)].
+template <typename C>
+inline void fill_stage_twiddles(const FftPlan& p, const C* table, C* out) {
+  int ns = p.nst > 0 ? p.radix[0] : 1;
+  for (int s = 1; s < p.nst; ++s) {
+    const int R = p.radix[s];
+    const int tstep = p.n / (ns * R);
+    for (int k = 0; k < ns; ++k)
+      for (int r = 1; r < R; ++r) out[p.twoff[s] + k * (R - 1) + (r - 1)] = table[r * k * tstep];
+    ns *= R;
+  }
 }
 
 }  // namespace cav

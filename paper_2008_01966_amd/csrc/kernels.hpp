@@ -23,7 +23,8 @@ struct Geo {
   int rows_ip;          // TBC row passes: 1 = in-place transforms allowed, 0 = ping-pong form
 };
 
-// An FFT length with its device twiddle tables (double and single precision).
+// An FFT length with its device stage twiddle tables (double and single precision; layout in
+// FftPlan).
 struct Fft {
   FftPlan p;
   const zd* tw;

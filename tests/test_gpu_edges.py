@@ -61,3 +61,31 @@ def test_edge_case_against_oracle(case, direct):
         assert np.linalg.norm(oes[i]) <= 1e-12 * fscale
         assert float(fields[i].abs().max()) <= 1e-12 * fscale
     plan.close()
+
+
+def test_misaligned_field_output_is_refused():
+    """Device outputs of complex values must be 16-byte aligned (the kernels move each value
+    as one 16-byte access): a field pointer 8 bytes into a buffer gives CAVITY_EINVAL from
+    cavity_solve, cavity_solve_batch and cavity_solve_group before any work is queued, and
+    the aligned call then succeeds."""
+    import ctypes
+
+    import torch
+    cav = EDGE[0][1]
+    plan = P.Plan.from_cavity(cav)
+    buf = torch.zeros(plan.nz + 2, 3 * (plan.ny + 1) * (plan.nx + 1), dtype=torch.complex128,
+                      device="cuda").reshape(-1)
+    bad = ctypes.c_void_p(buf.data_ptr() + 8)
+    lib = plan._lib
+    assert lib.cavity_solve(plan._h, 0.3, 0.2, W.TM, bad) == 1
+    th, ph, po = (ctypes.c_double * 1)(0.3), (ctypes.c_double * 1)(0.2), (ctypes.c_int * 1)(W.TM)
+    assert lib.cavity_solve_batch(plan._h, 1, th, ph, po, bad, None) == 1
+    plans = (ctypes.c_void_p * 1)(plan._h.value)
+    outs = (ctypes.c_void_p * 1)(bad.value)
+    assert lib.cavity_solve_group(1, plans, th, ph, po, outs) == 1
+    torch.cuda.synchronize()
+    assert float(buf.abs().max()) == 0.0
+    good = plan.solve(0.3, 0.2, W.TM)
+    torch.cuda.synchronize()
+    assert float(good.abs().max()) > 0.0
+    plan.close()

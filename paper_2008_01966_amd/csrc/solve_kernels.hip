@@ -14,6 +14,10 @@
 
 namespace cav {
 
+// Elements per thread per trip of the global-to-LDS load loops: the trip's loads are all
+// issued before its LDS stores, so their latencies overlap.
+constexpr int kLoadBatch = 4;
+
 __device__ inline zd exp_int(double w, double len) {
   const double th = 0.5 * w * len;
   double s, c;
@@ -275,12 +279,21 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   }
   for (int c = tid; c < C; c += nt) c0s[c] = mk<T>(0, 0);
   __syncthreads();
-  for (int w = tid; w < (g.M + 1) << lc; w += nt) {
-    const int m = w >> lc, c = w & (C - 1);
-    if (c >= Cb) continue;
-    const cx<T> x = X[(long long)m * g.ldx + k0 + c];
-    store_extension(a, L, xcos, m, x, lc, c);
-    if (m == 0) c0s[c] = x;
+  // kLoadBatch elements per thread per trip with every load issued before the stores
+  for (int w0 = tid; w0 < (g.M + 1) << lc; w0 += kLoadBatch * nt) {
+    cx<T> xv[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {   // indices clamped in range: no conditional loads
+      const int w = w0 + u * nt, m = min(w >> lc, g.M), c = min(w & (C - 1), Cb - 1);
+      xv[u] = X[(long long)m * g.ldx + k0 + c];
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int w = w0 + u * nt, m = w >> lc, c = w & (C - 1);
+      if (m > g.M || c >= Cb) continue;
+      store_extension(a, L, xcos, m, xv[u], lc, c);
+      if (m == 0) c0s[c] = xv[u];
+    }
   }
   __syncthreads();
   const cx<T>* tw_e = twiddles<T>(ext1);
@@ -360,9 +373,18 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
   cx<T>* b = a + ((long long)P << lc);
   const bool ycos = fam_ycos(f);
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int w = tid; w < P << lc; w += nt) {
-    const int c = div_p.quot(w), k = w - c * div_p.d;
-    a[(k << lc) + c] = c < Cb ? Y[(long long)(m0 + c) * g.ldx + k] : mk<T>(0, 0);
+  for (int w0 = tid; w0 < P << lc; w0 += kLoadBatch * nt) {
+    cx<T> yv[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {   // indices clamped in range: no conditional loads
+      const int w = min(w0 + u * nt, (P << lc) - 1), c = div_p.quot(w), k = w - c * div_p.d;
+      yv[u] = Y[(long long)(m0 + min(c, Cb - 1)) * g.ldx + k];
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int w = w0 + u * nt, c = div_p.quot(w), k = w - c * div_p.d;
+      if (w < P << lc) a[(k << lc) + c] = c < Cb ? yv[u] : mk<T>(0, 0);
+    }
   }
   __syncthreads();
   // in place: a holds the box transform (P), b the extension transform (2L)
@@ -1316,22 +1338,57 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int
     const zd* x = xap + r * xs;
     for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk(0.0, 0.0);
     __syncthreads();
-    for (int w = tid; w < rowlen * Cb; w += nt) {
-      const int c = div_row.quot(w), n = w - c * div_row.d;
-      const int m = m0 + c;
-      const long long mn = (long long)m * rowlen + n;
+    // two elements per thread per trip, every load of a trip issued before its stores
+    // (indices clamped in range: no conditional loads)
+    const long long jNM = (long long)j * NM;
+    for (int w0 = tid; w0 < rowlen * Cb; w0 += 2 * nt) {
+      long long mn[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int w = min(w0 + u * nt, rowlen * Cb - 1);
+        const int c = div_row.quot(w), n = w - c * div_row.d;
+        mn[u] = (long long)(m0 + c) * rowlen + n;
+      }
       if (q == 0) {
-        const zd p = pi_d[(long long)j * NM + mn];
-        zd v1 = p * x[mn], v2 = p * x[NM + mn];
-        if (theta_d) {
-          const zd t = theta_d[(long long)j * NM + mn] * x[2 * NM + mn];
-          v1 = v1 + (M_PI * m / g.a) * t;
-          v2 = v2 + (M_PI * n / g.b) * t;
+        zd pv[2], xa[2], xb[2], tv[2], x3[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          pv[u] = pi_d[jNM + mn[u]];
+          xa[u] = x[mn[u]];
+          xb[u] = x[NM + mn[u]];
+          if (theta_d) {
+            tv[u] = theta_d[jNM + mn[u]];
+            x3[u] = x[2 * NM + mn[u]];
+          }
         }
-        store_pair_extension(a, L, n, v2, v1, lc, c);
-        if (n == 0) c0s[c] = v2;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int w = w0 + u * nt;
+          if (w >= rowlen * Cb) continue;
+          const int c = div_row.quot(w), n = w - c * div_row.d;
+          zd v1 = pv[u] * xa[u], v2 = pv[u] * xb[u];
+          if (theta_d) {
+            const zd t = tv[u] * x3[u];
+            v1 = v1 + (M_PI * (m0 + c) / g.a) * t;
+            v2 = v2 + (M_PI * n / g.b) * t;
+          }
+          store_pair_extension(a, L, n, v2, v1, lc, c);
+          if (n == 0) c0s[c] = v2;
+        }
       } else {
-        store_extension(a, L, false, n, pi_n[(long long)j * NM + mn] * x[2 * NM + mn], lc, c);
+        zd pv[2], x3[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          pv[u] = pi_n[jNM + mn[u]];
+          x3[u] = x[2 * NM + mn[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int w = w0 + u * nt;
+          if (w >= rowlen * Cb) continue;
+          const int c = div_row.quot(w), n = w - c * div_row.d;
+          store_extension(a, L, false, n, pv[u] * x3[u], lc, c);
+        }
       }
     }
     __syncthreads();
@@ -1380,16 +1437,25 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < (2 * L) << lc; i += nt) a[i] = mk(0.0, 0.0);
   __syncthreads();
-  for (int w = tid; w < (g.M + 1) << lc; w += nt) {
-    const int m = w >> lc, c = w & (C - 1);
-    if (c >= Cb) continue;
-    const long long o = (long long)m * (g.ny + 1) + i0 + c;
-    if (q == 0) {
-      const zd x1 = src[o];
-      store_pair_extension(a, L, m, x1, src[slab + o], lc, c);
-      if (m == 0) c0s[c] = x1;
-    } else {
-      store_extension(a, L, false, m, src[o], lc, c);
+  for (int w0 = tid; w0 < (g.M + 1) << lc; w0 += kLoadBatch * nt) {
+    zd x1[kLoadBatch], x2[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {   // indices clamped in range: no conditional loads
+      const int w = w0 + u * nt, m = min(w >> lc, g.M), c = min(w & (C - 1), Cb - 1);
+      const long long o = (long long)m * (g.ny + 1) + i0 + c;
+      x1[u] = src[o];
+      x2[u] = src[(q == 0 ? slab : 0) + o];
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int w = w0 + u * nt, m = w >> lc, c = w & (C - 1);
+      if (m > g.M || c >= Cb) continue;
+      if (q == 0) {
+        store_pair_extension(a, L, m, x1[u], x2[u], lc, c);
+        if (m == 0) c0s[c] = x1[u];
+      } else {
+        store_extension(a, L, false, m, x1[u], lc, c);
+      }
     }
   }
   __syncthreads();

@@ -616,9 +616,25 @@ double mixed_inner_reduction() {
   return v;
 }
 
+// Classical Gram-Schmidt passes of the mixed-precision inner cycles: one by default.  Their
+// basis is stored in single precision (orthogonal to about 1e-7 whatever the passes), a
+// cycle only has to reduce its residual by the inner factor, and every restart recomputes
+// the residual with the double-precision operator, so the final accuracy does not rest on
+// the inner basis; a second pass left the iteration counts unchanged (23 at 256^2 and on
+// the layered batch, 27 at 512^2) for a third more basis traffic.  CAVITY_CGS_PASSES=2
+// restores it.  Double-precision solves always take two passes.
+int mixed_cgs_passes() {
+  static const int v = [] {
+    const char* e = std::getenv("CAVITY_CGS_PASSES");
+    return e && std::atoi(e) == 2 ? 2 : 1;
+  }();
+  return v;
+}
+
 // One Arnoldi step j for the lockstep group (kernels only, on stream st): w = A z_j,
-// classical Gram-Schmidt twice (the second pass's coefficients added into H), the Givens
-// step of column j, v_{j+1} = w / |w| and z = P^{-1} v_{j+1}.
+// classical Gram-Schmidt twice (the second pass's coefficients added into H; once in the
+// mixed-precision inner cycles, see mixed_cgs_passes), the Givens step of column j,
+// v_{j+1} = w / |w| and z = P^{-1} v_{j+1}.
 template <typename VT>
 int arnoldi_step(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipStream_t st) {
   const long long n = p->nvec();
@@ -635,6 +651,13 @@ int arnoldi_step(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipStream_t st) {
   const long long hstr = (long long)R * (R + 1);
   HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
                           nullptr, 0, kv.active, st));
+  if (mixed && mixed_cgs_passes() == 1) {   // one pass: update with hcol, then the norm
+    HIPCHK(cav::launch_update_norm(V, ldj, nv, hcol, hstr, p->w, n, nb, p->dnpart, nblk_u,
+                                   kv.active, st));
+    HIPCHK(cav::launch_next_vector(p->g, kv, j, p->dnpart, nblk_u, p->w, vn, n, p->cols, p->zb,
+                                   nb, st));
+    return CAVITY_OK;
+  }
   if (nv <= kFusedGsMax) {   // one pass: update with hcol, dot products of the updated w
     HIPCHK(cav::launch_update_dots(V, ldj, nv, R + 1, hcol, hstr, p->w, n, nb, p->dpart,
                                    p->nblk_red, p->h2, R + 1, hcol, hstr, kv.active, st));
@@ -690,7 +713,8 @@ int step_graph(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipGraphExec_t* out
   return CAVITY_OK;
 }
 
-// Right-preconditioned restarted GMRES with classical Gram-Schmidt applied twice, for nb
+// Right-preconditioned restarted GMRES with classical Gram-Schmidt applied twice (once in
+// the mixed-precision inner cycles), for nb
 // right-hand sides b (p->bvec) iterating in lockstep; solutions in x (nb x n).  The
 // Arnoldi step, the Givens rotations and the convergence test run on the device; the
 // host looks at the convergence flags every few iterations and once per restart cycle.

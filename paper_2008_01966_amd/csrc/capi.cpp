@@ -645,12 +645,26 @@ int arnoldi_step(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipStream_t st) {
   const bool mixed = p->opts.precision == CAVITY_MIXED;
   cav::cx<VT>* vn = V + (long long)(j + 1) * ldj;
   int s;
-  if ((s = run_operator(p, 0, nb, p->zb, p->w, kv.active, mixed, st))) return s;
   const int nv = j + 1;
   zd* hcol = kv.H + (long long)j * (R + 1);
   const long long hstr = (long long)R * (R + 1);
-  HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
-                          nullptr, 0, kv.active, st));
+  if (!p->use_spec() && nv <= kFusedGsMax) {
+    // w = A z_j with the first dot products V^H w computed from the epilogue's registers
+    if constexpr (sizeof(VT) == sizeof(float))
+      HIPCHK(cav::launch_operator_dots_f32(p->g, p->trig, p->khat_f, p->cols, nb, p->zb, n,
+                                           reinterpret_cast<cav::zf*>(p->X),
+                                           reinterpret_cast<cav::zf*>(p->Y), p->S, p->w, n, V, ldj,
+                                           nv, R + 1, p->dpart, p->nblk_red, hcol, hstr,
+                                           kv.active, st));
+    else
+      HIPCHK(cav::launch_operator_dots(p->g, p->trig, p->khat, p->cols, nb, p->zb, n, p->X, p->Y,
+                                       p->S, p->w, n, V, ldj, nv, R + 1, p->dpart, p->nblk_red,
+                                       hcol, hstr, kv.active, st));
+  } else {
+    if ((s = run_operator(p, 0, nb, p->zb, p->w, kv.active, mixed, st))) return s;
+    HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
+                            nullptr, 0, kv.active, st));
+  }
   if (mixed && mixed_cgs_passes() == 1) {   // one pass: update with hcol, then the norm
     HIPCHK(cav::launch_update_norm(V, ldj, nv, hcol, hstr, p->w, n, nb, p->dnpart, nblk_u,
                                    kv.active, st));

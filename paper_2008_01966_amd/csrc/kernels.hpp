@@ -163,6 +163,20 @@ hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, co
                                int precond, int nb, const zd* v, long long vs, zf* Xf, zf* Yf,
                                zd* S, zd* y,
                                long long ys, const int* active, hipStream_t st);
+// The operator on v (no preconditioner) into y, its epilogue fused with the first
+// Gram-Schmidt dot products against nv <= 16 basis vectors V (basis vector t of right-hand
+// side r at V + t ldj + r 3 NM): out[r * ostride + t] = sum conj(V_t,r) y_r, from nblk
+// per-block partial sums in `partial` (nb * nvmax * nblk entries).
+hipError_t launch_operator_dots(const Geo& g, const Trig& t, const zd* khat, const Cols& c,
+                                int nb, const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y,
+                                long long ys, const zd* V, long long ldj, int nv, int nvmax,
+                                zd* partial, int nblk, zd* out, long long ostride,
+                                const int* active, hipStream_t st);
+hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
+                                    int nb, const zd* v, long long vs, zf* Xf, zf* Yf, zd* S,
+                                    zd* y, long long ys, const zf* V, long long ldj, int nv,
+                                    int nvmax, zd* partial, int nblk, zd* out, long long ostride,
+                                    const int* active, hipStream_t st);
 // out[i] = (float) in[i]
 hipError_t launch_to_f32(const zd* in, zf* out, long long n, hipStream_t st);
 // One single-layer family on a coefficient grid (inspection path).

@@ -18,6 +18,12 @@ namespace cav {
 // issued before its LDS stores, so their latencies overlap.
 constexpr int kLoadBatch = 4;
 
+// Sum over the 64 lanes of a wave.
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ inline zd exp_int(double w, double len) {
   const double th = 0.5 * w * len;
   double s, c;
@@ -414,17 +420,11 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
 //  r1 = (rho_d - 1) z1 + mu (T + h) z3 + (h/q) (2k^2 S^cs z1 - 2 nu S^cc sigma)   on N1
 //  r2 = (rho_d - 1) z2 + nu (T + h) z3 + (h/c) (2k^2 S^sc z2 + 2 mu S^cc sigma)   on N2
 //  r3 = (rho_n - 1) z3 + mu h z1 + nu h z2                                        on N3
-__global__ void k_operator_epilogue(Geo g, Cols cl, int precond, const zd* __restrict__ vall,
-                                    long long vs, const zd* __restrict__ Sall,
-                                    zd* __restrict__ yall, long long ys,
-                                    const int* __restrict__ active) {
-  const int rhs = blockIdx.y;
-  if (active && !active[rhs]) return;
-  const int mn = blockIdx.x * blockDim.x + threadIdx.x;
-  if (mn >= g.NM) return;
-  const zd* v = vall + rhs * vs;
-  const zd* S = Sall + 3LL * rhs * g.NM;
-  zd* y = yall + rhs * ys;
+// Operator result of mode mn of right-hand side rhs (the three components r1, r2, r3 of y)
+// from its input v (P^{-1} applied first when precond) and the TBC results S: rows 1-3 of
+// the reduced system with the per-mode column data.
+__device__ inline void epilogue_mode(const Geo& g, const Cols& cl, int precond, const zd* v,
+                                     const zd* S, int rhs, int mn, zd* out) {
   const long long co = rhs * cl.cs;
   const zd* __restrict__ rho_d = cl.rho_d + co;
   const zd* __restrict__ T = cl.T + co;
@@ -451,9 +451,79 @@ __global__ void k_operator_epilogue(Geo g, Cols cl, int precond, const zd* __res
   if (n >= 1) r1 = rd * z[0] + mu * (th * z[2]) + hq * ((2.0 * k2) * scs - (2.0 * nu) * scc);
   if (m >= 1) r2 = rd * z[1] + nu * (th * z[2]) + hc * ((2.0 * k2) * ssc + (2.0 * mu) * scc);
   if (m >= 1 && n >= 1) r3 = rn * z[2] + (mu * h) * z[0] + (nu * h) * z[1];
-  y[mn] = r1;
-  y[g.NM + mn] = r2;
-  y[2LL * g.NM + mn] = r3;
+  out[0] = r1;
+  out[1] = r2;
+  out[2] = r3;
+}
+
+__global__ void k_operator_epilogue(Geo g, Cols cl, int precond, const zd* __restrict__ vall,
+                                    long long vs, const zd* __restrict__ Sall,
+                                    zd* __restrict__ yall, long long ys,
+                                    const int* __restrict__ active) {
+  const int rhs = blockIdx.y;
+  if (active && !active[rhs]) return;
+  const int mn = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mn >= g.NM) return;
+  zd r[3];
+  epilogue_mode(g, cl, precond, vall + rhs * vs, Sall + 3LL * rhs * g.NM, rhs, mn, r);
+  zd* y = yall + rhs * ys;
+  y[mn] = r[0];
+  y[g.NM + mn] = r[1];
+  y[2LL * g.NM + mn] = r[2];
+}
+
+// The epilogue fused with the first Gram-Schmidt pass of an Arnoldi step: y = A v as
+// above, and from the same registers the per-block partial sums of conj(V_t) y over the
+// nv <= G basis vectors (V_t of right-hand side rhs at V + t ldj + rhs 3 NM) in k_dots'
+// layout, partial[(rhs nvmax + t) gridDim.x + block].  Blocks stride over the modes; each
+// thread sums its modes in order, the three components of a mode in order.
+template <typename VT, int G>
+__global__ __launch_bounds__(256) void k_epilogue_dots(Geo g, Cols cl, int precond,
+                                                       const zd* __restrict__ vall, long long vs,
+                                                       const zd* __restrict__ Sall,
+                                                       zd* __restrict__ yall, long long ys,
+                                                       const cx<VT>* __restrict__ V,
+                                                       long long ldj, int nv, int nvmax,
+                                                       zd* __restrict__ partial,
+                                                       const int* __restrict__ active) {
+  __shared__ zd red[G][4];
+  const int rhs = blockIdx.y;
+  if (active && !active[rhs]) return;
+  const zd* v = vall + rhs * vs;
+  const zd* S = Sall + 3LL * rhs * g.NM;
+  zd* y = yall + rhs * ys;
+  const cx<VT>* Vr = V + rhs * 3LL * g.NM;
+  zd acc[G];
+  for (int t = 0; t < G; ++t) acc[t] = mk(0.0, 0.0);
+  for (int mn = blockIdx.x * blockDim.x + threadIdx.x; mn < g.NM;
+       mn += gridDim.x * blockDim.x) {
+    zd r[3];
+    epilogue_mode(g, cl, precond, v, S, rhs, mn, r);
+    y[mn] = r[0];
+    y[g.NM + mn] = r[1];
+    y[2LL * g.NM + mn] = r[2];
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+      if (t < nv) {
+        const cx<VT>* Vt = Vr + t * ldj;
+        const cx<VT> a0 = Vt[mn], a1 = Vt[g.NM + mn], a2 = Vt[2LL * g.NM + mn];
+        acc[t] = acc[t] + conj(widen(a0)) * r[0];
+        acc[t] = acc[t] + conj(widen(a1)) * r[1];
+        acc[t] = acc[t] + conj(widen(a2)) * r[2];
+      }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < G; ++t) {
+    const zd sum = mk(wave_sum(acc[t].re), wave_sum(acc[t].im));
+    if (lane == 0) red[t][wv] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    const int t = threadIdx.x;
+    partial[((long long)rhs * nvmax + t) * gridDim.x + blockIdx.x] =
+        red[t][0] + red[t][1] + red[t][2] + red[t][3];
+  }
 }
 
 // log2 of the transforms per block for an FFT kernel whose two LDS buffers hold len
@@ -600,6 +670,57 @@ hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, co
   return operator_impl<float>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S, y, ys, active, st);
 }
 
+__global__ void k_reduce_cols(const zd* __restrict__ partial, int nblk, int nvmax,
+                              zd* __restrict__ out, long long ostride, zd* __restrict__ acc,
+                              long long astride, const int* __restrict__ active);
+
+// The operator (no preconditioner on input) followed by the epilogue fused with the first
+// Gram-Schmidt dot products against the nv <= 16 basis vectors V (k_epilogue_dots), the
+// nblk per-block partial sums reduced into out[r * ostride + t].
+template <typename T>
+static hipError_t operator_dots_impl(const Geo& g, const Trig& t, const cx<T>* khat,
+                                     const Cols& c, int nb, const zd* v, long long vs, cx<T>* X,
+                                     cx<T>* Y, zd* S, zd* y, long long ys, const cx<T>* V,
+                                     long long ldj, int nv, int nvmax, zd* partial, int nblk,
+                                     zd* out, long long ostride, const int* active,
+                                     hipStream_t st) {
+  if (nv < 1 || nv > 16) return hipErrorInvalidValue;
+  hipError_t e = tbc_passes<T>(g, t, khat, c.pinv, c.cs, 0, -1, nb, v, vs, X, Y, S, active, st);
+  if (e != hipSuccess) return e;
+  probe_begin(K_EPILOGUE, st);
+  if (nv <= 8)
+    hipLaunchKernelGGL((k_epilogue_dots<T, 8>), dim3(nblk, nb), dim3(256), 0, st, g, c, 0, v, vs,
+                       S, y, ys, V, ldj, nv, nvmax, partial, active);
+  else
+    hipLaunchKernelGGL((k_epilogue_dots<T, 16>), dim3(nblk, nb), dim3(256), 0, st, g, c, 0, v,
+                       vs, S, y, ys, V, ldj, nv, nvmax, partial, active);
+  probe_end(K_EPILOGUE, st, sizeof(zd) * (double)g.NM * (nb * 9.0 + 3.0) +
+                                sizeof(cx<T>) * 3.0 * g.NM * nb * nv);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_cols, dim3(nv, nb), dim3(256), 0, st, partial, nblk, nvmax, out,
+                     ostride, nullptr, 0, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_operator_dots(const Geo& g, const Trig& t, const zd* khat, const Cols& c,
+                                int nb, const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y,
+                                long long ys, const zd* V, long long ldj, int nv, int nvmax,
+                                zd* partial, int nblk, zd* out, long long ostride,
+                                const int* active, hipStream_t st) {
+  return operator_dots_impl<double>(g, t, khat, c, nb, v, vs, X, Y, S, y, ys, V, ldj, nv, nvmax,
+                                    partial, nblk, out, ostride, active, st);
+}
+
+hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
+                                    int nb, const zd* v, long long vs, zf* Xf, zf* Yf, zd* S,
+                                    zd* y, long long ys, const zf* V, long long ldj, int nv,
+                                    int nvmax, zd* partial, int nblk, zd* out, long long ostride,
+                                    const int* active, hipStream_t st) {
+  return operator_dots_impl<float>(g, t, khat_f, c, nb, v, vs, Xf, Yf, S, y, ys, V, ldj, nv, nvmax,
+                                   partial, nblk, out, ostride, active, st);
+}
+
 __global__ void k_to_f32(const zd* __restrict__ in, zf* __restrict__ out, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -628,10 +749,6 @@ constexpr int kDotUnroll = 4;
 constexpr int kDotGroupWide = 16;   // basis vectors per group beyond kDotGroup
 constexpr int kDotUnrollWide = 2;
 
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 
 // partial[(r * nvmax + vi) * nblk + blk] = sum over the block's slice of conj(V_vi,r) w_r,

@@ -17,6 +17,8 @@
 // with F the forward DFT of length 2L of the even (or odd) extension.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -400,6 +402,94 @@ __device__ cx<T>* fft_lds_put(cx<T>* a, cx<T>* b, const FftPlan& p, const cx<T>*
     ns *= rdx;
   }
   return in;
+}
+
+// ---- transforms with a plan fixed at compile time ----------------------------------
+// The same Stockham stages with the length, the radices, the span and the batch 2^LC of a
+// block of NT threads known to the compiler: strides become immediate LDS offsets and the
+// work-item index arithmetic constant divisions, which takes the integer work of a stage
+// off the vector ALU.  Used for the transform shapes the hot kernels run at most (the
+// generic forms above cover every plan).
+template <int... Rs>
+struct CtRadices {};
+
+struct NoPut {};
+
+// One stage (see fft_stage); with LAST and a Put handler its outputs go to put(dst, pos,
+// col, v) (see fft_stage_put).
+template <int R, int N, int NS, int LC, int NT, typename T, bool INV, bool LAST, class Put>
+__device__ inline void fft_stage_ct(const cx<T>* __restrict__ in, cx<T>* out,
+                                    const cx<T>* __restrict__ tw, int tid, const Put& put) {
+  constexpr int NB = N / R;
+  constexpr int TOTAL = NB << LC;
+  constexpr int ISTR = NB << LC, OSTR = NS << LC;
+  constexpr int CM = (1 << LC) - 1;
+#pragma unroll
+  for (int w0 = 0; w0 < TOTAL; w0 += NT) {
+    const int w = w0 + tid;
+    if (TOTAL % NT == 0 || w < TOTAL) {
+      const int j = w >> LC;
+      const int col = w & CM;
+      const int q = j / NS, k = j - q * NS;
+      const cx<T>* ip = in + w;
+      cx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = ip[r * ISTR];
+      if constexpr (NS > 1) {
+        const cx<T>* tp = tw + k * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const cx<T> w2 = tp[r - 1];
+          v[r] = v[r] * (INV ? conj(w2) : w2);
+        }
+      }
+      Dft<R, T, INV>::run(v);
+      if constexpr (LAST) {
+        const int p0 = q * R * NS + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) put(out, p0 + r * NS, col, v[r]);
+      } else {
+        cx<T>* op = out + (((q * R * NS + k) << LC) + col);
+#pragma unroll
+        for (int r = 0; r < R; ++r) op[r * OSTR] = v[r];
+      }
+    }
+  }
+}
+
+template <int N, int NS, int LC, int NT, typename T, bool INV, class Put, int S, int R,
+          int... Rest>
+__device__ inline cx<T>* fft_ct_stages(cx<T>* in, cx<T>* out, const FftPlan& p,
+                                       const cx<T>* __restrict__ tw, int tid, const Put& put) {
+  constexpr bool last = sizeof...(Rest) == 0;
+  constexpr bool use_put = last && !std::is_same<Put, NoPut>::value;
+  fft_stage_ct<R, N, NS, LC, NT, T, INV, use_put, Put>(in, out, tw + p.twoff[S], tid, put);
+  __syncthreads();
+  if constexpr (last)
+    return out;
+  else
+    return fft_ct_stages<N, NS * R, LC, NT, T, INV, Put, S + 1, Rest...>(out, in, p, tw, tid,
+                                                                          put);
+}
+
+// fft_lds / fft_lds_put for a plan with the radices Rs (p must be that plan: its stage
+// twiddle table is used); put = NoPut{} for a plain transform.  Returns the buffer the
+// last stage wrote (or would have written), after a barrier.
+template <typename T, bool INV, int LC, int NT, class Put, int... Rs>
+__device__ inline cx<T>* fft_ct(cx<T>* a, cx<T>* b, CtRadices<Rs...>, const FftPlan& p,
+                                const cx<T>* __restrict__ tw, int tid, const Put& put) {
+  constexpr int N = (Rs * ...);
+  return fft_ct_stages<N, 1, LC, NT, T, INV, Put, 0, Rs...>(a, b, p, tw, tid, put);
+}
+
+// Whether plan p has exactly the radices Rs.
+template <int... Rs>
+__host__ __device__ inline bool plan_is(const FftPlan& p) {
+  constexpr int rs[] = {Rs...};
+  if (p.nst != (int)sizeof...(Rs)) return false;
+  for (int s = 0; s < p.nst; ++s)
+    if (p.radix[s] != rs[s]) return false;
+  return true;
 }
 
 // In-place form of a Stockham stage for one LDS buffer: work item w < (n/R) 2^lc (at most

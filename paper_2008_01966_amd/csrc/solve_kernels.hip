@@ -248,7 +248,9 @@ struct ColumnStore {
   }
 };
 
-template <typename T, int MR>
+// CTLC > 0: the transform shapes fixed at compile time (extension 8 x 8 x 8 = 512, box
+// 5 x 5 x 5 x 5 = 625, 2^CTLC columns per block; fft_ct) for the plans that have them.
+template <typename T, int MR, int CTLC = 0>
 __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
                                                   const cx<T>* __restrict__ khat, int fam_fixed,
                                                   int lc, const cx<T>* __restrict__ Xall,
@@ -307,7 +309,11 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   const T hq = (T)g.hq1;
   cx<T>* o;
   cx<T>* r;
-  if constexpr (MR <= kSmallRadix) {
+  if constexpr (CTLC > 0) {
+    o = fft_ct<T, false, CTLC, 256>(a, b, CtRadices<8, 8, 8>{}, ext1.p, tw_e, tid,
+                                    WeightPad<T>{c0s, L, lc, xcos, hq});
+    r = (o == a) ? b : a;
+  } else if constexpr (MR <= kSmallRadix) {
     // synthesis along x; its last stage applies the trapezoid weights and pads to P
     o = fft_lds_put<T, false, MR>(a, b, ext1.p, tw_e, tid, nt, lc,
                                   WeightPad<T>{c0s, L, lc, xcos, hq});
@@ -330,11 +336,20 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
     __syncthreads();
   }
   // the product with K-hat rides on the transform's last stage
-  cx<T>* r2 = fft_lds_put<T, false, MR>(o, r, box1.p, tw_b, tid, nt, lc,
-                                        SpectrumProduct<T>{khat + k0, g.P2, Cb, lc});
+  cx<T>* r2;
+  if constexpr (CTLC > 0)
+    r2 = fft_ct<T, false, CTLC, 256>(o, r, CtRadices<5, 5, 5, 5>{}, box1.p, tw_b, tid,
+                                     SpectrumProduct<T>{khat + k0, g.P2, Cb, lc});
+  else
+    r2 = fft_lds_put<T, false, MR>(o, r, box1.p, tw_b, tid, nt, lc,
+                                   SpectrumProduct<T>{khat + k0, g.P2, Cb, lc});
   cx<T>* o3;
   cx<T>* r3;
-  if constexpr (MR <= kSmallRadix) {
+  if constexpr (CTLC > 0) {
+    o3 = fft_ct<T, true, CTLC, 256>(r2, (r2 == a) ? b : a, CtRadices<5, 5, 5, 5>{}, box1.p, tw_b,
+                                    tid, ExtendCrop<T>{L, lc, xcos});
+    r3 = (o3 == a) ? b : a;
+  } else if constexpr (MR <= kSmallRadix) {
     // inverse transform; its last stage crops to the grid and writes the extension
     o3 = fft_lds_put<T, true, MR>(r2, (r2 == a) ? b : a, box1.p, tw_b, tid, nt, lc,
                                   ExtendCrop<T>{L, lc, xcos});
@@ -349,8 +364,12 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
     __syncthreads();
   }
   // the last stage writes the projected entries m = 0..M straight to Y
-  fft_lds_put<T, false, MR>(o3, r3, ext1.p, tw_e, tid, nt, lc,
-                            ColumnStore<T>{Y + k0, g.ldx, g.M + 1, Cb, xcos, hq});
+  if constexpr (CTLC > 0)
+    fft_ct<T, false, CTLC, 256>(o3, r3, CtRadices<8, 8, 8>{}, ext1.p, tw_e, tid,
+                                ColumnStore<T>{Y + k0, g.ldx, g.M + 1, Cb, xcos, hq});
+  else
+    fft_lds_put<T, false, MR>(o3, r3, ext1.p, tw_e, tid, nt, lc,
+                              ColumnStore<T>{Y + k0, g.ldx, g.M + 1, Cb, xcos, hq});
 }
 
 // Pass 3: rows m0 .. m0+Cb-1 backward; writes S[slot][mn] in double.
@@ -599,7 +618,14 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
       tbc_shape(t.ext1.p, t.box1.p, g.nq1, g.P1, (int)tb, g.P2, g.lds_budget, false);
   probe_begin(id_cols, st);
   const dim3 gc((g.P2 + (1 << sc.lc) - 1) >> sc.lc, nf, nb);
-  if (t.maxr <= 8)
+  const bool ct = plan_is<8, 8, 8>(t.ext1.p) && plan_is<5, 5, 5, 5>(t.box1.p);
+  if (ct && sc.lc == 2)
+    hipLaunchKernelGGL((k_tbc_cols<T, 8, 2>), gc, dim3(256), sc.smem, st, g, t.ext1, t.box1, khat,
+                       fam_fixed, sc.lc, X, Y, active);
+  else if (ct && sc.lc == 1)
+    hipLaunchKernelGGL((k_tbc_cols<T, 8, 1>), gc, dim3(256), sc.smem, st, g, t.ext1, t.box1, khat,
+                       fam_fixed, sc.lc, X, Y, active);
+  else if (t.maxr <= 8)
     hipLaunchKernelGGL((k_tbc_cols<T, 8>), gc, dim3(256), sc.smem, st, g, t.ext1, t.box1, khat,
                        fam_fixed, sc.lc, X, Y, active);
   else

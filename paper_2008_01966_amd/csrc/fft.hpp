@@ -482,6 +482,68 @@ __device__ inline cx<T>* fft_ct(cx<T>* a, cx<T>* b, CtRadices<Rs...>, const FftP
   return fft_ct_stages<N, 1, LC, NT, T, INV, Put, 0, Rs...>(a, b, p, tw, tid, put);
 }
 
+// In-place stage with the shape fixed at compile time (see fft_stage_ip): every work item
+// (at most one per thread) loads, transforms, waits for the block, then overwrites.
+template <int R, int N, int NS, int LC, int NT, typename T, bool INV>
+__device__ inline void fft_stage_ct_ip(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+  constexpr int NB = N / R;
+  constexpr int TOTAL = NB << LC;
+  static_assert(TOTAL <= NT, "in-place stages need at most one work item per thread");
+  constexpr int ISTR = NB << LC, OSTR = NS << LC;
+  constexpr int CM = (1 << LC) - 1;
+  const bool act = TOTAL == NT || tid < TOTAL;
+  cx<T> v[R];
+  cx<T>* op = buf;
+  if (act) {
+    const int j = tid >> LC;
+    const int col = tid & CM;
+    const int q = j / NS, k = j - q * NS;
+    const cx<T>* ip = buf + tid;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = ip[r * ISTR];
+    if constexpr (NS > 1) {
+      const cx<T>* tp = tw + k * (R - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const cx<T> w2 = tp[r - 1];
+        v[r] = v[r] * (INV ? conj(w2) : w2);
+      }
+    }
+    Dft<R, T, INV>::run(v);
+    op = buf + (((q * R * NS + k) << LC) + col);
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) op[r * OSTR] = v[r];
+  }
+}
+
+template <int N, int NS, int LC, int NT, typename T, bool INV, int S, int R, int... Rest>
+__device__ inline void fft_ct_ip_stages(cx<T>* buf, const FftPlan& p,
+                                        const cx<T>* __restrict__ tw, int tid) {
+  fft_stage_ct_ip<R, N, NS, LC, NT, T, INV>(buf, tw + p.twoff[S], tid);
+  __syncthreads();
+  if constexpr (sizeof...(Rest) > 0)
+    fft_ct_ip_stages<N, NS * R, LC, NT, T, INV, S + 1, Rest...>(buf, p, tw, tid);
+}
+
+// fft_lds_ip for a plan with the radices Rs; the result is in buf, after a barrier.
+template <typename T, bool INV, int LC, int NT, int... Rs>
+__device__ inline void fft_ct_ip(cx<T>* buf, CtRadices<Rs...>, const FftPlan& p,
+                                 const cx<T>* __restrict__ tw, int tid) {
+  constexpr int N = (Rs * ...);
+  fft_ct_ip_stages<N, 1, LC, NT, T, INV, 0, Rs...>(buf, p, tw, tid);
+}
+
+// Whether every stage of a length-(Rs product) transform with radices Rs, 2^LC of them
+// interleaved, has at most NT work items (the in-place form's condition).
+template <int LC, int NT, int... Rs>
+constexpr bool ct_ip_fits() {
+  constexpr int N = (Rs * ...);
+  return ((((N / Rs) << LC) <= NT) && ...);
+}
+
 // Whether plan p has exactly the radices Rs.
 template <int... Rs>
 __host__ __device__ inline bool plan_is(const FftPlan& p) {

@@ -18,6 +18,29 @@ namespace cav {
 // issued before its LDS stores, so their latencies overlap.
 constexpr int kLoadBatch = 4;
 
+// 2^lc interleaved transforms of plan p in LDS, in place in a (ip) or ping-pong between a
+// and b; returns the buffer holding the result.  CTLC > 0: the plan has the radices Rs and
+// lc == CTLC, both fixed at compile time (fft_ct, fft_ct_ip); ip then needs ct_ip_fits.
+template <typename T, bool INV, int MR, int CTLC, int... Rs>
+__device__ inline cx<T>* lds_fft(cx<T>* a, cx<T>* b, CtRadices<Rs...> rs, const FftPlan& p,
+                                 const cx<T>* __restrict__ tw, int tid, int nt, int lc, int ip) {
+  if constexpr (CTLC > 0) {
+    if constexpr (ct_ip_fits<CTLC, 256, Rs...>()) {
+      if (ip) {
+        fft_ct_ip<T, INV, CTLC, 256>(a, rs, p, tw, tid);
+        return a;
+      }
+    }
+    return fft_ct<T, INV, CTLC, 256>(a, b, rs, p, tw, tid, NoPut{});
+  } else {
+    if (ip) {
+      fft_lds_ip<T, INV, MR>(a, p, tw, tid, lc);
+      return a;
+    }
+    return fft_lds<T, INV, MR>(a, b, p, tw, tid, nt, lc);
+  }
+}
+
 // Sum over the 64 lanes of a wave.
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -106,11 +129,11 @@ __device__ inline bool fam_ycos(int f) { return f != 0; }
 // Pass 1: rows m0 .. m0+Cb-1 of one family.  fam_fixed >= 0: `v` is the coefficient grid
 // of that family (inspection path); otherwise `v` is a padded aperture vector, optionally
 // preconditioned first.
-template <typename T, int MR>
+template <typename T, int MR, int CTLC = 0>
 __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
                                                       const zd* __restrict__ pinv_all,
                                                       long long pcs, int precond,
-                                                      int fam_fixed, int lc, int ip,
+                                                      int fam_fixed, int lc_arg, int ip,
                                                       const zd* __restrict__ vall, long long vs,
                                                       cx<T>* __restrict__ Xall,
                                                       const int* __restrict__ active) {
@@ -125,6 +148,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
   const zd* pinv = pinv_all + rhs * pcs;
   const int nf = fam_fixed >= 0 ? 1 : 3;
   cx<T>* X = Xall + (long long)rhs * nf * (g.M + 1) * g.ldx;
+  const int lc = CTLC > 0 ? CTLC : lc_arg;
   const int C = 1 << lc;
   const int m0 = bid.x << lc;
   const int Cb = min(C, g.M + 1 - m0);
@@ -166,9 +190,8 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
     if (n == 0) c0s[c] = tv;
   }
   __syncthreads();
-  cx<T>* r = a;
-  if (ip) fft_lds_ip<T, false, MR>(a, ext2.p, twiddles<T>(ext2), tid, lc);
-  else r = fft_lds<T, false, MR>(a, b, ext2.p, twiddles<T>(ext2), tid, nt, lc);
+  cx<T>* r = lds_fft<T, false, MR, CTLC>(a, b, CtRadices<8, 8, 8>{}, ext2.p, twiddles<T>(ext2),
+                                         tid, nt, lc, ip);
   cx<T>* o = (r == a) ? b : a;
   const T hq = (T)g.hq2;
   for (int w = tid; w < P << lc; w += nt) {
@@ -182,9 +205,8 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
     o[w] = val;
   }
   __syncthreads();
-  cx<T>* r2 = o;
-  if (ip) fft_lds_ip<T, false, MR>(o, box2.p, twiddles<T>(box2), tid, lc);
-  else r2 = fft_lds<T, false, MR>(o, r, box2.p, twiddles<T>(box2), tid, nt, lc);
+  cx<T>* r2 = lds_fft<T, false, MR, CTLC>(o, r, CtRadices<5, 5, 5, 5>{}, box2.p,
+                                          twiddles<T>(box2), tid, nt, lc, ip);
   cx<T>* dst = X + ((long long)slot * (g.M + 1) + m0) * g.ldx;
   for (int w = tid; w < P * Cb; w += nt) {
     const int c = div_p.quot(w), k = w - c * div_p.d;
@@ -253,11 +275,12 @@ struct ColumnStore {
 template <typename T, int MR, int CTLC = 0>
 __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
                                                   const cx<T>* __restrict__ khat, int fam_fixed,
-                                                  int lc, const cx<T>* __restrict__ Xall,
+                                                  int lc_arg, const cx<T>* __restrict__ Xall,
                                                   cx<T>* __restrict__ Yall,
                                                   const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ cx<T> c0s[64];
+  const int lc = CTLC > 0 ? CTLC : lc_arg;
   // the strips of one 128-byte line of X and Y run together (their blocks share the line),
   // and the nb x 3 blocks of a strip, which share its K-hat columns, stay close
   const BlockId bid = xcd_block_x_grouped(max(1, 128 / ((int)sizeof(cx<T>) << lc)));
@@ -373,9 +396,9 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
 }
 
 // Pass 3: rows m0 .. m0+Cb-1 backward; writes S[slot][mn] in double.
-template <typename T, int MR>
+template <typename T, int MR, int CTLC = 0>
 __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed,
-                                                      int lc, int ip,
+                                                      int lc_arg, int ip,
                                                       const cx<T>* __restrict__ Yall,
                                                       zd* __restrict__ Sall,
                                                       const int* __restrict__ active) {
@@ -389,6 +412,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
   const cx<T>* Y =
       Yall + (long long)rhs * nf * (g.M + 1) * g.ldx + (long long)slot * (g.M + 1) * g.ldx;
   zd* S = Sall + (long long)rhs * nf * g.NM + (long long)slot * g.NM;
+  const int lc = CTLC > 0 ? CTLC : lc_arg;
   const int C = 1 << lc;
   const int m0 = bid.x << lc;
   const int Cb = min(C, g.M + 1 - m0);
@@ -413,18 +437,16 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
   }
   __syncthreads();
   // in place: a holds the box transform (P), b the extension transform (2L)
-  cx<T>* r = a;
-  if (ip) fft_lds_ip<T, true, MR>(a, box2.p, twiddles<T>(box2), tid, lc);
-  else r = fft_lds<T, true, MR>(a, b, box2.p, twiddles<T>(box2), tid, nt, lc);
+  cx<T>* r = lds_fft<T, true, MR, CTLC>(a, b, CtRadices<5, 5, 5, 5>{}, box2.p, twiddles<T>(box2),
+                                        tid, nt, lc, ip);
   cx<T>* o = (r == a) ? b : a;
   for (int w = tid; w < (L + 1) << lc; w += nt) {
     const int i = w >> lc, c = w & (C - 1);
     store_extension(o, L, ycos, i, r[w], lc, c);
   }
   __syncthreads();
-  cx<T>* r2 = o;
-  if (ip) fft_lds_ip<T, false, MR>(o, ext2.p, twiddles<T>(ext2), tid, lc);
-  else r2 = fft_lds<T, false, MR>(o, r, ext2.p, twiddles<T>(ext2), tid, nt, lc);
+  cx<T>* r2 = lds_fft<T, false, MR, CTLC>(o, r, CtRadices<8, 8, 8>{}, ext2.p,
+                                          twiddles<T>(ext2), tid, nt, lc, ip);
   const int rowlen = g.N + 1;
   const DivBy div_row(rowlen);
   for (int w = tid; w < rowlen * Cb; w += nt) {
@@ -601,8 +623,20 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
   const TbcShape sr =
       tbc_shape(t.ext2.p, t.box2.p, g.nq2, g.P2, (int)tb, g.M + 1, g.lds_budget, g.rows_ip);
   const int gr = (g.M + 1 + (1 << sr.lc) - 1) >> sr.lc;
+  // transforms fixed at compile time for the extension 8 x 8 x 8 and box 5 x 5 x 5 x 5 plans
+  // (the in-place form, which tbc_shape allows only when every stage fits the block, exists
+  // for 2^1 transforms per block)
+  const bool ct_rows = plan_is<8, 8, 8>(t.ext2.p) && plan_is<5, 5, 5, 5>(t.box2.p);
   probe_begin(id_fwd, st);
-  if (t.maxr <= 8)
+  if (ct_rows && sr.lc == 2 && !sr.ip)
+    hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8, 2>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
+                       t.ext2, t.box2, pinv, pcs, precond, fam_fixed, sr.lc, sr.ip, v, vs, X,
+                       active);
+  else if (ct_rows && sr.lc == 1)
+    hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8, 1>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
+                       t.ext2, t.box2, pinv, pcs, precond, fam_fixed, sr.lc, sr.ip, v, vs, X,
+                       active);
+  else if (t.maxr <= 8)
     hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g, t.ext2,
                        t.box2, pinv, pcs, precond, fam_fixed, sr.lc, sr.ip, v, vs, X, active);
   else
@@ -635,7 +669,13 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   probe_begin(id_bwd, st);
-  if (t.maxr <= 8)
+  if (ct_rows && sr.lc == 2 && !sr.ip)
+    hipLaunchKernelGGL((k_tbc_rows_bwd<T, 8, 2>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
+                       t.ext2, t.box2, fam_fixed, sr.lc, sr.ip, Y, S, active);
+  else if (ct_rows && sr.lc == 1)
+    hipLaunchKernelGGL((k_tbc_rows_bwd<T, 8, 1>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
+                       t.ext2, t.box2, fam_fixed, sr.lc, sr.ip, Y, S, active);
+  else if (t.maxr <= 8)
     hipLaunchKernelGGL((k_tbc_rows_bwd<T, 8>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g, t.ext2,
                        t.box2, fam_fixed, sr.lc, sr.ip, Y, S, active);
   else
@@ -1535,9 +1575,7 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int
       }
     }
     __syncthreads();
-    zd* rr = a;
-    if (ip) fft_lds_ip<double, false, MR>(a, out2.p, out2.tw, tid, lc);
-    else rr = fft_lds<double, false, MR>(a, b, out2.p, out2.tw, tid, nt, lc);
+    zd* rr = lds_fft<double, false, MR, 0>(a, b, CtRadices<>{}, out2.p, out2.tw, tid, nt, lc, ip);
     zd* dst = tbuf + ((((long long)r * 3 + (q == 0 ? 0 : 2)) * jn + jj) * (g.M + 1) + m0) *
                          (g.ny + 1);
     for (int w = tid; w < (L + 1) * Cb; w += nt) {
@@ -1602,9 +1640,7 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
     }
   }
   __syncthreads();
-  zd* rr = a;
-  if (ip) fft_lds_ip<double, false, MR>(a, out1.p, out1.tw, tid, lc);
-  else rr = fft_lds<double, false, MR>(a, b, out1.p, out1.tw, tid, nt, lc);
+  zd* rr = lds_fft<double, false, MR, 0>(a, b, CtRadices<>{}, out1.p, out1.tw, tid, nt, lc, ip);
   const long long plane = (long long)(g.Nz + 1) * (g.ny + 1) * (g.nx + 1);   // one component
   zd* dst = eout + r * es + (q == 0 ? 0 : 2 * plane) +
             ((long long)j * (g.ny + 1) + i0) * (g.nx + 1);

@@ -631,10 +631,32 @@ int mixed_cgs_passes() {
   return v;
 }
 
+// Whether the preconditioned basis vector z = P^{-1} v (p->zb) is stored in single
+// precision: in the mixed-precision inner cycles of the FFT operator, whose convolutions
+// take their input in single precision anyway (the spectral operator's stay double).
+bool z_single(cavity_plan p) { return p->opts.precision == CAVITY_MIXED && !p->use_spec(); }
+
+// v_{j+1} = w / |w| into vn and z = P^{-1} v_{j+1} into p->zb (see launch_next_vector).
+template <typename VT>
+int next_vector(cavity_plan p, cav::Krylov& kv, int j, const double* npart, int nparts,
+                const zd* w, cav::cx<VT>* vn, int nb, hipStream_t st) {
+  const long long n = p->nvec();
+  if constexpr (sizeof(VT) == sizeof(float)) {
+    if (z_single(p)) {
+      HIPCHK(cav::launch_next_vector(p->g, kv, j, npart, nparts, w, vn, n, p->cols,
+                                     reinterpret_cast<cav::zf*>(p->zb), nb, st));
+      return CAVITY_OK;
+    }
+  }
+  HIPCHK(cav::launch_next_vector(p->g, kv, j, npart, nparts, w, vn, n, p->cols, p->zb, nb, st));
+  return CAVITY_OK;
+}
+
 // One Arnoldi step j for the lockstep group (kernels only, on stream st): w = A z_j,
 // classical Gram-Schmidt twice (the second pass's coefficients added into H; once in the
 // mixed-precision inner cycles, see mixed_cgs_passes), the Givens step of column j,
-// v_{j+1} = w / |w| and z = P^{-1} v_{j+1}.
+// v_{j+1} = w / |w| and z = P^{-1} v_{j+1} (in single precision in the mixed-precision
+// inner cycles, see z_single).
 template <typename VT>
 int arnoldi_step(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipStream_t st) {
   const long long n = p->nvec();
@@ -650,26 +672,40 @@ int arnoldi_step(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipStream_t st) {
   const long long hstr = (long long)R * (R + 1);
   if (!p->use_spec() && nv <= kFusedGsMax) {
     // w = A z_j with the first dot products V^H w computed from the epilogue's registers
-    if constexpr (sizeof(VT) == sizeof(float))
-      HIPCHK(cav::launch_operator_dots_f32(p->g, p->trig, p->khat_f, p->cols, nb, p->zb, n,
-                                           reinterpret_cast<cav::zf*>(p->X),
-                                           reinterpret_cast<cav::zf*>(p->Y), p->S, p->w, n, V, ldj,
-                                           nv, R + 1, p->dpart, p->nblk_red, hcol, hstr,
-                                           kv.active, st));
-    else
-      HIPCHK(cav::launch_operator_dots(p->g, p->trig, p->khat, p->cols, nb, p->zb, n, p->X, p->Y,
-                                       p->S, p->w, n, V, ldj, nv, R + 1, p->dpart, p->nblk_red,
-                                       hcol, hstr, kv.active, st));
+    if constexpr (sizeof(VT) == sizeof(float)) {
+      cav::zf* Xf = reinterpret_cast<cav::zf*>(p->X);
+      cav::zf* Yf = reinterpret_cast<cav::zf*>(p->Y);
+      if (z_single(p))
+        HIPCHK(cav::launch_operator_dots_f32(p->g, p->trig, p->khat_f, p->cols, 0, nb,
+                                             reinterpret_cast<const cav::zf*>(p->zb), n, Xf, Yf,
+                                             p->S, p->w, n, V, ldj, nv, R + 1, p->dpart,
+                                             p->nblk_red, hcol, hstr, kv.active, st));
+      else
+        HIPCHK(cav::launch_operator_dots_f32(p->g, p->trig, p->khat_f, p->cols, 0, nb, p->zb, n,
+                                             Xf, Yf, p->S, p->w, n, V, ldj, nv, R + 1, p->dpart,
+                                             p->nblk_red, hcol, hstr, kv.active, st));
+    } else {
+      HIPCHK(cav::launch_operator_dots(p->g, p->trig, p->khat, p->cols, 0, nb, p->zb, n, p->X,
+                                       p->Y, p->S, p->w, n, V, ldj, nv, R + 1, p->dpart,
+                                       p->nblk_red, hcol, hstr, kv.active, st));
+    }
   } else {
-    if ((s = run_operator(p, 0, nb, p->zb, p->w, kv.active, mixed, st))) return s;
+    if (z_single(p)) {
+      HIPCHK(cav::launch_operator_f32(p->g, p->trig, p->khat_f, p->cols, 0, nb,
+                                      reinterpret_cast<const cav::zf*>(p->zb), n,
+                                      reinterpret_cast<cav::zf*>(p->X),
+                                      reinterpret_cast<cav::zf*>(p->Y), p->S, p->w, n, kv.active,
+                                      st));
+    } else if ((s = run_operator(p, 0, nb, p->zb, p->w, kv.active, mixed, st))) {
+      return s;
+    }
     HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
                             nullptr, 0, kv.active, st));
   }
   if (mixed && mixed_cgs_passes() == 1) {   // one pass: update with hcol, then the norm
     HIPCHK(cav::launch_update_norm(V, ldj, nv, hcol, hstr, p->w, n, nb, p->dnpart, nblk_u,
                                    kv.active, st));
-    HIPCHK(cav::launch_next_vector(p->g, kv, j, p->dnpart, nblk_u, p->w, vn, n, p->cols, p->zb,
-                                   nb, st));
+    if ((s = next_vector(p, kv, j, p->dnpart, nblk_u, p->w, vn, nb, st))) return s;
     return CAVITY_OK;
   }
   if (nv <= kFusedGsMax) {   // one pass: update with hcol, dot products of the updated w
@@ -682,9 +718,7 @@ int arnoldi_step(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipStream_t st) {
   }
   HIPCHK(cav::launch_update_norm(V, ldj, nv, p->h2, R + 1, p->w, n, nb, p->dnpart, nblk_u,
                                  kv.active, st));
-  HIPCHK(cav::launch_next_vector(p->g, kv, j, p->dnpart, nblk_u, p->w, vn, n, p->cols, p->zb, nb,
-                                 st));
-  return CAVITY_OK;
+  return next_vector(p, kv, j, p->dnpart, nblk_u, p->w, vn, nb, st);
 }
 
 // Whether the Arnoldi steps run as captured graphs (one capture per step index and group
@@ -805,7 +839,7 @@ int gmres_batch_t(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
     // per-step flag slots start at -1 ("not written yet"); the device writes 0 or 1
     for (size_t i = (size_t)2 * nb; i < (size_t)(2 + R) * nb; ++i) hstat[i] = -1;
     // v_0 = r / |r| and z = P^{-1} v_0 (norms already in kv.nrm2)
-    HIPCHK(cav::launch_next_vector(p->g, kv, -1, nullptr, 0, r0, V, n, p->cols, p->zb, nb, p->st));
+    if ((s = next_vector(p, kv, -1, nullptr, 0, r0, V, nb, p->st))) return s;
     int seen = 0;   // first step whose flags the host has not looked at
     const bool graphs = use_step_graphs();
     for (int j = 0; j < budget; ++j) {

@@ -157,26 +157,38 @@ hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const Co
                            zd* y, long long ys,
                            const int* active, hipStream_t st);
 // The same operator with the three single-layer convolutions in single precision
-// (spectrum khat_f, workspaces Xf, Yf of the same element count as X, Y); the vectors v, y
-// and the local terms stay double.
+// (spectrum khat_f, workspaces Xf, Yf of the same element count as X, Y; S holds the TBC
+// results in single precision); the vectors v, y and the local terms stay double.
 hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
                                int precond, int nb, const zd* v, long long vs, zf* Xf, zf* Yf,
                                zd* S, zd* y,
                                long long ys, const int* active, hipStream_t st);
-// The operator on v (no preconditioner) into y, its epilogue fused with the first
-// Gram-Schmidt dot products against nv <= 16 basis vectors V (basis vector t of right-hand
-// side r at V + t ldj + r 3 NM): out[r * ostride + t] = sum conj(V_t,r) y_r, from nblk
-// per-block partial sums in `partial` (nb * nvmax * nblk entries).
+// ... on a vector v stored in single precision.
+hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
+                               int precond, int nb, const zf* v, long long vs, zf* Xf, zf* Yf,
+                               zd* S, zd* y, long long ys, const int* active, hipStream_t st);
+// The operator on v (P^{-1} applied to it first when precond) into y, its epilogue fused
+// with the first Gram-Schmidt dot products against nv <= 16 basis vectors V (basis vector
+// t of right-hand side r at V + t ldj + r 3 NM): out[r * ostride + t] = sum conj(V_t,r) y_r,
+// from nblk per-block partial sums in `partial` (nb * nvmax * nblk entries).  The input
+// may be stored in single precision (last overload).
 hipError_t launch_operator_dots(const Geo& g, const Trig& t, const zd* khat, const Cols& c,
-                                int nb, const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y,
-                                long long ys, const zd* V, long long ldj, int nv, int nvmax,
-                                zd* partial, int nblk, zd* out, long long ostride,
+                                int precond, int nb, const zd* v, long long vs, zd* X, zd* Y,
+                                zd* S, zd* y, long long ys, const zd* V, long long ldj, int nv,
+                                int nvmax, zd* partial, int nblk, zd* out, long long ostride,
                                 const int* active, hipStream_t st);
 hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
-                                    int nb, const zd* v, long long vs, zf* Xf, zf* Yf, zd* S,
-                                    zd* y, long long ys, const zf* V, long long ldj, int nv,
-                                    int nvmax, zd* partial, int nblk, zd* out, long long ostride,
-                                    const int* active, hipStream_t st);
+                                    int precond, int nb, const zd* v, long long vs, zf* Xf,
+                                    zf* Yf, zd* S, zd* y, long long ys, const zf* V,
+                                    long long ldj, int nv, int nvmax, zd* partial, int nblk,
+                                    zd* out, long long ostride, const int* active,
+                                    hipStream_t st);
+hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
+                                    int precond, int nb, const zf* v, long long vs, zf* Xf,
+                                    zf* Yf, zd* S, zd* y, long long ys, const zf* V,
+                                    long long ldj, int nv, int nvmax, zd* partial, int nblk,
+                                    zd* out, long long ostride, const int* active,
+                                    hipStream_t st);
 // out[i] = (float) in[i]
 hipError_t launch_to_f32(const zd* in, zf* out, long long n, hipStream_t st);
 // One single-layer family on a coefficient grid (inspection path).
@@ -221,13 +233,17 @@ hipError_t launch_update_norm(const zf* V, long long ldj, int nv, const zd* h, l
                               zd* w, long long n, int nb, double* npart, int nblk,
                               const int* active, hipStream_t st);
 // |w_r|^2 (from nparts partials, or kv.nrm2 when nparts == 0), Givens step of column j
-// (j >= 0), v_r = w_r / |w_r| (v_r at v + r vstride) and z_r = P^{-1} v_r (z_r at z + r n).
+// (j >= 0), v_r = w_r / |w_r| (v_r at v + r vstride) and z_r = P^{-1} v_r (z_r at z + r n,
+// stored in double or, last overload, single precision).
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
                               int nparts, const zd* w, zd* v, long long vstride, const Cols& c,
                               zd* z, int nb, hipStream_t st);
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
                               int nparts, const zd* w, zf* v, long long vstride, const Cols& c,
                               zd* z, int nb, hipStream_t st);
+hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
+                              int nparts, const zd* w, zf* v, long long vstride, const Cols& c,
+                              zf* z, int nb, hipStream_t st);
 hipError_t launch_solve_y(const Krylov& kv, int nb, hipStream_t st);
 // Restart bookkeeping on the device.  init: |b_r| = sqrt(nrm2[r]), iterations zero.
 // cycle_start (after nrm2[r] = |r_r|^2 of the current residual): relative residual, stop

@@ -128,13 +128,13 @@ __device__ inline bool fam_ycos(int f) { return f != 0; }
 
 // Pass 1: rows m0 .. m0+Cb-1 of one family.  fam_fixed >= 0: `v` is the coefficient grid
 // of that family (inspection path); otherwise `v` is a padded aperture vector, optionally
-// preconditioned first.
-template <typename T, int MR, int CTLC = 0>
+// preconditioned first (in double precision whatever its storage precision VI).
+template <typename T, int MR, int CTLC = 0, typename VI = double>
 __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
                                                       const zd* __restrict__ pinv_all,
                                                       long long pcs, int precond,
                                                       int fam_fixed, int lc_arg, int ip,
-                                                      const zd* __restrict__ vall, long long vs,
+                                                      const cx<VI>* __restrict__ vall, long long vs,
                                                       cx<T>* __restrict__ Xall,
                                                       const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
   const BlockId bid = xcd_block_x_slow();
   const int rhs = bid.z;
   if (active && !active[rhs]) return;
-  const zd* v = vall + rhs * vs;
+  const cx<VI>* v = vall + rhs * vs;
   const zd* pinv = pinv_all + rhs * pcs;
   const int nf = fam_fixed >= 0 ? 1 : 3;
   cx<T>* X = Xall + (long long)rhs * nf * (g.M + 1) * g.ldx;
@@ -171,19 +171,21 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
     const long long mn = (long long)m * rowlen + n;
     zd val;
     if (fam_fixed >= 0) {
-      val = v[mn];
-    } else {
-      zd z[3] = {v[mn], v[g.NM + mn], v[2LL * g.NM + mn]};
-      if (precond) {
-        zd y[3];
-        for (int r = 0; r < 3; ++r)
-          y[r] = pinv[(3 * r) * (long long)g.NM + mn] * z[0] +
-                 pinv[(3 * r + 1) * (long long)g.NM + mn] * z[1] +
-                 pinv[(3 * r + 2) * (long long)g.NM + mn] * z[2];
-        z[0] = y[0]; z[1] = y[1]; z[2] = y[2];
-      }
+      val = widen(v[mn]);
+    } else if (precond) {
+      zd z[3] = {widen(v[mn]), widen(v[g.NM + mn]), widen(v[2LL * g.NM + mn])};
+      zd y[3];
+      for (int r = 0; r < 3; ++r)
+        y[r] = pinv[(3 * r) * (long long)g.NM + mn] * z[0] +
+               pinv[(3 * r + 1) * (long long)g.NM + mn] * z[1] +
+               pinv[(3 * r + 2) * (long long)g.NM + mn] * z[2];
       const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
-      val = f == 0 ? z[0] : (f == 1 ? z[1] : (nu * z[0] - mu * z[1]));
+      val = f == 0 ? y[0] : (f == 1 ? y[1] : (nu * y[0] - mu * y[1]));
+    } else {   // only the components the family uses (f is uniform over the block)
+      const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
+      val = f == 0 ? widen(v[mn])
+                   : (f == 1 ? widen(v[g.NM + mn])
+                             : (nu * widen(v[mn]) - mu * widen(v[g.NM + mn])));
     }
     const cx<T> tv = cvt<T>(val);
     store_extension(a, L, ycos, n, tv, lc, c);
@@ -400,7 +402,7 @@ template <typename T, int MR, int CTLC = 0>
 __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed,
                                                       int lc_arg, int ip,
                                                       const cx<T>* __restrict__ Yall,
-                                                      zd* __restrict__ Sall,
+                                                      cx<T>* __restrict__ Sall,
                                                       const int* __restrict__ active) {
   CAV_DYN_SMEM(smem_raw);
   const BlockId bid = xcd_block();
@@ -411,7 +413,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
   const int slot = fam_fixed >= 0 ? 0 : bid.y;
   const cx<T>* Y =
       Yall + (long long)rhs * nf * (g.M + 1) * g.ldx + (long long)slot * (g.M + 1) * g.ldx;
-  zd* S = Sall + (long long)rhs * nf * g.NM + (long long)slot * g.NM;
+  cx<T>* S = Sall + (long long)rhs * nf * g.NM + (long long)slot * g.NM;
   const int lc = CTLC > 0 ? CTLC : lc_arg;
   const int C = 1 << lc;
   const int m0 = bid.x << lc;
@@ -453,7 +455,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
     const int c = div_row.quot(w), n = w - c * div_row.d;
     const cx<T> F = r2[(n << lc) + c];
     const zd s = widen(ycos ? (T)0.5 * F : (T)0.5 * mul_i(F));
-    S[(long long)(m0 + c) * rowlen + n] = g.hq2 * s;
+    S[(long long)(m0 + c) * rowlen + n] = cvt<T>(g.hq2 * s);
   }
 }
 
@@ -464,8 +466,9 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
 // Operator result of mode mn of right-hand side rhs (the three components r1, r2, r3 of y)
 // from its input v (P^{-1} applied first when precond) and the TBC results S: rows 1-3 of
 // the reduced system with the per-mode column data.
-__device__ inline void epilogue_mode(const Geo& g, const Cols& cl, int precond, const zd* v,
-                                     const zd* S, int rhs, int mn, zd* out) {
+template <typename VI, typename ST>
+__device__ inline void epilogue_mode(const Geo& g, const Cols& cl, int precond, const cx<VI>* v,
+                                     const cx<ST>* S, int rhs, int mn, zd* out) {
   const long long co = rhs * cl.cs;
   const zd* __restrict__ rho_d = cl.rho_d + co;
   const zd* __restrict__ T = cl.T + co;
@@ -474,7 +477,7 @@ __device__ inline void epilogue_mode(const Geo& g, const Cols& cl, int precond, 
   const int m = mn / (g.N + 1), n = mn % (g.N + 1);
   const double h = cl.hs ? cl.hs[rhs] : g.h;
   const double mu = M_PI * m / g.a, nu = M_PI * n / g.b, k2 = g.k * g.k;
-  zd z[3] = {v[mn], v[g.NM + mn], v[2LL * g.NM + mn]};
+  zd z[3] = {widen(v[mn]), widen(v[g.NM + mn]), widen(v[2LL * g.NM + mn])};
   if (precond) {
     zd t[3];
     for (int r = 0; r < 3; ++r)
@@ -483,7 +486,7 @@ __device__ inline void epilogue_mode(const Geo& g, const Cols& cl, int precond, 
              pinv[(3 * r + 2) * (long long)g.NM + mn] * z[2];
     z[0] = t[0]; z[1] = t[1]; z[2] = t[2];
   }
-  const zd scs = S[mn], ssc = S[g.NM + mn], scc = S[2LL * g.NM + mn];
+  const zd scs = widen(S[mn]), ssc = widen(S[g.NM + mn]), scc = widen(S[2LL * g.NM + mn]);
   const zd rd = rho_d[mn] - mk(1.0, 0.0), rn = rho_n[mn] - mk(1.0, 0.0);
   const zd th = T[mn] + mk(h, 0.0);
   const double hq = h / ((m == 0 ? 0.5 : 0.25) * g.a * g.b);
@@ -497,8 +500,9 @@ __device__ inline void epilogue_mode(const Geo& g, const Cols& cl, int precond, 
   out[2] = r3;
 }
 
-__global__ void k_operator_epilogue(Geo g, Cols cl, int precond, const zd* __restrict__ vall,
-                                    long long vs, const zd* __restrict__ Sall,
+template <typename VI, typename ST>
+__global__ void k_operator_epilogue(Geo g, Cols cl, int precond, const cx<VI>* __restrict__ vall,
+                                    long long vs, const cx<ST>* __restrict__ Sall,
                                     zd* __restrict__ yall, long long ys,
                                     const int* __restrict__ active) {
   const int rhs = blockIdx.y;
@@ -518,10 +522,11 @@ __global__ void k_operator_epilogue(Geo g, Cols cl, int precond, const zd* __res
 // nv <= G basis vectors (V_t of right-hand side rhs at V + t ldj + rhs 3 NM) in k_dots'
 // layout, partial[(rhs nvmax + t) gridDim.x + block].  Blocks stride over the modes; each
 // thread sums its modes in order, the three components of a mode in order.
-template <typename VT, int G>
+template <typename VT, int G, typename VI>
 __global__ __launch_bounds__(256) void k_epilogue_dots(Geo g, Cols cl, int precond,
-                                                       const zd* __restrict__ vall, long long vs,
-                                                       const zd* __restrict__ Sall,
+                                                       const cx<VI>* __restrict__ vall,
+                                                       long long vs,
+                                                       const cx<VT>* __restrict__ Sall,
                                                        zd* __restrict__ yall, long long ys,
                                                        const cx<VT>* __restrict__ V,
                                                        long long ldj, int nv, int nvmax,
@@ -530,8 +535,8 @@ __global__ __launch_bounds__(256) void k_epilogue_dots(Geo g, Cols cl, int preco
   __shared__ zd red[G][4];
   const int rhs = blockIdx.y;
   if (active && !active[rhs]) return;
-  const zd* v = vall + rhs * vs;
-  const zd* S = Sall + 3LL * rhs * g.NM;
+  const cx<VI>* v = vall + rhs * vs;
+  const cx<VT>* S = Sall + 3LL * rhs * g.NM;
   zd* y = yall + rhs * ys;
   const cx<VT>* Vr = V + rhs * 3LL * g.NM;
   zd acc[G];
@@ -607,15 +612,16 @@ static TbcShape tbc_shape(const FftPlan& ext, const FftPlan& box, int L, int P, 
   return {lc, 0, (size_t)2 * P * elem << lc};
 }
 
-template <typename T>
+template <typename T, typename VI = double>
 static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, const zd* pinv,
-                             long long pcs, int precond, int fam_fixed, int nb, const zd* v,
+                             long long pcs, int precond, int fam_fixed, int nb, const cx<VI>* v,
                              long long vs,
-                             cx<T>* X, cx<T>* Y, zd* S, const int* active, hipStream_t st) {
+                             cx<T>* X, cx<T>* Y, cx<T>* S, const int* active, hipStream_t st) {
   const int nf = fam_fixed >= 0 ? 1 : 3;
   const double zb = sizeof(zd), tb = sizeof(cx<T>);
   const double xbytes = tb * nb * nf * (g.M + 1) * (double)g.P2;   // one X or Y workspace
-  const double vin = nb * (zb * (fam_fixed >= 0 ? 1.0 : 3.0) * g.NM) + (precond ? zb * 9.0 * g.NM : 0.0);
+  const double vin = nb * (sizeof(cx<VI>) * (fam_fixed >= 0 ? 1.0 : 3.0) * g.NM) +
+                     (precond ? zb * 9.0 * g.NM : 0.0);
   const bool single = sizeof(T) == sizeof(float);
   const int id_fwd = single ? K_TBC_ROWS_FWD_F32 : K_TBC_ROWS_FWD;
   const int id_cols = single ? K_TBC_COLS_F32 : K_TBC_COLS;
@@ -629,18 +635,18 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
   const bool ct_rows = plan_is<8, 8, 8>(t.ext2.p) && plan_is<5, 5, 5, 5>(t.box2.p);
   probe_begin(id_fwd, st);
   if (ct_rows && sr.lc == 2 && !sr.ip)
-    hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8, 2>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
+    hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8, 2, VI>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
                        t.ext2, t.box2, pinv, pcs, precond, fam_fixed, sr.lc, sr.ip, v, vs, X,
                        active);
   else if (ct_rows && sr.lc == 1)
-    hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8, 1>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
+    hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8, 1, VI>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
                        t.ext2, t.box2, pinv, pcs, precond, fam_fixed, sr.lc, sr.ip, v, vs, X,
                        active);
   else if (t.maxr <= 8)
-    hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g, t.ext2,
+    hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8, 0, VI>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g, t.ext2,
                        t.box2, pinv, pcs, precond, fam_fixed, sr.lc, sr.ip, v, vs, X, active);
   else
-    hipLaunchKernelGGL((k_tbc_rows_fwd<T, kMaxRadix>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
+    hipLaunchKernelGGL((k_tbc_rows_fwd<T, kMaxRadix, 0, VI>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
                        t.ext2, t.box2, pinv, pcs, precond, fam_fixed, sr.lc, sr.ip, v, vs, X,
                        active);
   probe_end(id_fwd, st, vin + xbytes);
@@ -681,7 +687,7 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
   else
     hipLaunchKernelGGL((k_tbc_rows_bwd<T, kMaxRadix>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
                        t.ext2, t.box2, fam_fixed, sr.lc, sr.ip, Y, S, active);
-  probe_end(id_bwd, st, xbytes + zb * nb * nf * g.NM);
+  probe_end(id_bwd, st, xbytes + tb * nb * nf * g.NM);
   return hipGetLastError();
 }
 
@@ -692,19 +698,23 @@ static hipError_t launch_tbc_passes(const Geo& g, const Trig& t, const zd* khat,
                             st);
 }
 
-template <typename T>
+// S (3 NM entries per right-hand side in the workspace of that many double entries) holds
+// the TBC results in the operator's precision T.
+template <typename T, typename VI>
 static hipError_t operator_impl(const Geo& g, const Trig& t, const cx<T>* khat, const Cols& c,
-                                int precond, int nb, const zd* v, long long vs, cx<T>* X,
+                                int precond, int nb, const cx<VI>* v, long long vs, cx<T>* X,
                                 cx<T>* Y, zd* S, zd* y, long long ys, const int* active,
                                 hipStream_t st) {
-  hipError_t e = tbc_passes<T>(g, t, khat, c.pinv, c.cs, precond, -1, nb, v, vs, X, Y, S, active,
-                               st);
+  cx<T>* St = reinterpret_cast<cx<T>*>(S);
+  hipError_t e = tbc_passes<T, VI>(g, t, khat, c.pinv, c.cs, precond, -1, nb, v, vs, X, Y, St,
+                                   active, st);
   if (e != hipSuccess) return e;
   const int blk = 256;
   probe_begin(K_EPILOGUE, st);
-  hipLaunchKernelGGL(k_operator_epilogue, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g,
-                     c, precond, v, vs, S, y, ys, active);
-  probe_end(K_EPILOGUE, st, sizeof(zd) * (double)g.NM * (nb * 9.0 + 3.0 + (precond ? 9.0 : 0.0)));
+  hipLaunchKernelGGL((k_operator_epilogue<VI, T>), dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0,
+                     st, g, c, precond, v, vs, St, y, ys, active);
+  probe_end(K_EPILOGUE, st, (sizeof(zd) + sizeof(cx<VI>) + sizeof(cx<T>)) * 3.0 * g.NM * nb +
+                                sizeof(zd) * (double)g.NM * (3.0 + (precond ? 9.0 : 0.0)));
   return hipGetLastError();
 }
 
@@ -719,49 +729,65 @@ hipError_t launch_operator_spec(const Geo& g, const SpecMats& sm, const zd* khat
                                     active, st);
   if (e != hipSuccess) return e;
   const int blk = 256;
-  hipLaunchKernelGGL(k_operator_epilogue, dim3((g.NM + blk - 1) / blk, nb), dim3(blk), 0, st, g,
-                     c, precond, v, vs, S, y, ys, active);
+  hipLaunchKernelGGL((k_operator_epilogue<double, double>), dim3((g.NM + blk - 1) / blk, nb),
+                     dim3(blk), 0, st, g, c, precond, v, vs, S, y, ys, active);
   return hipGetLastError();
 }
 
 hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const Cols& c,
                            int precond, int nb, const zd* v, long long vs, zd* X, zd* Y, zd* S,
                            zd* y, long long ys, const int* active, hipStream_t st) {
-  return operator_impl<double>(g, t, khat, c, precond, nb, v, vs, X, Y, S, y, ys, active, st);
+  return operator_impl<double, double>(g, t, khat, c, precond, nb, v, vs, X, Y, S, y, ys, active,
+                                       st);
 }
 
 hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
                                int precond, int nb, const zd* v, long long vs, zf* Xf, zf* Yf,
                                zd* S, zd* y, long long ys, const int* active, hipStream_t st) {
-  return operator_impl<float>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S, y, ys, active, st);
+  return operator_impl<float, double>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S, y, ys,
+                                      active, st);
+}
+
+hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
+                               int precond, int nb, const zf* v, long long vs, zf* Xf, zf* Yf,
+                               zd* S, zd* y, long long ys, const int* active, hipStream_t st) {
+  return operator_impl<float, float>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S, y, ys,
+                                     active, st);
 }
 
 __global__ void k_reduce_cols(const zd* __restrict__ partial, int nblk, int nvmax,
                               zd* __restrict__ out, long long ostride, zd* __restrict__ acc,
                               long long astride, const int* __restrict__ active);
 
-// The operator (no preconditioner on input) followed by the epilogue fused with the first
-// Gram-Schmidt dot products against the nv <= 16 basis vectors V (k_epilogue_dots), the
-// nblk per-block partial sums reduced into out[r * ostride + t].
-template <typename T>
+// The operator on input v (P^{-1} applied to it first when precond) followed by the
+// epilogue fused with the first Gram-Schmidt dot products against the nv <= 16 basis
+// vectors V (k_epilogue_dots), the nblk per-block partial sums reduced into
+// out[r * ostride + t].  v is stored in double or in single precision (VI); S, in the
+// workspace of 3 NM double entries per right-hand side, holds the TBC results in
+// precision T.
+template <typename T, typename VI>
 static hipError_t operator_dots_impl(const Geo& g, const Trig& t, const cx<T>* khat,
-                                     const Cols& c, int nb, const zd* v, long long vs, cx<T>* X,
-                                     cx<T>* Y, zd* S, zd* y, long long ys, const cx<T>* V,
-                                     long long ldj, int nv, int nvmax, zd* partial, int nblk,
-                                     zd* out, long long ostride, const int* active,
-                                     hipStream_t st) {
+                                     const Cols& c, int precond, int nb, const cx<VI>* v,
+                                     long long vs, cx<T>* X, cx<T>* Y, zd* S, zd* y, long long ys,
+                                     const cx<T>* V, long long ldj, int nv, int nvmax,
+                                     zd* partial, int nblk, zd* out, long long ostride,
+                                     const int* active, hipStream_t st) {
   if (nv < 1 || nv > 16) return hipErrorInvalidValue;
-  hipError_t e = tbc_passes<T>(g, t, khat, c.pinv, c.cs, 0, -1, nb, v, vs, X, Y, S, active, st);
+  cx<T>* St = reinterpret_cast<cx<T>*>(S);
+  hipError_t e =
+      tbc_passes<T, VI>(g, t, khat, c.pinv, c.cs, precond, -1, nb, v, vs, X, Y, St, active, st);
   if (e != hipSuccess) return e;
   probe_begin(K_EPILOGUE, st);
   if (nv <= 8)
-    hipLaunchKernelGGL((k_epilogue_dots<T, 8>), dim3(nblk, nb), dim3(256), 0, st, g, c, 0, v, vs,
-                       S, y, ys, V, ldj, nv, nvmax, partial, active);
+    hipLaunchKernelGGL((k_epilogue_dots<T, 8, VI>), dim3(nblk, nb), dim3(256), 0, st, g, c,
+                       precond, v, vs, St, y, ys, V, ldj, nv, nvmax, partial, active);
   else
-    hipLaunchKernelGGL((k_epilogue_dots<T, 16>), dim3(nblk, nb), dim3(256), 0, st, g, c, 0, v,
-                       vs, S, y, ys, V, ldj, nv, nvmax, partial, active);
-  probe_end(K_EPILOGUE, st, sizeof(zd) * (double)g.NM * (nb * 9.0 + 3.0) +
-                                sizeof(cx<T>) * 3.0 * g.NM * nb * nv);
+    hipLaunchKernelGGL((k_epilogue_dots<T, 16, VI>), dim3(nblk, nb), dim3(256), 0, st, g, c,
+                       precond, v, vs, St, y, ys, V, ldj, nv, nvmax, partial, active);
+  probe_end(K_EPILOGUE, st,
+            (sizeof(cx<VI>) + sizeof(cx<T>) + sizeof(zd)) * 3.0 * g.NM * nb +
+                sizeof(zd) * (double)g.NM * (3.0 + (precond ? 9.0 : 0.0)) +
+                sizeof(cx<T>) * 3.0 * g.NM * nb * nv);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_cols, dim3(nv, nb), dim3(256), 0, st, partial, nblk, nvmax, out,
@@ -770,21 +796,35 @@ static hipError_t operator_dots_impl(const Geo& g, const Trig& t, const cx<T>* k
 }
 
 hipError_t launch_operator_dots(const Geo& g, const Trig& t, const zd* khat, const Cols& c,
-                                int nb, const zd* v, long long vs, zd* X, zd* Y, zd* S, zd* y,
-                                long long ys, const zd* V, long long ldj, int nv, int nvmax,
-                                zd* partial, int nblk, zd* out, long long ostride,
+                                int precond, int nb, const zd* v, long long vs, zd* X, zd* Y,
+                                zd* S, zd* y, long long ys, const zd* V, long long ldj, int nv,
+                                int nvmax, zd* partial, int nblk, zd* out, long long ostride,
                                 const int* active, hipStream_t st) {
-  return operator_dots_impl<double>(g, t, khat, c, nb, v, vs, X, Y, S, y, ys, V, ldj, nv, nvmax,
-                                    partial, nblk, out, ostride, active, st);
+  return operator_dots_impl<double, double>(g, t, khat, c, precond, nb, v, vs, X, Y, S, y, ys, V,
+                                            ldj, nv, nvmax, partial, nblk, out, ostride, active,
+                                            st);
 }
 
 hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
-                                    int nb, const zd* v, long long vs, zf* Xf, zf* Yf, zd* S,
-                                    zd* y, long long ys, const zf* V, long long ldj, int nv,
-                                    int nvmax, zd* partial, int nblk, zd* out, long long ostride,
-                                    const int* active, hipStream_t st) {
-  return operator_dots_impl<float>(g, t, khat_f, c, nb, v, vs, Xf, Yf, S, y, ys, V, ldj, nv, nvmax,
-                                   partial, nblk, out, ostride, active, st);
+                                    int precond, int nb, const zd* v, long long vs, zf* Xf,
+                                    zf* Yf, zd* S, zd* y, long long ys, const zf* V,
+                                    long long ldj, int nv, int nvmax, zd* partial, int nblk,
+                                    zd* out, long long ostride, const int* active,
+                                    hipStream_t st) {
+  return operator_dots_impl<float, double>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S, y, ys,
+                                           V, ldj, nv, nvmax, partial, nblk, out, ostride, active,
+                                           st);
+}
+
+hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
+                                    int precond, int nb, const zf* v, long long vs, zf* Xf,
+                                    zf* Yf, zd* S, zd* y, long long ys, const zf* V,
+                                    long long ldj, int nv, int nvmax, zd* partial, int nblk,
+                                    zd* out, long long ostride, const int* active,
+                                    hipStream_t st) {
+  return operator_dots_impl<float, float>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S, y, ys,
+                                          V, ldj, nv, nvmax, partial, nblk, out, ostride, active,
+                                          st);
 }
 
 __global__ void k_to_f32(const zd* __restrict__ in, zf* __restrict__ out, long long n) {
@@ -1392,16 +1432,17 @@ hipError_t launch_update_norm(const zf* V, long long ldj, int nv, const zd* h, l
 
 // Next basis vector: |w_r|^2 from the nparts partials of k_update_norm (nparts == 0: from
 // kv.nrm2), then (j >= 0) the Givens step of column j by block 0, and v_r = w_r / |w_r|
-// with its preconditioned copy z_r = P^{-1} v_r.  Threads run over modes; vectors are
+// with its preconditioned copy z_r = P^{-1} v_r, computed in double precision and stored
+// in precision ZT.  Threads run over modes; vectors are
 // component-major.  Blocks read the active flag before block 0 may clear it; a rhs that
 // stops here never uses the vector written for it.
-template <typename VT>
+template <typename VT, typename ZT>
 __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
                                                      const double* __restrict__ npart, int nparts,
                                                      const zd* __restrict__ wall,
                                                      cx<VT>* __restrict__ vall, long long vstride,
                                                      const zd* __restrict__ pinv_all,
-                                                     long long pcs, zd* __restrict__ zall) {
+                                                     long long pcs, cx<ZT>* __restrict__ zall) {
   __shared__ double red[4];
   __shared__ double s_nrm;
   const int r = blockIdx.y;
@@ -1430,7 +1471,7 @@ __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
   const long long n = 3LL * g.NM;
   const zd* w = wall + r * n;
   cx<VT>* v = vall + r * vstride;
-  zd* z = zall + r * n;
+  cx<ZT>* z = zall + r * n;
   const zd* __restrict__ pinv = pinv_all + r * pcs;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long mn = (long long)blockIdx.x * blockDim.x + threadIdx.x; mn < g.NM; mn += stride) {
@@ -1443,33 +1484,39 @@ __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      z[k * g.NM + mn] = pinv[(3 * k) * (long long)g.NM + mn] * u[0] +
-                         pinv[(3 * k + 1) * (long long)g.NM + mn] * u[1] +
-                         pinv[(3 * k + 2) * (long long)g.NM + mn] * u[2];
+      z[k * g.NM + mn] = cvt<ZT>(pinv[(3 * k) * (long long)g.NM + mn] * u[0] +
+                                 pinv[(3 * k + 1) * (long long)g.NM + mn] * u[1] +
+                                 pinv[(3 * k + 2) * (long long)g.NM + mn] * u[2]);
   }
 }
 
-template <typename VT>
+template <typename VT, typename ZT>
 static hipError_t next_vector_impl(const Geo& g, const Krylov& kv, int j, const double* npart,
                                    int nparts, const zd* w, cx<VT>* v, long long vstride,
-                                   const Cols& c, zd* z, int nb, hipStream_t st) {
+                                   const Cols& c, cx<ZT>* z, int nb, hipStream_t st) {
   int nblk = (g.NM + 255) / 256;
   if (nblk > 1024) nblk = 1024;
-  hipLaunchKernelGGL((k_next_vector<VT>), dim3(nblk, nb), dim3(256), 0, st, g, kv, j, npart, nparts,
-                     w, v, vstride, c.pinv, c.cs, z);
+  hipLaunchKernelGGL((k_next_vector<VT, ZT>), dim3(nblk, nb), dim3(256), 0, st, g, kv, j, npart,
+                     nparts, w, v, vstride, c.pinv, c.cs, z);
   return hipGetLastError();
 }
 
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
                               int nparts, const zd* w, zd* v, long long vstride, const Cols& c,
                               zd* z, int nb, hipStream_t st) {
-  return next_vector_impl<double>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb, st);
+  return next_vector_impl<double, double>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb, st);
 }
 
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
                               int nparts, const zd* w, zf* v, long long vstride, const Cols& c,
                               zd* z, int nb, hipStream_t st) {
-  return next_vector_impl<float>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb, st);
+  return next_vector_impl<float, double>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb, st);
+}
+
+hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
+                              int nparts, const zd* w, zf* v, long long vstride, const Cols& c,
+                              zf* z, int nb, hipStream_t st) {
+  return next_vector_impl<float, float>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb, st);
 }
 
 // ---------------------------------------------------------------------------------

@@ -636,10 +636,11 @@ int mixed_cgs_passes() {
 // take their input in single precision anyway (the spectral operator's stay double).
 bool z_single(cavity_plan p) { return p->opts.precision == CAVITY_MIXED && !p->use_spec(); }
 
-// v_{j+1} = w / |w| into vn and z = P^{-1} v_{j+1} into p->zb (see launch_next_vector).
-template <typename VT>
+// v_{j+1} = w / |w| into vn and z = P^{-1} v_{j+1} into p->zb (see launch_next_vector);
+// w in single precision (WT = float) only in the mixed-precision inner steps.
+template <typename VT, typename WT>
 int next_vector(cavity_plan p, cav::Krylov& kv, int j, const double* npart, int nparts,
-                const zd* w, cav::cx<VT>* vn, int nb, hipStream_t st) {
+                const cav::cx<WT>* w, cav::cx<VT>* vn, int nb, hipStream_t st) {
   const long long n = p->nvec();
   if constexpr (sizeof(VT) == sizeof(float)) {
     if (z_single(p)) {
@@ -648,8 +649,12 @@ int next_vector(cavity_plan p, cav::Krylov& kv, int j, const double* npart, int 
       return CAVITY_OK;
     }
   }
-  HIPCHK(cav::launch_next_vector(p->g, kv, j, npart, nparts, w, vn, n, p->cols, p->zb, nb, st));
-  return CAVITY_OK;
+  if constexpr (sizeof(WT) == sizeof(double)) {
+    HIPCHK(cav::launch_next_vector(p->g, kv, j, npart, nparts, w, vn, n, p->cols, p->zb, nb, st));
+    return CAVITY_OK;
+  } else {
+    return fail(CAVITY_ENOTIMPL, "single-precision w outside the mixed inner steps");
+  }
 }
 
 // One Arnoldi step j for the lockstep group (kernels only, on stream st): w = A z_j,
@@ -670,15 +675,25 @@ int arnoldi_step(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipStream_t st) {
   const int nv = j + 1;
   zd* hcol = kv.H + (long long)j * (R + 1);
   const long long hstr = (long long)R * (R + 1);
-  if (!p->use_spec() && nv <= kFusedGsMax) {
+  const bool fused = !p->use_spec() && nv <= kFusedGsMax;
+  // the fused single-pass steps of the mixed-precision inner cycles keep w in single
+  // precision too (updated in double, see k_update_norm)
+  const bool w_single = sizeof(VT) == sizeof(float) && fused && z_single(p) &&
+                        mixed_cgs_passes() == 1;
+  cav::zf* wf = reinterpret_cast<cav::zf*>(p->w);
+  if (fused) {
     // w = A z_j with the first dot products V^H w computed from the epilogue's registers
     if constexpr (sizeof(VT) == sizeof(float)) {
       cav::zf* Xf = reinterpret_cast<cav::zf*>(p->X);
       cav::zf* Yf = reinterpret_cast<cav::zf*>(p->Y);
-      if (z_single(p))
-        HIPCHK(cav::launch_operator_dots_f32(p->g, p->trig, p->khat_f, p->cols, 0, nb,
-                                             reinterpret_cast<const cav::zf*>(p->zb), n, Xf, Yf,
-                                             p->S, p->w, n, V, ldj, nv, R + 1, p->dpart,
+      const cav::zf* zf = reinterpret_cast<const cav::zf*>(p->zb);
+      if (w_single)
+        HIPCHK(cav::launch_operator_dots_f32(p->g, p->trig, p->khat_f, p->cols, 0, nb, zf, n, Xf,
+                                             Yf, p->S, wf, n, V, ldj, nv, R + 1, p->dpart,
+                                             p->nblk_red, hcol, hstr, kv.active, st));
+      else if (z_single(p))
+        HIPCHK(cav::launch_operator_dots_f32(p->g, p->trig, p->khat_f, p->cols, 0, nb, zf, n, Xf,
+                                             Yf, p->S, p->w, n, V, ldj, nv, R + 1, p->dpart,
                                              p->nblk_red, hcol, hstr, kv.active, st));
       else
         HIPCHK(cav::launch_operator_dots_f32(p->g, p->trig, p->khat_f, p->cols, 0, nb, p->zb, n,
@@ -701,6 +716,13 @@ int arnoldi_step(cavity_plan p, int nb, int j, cav::cx<VT>* V, hipStream_t st) {
     }
     HIPCHK(cav::launch_dots(V, ldj, nv, R + 1, p->w, n, nb, p->dpart, p->nblk_red, hcol, hstr,
                             nullptr, 0, kv.active, st));
+  }
+  if (w_single) {   // one pass: update with hcol, then the norm
+    if constexpr (sizeof(VT) == sizeof(float)) {
+      HIPCHK(cav::launch_update_norm(V, ldj, nv, hcol, hstr, wf, n, nb, p->dnpart, nblk_u,
+                                     kv.active, st));
+      return next_vector(p, kv, j, p->dnpart, nblk_u, wf, vn, nb, st);
+    }
   }
   if (mixed && mixed_cgs_passes() == 1) {   // one pass: update with hcol, then the norm
     HIPCHK(cav::launch_update_norm(V, ldj, nv, hcol, hstr, p->w, n, nb, p->dnpart, nblk_u,

@@ -171,7 +171,7 @@ hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, co
 // with the first Gram-Schmidt dot products against nv <= 16 basis vectors V (basis vector
 // t of right-hand side r at V + t ldj + r 3 NM): out[r * ostride + t] = sum conj(V_t,r) y_r,
 // from nblk per-block partial sums in `partial` (nb * nvmax * nblk entries).  The input
-// may be stored in single precision (last overload).
+// and the output may be stored in single precision (last two overloads).
 hipError_t launch_operator_dots(const Geo& g, const Trig& t, const zd* khat, const Cols& c,
                                 int precond, int nb, const zd* v, long long vs, zd* X, zd* Y,
                                 zd* S, zd* y, long long ys, const zd* V, long long ldj, int nv,
@@ -186,6 +186,12 @@ hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_
 hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
                                     int precond, int nb, const zf* v, long long vs, zf* Xf,
                                     zf* Yf, zd* S, zd* y, long long ys, const zf* V,
+                                    long long ldj, int nv, int nvmax, zd* partial, int nblk,
+                                    zd* out, long long ostride, const int* active,
+                                    hipStream_t st);
+hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
+                                    int precond, int nb, const zf* v, long long vs, zf* Xf,
+                                    zf* Yf, zd* S, zf* y, long long ys, const zf* V,
                                     long long ldj, int nv, int nvmax, zd* partial, int nblk,
                                     zd* out, long long ostride, const int* active,
                                     hipStream_t st);
@@ -232,6 +238,10 @@ hipError_t launch_update_norm(const zd* V, long long ldj, int nv, const zd* h, l
 hipError_t launch_update_norm(const zf* V, long long ldj, int nv, const zd* h, long long hstride,
                               zd* w, long long n, int nb, double* npart, int nblk,
                               const int* active, hipStream_t st);
+// ... with w stored in single precision (updated in double precision).
+hipError_t launch_update_norm(const zf* V, long long ldj, int nv, const zd* h, long long hstride,
+                              zf* w, long long n, int nb, double* npart, int nblk,
+                              const int* active, hipStream_t st);
 // |w_r|^2 (from nparts partials, or kv.nrm2 when nparts == 0), Givens step of column j
 // (j >= 0), v_r = w_r / |w_r| (v_r at v + r vstride) and z_r = P^{-1} v_r (z_r at z + r n,
 // stored in double or, last overload, single precision).
@@ -243,6 +253,9 @@ hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const doubl
                               zd* z, int nb, hipStream_t st);
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
                               int nparts, const zd* w, zf* v, long long vstride, const Cols& c,
+                              zf* z, int nb, hipStream_t st);
+hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
+                              int nparts, const zf* w, zf* v, long long vstride, const Cols& c,
                               zf* z, int nb, hipStream_t st);
 hipError_t launch_solve_y(const Krylov& kv, int nb, hipStream_t st);
 // Restart bookkeeping on the device.  init: |b_r| = sqrt(nrm2[r]), iterations zero.

@@ -522,12 +522,12 @@ __global__ void k_operator_epilogue(Geo g, Cols cl, int precond, const cx<VI>* _
 // nv <= G basis vectors (V_t of right-hand side rhs at V + t ldj + rhs 3 NM) in k_dots'
 // layout, partial[(rhs nvmax + t) gridDim.x + block].  Blocks stride over the modes; each
 // thread sums its modes in order, the three components of a mode in order.
-template <typename VT, int G, typename VI>
+template <typename VT, int G, typename VI, typename WT>
 __global__ __launch_bounds__(256) void k_epilogue_dots(Geo g, Cols cl, int precond,
                                                        const cx<VI>* __restrict__ vall,
                                                        long long vs,
                                                        const cx<VT>* __restrict__ Sall,
-                                                       zd* __restrict__ yall, long long ys,
+                                                       cx<WT>* __restrict__ yall, long long ys,
                                                        const cx<VT>* __restrict__ V,
                                                        long long ldj, int nv, int nvmax,
                                                        zd* __restrict__ partial,
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(256) void k_epilogue_dots(Geo g, Cols cl, int preco
   if (active && !active[rhs]) return;
   const cx<VI>* v = vall + rhs * vs;
   const cx<VT>* S = Sall + 3LL * rhs * g.NM;
-  zd* y = yall + rhs * ys;
+  cx<WT>* y = yall + rhs * ys;
   const cx<VT>* Vr = V + rhs * 3LL * g.NM;
   zd acc[G];
   for (int t = 0; t < G; ++t) acc[t] = mk(0.0, 0.0);
@@ -545,9 +545,9 @@ __global__ __launch_bounds__(256) void k_epilogue_dots(Geo g, Cols cl, int preco
        mn += gridDim.x * blockDim.x) {
     zd r[3];
     epilogue_mode(g, cl, precond, v, S, rhs, mn, r);
-    y[mn] = r[0];
-    y[g.NM + mn] = r[1];
-    y[2LL * g.NM + mn] = r[2];
+    y[mn] = cvt<WT>(r[0]);
+    y[g.NM + mn] = cvt<WT>(r[1]);
+    y[2LL * g.NM + mn] = cvt<WT>(r[2]);
 #pragma unroll
     for (int t = 0; t < G; ++t)
       if (t < nv) {
@@ -765,10 +765,11 @@ __global__ void k_reduce_cols(const zd* __restrict__ partial, int nblk, int nvma
 // out[r * ostride + t].  v is stored in double or in single precision (VI); S, in the
 // workspace of 3 NM double entries per right-hand side, holds the TBC results in
 // precision T.
-template <typename T, typename VI>
+template <typename T, typename VI, typename WT>
 static hipError_t operator_dots_impl(const Geo& g, const Trig& t, const cx<T>* khat,
                                      const Cols& c, int precond, int nb, const cx<VI>* v,
-                                     long long vs, cx<T>* X, cx<T>* Y, zd* S, zd* y, long long ys,
+                                     long long vs, cx<T>* X, cx<T>* Y, zd* S, cx<WT>* y,
+                                     long long ys,
                                      const cx<T>* V, long long ldj, int nv, int nvmax,
                                      zd* partial, int nblk, zd* out, long long ostride,
                                      const int* active, hipStream_t st) {
@@ -779,13 +780,13 @@ static hipError_t operator_dots_impl(const Geo& g, const Trig& t, const cx<T>* k
   if (e != hipSuccess) return e;
   probe_begin(K_EPILOGUE, st);
   if (nv <= 8)
-    hipLaunchKernelGGL((k_epilogue_dots<T, 8, VI>), dim3(nblk, nb), dim3(256), 0, st, g, c,
+    hipLaunchKernelGGL((k_epilogue_dots<T, 8, VI, WT>), dim3(nblk, nb), dim3(256), 0, st, g, c,
                        precond, v, vs, St, y, ys, V, ldj, nv, nvmax, partial, active);
   else
-    hipLaunchKernelGGL((k_epilogue_dots<T, 16, VI>), dim3(nblk, nb), dim3(256), 0, st, g, c,
+    hipLaunchKernelGGL((k_epilogue_dots<T, 16, VI, WT>), dim3(nblk, nb), dim3(256), 0, st, g, c,
                        precond, v, vs, St, y, ys, V, ldj, nv, nvmax, partial, active);
   probe_end(K_EPILOGUE, st,
-            (sizeof(cx<VI>) + sizeof(cx<T>) + sizeof(zd)) * 3.0 * g.NM * nb +
+            (sizeof(cx<VI>) + sizeof(cx<T>) + sizeof(cx<WT>)) * 3.0 * g.NM * nb +
                 sizeof(zd) * (double)g.NM * (3.0 + (precond ? 9.0 : 0.0)) +
                 sizeof(cx<T>) * 3.0 * g.NM * nb * nv);
   e = hipGetLastError();
@@ -800,7 +801,7 @@ hipError_t launch_operator_dots(const Geo& g, const Trig& t, const zd* khat, con
                                 zd* S, zd* y, long long ys, const zd* V, long long ldj, int nv,
                                 int nvmax, zd* partial, int nblk, zd* out, long long ostride,
                                 const int* active, hipStream_t st) {
-  return operator_dots_impl<double, double>(g, t, khat, c, precond, nb, v, vs, X, Y, S, y, ys, V,
+  return operator_dots_impl<double, double, double>(g, t, khat, c, precond, nb, v, vs, X, Y, S, y, ys, V,
                                             ldj, nv, nvmax, partial, nblk, out, ostride, active,
                                             st);
 }
@@ -811,7 +812,7 @@ hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_
                                     long long ldj, int nv, int nvmax, zd* partial, int nblk,
                                     zd* out, long long ostride, const int* active,
                                     hipStream_t st) {
-  return operator_dots_impl<float, double>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S, y, ys,
+  return operator_dots_impl<float, double, double>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S, y, ys,
                                            V, ldj, nv, nvmax, partial, nblk, out, ostride, active,
                                            st);
 }
@@ -822,9 +823,20 @@ hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_
                                     long long ldj, int nv, int nvmax, zd* partial, int nblk,
                                     zd* out, long long ostride, const int* active,
                                     hipStream_t st) {
-  return operator_dots_impl<float, float>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S, y, ys,
-                                          V, ldj, nv, nvmax, partial, nblk, out, ostride, active,
-                                          st);
+  return operator_dots_impl<float, float, double>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S,
+                                                  y, ys, V, ldj, nv, nvmax, partial, nblk, out,
+                                                  ostride, active, st);
+}
+
+hipError_t launch_operator_dots_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
+                                    int precond, int nb, const zf* v, long long vs, zf* Xf,
+                                    zf* Yf, zd* S, zf* y, long long ys, const zf* V,
+                                    long long ldj, int nv, int nvmax, zd* partial, int nblk,
+                                    zd* out, long long ostride, const int* active,
+                                    hipStream_t st) {
+  return operator_dots_impl<float, float, float>(g, t, khat_f, c, precond, nb, v, vs, Xf, Yf, S, y,
+                                                 ys, V, ldj, nv, nvmax, partial, nblk, out,
+                                                 ostride, active, st);
 }
 
 __global__ void k_to_f32(const zd* __restrict__ in, zf* __restrict__ out, long long n) {
@@ -1378,12 +1390,12 @@ hipError_t launch_combine(const Geo& g, const Krylov& kv, const zf* V, long long
 // Fused Arnoldi steps: the second Gram-Schmidt update with the norm of the result, and the
 // normalisation with the Givens step and the preconditioner.
 // ---------------------------------------------------------------------------------
-// w_r -= sum_i h[r * hstride + i] V_i,r, then partial[r * gridDim.x + block] = block's
-// share of |w_r|^2.
-template <typename VT>
+// w_r -= sum_i h[r * hstride + i] V_i,r (in double precision, w stored in precision WT),
+// then partial[r * gridDim.x + block] = block's share of |w_r|^2.
+template <typename VT, typename WT>
 __global__ __launch_bounds__(256) void k_update_norm(const cx<VT>* __restrict__ V, long long ldj, int nv,
                                                      const zd* __restrict__ h, long long hstride,
-                                                     zd* __restrict__ wall, long long n,
+                                                     cx<WT>* __restrict__ wall, long long n,
                                                      double* __restrict__ partial,
                                                      const int* __restrict__ active) {
   __shared__ zd hs[256];
@@ -1392,14 +1404,14 @@ __global__ __launch_bounds__(256) void k_update_norm(const cx<VT>* __restrict__ 
   if (active && !active[r]) return;
   for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[r * hstride + i];
   __syncthreads();
-  zd* w = wall + r * n;
+  cx<WT>* w = wall + r * n;
   const cx<VT>* Vr = V + r * n;
   double nrm = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    zd a = w[i];
+    zd a = widen(w[i]);
     for (int vi = 0; vi < nv; ++vi) a = a - hs[vi] * widen(Vr[vi * ldj + i]);
-    w[i] = a;
+    w[i] = cvt<WT>(a);
     nrm += cabs2(a);
   }
   nrm = wave_sum(nrm);
@@ -1409,25 +1421,34 @@ __global__ __launch_bounds__(256) void k_update_norm(const cx<VT>* __restrict__ 
     partial[(long long)r * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-template <typename VT>
+template <typename VT, typename WT>
 static hipError_t update_norm_impl(const cx<VT>* V, long long ldj, int nv, const zd* h,
-                                   long long hstride, zd* w, long long n, int nb, double* partial,
-                                   int nblk, const int* active, hipStream_t st) {
-  hipLaunchKernelGGL((k_update_norm<VT>), dim3(nblk, nb), dim3(256), 0, st, V, ldj, nv, h, hstride,
-                     w, n, partial, active);
+                                   long long hstride, cx<WT>* w, long long n, int nb,
+                                   double* partial, int nblk, const int* active, hipStream_t st) {
+  hipLaunchKernelGGL((k_update_norm<VT, WT>), dim3(nblk, nb), dim3(256), 0, st, V, ldj, nv, h,
+                     hstride, w, n, partial, active);
   return hipGetLastError();
 }
 
 hipError_t launch_update_norm(const zd* V, long long ldj, int nv, const zd* h, long long hstride,
                               zd* w, long long n, int nb, double* partial, int nblk,
                               const int* active, hipStream_t st) {
-  return update_norm_impl<double>(V, ldj, nv, h, hstride, w, n, nb, partial, nblk, active, st);
+  return update_norm_impl<double, double>(V, ldj, nv, h, hstride, w, n, nb, partial, nblk, active,
+                                          st);
 }
 
 hipError_t launch_update_norm(const zf* V, long long ldj, int nv, const zd* h, long long hstride,
                               zd* w, long long n, int nb, double* partial, int nblk,
                               const int* active, hipStream_t st) {
-  return update_norm_impl<float>(V, ldj, nv, h, hstride, w, n, nb, partial, nblk, active, st);
+  return update_norm_impl<float, double>(V, ldj, nv, h, hstride, w, n, nb, partial, nblk, active,
+                                         st);
+}
+
+hipError_t launch_update_norm(const zf* V, long long ldj, int nv, const zd* h, long long hstride,
+                              zf* w, long long n, int nb, double* partial, int nblk,
+                              const int* active, hipStream_t st) {
+  return update_norm_impl<float, float>(V, ldj, nv, h, hstride, w, n, nb, partial, nblk, active,
+                                        st);
 }
 
 // Next basis vector: |w_r|^2 from the nparts partials of k_update_norm (nparts == 0: from
@@ -1436,10 +1457,10 @@ hipError_t launch_update_norm(const zf* V, long long ldj, int nv, const zd* h, l
 // in precision ZT.  Threads run over modes; vectors are
 // component-major.  Blocks read the active flag before block 0 may clear it; a rhs that
 // stops here never uses the vector written for it.
-template <typename VT, typename ZT>
+template <typename VT, typename ZT, typename WT>
 __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
                                                      const double* __restrict__ npart, int nparts,
-                                                     const zd* __restrict__ wall,
+                                                     const cx<WT>* __restrict__ wall,
                                                      cx<VT>* __restrict__ vall, long long vstride,
                                                      const zd* __restrict__ pinv_all,
                                                      long long pcs, cx<ZT>* __restrict__ zall) {
@@ -1469,7 +1490,7 @@ __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
   }
   const double sc = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
   const long long n = 3LL * g.NM;
-  const zd* w = wall + r * n;
+  const cx<WT>* w = wall + r * n;
   cx<VT>* v = vall + r * vstride;
   cx<ZT>* z = zall + r * n;
   const zd* __restrict__ pinv = pinv_all + r * pcs;
@@ -1478,7 +1499,7 @@ __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
     zd u[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const cx<VT> t = cvt<VT>(sc * w[c * g.NM + mn]);
+      const cx<VT> t = cvt<VT>(sc * widen(w[c * g.NM + mn]));
       v[c * g.NM + mn] = t;
       u[c] = widen(t);   // z from the stored (possibly rounded) basis vector
     }
@@ -1490,33 +1511,43 @@ __global__ __launch_bounds__(256) void k_next_vector(Geo g, Krylov kv, int j,
   }
 }
 
-template <typename VT, typename ZT>
+template <typename VT, typename ZT, typename WT>
 static hipError_t next_vector_impl(const Geo& g, const Krylov& kv, int j, const double* npart,
-                                   int nparts, const zd* w, cx<VT>* v, long long vstride,
+                                   int nparts, const cx<WT>* w, cx<VT>* v, long long vstride,
                                    const Cols& c, cx<ZT>* z, int nb, hipStream_t st) {
   int nblk = (g.NM + 255) / 256;
   if (nblk > 1024) nblk = 1024;
-  hipLaunchKernelGGL((k_next_vector<VT, ZT>), dim3(nblk, nb), dim3(256), 0, st, g, kv, j, npart,
-                     nparts, w, v, vstride, c.pinv, c.cs, z);
+  hipLaunchKernelGGL((k_next_vector<VT, ZT, WT>), dim3(nblk, nb), dim3(256), 0, st, g, kv, j,
+                     npart, nparts, w, v, vstride, c.pinv, c.cs, z);
   return hipGetLastError();
 }
 
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
                               int nparts, const zd* w, zd* v, long long vstride, const Cols& c,
                               zd* z, int nb, hipStream_t st) {
-  return next_vector_impl<double, double>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb, st);
+  return next_vector_impl<double, double, double>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb,
+                                                  st);
 }
 
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
                               int nparts, const zd* w, zf* v, long long vstride, const Cols& c,
                               zd* z, int nb, hipStream_t st) {
-  return next_vector_impl<float, double>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb, st);
+  return next_vector_impl<float, double, double>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb,
+                                                 st);
 }
 
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
                               int nparts, const zd* w, zf* v, long long vstride, const Cols& c,
                               zf* z, int nb, hipStream_t st) {
-  return next_vector_impl<float, float>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb, st);
+  return next_vector_impl<float, float, double>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb,
+                                                st);
+}
+
+hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
+                              int nparts, const zf* w, zf* v, long long vstride, const Cols& c,
+                              zf* z, int nb, hipStream_t st) {
+  return next_vector_impl<float, float, float>(g, kv, j, npart, nparts, w, v, vstride, c, z, nb,
+                                               st);
 }
 
 // ---------------------------------------------------------------------------------

@@ -42,6 +42,27 @@ def log(msg):
 
 METRIC = "cavity unknowns solved/s + p50/p99 latency, mixed vs FP64 at ≤1e-8 rel err"
 HBM_PEAK_GBS = 8000.0
+# published vector peaks of the chip (fp32 counts packed two-wide FMA; code without packed
+# math tops out at half of it, the fp64 figure)
+VECTOR_PEAK_TFLOPS = {"tbc_cols_f32": 157.3, "tbc_cols": 78.6}
+
+
+def fft_flops(n):
+    """Nominal arithmetic of one complex transform of length n (5 n log2 n)."""
+    import math
+    return 5.0 * n * math.log2(n)
+
+
+def tbc_cols_flops(info, nq1, bytes_per_launch, elem):
+    """Algorithmic flops of one column-pass launch: per column of the 3 families of every
+    right-hand side, the extension transform (length 2 nq1) in and out, the box transform
+    (length P1) forward and inverse, and the product with the spectrum (6 flops per entry).
+    The right-hand sides per launch come from the probe's algorithmic bytes, elem bytes per
+    entry times (2 x 3 nb (M+1) P2 [X in, Y out] + P1 P2 [spectrum])."""
+    P1, P2, M = int(info.P1), int(info.P2), int(info.M)
+    nb = (bytes_per_launch / elem - P1 * P2) / (6.0 * (M + 1) * P2)
+    per_column = 2 * fft_flops(2 * nq1) + 2 * fft_flops(P1) + 6.0 * P1
+    return 3.0 * nb * P2 * per_column
 
 
 def cpu_baseline(wl, gpu_fields, gpu_sigma, indices):
@@ -100,10 +121,11 @@ def sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, info=None):
     """HBM bytes per launch of `kernel` on `workload` from the committed hardware-counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None when
-    there is none or the kernel's sources changed since it was taken."""
+    there is none, the kernel's sources changed since it was taken, or this run's tuned
+    launch configuration (info: LDS budget, row passes in place) is not the measured one."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None, None
@@ -116,6 +138,12 @@ def measured_traffic(kernel, workload):
     rel = os.path.relpath(path, ROOT)
     if kv.get("source_sha256") != sources_sha256():
         return None, rel + " (stale: kernel sources changed since)"
+    if info is not None and "lds_budget" in kv:
+        run_cfg = (int(info.lds_budget), int(info.tbc_rows_in_place))
+        file_cfg = (int(kv["lds_budget"]), int(kv["tbc_rows_in_place"]))
+        if run_cfg != file_cfg:
+            return None, (rel + f" (measured at LDS budget {file_cfg[0]}, rows in place "
+                          f"{file_cfg[1]}; this run tuned {run_cfg[0]}, {run_cfg[1]})")
     return float(kv["traffic_bytes_per_launch"]), rel
 
 
@@ -437,8 +465,38 @@ def main() -> int:
             info, (launches, k_ms, k_bytes) = info_p, probe_res
 
     value = runs[head]["value"]
-    traffic, traffic_src = measured_traffic(args.probe, wl.name)
+    traffic, traffic_src = measured_traffic(args.probe, wl.name, info)
     achieved = (k_bytes / (k_ms * 1e-3)) / 1e9 if k_ms > 0 else None
+    avg_ms = k_ms / max(launches, 1)
+    bytes_per_launch = k_bytes / max(launches, 1)
+    roofline = {
+        "kernel": args.probe,
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
+        "traffic": traffic,
+        "traffic_source": traffic_src,
+        "launches": launches,
+        "avg_launch_ms": avg_ms,
+        "algorithmic_bytes_per_launch": bytes_per_launch,
+    }
+    if args.probe in VECTOR_PEAK_TFLOPS and k_ms > 0:
+        # the column pass runs its four transforms per column in LDS on one HBM round trip:
+        # about 25 flop per byte in single precision, above the vector ALU's ridge, so the
+        # vector ALU bounds it; the HBM figures stay beside it
+        elem = 8 if args.probe.endswith("_f32") else 16
+        flops = tbc_cols_flops(info, wl.cavity.tbc_oversample * wl.cavity.nx, bytes_per_launch,
+                               elem)
+        tflops = flops / (avg_ms * 1e-3) / 1e12
+        peak = VECTOR_PEAK_TFLOPS[args.probe]
+        roofline.update({
+            "bound": "alu", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
+            "frac": tflops / peak, "algorithmic_flops_per_launch": flops,
+            "hbm_achieved_gbs": achieved, "hbm_peak_gbs": HBM_PEAK_GBS,
+            "hbm_frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
+        })
     out = {
         "metric": METRIC,
         "value": value,
@@ -486,19 +544,7 @@ def main() -> int:
             "preconditioner": info.ms_preconditioner, "rhs_last": info.ms_rhs,
             "krylov_last": info.ms_krylov, "synthesis_last": info.ms_synthesis,
         },
-        "roofline": {
-            "kernel": args.probe,
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
-            "traffic": traffic,
-            "traffic_source": traffic_src,
-            "launches": launches,
-            "avg_launch_ms": k_ms / max(launches, 1),
-            "algorithmic_bytes_per_launch": k_bytes / max(launches, 1),
-        },
+        "roofline": roofline,
     }
     if "fp64" in fields_by and "mixed" in fields_by:
         a64, amx = fields_by["fp64"], fields_by["mixed"]

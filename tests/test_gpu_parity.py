@@ -132,6 +132,24 @@ def test_batch_matches_single(pair):
         assert float((fields[i] - single).abs().max()) <= 1e-13 * float(single.abs().max())
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_call_of_several_groups_matches_single(pair, precision):
+    """A call of several lockstep groups (5 incidences in groups of 2, the last one alone):
+    every field equals the field of the same incidence solved alone (the kernels do not
+    depend on the group), read on the caller's stream right after the call."""
+    wl, prob, gpu, ora = pair
+    plan = P.Plan.from_cavity(wl.cavity, batch=2, precision=precision, direct="never")
+    incs = [W.Incidence(0.1 + 0.15 * i, 0.3 * i, W.TM if i % 2 else W.TE) for i in range(5)]
+    fields = plan.solve_batch([i.theta for i in incs], [i.phi for i in incs],
+                              [i.pol for i in incs])
+    peaks = [float(f.abs().max()) for f in fields]
+    for i, inc in enumerate(incs):
+        single = plan.solve(inc.theta, inc.phi, inc.pol)
+        assert abs(peaks[i] - float(single.abs().max())) <= 1e-13 * peaks[i]
+        assert float((fields[i] - single).abs().max()) <= 1e-13 * float(single.abs().max())
+    plan.close()
+
+
 def test_mixed_precision_solve(pair):
     """Mixed precision (single-precision convolutions inside GMRES, double-precision
     residuals at every restart): the field and RCS against the double-precision oracle

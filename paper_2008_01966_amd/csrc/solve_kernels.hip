@@ -18,6 +18,12 @@ namespace cav {
 // issued before its LDS stores, so their latencies overlap.
 constexpr int kLoadBatch = 4;
 
+// Lengths of the transforms the compile-time kernel variants are built for (the host
+// dispatches them only for plans of exactly these radices): extension 8 x 8 x 8 = 2 L with
+// L = 256, box 5 x 5 x 5 x 5 = P.
+constexpr int kCtHalfExt = 256;
+constexpr int kCtBox = 625;
+
 // 2^lc interleaved transforms of plan p in LDS, in place in a (ip) or ping-pong between a
 // and b; returns the buffer holding the result.  CTLC > 0: the plan has the radices Rs and
 // lc == CTLC, both fixed at compile time (fft_ct, fft_ct_ip); ip then needs ct_ip_fits.
@@ -154,7 +160,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
   const int Cb = min(C, g.M + 1 - m0);
   const int f = fam_fixed >= 0 ? fam_fixed : bid.y;
   const int slot = fam_fixed >= 0 ? 0 : bid.y;
-  const int L = g.nq2, P = g.P2;
+  const int L = CTLC > 0 ? kCtHalfExt : g.nq2, P = CTLC > 0 ? kCtBox : g.P2;
   const DivBy div_p(P);
   // ping-pong: two buffers of P; in place: the extension transform's 2L, then the box's P
   cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw);
@@ -297,7 +303,7 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
   const int C = 1 << lc;
   const int k0 = bid.x << lc;
   const int Cb = min(C, g.P2 - k0);
-  const int L = g.nq1, P = g.P1;
+  const int L = CTLC > 0 ? kCtHalfExt : g.nq1, P = CTLC > 0 ? kCtBox : g.P1;
   // two ping-pong buffers of P (> 2L) entries per column
   cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* b = a + ((long long)P << lc);
@@ -418,7 +424,7 @@ __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2,
   const int C = 1 << lc;
   const int m0 = bid.x << lc;
   const int Cb = min(C, g.M + 1 - m0);
-  const int L = g.nq2, P = g.P2;
+  const int L = CTLC > 0 ? kCtHalfExt : g.nq2, P = CTLC > 0 ? kCtBox : g.P2;
   const DivBy div_p(P);
   cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* b = a + ((long long)P << lc);

@@ -1572,8 +1572,8 @@ hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const doubl
 // ---------------------------------------------------------------------------------
 constexpr int kSynthRhsPerBlock = 4;
 
-template <int MR>
-__global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int ip,
+template <int MR, int CTLC = 0>
+__global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc_arg, int ip,
                                                     const zd* __restrict__ pi_d,
                                                     const zd* __restrict__ theta_d,
                                                     const zd* __restrict__ pi_n,
@@ -1587,6 +1587,7 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int
   // transform of the paired extension, q = 1 sums E3 (sine along y)
   const int jj = bid.y >> 1, q = bid.y & 1;
   const int j = j0 + jj;
+  const int lc = CTLC > 0 ? CTLC : lc_arg;
   const int C = 1 << lc;
   const int m0 = bid.x << lc;
   const int Cb = min(C, g.M + 1 - m0);
@@ -1659,7 +1660,8 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int
       }
     }
     __syncthreads();
-    zd* rr = lds_fft<double, false, MR, 0>(a, b, CtRadices<>{}, out2.p, out2.tw, tid, nt, lc, ip);
+    zd* rr = lds_fft<double, false, MR, CTLC>(a, b, CtRadices<8, 8, 8>{}, out2.p, out2.tw, tid,
+                                              nt, lc, ip);
     zd* dst = tbuf + ((((long long)r * 3 + (q == 0 ? 0 : 2)) * jn + jj) * (g.M + 1) + m0) *
                          (g.ny + 1);
     for (int w = tid; w < (L + 1) * Cb; w += nt) {
@@ -1681,8 +1683,9 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc, int
 // Columns: blockIdx.y = 2 jj + q (q = 0: E1, cosine along x, with E2, sine along x, in
 // one transform; q = 1: E3, sine along x), blockIdx.z = right-hand side r; field r at
 // eout + r es.
-template <int MR>
-__global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int ip, int j0, int jn,
+template <int MR, int CTLC = 0>
+__global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc_arg, int ip, int j0,
+                                                    int jn,
                                                     const zd* __restrict__ tbuf,
                                                     zd* __restrict__ eout, long long es) {
   CAV_DYN_SMEM(smem_raw);
@@ -1690,6 +1693,7 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
   const BlockId bid = xcd_block();
   const int jj = bid.y >> 1, q = bid.y & 1, r = bid.z;
   const int j = j0 + jj;
+  const int lc = CTLC > 0 ? CTLC : lc_arg;
   const int C = 1 << lc;
   const int i0 = bid.x << lc;
   const int Cb = min(C, g.ny + 1 - i0);
@@ -1724,7 +1728,8 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc, int
     }
   }
   __syncthreads();
-  zd* rr = lds_fft<double, false, MR, 0>(a, b, CtRadices<>{}, out1.p, out1.tw, tid, nt, lc, ip);
+  zd* rr = lds_fft<double, false, MR, CTLC>(a, b, CtRadices<8, 8, 8>{}, out1.p, out1.tw, tid, nt,
+                                            lc, ip);
   const long long plane = (long long)(g.Nz + 1) * (g.ny + 1) * (g.nx + 1);   // one component
   zd* dst = eout + r * es + (q == 0 ? 0 : 2 * plane) +
             ((long long)j * (g.ny + 1) + i0) * (g.nx + 1);
@@ -1775,7 +1780,10 @@ hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const z
   const int rgroups = (nr + kSynthRhsPerBlock - 1) / kSynthRhsPerBlock;
   probe_begin(K_SYNTH_ROWS, st);
   const dim3 grs((g.M + 1 + (1 << sr.lc) - 1) >> sr.lc, 2 * jn, rgroups);
-  if (t.maxr <= 8)
+  if (plan_is<8, 8, 8>(t.out2.p) && sr.ip && sr.lc == 2)
+    hipLaunchKernelGGL((k_synth_rows<8, 2>), grs, dim3(256), sr.smem, st, g, t.out2, sr.lc, sr.ip,
+                       pi_d, theta_d, pi_n, xap, xs, nr, j0, jn, tbuf);
+  else if (t.maxr <= 8)
     hipLaunchKernelGGL(k_synth_rows<8>, grs, dim3(256), sr.smem, st, g, t.out2, sr.lc, sr.ip, pi_d,
                        theta_d, pi_n, xap, xs, nr, j0, jn, tbuf);
   else

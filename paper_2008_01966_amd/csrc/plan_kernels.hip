@@ -150,8 +150,57 @@ hipError_t launch_spectrum(const Geo& g, double R, double scale, int method, zd*
 //   (tangential-curl continuity with one-sided differences): pivot q alpha_j - (1 + q),
 //   b_{j+1} = (source - q b_j) / pivot.  With one step everywhere q = 1.
 // rho = alpha_Nz, T = b_Nz; profiles by back-substitution from the aperture (value 1).
-// The up-sweep stores alpha_j in the profile slot j; the down-sweep overwrites it.
+// The back-substitution needs the alphas (and b) in reverse order.  The up-sweep keeps
+// only the first value of every segment of kElimSeg levels (checkpoints, in the profile
+// slot of that level); the down-sweep recomputes a segment's values from its checkpoint
+// with the same per-level step, holds them in registers and walks them backwards, so each
+// profile entry is written once instead of written, read back and overwritten.
 // ---------------------------------------------------------------------------------
+constexpr int kElimSeg = 8;
+
+// E3 step at node j: alpha_{j+1} from alpha_j (piv: the pivot).
+__device__ inline zd elim_e3_step(const Layers& ly, int j, double mn2, zd al, zd* piv) {
+  const int code = ly.node_code[j];
+  if (code >= 0) {
+    const zd k2 = ly.kappa2[code];
+    const double h2 = ly.h[code] * ly.h[code];
+    *piv = mk(al.re - 2.0 + h2 * (k2.re - mn2), al.im + h2 * k2.im);
+    return cdiv(mk(-1.0, 0.0), *piv);
+  }
+  const int s = -code - 1;
+  const double q = ly.h[s + 1] / ly.h[s];
+  const zd r = ly.ratio[s];
+  const zd one_m = mk(1.0 - al.re, -al.im);
+  *piv = mk(1.0, 0.0) + one_m * (q * r);
+  return cdiv(mk(1.0, 0.0), *piv);
+}
+
+// E1/E2 step at node j: (alpha, b)_{j+1} from (alpha, b)_j; p3 = Pi3_j (read at interfaces
+// only, when has3).
+__device__ inline void elim_d_step(const Layers& ly, int j, double mn2, bool has3,
+                                   const zd* __restrict__ pi_n_j, zd* al, zd* bb, zd* piv) {
+  const int code = ly.node_code[j];
+  zd f = mk(0.0, 0.0);
+  double q = 1.0;
+  if (code >= 0) {
+    const zd k2 = ly.kappa2[code];
+    const double h2 = ly.h[code] * ly.h[code];
+    *piv = mk(al->re - 2.0 + h2 * (k2.re - mn2), al->im + h2 * k2.im);
+  } else {
+    const int s = -code - 1;
+    const double h_up = ly.h[s + 1];
+    q = h_up / ly.h[s];
+    *piv = mk(q * al->re - (1.0 + q), q * al->im);
+    if (has3) {
+      const zd r = ly.ratio[s];
+      f = h_up * (mk(1.0 - r.re, -r.im) * *pi_n_j);
+    }
+  }
+  const zd inv = cdiv(mk(1.0, 0.0), *piv);
+  *al = mk(-inv.re, -inv.im);
+  *bb = (f - q * *bb) * inv;
+}
+
 __global__ void k_elimination(Geo g, Layers ly, zd* __restrict__ rho_d, zd* __restrict__ Tout,
                               zd* __restrict__ rho_n, zd* __restrict__ pi_d,
                               zd* __restrict__ theta_d, zd* __restrict__ pi_n,
@@ -165,38 +214,39 @@ __global__ void k_elimination(Geo g, Layers ly, zd* __restrict__ rho_d, zd* __re
   const int Nz = g.Nz;
   const bool has3 = (m >= 1 && n >= 1);
   double pmin = 1e300;
+  constexpr int K = kElimSeg;
+  const int nseg = (Nz + K - 1) / K;   // segment s: alphas of levels s K + 1 .. (s + 1) K
 
   // ---- E3 column ----
   if (has3) {
-    zd al = mk(1.0, 0.0);
+    zd al = mk(1.0, 0.0);   // alpha_1
     pi_n[1 * NM + mn] = al;
     for (int j = 1; j < Nz; ++j) {
-      const int code = ly.node_code[j];
       zd piv;
-      if (code >= 0) {
-        const zd k2 = ly.kappa2[code];
-        const double h2 = ly.h[code] * ly.h[code];
-        piv = mk(al.re - 2.0 + h2 * (k2.re - mn2), al.im + h2 * k2.im);
-        al = cdiv(mk(-1.0, 0.0), piv);
-      } else {
-        const int s = -code - 1;
-        const double q = ly.h[s + 1] / ly.h[s];
-        const zd r = ly.ratio[s];
-        const zd one_m = mk(1.0 - al.re, -al.im);
-        piv = mk(1.0, 0.0) + one_m * (q * r);
-        al = cdiv(mk(1.0, 0.0), piv);
-      }
+      al = elim_e3_step(ly, j, mn2, al, &piv);
       pmin = fmin(pmin, sqrt(cabs2(piv)));
-      pi_n[(long long)(j + 1) * NM + mn] = al;
+      if (j % K == 0) pi_n[(long long)(j + 1) * NM + mn] = al;   // checkpoint alpha_{j+1}
     }
     rho_n[mn] = al;
     zd cur = mk(1.0, 0.0);
-    for (int j = Nz; j >= 1; --j) {
-      zd aj = pi_n[(long long)j * NM + mn];
-      pi_n[(long long)j * NM + mn] = cur;
-      const int code = ly.node_code[j];
-      if (code < 0) aj = aj * ly.ratio[-code - 1];
-      cur = aj * cur;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+      const int j0 = sg * K + 1, cnt = min(K, Nz - j0 + 1);
+      zd A[K];
+      A[0] = pi_n[(long long)j0 * NM + mn];
+#pragma unroll
+      for (int t = 1; t < K; ++t) {
+        zd piv;
+        if (t < cnt) A[t] = elim_e3_step(ly, j0 + t - 1, mn2, A[t - 1], &piv);
+      }
+#pragma unroll
+      for (int t = K - 1; t >= 0; --t) {
+        if (t >= cnt) continue;
+        const int j = j0 + t;
+        pi_n[(long long)j * NM + mn] = cur;
+        const int code = ly.node_code[j];
+        const zd aj = code < 0 ? A[t] * ly.ratio[-code - 1] : A[t];
+        cur = aj * cur;
+      }
     }
     pi_n[mn] = cur;
   } else {
@@ -205,48 +255,48 @@ __global__ void k_elimination(Geo g, Layers ly, zd* __restrict__ rho_d, zd* __re
   }
 
   // ---- E1/E2 column ----
-  zd al = mk(0.0, 0.0), bb = mk(0.0, 0.0);
+  zd al = mk(0.0, 0.0), bb = mk(0.0, 0.0);   // alpha_1, b_1
   pi_d[1 * NM + mn] = al;
   if (ly.layered) theta_d[1 * NM + mn] = bb;
   for (int j = 1; j < Nz; ++j) {
-    const int code = ly.node_code[j];
-    zd piv, f = mk(0.0, 0.0);
-    double q = 1.0;
-    if (code >= 0) {
-      const zd k2 = ly.kappa2[code];
-      const double h2 = ly.h[code] * ly.h[code];
-      piv = mk(al.re - 2.0 + h2 * (k2.re - mn2), al.im + h2 * k2.im);
-    } else {
-      const int s = -code - 1;
-      const double h_up = ly.h[s + 1];
-      q = h_up / ly.h[s];
-      piv = mk(q * al.re - (1.0 + q), q * al.im);
-      if (has3) {
-        const zd r = ly.ratio[s];
-        const zd p3 = pi_n[(long long)j * NM + mn];
-        f = h_up * (mk(1.0 - r.re, -r.im) * p3);
-      }
-    }
+    zd piv;
+    elim_d_step(ly, j, mn2, has3, pi_n + (long long)j * NM + mn, &al, &bb, &piv);
     if (mn != 0) pmin = fmin(pmin, sqrt(cabs2(piv)));
-    const zd inv = cdiv(mk(1.0, 0.0), piv);
-    al = mk(-inv.re, -inv.im);
-    bb = (f - q * bb) * inv;
-    pi_d[(long long)(j + 1) * NM + mn] = al;
-    if (ly.layered) theta_d[(long long)(j + 1) * NM + mn] = bb;
+    if (j % K == 0) {   // checkpoint (alpha, b)_{j+1}
+      pi_d[(long long)(j + 1) * NM + mn] = al;
+      if (ly.layered) theta_d[(long long)(j + 1) * NM + mn] = bb;
+    }
   }
   rho_d[mn] = al;
   Tout[mn] = has3 ? bb : mk(0.0, 0.0);
   zd cp = mk(1.0, 0.0), ct = mk(0.0, 0.0);
-  for (int j = Nz; j >= 1; --j) {
-    const zd aj = pi_d[(long long)j * NM + mn];
-    pi_d[(long long)j * NM + mn] = cp;
-    zd bj = mk(0.0, 0.0);
-    if (ly.layered) {
-      bj = theta_d[(long long)j * NM + mn];
-      theta_d[(long long)j * NM + mn] = has3 ? ct : mk(0.0, 0.0);
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int j0 = sg * K + 1, cnt = min(K, Nz - j0 + 1);
+    zd A[K], B[K];
+    A[0] = pi_d[(long long)j0 * NM + mn];
+    B[0] = ly.layered ? theta_d[(long long)j0 * NM + mn] : mk(0.0, 0.0);
+#pragma unroll
+    for (int t = 1; t < K; ++t) {
+      if (t >= cnt) continue;
+      zd a = A[t - 1], b = B[t - 1], piv;
+      elim_d_step(ly, j0 + t - 1, mn2, has3, pi_n + (long long)(j0 + t - 1) * NM + mn, &a, &b,
+                  &piv);
+      A[t] = a;
+      B[t] = b;
     }
-    ct = aj * ct + bj;
-    cp = aj * cp;
+#pragma unroll
+    for (int t = K - 1; t >= 0; --t) {
+      if (t >= cnt) continue;
+      const int j = j0 + t;
+      pi_d[(long long)j * NM + mn] = cp;
+      zd bj = mk(0.0, 0.0);
+      if (ly.layered) {
+        bj = B[t];
+        theta_d[(long long)j * NM + mn] = has3 ? ct : mk(0.0, 0.0);
+      }
+      ct = A[t] * ct + bj;
+      cp = A[t] * cp;
+    }
   }
   pi_d[mn] = cp;
   if (ly.layered) theta_d[mn] = mk(0.0, 0.0);

@@ -556,8 +556,10 @@ int autotune_lds(cavity_plan p) {
       return CAVITY_OK;
     }
   }
-  // timed with two right-hand sides in flight (the smallest lockstep group of a batch)
-  const int nbt = std::min(2, p->opts.batch);
+  // timed with up to 8 right-hand sides in flight: with 2 the candidates were within the
+  // timing noise of each other, and a choice that won there by a few per cent could lose by
+  // a tenth at the 32 of a large batch (20 KB two-buffer rows against the default)
+  const int nbt = std::min(8, p->opts.batch);
   int s = ensure_work(p, nbt);
   if (s) return s;
   const long long n = p->nvec();

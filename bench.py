@@ -139,7 +139,9 @@ def measured_traffic(kernel, workload, info=None):
     if kv.get("source_sha256") != sources_sha256():
         return None, rel + " (stale: kernel sources changed since)"
     if info is not None and "lds_budget" in kv:
-        run_cfg = (int(info.lds_budget), int(info.tbc_rows_in_place))
+        # lds_budget 0: the library's default, 40000 bytes or CAVITY_LDS_BUDGET
+        lds = int(info.lds_budget) or int(os.environ.get("CAVITY_LDS_BUDGET", "40000"))
+        run_cfg = (lds, int(info.tbc_rows_in_place))
         file_cfg = (int(kv["lds_budget"]), int(kv["tbc_rows_in_place"]))
         if run_cfg != file_cfg:
             return None, (rel + f" (measured at LDS budget {file_cfg[0]}, rows in place "

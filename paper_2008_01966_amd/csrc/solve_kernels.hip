@@ -636,9 +636,11 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
       tbc_shape(t.ext2.p, t.box2.p, g.nq2, g.P2, (int)tb, g.M + 1, g.lds_budget, g.rows_ip);
   const int gr = (g.M + 1 + (1 << sr.lc) - 1) >> sr.lc;
   // transforms fixed at compile time for the extension 8 x 8 x 8 and box 5 x 5 x 5 x 5 plans
-  // (the in-place form, which tbc_shape allows only when every stage fits the block, exists
-  // for 2^1 transforms per block)
-  const bool ct_rows = plan_is<8, 8, 8>(t.ext2.p) && plan_is<5, 5, 5, 5>(t.box2.p);
+  // of the radix-8 build (CAVITY_FFT_MAXR=16 keeps the generic kernels); the in-place form,
+  // which tbc_shape allows only when every stage fits the block, exists for 2^1 transforms
+  // per block
+  const bool ct_rows = t.maxr <= kSmallRadix && plan_is<8, 8, 8>(t.ext2.p) &&
+                       plan_is<5, 5, 5, 5>(t.box2.p);
   probe_begin(id_fwd, st);
   if (ct_rows && sr.lc == 2 && !sr.ip)
     hipLaunchKernelGGL((k_tbc_rows_fwd<T, 8, 2, VI>), dim3(gr, nf, nb), dim3(256), sr.smem, st, g,
@@ -664,7 +666,8 @@ static hipError_t tbc_passes(const Geo& g, const Trig& t, const cx<T>* khat, con
       tbc_shape(t.ext1.p, t.box1.p, g.nq1, g.P1, (int)tb, g.P2, g.lds_budget, false);
   probe_begin(id_cols, st);
   const dim3 gc((g.P2 + (1 << sc.lc) - 1) >> sc.lc, nf, nb);
-  const bool ct = plan_is<8, 8, 8>(t.ext1.p) && plan_is<5, 5, 5, 5>(t.box1.p);
+  const bool ct = t.maxr <= kSmallRadix && plan_is<8, 8, 8>(t.ext1.p) &&
+                  plan_is<5, 5, 5, 5>(t.box1.p);
   if (ct && sc.lc == 2)
     hipLaunchKernelGGL((k_tbc_cols<T, 8, 2>), gc, dim3(256), sc.smem, st, g, t.ext1, t.box1, khat,
                        fam_fixed, sc.lc, X, Y, active);
@@ -1780,7 +1783,7 @@ hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const z
   const int rgroups = (nr + kSynthRhsPerBlock - 1) / kSynthRhsPerBlock;
   probe_begin(K_SYNTH_ROWS, st);
   const dim3 grs((g.M + 1 + (1 << sr.lc) - 1) >> sr.lc, 2 * jn, rgroups);
-  if (plan_is<8, 8, 8>(t.out2.p) && sr.ip && sr.lc == 2)
+  if (t.maxr <= kSmallRadix && plan_is<8, 8, 8>(t.out2.p) && sr.ip && sr.lc == 2)
     hipLaunchKernelGGL((k_synth_rows<8, 2>), grs, dim3(256), sr.smem, st, g, t.out2, sr.lc, sr.ip,
                        pi_d, theta_d, pi_n, xap, xs, nr, j0, jn, tbuf);
   else if (t.maxr <= 8)

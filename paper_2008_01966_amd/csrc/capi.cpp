@@ -592,8 +592,8 @@ int autotune_lds(cavity_plan p) {
     }
   }
   // the default (40000 bytes, in place) stays unless a candidate beats it by 3 %: candidates
-  // closer than that are within the timing noise at two right-hand sides, and the choice
-  // then no longer flips between runs of the same workload
+  // closer than that are within the timing noise of these short runs, and the choice then
+  // no longer flips between runs of the same workload
   constexpr int kDefault = 4;
   int best = kDefault;
   for (int ci = 0; ci < kCand; ++ci)

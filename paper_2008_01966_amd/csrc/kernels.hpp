@@ -158,7 +158,7 @@ hipError_t launch_operator(const Geo& g, const Trig& t, const zd* khat, const Co
                            const int* active, hipStream_t st);
 // The same operator with the three single-layer convolutions in single precision
 // (spectrum khat_f, workspaces Xf, Yf of the same element count as X, Y; S holds the TBC
-// results in single precision); the vectors v, y and the local terms stay double.
+// results in single precision); y and the local terms stay double.
 hipError_t launch_operator_f32(const Geo& g, const Trig& t, const zf* khat_f, const Cols& c,
                                int precond, int nb, const zd* v, long long vs, zf* Xf, zf* Yf,
                                zd* S, zd* y,
@@ -243,8 +243,8 @@ hipError_t launch_update_norm(const zf* V, long long ldj, int nv, const zd* h, l
                               zf* w, long long n, int nb, double* npart, int nblk,
                               const int* active, hipStream_t st);
 // |w_r|^2 (from nparts partials, or kv.nrm2 when nparts == 0), Givens step of column j
-// (j >= 0), v_r = w_r / |w_r| (v_r at v + r vstride) and z_r = P^{-1} v_r (z_r at z + r n,
-// stored in double or, last overload, single precision).
+// (j >= 0), v_r = w_r / |w_r| (v_r at v + r vstride) and z_r = P^{-1} v_r (z_r at z + r n),
+// each of w, v, z stored in double or single precision as the overload says.
 hipError_t launch_next_vector(const Geo& g, const Krylov& kv, int j, const double* npart,
                               int nparts, const zd* w, zd* v, long long vstride, const Cols& c,
                               zd* z, int nb, hipStream_t st);

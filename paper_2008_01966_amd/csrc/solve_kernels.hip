@@ -128,9 +128,10 @@ __device__ inline bool fam_ycos(int f) { return f != 0; }
 // (pos, c) at buf[(pos << lc) + c]; global loads and stores map consecutive lanes to
 // consecutive addresses, and blocks are renumbered so neighbouring strips share an XCD.
 // The last block of a grid may hold fewer live transforms (Cb); its other LDS columns
-// hold zeros and are never stored.  T is the precision of the workspaces X, Y and of the
-// transforms (double, or float for the mixed-precision inner solve); the aperture vectors
-// in and out stay double.
+// hold zeros and are never stored.  T is the precision of the workspaces X, Y, of the
+// transforms and of the TBC results S (double, or float for the mixed-precision inner
+// solve); the input vector is stored in double or single precision (VI) and read into
+// double.
 
 // Pass 1: rows m0 .. m0+Cb-1 of one family.  fam_fixed >= 0: `v` is the coefficient grid
 // of that family (inspection path); otherwise `v` is a padded aperture vector, optionally
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(256) void k_tbc_cols(Geo g, Fft ext1, Fft box1,
                               ColumnStore<T>{Y + k0, g.ldx, g.M + 1, Cb, xcos, hq});
 }
 
-// Pass 3: rows m0 .. m0+Cb-1 backward; writes S[slot][mn] in double.
+// Pass 3: rows m0 .. m0+Cb-1 backward; writes S[slot][mn] in precision T.
 template <typename T, int MR, int CTLC = 0>
 __global__ __launch_bounds__(256) void k_tbc_rows_bwd(Geo g, Fft ext2, Fft box2, int fam_fixed,
                                                       int lc_arg, int ip,
@@ -527,7 +528,9 @@ __global__ void k_operator_epilogue(Geo g, Cols cl, int precond, const cx<VI>* _
 // above, and from the same registers the per-block partial sums of conj(V_t) y over the
 // nv <= G basis vectors (V_t of right-hand side rhs at V + t ldj + rhs 3 NM) in k_dots'
 // layout, partial[(rhs nvmax + t) gridDim.x + block].  Blocks stride over the modes; each
-// thread sums its modes in order, the three components of a mode in order.
+// thread sums its modes in order, the three components of a mode in order.  S and the
+// basis are in the operator's precision VT, v is stored in VI and y in WT; the sums run
+// in double from y before it is rounded to WT.
 template <typename VT, int G, typename VI, typename WT>
 __global__ __launch_bounds__(256) void k_epilogue_dots(Geo g, Cols cl, int precond,
                                                        const cx<VI>* __restrict__ vall,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -387,12 +388,23 @@ void resolve_timers(cavity_plan p) {
   }
 }
 
-void twiddle_table(int n, zd* out) {
-  const long double two_pi = 6.283185307179586476925286766559L;
-  for (int t = 0; t < n; ++t) {
-    const long double ang = -two_pi * (long double)t / (long double)n;
-    out[t] = cav::mk((double)cosl(ang), (double)sinl(ang));
+// exp(-2 pi i t / n), t = 0 .. n-1, from extended-precision cos and sin.  Kept per length
+// for the process: at n = 512 and 625 the extended-precision functions took about 0.8 ms
+// per plan, most of a plan's set-up on a cached aperture.
+const std::vector<zd>& twiddle_table(int n) {
+  static std::mutex mu;
+  static std::map<int, std::vector<zd>> tables;
+  std::lock_guard<std::mutex> lk(mu);
+  std::vector<zd>& out = tables[n];
+  if ((int)out.size() != n) {
+    out.resize(n);
+    const long double two_pi = 6.283185307179586476925286766559L;
+    for (int t = 0; t < n; ++t) {
+      const long double ang = -two_pi * (long double)t / (long double)n;
+      out[t] = cav::mk((double)cosl(ang), (double)sinl(ang));
+    }
   }
+  return out;
 }
 
 size_t plan_bytes(const cav::Geo& g, bool layered, int chunk, int nlayers, int* twn) {
@@ -1562,6 +1574,16 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
                        cavity_plan* out) {
   if (!out) return fail(CAVITY_EINVAL, "NULL plan output");
   *out = nullptr;
+  // CAVITY_TRACE: host time of the plan's set-up steps on stderr
+  static const bool trace = std::getenv("CAVITY_TRACE") != nullptr;
+  auto t_prev = std::chrono::steady_clock::now();
+  auto lap = [&](const char* what) {
+    if (!trace) return;
+    const auto t = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[plan] %s %.1f us\n", what,
+                 std::chrono::duration<double, std::micro>(t - t_prev).count());
+    t_prev = t;
+  };
   PlanSpec ps;
   {
     const int st0 = prepare_plan(a, b, c, Nx, Ny, Nz, eps, k, opts, &ps);
@@ -1587,6 +1609,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     return fail(CAVITY_ENOMEM, "plan needs " + std::to_string(need) + " bytes, budget " +
                                    std::to_string(budget));
 
+  lap("prepare + memory info");
   cavity_plan p = new cavity_plan_s();
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
@@ -1610,6 +1633,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
       hipHostMalloc((void**)&p->hratio, (size_t)(o.restart + 2) * 64 * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void**)&p->hn, 64 * sizeof(double)) != hipSuccess)
     return bail(fail(CAVITY_EDEVICE, "hipHostMalloc failed"));
+  lap("events + pinned flags");
 
   // one arena for all plan data
   const long long NM = g.NM;
@@ -1646,6 +1670,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     p->plan_arena = {base, L.bytes};
     L.bind(base);
   }
+  lap("arena");
 
   // host tables: twiddles, node codes, k^2 eps per layer, eps ratios per interface
   std::vector<zd> tw(twn);
@@ -1655,11 +1680,9 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     cav::Fft* dst[6] = {&p->trig.ext1, &p->trig.ext2, &p->trig.box1, &p->trig.box2,
                         &p->trig.out1, &p->trig.out2};
     p->trig.maxr = 1;
-    std::vector<zd> table;
     for (int i = 0; i < 6; ++i) {
       dst[i]->p = make_fft_plan(fft_len[i]);
-      table.resize(fft_len[i]);
-      twiddle_table(fft_len[i], table.data());
+      const std::vector<zd>& table = twiddle_table(fft_len[i]);
       cav::fill_stage_twiddles(dst[i]->p, table.data(), tw.data() + off);
       dst[i]->tw = p->twiddles + off;
       dst[i]->twf = p->twiddles_f + off;
@@ -1691,6 +1714,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
       kap[l] = cav::mk(k2.real(), k2.imag());
     }
   }
+  lap("host tables");
   auto chk = [&](hipError_t e, const char* what) {
     if (e != hipSuccess) {
       fail(CAVITY_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -1711,6 +1735,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
       !chk(hipMemcpyAsync(p->hl, ps.lh.data(), ps.lh.size() * sizeof(double),
                           hipMemcpyHostToDevice, p->st), "layer upload"))
     return bail(CAVITY_EDEVICE);
+  lap("uploads");
 
   // spectrum (scaled for the unnormalised inverse FFT and the grid cell)
   const double scale = 1.0 / (g.hq1 * g.hq2 * (double)g.P1 * (double)g.P2);
@@ -1750,6 +1775,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
            "preconditioner"))
     return bail(CAVITY_EDEVICE);
   if ((st = mark(p, 2, true))) return bail(st);
+  lap("launches");
   if (!chk(cav::launch_min(p->pivmin, NM, p->dmin, p->st), "pivot minimum") ||
       !chk(hipMemcpyAsync(p->hn, p->dmin, sizeof(double), hipMemcpyDeviceToHost, p->st),
            "pivot copy") ||
@@ -1758,8 +1784,10 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   p->info.min_pivot = p->hn[0];
   if (!(p->info.min_pivot > 1e-13))
     return bail(fail(CAVITY_ERESONANT, "z-elimination pivot below 1e-13"));
+  lap("device work + sync");
   p->info.tbc_rows_in_place = p->g.rows_ip;
   if ((st = autotune_lds(p))) return bail(st);
+  lap("tuning");
   // CAVITY_TBC_ROWS_IP=0 or 1 fixes the form of the TBC row passes (after any tuning)
   if (const char* e = std::getenv("CAVITY_TBC_ROWS_IP")) {
     p->g.rows_ip = std::atoi(e) != 0 ? 1 : 0;

@@ -209,6 +209,67 @@ void arena_release(void* ptr, size_t bytes) {
   for (auto& b : drop) (void)hipFree(b.ptr);
 }
 
+// ---- events and pinned host buffers: process-wide free lists -----------------------
+// A served request creates a plan and later drops it; the plan's events (phase timers, one
+// per Arnoldi step for the convergence polls) and its pinned flag buffers come from these
+// lists, so creating plans repeatedly does not pay hipEventCreate and hipHostMalloc
+// (about 0.1 ms per plan together).  Returned only when no work on them is pending.
+std::mutex g_pool_mu;
+struct PooledEvent {
+  hipEvent_t ev;
+  int device;
+  bool timing;
+};
+std::vector<PooledEvent> g_events;
+struct PooledPinned {
+  void* ptr;
+  size_t bytes;
+};
+std::vector<PooledPinned> g_pinned;
+
+hipError_t event_get(hipEvent_t* out, bool timing) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (size_t i = g_events.size(); i-- > 0;)
+      if (g_events[i].device == dev && g_events[i].timing == timing) {
+        *out = g_events[i].ev;
+        g_events.erase(g_events.begin() + i);
+        return hipSuccess;
+      }
+  }
+  return timing ? hipEventCreate(out) : hipEventCreateWithFlags(out, hipEventDisableTiming);
+}
+
+void event_put(hipEvent_t ev, bool timing) {
+  if (!ev) return;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_events.push_back({ev, dev, timing});
+}
+
+hipError_t pinned_get(size_t bytes, void** out) {
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (size_t i = g_pinned.size(); i-- > 0;)
+      if (g_pinned[i].bytes == bytes) {
+        *out = g_pinned[i].ptr;
+        g_pinned.erase(g_pinned.begin() + i);
+        return hipSuccess;
+      }
+  }
+  return hipHostMalloc(out, bytes);
+}
+
+void pinned_put(void* ptr, size_t bytes) {
+  if (!ptr) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pinned.push_back({ptr, bytes});
+}
+
 // Two-phase layout: register every buffer, then bind them into one arena.
 struct Layout {
   struct Item {
@@ -338,6 +399,12 @@ int plan_set_stream(cavity_plan p, hipStream_t st) {
 
 namespace {
 
+// Sizes of a plan's pinned host buffers: per-step convergence flags and residual ratios for
+// up to 64 right-hand sides, and a few doubles for small read-backs.
+size_t flag_bytes(int restart) { return (size_t)(restart + 2) * 64 * sizeof(int); }
+size_t ratio_bytes(int restart) { return (size_t)(restart + 2) * 64 * sizeof(double); }
+size_t norm_bytes() { return 64 * sizeof(double); }
+
 void release(cavity_plan p) {
   if (!p) return;
   if (p->st) (void)hipStreamSynchronize(p->st);
@@ -349,13 +416,11 @@ void release(cavity_plan p) {
   arena_release(p->rcs_arena.ptr, p->rcs_arena.bytes);
   arena_release(p->spec_arena.ptr, p->spec_arena.bytes);
   arena_release(p->group_arena.ptr, p->group_arena.bytes);
-  if (p->hflags) (void)hipHostFree(p->hflags);
-  if (p->hn) (void)hipHostFree(p->hn);
-  if (p->hratio) (void)hipHostFree(p->hratio);
-  for (hipEvent_t e : p->ev)
-    if (e) (void)hipEventDestroy(e);
-  for (hipEvent_t e : p->poll_ev)
-    if (e) (void)hipEventDestroy(e);
+  pinned_put(p->hflags, flag_bytes(p->opts.restart));
+  pinned_put(p->hn, norm_bytes());
+  pinned_put(p->hratio, ratio_bytes(p->opts.restart));
+  for (hipEvent_t e : p->ev) event_put(e, true);
+  for (hipEvent_t e : p->poll_ev) event_put(e, false);
   for (auto& kv : p->step_graphs) (void)hipGraphExecDestroy(kv.second);
   if (p->cap_st) (void)hipStreamDestroy(p->cap_st);
   delete p;
@@ -826,7 +891,7 @@ int gmres_batch_t(cavity_plan p, int nb, zd* x, std::vector<double>* relres_out,
     const size_t old = p->poll_ev.size();
     p->poll_ev.resize(R + 1, nullptr);
     for (size_t i = old; i < p->poll_ev.size(); ++i)
-      HIPCHK(hipEventCreateWithFlags(&p->poll_ev[i], hipEventDisableTiming));
+      HIPCHK(event_get(&p->poll_ev[i], false));
   }
   int* hstat = p->hflags;   // pinned: [0, nb) active, [nb, 2 nb) iterations, then per step
   {
@@ -1628,10 +1693,10 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     return code;
   };
   for (auto& e : p->ev)
-    if (hipEventCreate(&e) != hipSuccess) return bail(fail(CAVITY_EDEVICE, "hipEventCreate failed"));
-  if (hipHostMalloc((void**)&p->hflags, (size_t)(o.restart + 2) * 64 * sizeof(int)) != hipSuccess ||
-      hipHostMalloc((void**)&p->hratio, (size_t)(o.restart + 2) * 64 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc((void**)&p->hn, 64 * sizeof(double)) != hipSuccess)
+    if (event_get(&e, true) != hipSuccess) return bail(fail(CAVITY_EDEVICE, "hipEventCreate failed"));
+  if (pinned_get(flag_bytes(o.restart), (void**)&p->hflags) != hipSuccess ||
+      pinned_get(ratio_bytes(o.restart), (void**)&p->hratio) != hipSuccess ||
+      pinned_get(norm_bytes(), (void**)&p->hn) != hipSuccess)
     return bail(fail(CAVITY_EDEVICE, "hipHostMalloc failed"));
   lap("events + pinned flags");
 

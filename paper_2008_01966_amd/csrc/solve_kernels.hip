@@ -1690,10 +1690,28 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc_arg,
 // one transform; q = 1: E3, sine along x), blockIdx.z = right-hand side r; field r at
 // eout + r es.
 template <int MR, int CTLC = 0>
+__device__ inline void synth_cols_body(Geo g, Fft out1, int lc_arg, int ip, int j0, int jn,
+                                       const zd* __restrict__ tbuf, zd* __restrict__ eout,
+                                       long long es);
+
+template <int MR>
 __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc_arg, int ip, int j0,
-                                                    int jn,
-                                                    const zd* __restrict__ tbuf,
+                                                    int jn, const zd* __restrict__ tbuf,
                                                     zd* __restrict__ eout, long long es) {
+  synth_cols_body<MR, 0>(g, out1, lc_arg, ip, j0, jn, tbuf, eout, es);
+}
+
+__global__ __launch_bounds__(256, 5) void k_synth_cols_ct(Geo g, Fft out1, int lc_arg, int ip,
+                                                          int j0, int jn,
+                                                          const zd* __restrict__ tbuf,
+                                                          zd* __restrict__ eout, long long es) {
+  synth_cols_body<8, 2>(g, out1, lc_arg, ip, j0, jn, tbuf, eout, es);
+}
+
+template <int MR, int CTLC>
+__device__ inline void synth_cols_body(Geo g, Fft out1, int lc_arg, int ip, int j0, int jn,
+                                       const zd* __restrict__ tbuf, zd* __restrict__ eout,
+                                       long long es) {
   CAV_DYN_SMEM(smem_raw);
   __shared__ zd c0s[64];
   const BlockId bid = xcd_block();
@@ -1801,7 +1819,10 @@ hipError_t launch_synthesis(const Geo& g, const Trig& t, const zd* pi_d, const z
   const SynthShape sc = synth_shape(t.out1.p, g.nx, g.ny + 1, synth_budget);
   probe_begin(K_SYNTH_COLS, st);
   const dim3 gcs((g.ny + 1 + (1 << sc.lc) - 1) >> sc.lc, 2 * jn, nr);
-  if (t.maxr <= 8)
+  if (t.maxr <= kSmallRadix && plan_is<8, 8, 8>(t.out1.p) && sc.ip && sc.lc == 2)
+    hipLaunchKernelGGL(k_synth_cols_ct, gcs, dim3(256), sc.smem, st, g, t.out1, sc.lc, sc.ip, j0,
+                       jn, tbuf, eout, es);
+  else if (t.maxr <= 8)
     hipLaunchKernelGGL(k_synth_cols<8>, gcs, dim3(256), sc.smem, st, g, t.out1, sc.lc, sc.ip, j0,
                        jn, tbuf, eout, es);
   else

@@ -1538,6 +1538,9 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   g.k = k;
   g.hq1 = a / g.nq1;
   g.hq2 = b / g.nq2;
+  g.pa = M_PI / a;
+  g.pb = M_PI / b;
+  g.iab = 1.0 / (a * b);
   g.rows_ip = 1;
   const double R = std::sqrt(2.0) * std::max(a, b);
   g.P1 = next_5smooth((long long)std::ceil((a + R) / g.hq1));

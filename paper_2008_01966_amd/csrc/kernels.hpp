@@ -19,6 +19,8 @@ struct Geo {
   int nx, ny;           // output grid intervals (Nx, Ny)
   double a, b, h, k;
   double hq1, hq2;
+  double pa, pb, iab;   // pi / a, pi / b, 1 / (a b): mode wavenumbers mu = m pa, nu = n pb
+                        // without a division per mode in the hot loops
   int lds_budget;       // LDS bytes per block the TBC FFT kernels size their batch for (0: default)
   int rows_ip;          // TBC row passes: 1 = in-place transforms allowed, 0 = ping-pong form
 };

@@ -186,10 +186,10 @@ __global__ __launch_bounds__(256) void k_tbc_rows_fwd(Geo g, Fft ext2, Fft box2,
         y[r] = pinv[(3 * r) * (long long)g.NM + mn] * z[0] +
                pinv[(3 * r + 1) * (long long)g.NM + mn] * z[1] +
                pinv[(3 * r + 2) * (long long)g.NM + mn] * z[2];
-      const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
+      const double mu = g.pa * m, nu = g.pb * n;
       val = f == 0 ? y[0] : (f == 1 ? y[1] : (nu * y[0] - mu * y[1]));
     } else {   // only the components the family uses (f is uniform over the block)
-      const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
+      const double mu = g.pa * m, nu = g.pb * n;
       val = f == 0 ? widen(v[mn])
                    : (f == 1 ? widen(v[g.NM + mn])
                              : (nu * widen(v[mn]) - mu * widen(v[g.NM + mn])));
@@ -483,7 +483,7 @@ __device__ inline void epilogue_mode(const Geo& g, const Cols& cl, int precond, 
   const zd* __restrict__ pinv = cl.pinv + co;
   const int m = mn / (g.N + 1), n = mn % (g.N + 1);
   const double h = cl.hs ? cl.hs[rhs] : g.h;
-  const double mu = M_PI * m / g.a, nu = M_PI * n / g.b, k2 = g.k * g.k;
+  const double mu = g.pa * m, nu = g.pb * n, k2 = g.k * g.k;
   zd z[3] = {widen(v[mn]), widen(v[g.NM + mn]), widen(v[2LL * g.NM + mn])};
   if (precond) {
     zd t[3];
@@ -496,8 +496,8 @@ __device__ inline void epilogue_mode(const Geo& g, const Cols& cl, int precond, 
   const zd scs = widen(S[mn]), ssc = widen(S[g.NM + mn]), scc = widen(S[2LL * g.NM + mn]);
   const zd rd = rho_d[mn] - mk(1.0, 0.0), rn = rho_n[mn] - mk(1.0, 0.0);
   const zd th = T[mn] + mk(h, 0.0);
-  const double hq = h / ((m == 0 ? 0.5 : 0.25) * g.a * g.b);
-  const double hc = h / ((n == 0 ? 0.5 : 0.25) * g.a * g.b);
+  const double hq = h * ((m == 0 ? 2.0 : 4.0) * g.iab);
+  const double hc = h * ((n == 0 ? 2.0 : 4.0) * g.iab);
   zd r1 = mk(0.0, 0.0), r2 = mk(0.0, 0.0), r3 = mk(0.0, 0.0);
   if (n >= 1) r1 = rd * z[0] + mu * (th * z[2]) + hq * ((2.0 * k2) * scs - (2.0 * nu) * scc);
   if (m >= 1) r2 = rd * z[1] + nu * (th * z[2]) + hc * ((2.0 * k2) * ssc + (2.0 * mu) * scc);
@@ -1643,8 +1643,8 @@ __global__ __launch_bounds__(256) void k_synth_rows(Geo g, Fft out2, int lc_arg,
           zd v1 = pv[u] * xa[u], v2 = pv[u] * xb[u];
           if (theta_d) {
             const zd t = tv[u] * x3[u];
-            v1 = v1 + (M_PI * (m0 + c) / g.a) * t;
-            v2 = v2 + (M_PI * n / g.b) * t;
+            v1 = v1 + (g.pa * (m0 + c)) * t;
+            v2 = v2 + (g.pb * n) * t;
           }
           store_pair_extension(a, L, n, v2, v1, lc, c);
           if (n == 0) c0s[c] = v2;

@@ -218,7 +218,7 @@ __global__ void k_spec_input(Geo g, const zd* __restrict__ pinv, int precond, in
     z[0] = y[0]; z[1] = y[1]; z[2] = y[2];
   }
   const int m = mn / (g.N + 1), n = mn - m * (g.N + 1);
-  const double mu = M_PI * m / g.a, nu = M_PI * n / g.b;
+  const double mu = g.pa * m, nu = g.pb * n;
   o[mn] = z[0];
   o[g.NM + mn] = z[1];
   o[2LL * g.NM + mn] = nu * z[0] - mu * z[1];

@@ -1701,6 +1701,9 @@ __global__ __launch_bounds__(256) void k_synth_cols(Geo g, Fft out1, int lc_arg,
   synth_cols_body<MR, 0>(g, out1, lc_arg, ip, j0, jn, tbuf, eout, es);
 }
 
+// The compile-time form (extension transform 8 x 8 x 8, 4 columns per block, in place) as a
+// kernel of its own, so that its bound of 5 waves per SIMD holds the fully unrolled stages
+// to about 66 registers (about 114 without the bound, and fewer waves per SIMD).
 __global__ __launch_bounds__(256, 5) void k_synth_cols_ct(Geo g, Fft out1, int lc_arg, int ip,
                                                           int j0, int jn,
                                                           const zd* __restrict__ tbuf,

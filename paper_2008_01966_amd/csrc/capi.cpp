@@ -51,13 +51,14 @@ int next_5smooth(long long n) {
   return (int)n;
 }
 
-// Stages of radix at most 8 when n factors that way in no more stages than with the larger
-// radices (the kernels compiled for radices up to 8 hold half the registers), else up to the
-// largest compiled radix.
+// Stages of radix at most 8 when n factors that way in at most one stage more than with the
+// larger radices (the kernels compiled for radices up to 8 hold half the registers, which
+// outweighs one more LDS round trip: 128 -> 8.4.4 instead of 16.8, 768 -> 8.8.4.3 instead
+// of 16.16.3), else up to the largest compiled radix.
 cav::FftPlan make_fft_plan(int n) {
   const cav::FftPlan small = cav::plan_fft(n, cav::kSmallRadix);
   const cav::FftPlan big = cav::plan_fft(n, cav::kMaxRadix);
-  return (small.nst > 0 && small.nst <= big.nst) || n <= 1 ? small : big;
+  return (small.nst > 0 && small.nst <= big.nst + 1) || n <= 1 ? small : big;
 }
 int plan_max_radix(const cav::FftPlan& p) {
   int r = 1;

@@ -51,14 +51,31 @@ int next_5smooth(long long n) {
   return (int)n;
 }
 
-// Stages of radix at most 8 when n factors that way in at most one stage more than with the
-// larger radices (the kernels compiled for radices up to 8 hold half the registers, which
-// outweighs one more LDS round trip: 128 -> 8.4.4 instead of 16.8, 768 -> 8.8.4.3 instead
-// of 16.16.3), else up to the largest compiled radix.
-cav::FftPlan make_fft_plan(int n) {
+// Stages of radix at most 8 (the kernels compiled for radices up to 8 hold about half the
+// registers) or up to the largest compiled radix, chosen for the six transform lengths of a
+// plan together: one length that needs the larger radices puts every kernel of the plan in
+// its larger form.  All six lengths take radices up to 8 when each factors that way in at
+// most one stage more than with the larger radices, the extra stage allowed on lengths up
+// to 1000 points (the registers saved outweigh one more LDS round trip there: cavities of
+// 2, 4 and 12 wavelengths at 32 nodes per wavelength, lengths 128-960, solve 3-11 % faster;
+// with 1024 and 1250 points the extra stage cost 3 %).  Otherwise each length takes
+// radices up to 8 only when they need no more stages than the larger ones.
+constexpr int kExtraStageMaxLen = 1000;
+bool small_radix_plans(const int* len, int count) {
+  for (int i = 0; i < count; ++i) {
+    if (len[i] <= 1) continue;
+    const cav::FftPlan small = cav::plan_fft(len[i], cav::kSmallRadix);
+    const cav::FftPlan big = cav::plan_fft(len[i], cav::kMaxRadix);
+    if (small.nst == 0 || small.nst > big.nst + (len[i] <= kExtraStageMaxLen ? 1 : 0))
+      return false;
+  }
+  return true;
+}
+cav::FftPlan make_fft_plan(int n, bool small_radices) {
   const cav::FftPlan small = cav::plan_fft(n, cav::kSmallRadix);
+  if (small_radices || n <= 1) return small;
   const cav::FftPlan big = cav::plan_fft(n, cav::kMaxRadix);
-  return (small.nst > 0 && small.nst <= big.nst + 1) || n <= 1 ? small : big;
+  return small.nst > 0 && small.nst <= big.nst ? small : big;
 }
 int plan_max_radix(const cav::FftPlan& p) {
   int r = 1;
@@ -1558,7 +1575,8 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   chunk = (int)std::min<long long>(chunk, (long long)(Nz + 1) * o.batch);
   const int fft_len[6] = {2 * g.nq1, 2 * g.nq2, g.P1, g.P2, 2 * g.nx, 2 * g.ny};
   int twn = 0;   // stage twiddle tables of the six transform lengths
-  for (int l : fft_len) twn += std::max(1, make_fft_plan(l).ntw);
+  const bool small_radices = small_radix_plans(fft_len, 6);
+  for (int l : fft_len) twn += std::max(1, make_fft_plan(l, small_radices).ntw);
   const int nb0 = 1;
   const size_t need = plan_bytes(g, layered, chunk, (int)lnz.size(), &twn) +
                       work_bytes(g, o.restart, nb0, dot_blocks(3LL * g.NM),
@@ -1749,8 +1767,9 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     cav::Fft* dst[6] = {&p->trig.ext1, &p->trig.ext2, &p->trig.box1, &p->trig.box2,
                         &p->trig.out1, &p->trig.out2};
     p->trig.maxr = 1;
+    const bool small_radices = small_radix_plans(fft_len, 6);
     for (int i = 0; i < 6; ++i) {
-      dst[i]->p = make_fft_plan(fft_len[i]);
+      dst[i]->p = make_fft_plan(fft_len[i], small_radices);
       const std::vector<zd>& table = twiddle_table(fft_len[i]);
       cav::fill_stage_twiddles(dst[i]->p, table.data(), tw.data() + off);
       dst[i]->tw = p->twiddles + off;

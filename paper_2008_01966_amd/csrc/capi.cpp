@@ -61,21 +61,35 @@ int next_5smooth(long long n) {
 // with 1024 and 1250 points the extra stage cost 3 %).  Otherwise each length takes
 // radices up to 8 only when they need no more stages than the larger ones.
 constexpr int kExtraStageMaxLen = 1000;
+// The planner's two factorisations of a length (radices up to 8, up to the largest
+// compiled radix), kept for the process: the searches take 1-8 us per length and every
+// plan creation asks for its six lengths several times.
+struct FftPlanPair {
+  cav::FftPlan small, big;
+};
+const FftPlanPair& fft_plans(int n) {
+  static std::mutex mu;
+  static std::map<int, FftPlanPair> cache;   // entries are never erased
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(n);
+  if (it == cache.end())
+    it = cache.emplace(n, FftPlanPair{cav::plan_fft(n, cav::kSmallRadix),
+                                      cav::plan_fft(n, cav::kMaxRadix)}).first;
+  return it->second;
+}
 bool small_radix_plans(const int* len, int count) {
   for (int i = 0; i < count; ++i) {
     if (len[i] <= 1) continue;
-    const cav::FftPlan small = cav::plan_fft(len[i], cav::kSmallRadix);
-    const cav::FftPlan big = cav::plan_fft(len[i], cav::kMaxRadix);
-    if (small.nst == 0 || small.nst > big.nst + (len[i] <= kExtraStageMaxLen ? 1 : 0))
+    const FftPlanPair& pp = fft_plans(len[i]);
+    if (pp.small.nst == 0 || pp.small.nst > pp.big.nst + (len[i] <= kExtraStageMaxLen ? 1 : 0))
       return false;
   }
   return true;
 }
 cav::FftPlan make_fft_plan(int n, bool small_radices) {
-  const cav::FftPlan small = cav::plan_fft(n, cav::kSmallRadix);
-  if (small_radices || n <= 1) return small;
-  const cav::FftPlan big = cav::plan_fft(n, cav::kMaxRadix);
-  return small.nst > 0 && small.nst <= big.nst ? small : big;
+  const FftPlanPair& pp = fft_plans(n);
+  if (small_radices || n <= 1) return pp.small;
+  return pp.small.nst > 0 && pp.small.nst <= pp.big.nst ? pp.small : pp.big;
 }
 int plan_max_radix(const cav::FftPlan& p) {
   int r = 1;
@@ -1502,7 +1516,7 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   // the sine/cosine transforms run as FFTs of length 2 s Nx, 2 s Ny, 2 Nx and 2 Ny, built
   // from radices with the prime factors 2, 3, 5, 7, 11 and 13
   for (long long len : {2LL * s * Nx, 2LL * s * Ny, 2LL * Nx, 2LL * Ny})
-    if (len > (1 << 20) || cav::plan_fft((int)len, cav::kMaxRadix).nst == 0)
+    if (len > (1 << 20) || fft_plans((int)len).big.nst == 0)
       return fail(CAVITY_ENOTIMPL, "transform length " + std::to_string(len) +
                                        " has a prime factor above 13 (Nx, Ny and s*Nx, s*Ny "
                                        "need prime factors 2, 3, 5, 7, 11, 13)");

@@ -354,9 +354,8 @@ struct cavity_plan_s {
   zd *pi_d = nullptr, *theta_d = nullptr, *pi_n = nullptr, *pinv = nullptr, *diag = nullptr;
   double *pivmin = nullptr, *dmin = nullptr;
   int* node_code = nullptr;
-  zd *kappa2 = nullptr, *ratio = nullptr, *twiddles = nullptr;
+  zd *kappa2 = nullptr, *ratio = nullptr;
   double* hl = nullptr;   // grid step per layer
-  cav::zf* twiddles_f = nullptr;
   cav::zf* khat_f = nullptr;   // single-precision spectrum for the mixed-precision inner solve
   double *pw1 = nullptr, *pw2 = nullptr;
   zd* ctmp = nullptr;
@@ -504,7 +503,54 @@ const std::vector<zd>& twiddle_table(int n) {
   return out;
 }
 
-size_t plan_bytes(const cav::Geo& g, bool layered, int chunk, int nlayers, int* twn) {
+// Stage twiddle tables (double and single precision) of a plan's six transforms, kept on
+// each device for the process and shared by the plans with the same transform lengths and
+// radix choice: a plan then neither fills nor uploads them.  An entry is complete on the
+// device before any other plan can find it.
+struct StageTwiddles {
+  const zd* tw = nullptr;
+  const cav::zf* twf = nullptr;
+};
+int stage_twiddles(int device, const int* len, bool small_radices, const cav::FftPlan* plans,
+                   int twn, hipStream_t st, StageTwiddles* out) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int, int, int, int, int>, StageTwiddles> cache;
+  const auto key = std::make_tuple(device, len[0], len[1], len[2], len[3], len[4], len[5],
+                                   small_radices ? 1 : 0);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    *out = it->second;
+    return CAVITY_OK;
+  }
+  std::vector<zd> tw(twn);
+  std::vector<cav::zf> twf(twn);
+  int off = 0;
+  for (int i = 0; i < 6; ++i) {
+    cav::fill_stage_twiddles(plans[i], twiddle_table(len[i]).data(), tw.data() + off);
+    off += std::max(1, plans[i].ntw);
+  }
+  for (int t = 0; t < twn; ++t) twf[t] = cav::cvt<float>(tw[t]);
+  zd* dtw = nullptr;
+  cav::zf* dtwf = nullptr;
+  if (hipMalloc(&dtw, (size_t)twn * sizeof(zd)) != hipSuccess ||
+      hipMalloc(&dtwf, (size_t)twn * sizeof(cav::zf)) != hipSuccess ||
+      hipMemcpyAsync(dtw, tw.data(), (size_t)twn * sizeof(zd), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(dtwf, twf.data(), (size_t)twn * sizeof(cav::zf), hipMemcpyHostToDevice,
+                     st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    if (dtw) (void)hipFree(dtw);
+    if (dtwf) (void)hipFree(dtwf);
+    return fail(CAVITY_EDEVICE, "stage twiddle tables: device allocation or upload failed");
+  }
+  const StageTwiddles e{dtw, dtwf};
+  cache.emplace(key, e);
+  *out = e;
+  return CAVITY_OK;
+}
+
+size_t plan_bytes(const cav::Geo& g, bool layered, int chunk, int nlayers) {
   Layout L;
   zd* z = nullptr;
   double* d = nullptr;
@@ -518,9 +564,7 @@ size_t plan_bytes(const cav::Geo& g, bool layered, int chunk, int nlayers, int* 
   L.add(&z, 9 * NM); L.add(&z, 3 * NM);
   L.add(&d, NM); L.add(&d, 1);
   L.add(&i, g.Nz + 1); L.add(&z, nlayers); L.add(&z, nlayers); L.add(&d, nlayers);
-  L.add(&z, *twn);
   cav::zf* zf1 = nullptr;
-  L.add(&zf1, *twn);
   L.add(&zf1, (size_t)g.P1 * g.P2);
   L.add(&d, (size_t)2 * (g.M + 1) * g.P1); L.add(&d, (size_t)2 * g.P2 * (g.N + 1));
   L.add(&z, (size_t)2 * g.P1 * (g.N + 1));
@@ -1588,11 +1632,11 @@ int prepare_plan(double a, double b, double c, int Nx, int Ny, int Nz, const cav
   int chunk = (int)std::max<size_t>(1, slab / per_level);
   chunk = (int)std::min<long long>(chunk, (long long)(Nz + 1) * o.batch);
   const int fft_len[6] = {2 * g.nq1, 2 * g.nq2, g.P1, g.P2, 2 * g.nx, 2 * g.ny};
-  int twn = 0;   // stage twiddle tables of the six transform lengths
+  int twn = 0;   // entries of the stage twiddle tables of the six transform lengths
   const bool small_radices = small_radix_plans(fft_len, 6);
   for (int l : fft_len) twn += std::max(1, make_fft_plan(l, small_radices).ntw);
   const int nb0 = 1;
-  const size_t need = plan_bytes(g, layered, chunk, (int)lnz.size(), &twn) +
+  const size_t need = plan_bytes(g, layered, chunk, (int)lnz.size()) +
                       work_bytes(g, o.restart, nb0, dot_blocks(3LL * g.NM),
                                  o.tbc_operator == CAVITY_TBC_SPEC) +
                       3ull * g.NM * sizeof(zd);
@@ -1754,8 +1798,6 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   L.add(&p->kappa2, lnz.size());
   L.add(&p->ratio, lnz.size());
   L.add(&p->hl, lnz.size());
-  L.add(&p->twiddles, twn);
-  L.add(&p->twiddles_f, twn);
   L.add(&p->khat_f, (size_t)g.P1 * g.P2);
   L.add(&p->pw1, (size_t)2 * (g.M + 1) * g.P1);
   L.add(&p->pw2, (size_t)2 * g.P2 * (g.N + 1));
@@ -1773,28 +1815,31 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
   }
   lap("arena");
 
-  // host tables: twiddles, node codes, k^2 eps per layer, eps ratios per interface
-  std::vector<zd> tw(twn);
-  std::vector<cav::zf> twf(twn);
+  // transform plans and their stage twiddles (shared device tables); host tables: node
+  // codes, k^2 eps per layer, eps ratios per interface
   {
-    int off = 0;
     cav::Fft* dst[6] = {&p->trig.ext1, &p->trig.ext2, &p->trig.box1, &p->trig.box2,
                         &p->trig.out1, &p->trig.out2};
+    cav::FftPlan plans[6];
     p->trig.maxr = 1;
     const bool small_radices = small_radix_plans(fft_len, 6);
     for (int i = 0; i < 6; ++i) {
-      dst[i]->p = make_fft_plan(fft_len[i], small_radices);
-      const std::vector<zd>& table = twiddle_table(fft_len[i]);
-      cav::fill_stage_twiddles(dst[i]->p, table.data(), tw.data() + off);
-      dst[i]->tw = p->twiddles + off;
-      dst[i]->twf = p->twiddles_f + off;
-      p->trig.maxr = std::max(p->trig.maxr, plan_max_radix(dst[i]->p));
-      off += std::max(1, dst[i]->p.ntw);
+      plans[i] = make_fft_plan(fft_len[i], small_radices);
+      p->trig.maxr = std::max(p->trig.maxr, plan_max_radix(plans[i]));
+    }
+    StageTwiddles stw;
+    if (const int s0 = stage_twiddles(p->device, fft_len, small_radices, plans, twn, p->st, &stw))
+      return bail(s0);
+    int off = 0;
+    for (int i = 0; i < 6; ++i) {
+      dst[i]->p = plans[i];
+      dst[i]->tw = stw.tw + off;
+      dst[i]->twf = stw.twf + off;
+      off += std::max(1, plans[i].ntw);
     }
     // CAVITY_FFT_MAXR=16: the same plans run by the kernels compiled for radices up to 16
     if (const char* e = std::getenv("CAVITY_FFT_MAXR"))
       if (std::atoi(e) == cav::kMaxRadix) p->trig.maxr = cav::kMaxRadix;
-    for (int t = 0; t < twn; ++t) twf[t] = cav::cvt<float>(tw[t]);
   }
   std::vector<int> code(Nz + 1, 0);
   std::vector<zd> kap(lnz.size()), rat(lnz.size(), cav::mk(1.0, 0.0));
@@ -1824,11 +1869,7 @@ int cavity_plan_create(double a, double b, double c, int Nx, int Ny, int Nz,
     }
     return true;
   };
-  if (!chk(hipMemcpyAsync(p->twiddles, tw.data(), tw.size() * sizeof(zd), hipMemcpyHostToDevice,
-                          p->st), "twiddle upload") ||
-      !chk(hipMemcpyAsync(p->twiddles_f, twf.data(), twf.size() * sizeof(cav::zf),
-                          hipMemcpyHostToDevice, p->st), "twiddle upload") ||
-      !chk(hipMemcpyAsync(p->node_code, code.data(), code.size() * sizeof(int),
+  if (!chk(hipMemcpyAsync(p->node_code, code.data(), code.size() * sizeof(int),
                           hipMemcpyHostToDevice, p->st), "layer upload") ||
       !chk(hipMemcpyAsync(p->kappa2, kap.data(), kap.size() * sizeof(zd), hipMemcpyHostToDevice,
                           p->st), "layer upload") ||

@@ -378,6 +378,14 @@ int cavity_debug_operator(cavity_plan plan, const cavity_c128* in, cavity_c128* 
 /* Right-hand side grids g1, g2 of one incidence. */
 int cavity_debug_rhs(cavity_plan plan, double theta, double phi, int pol, cavity_c128* g1,
                      cavity_c128* g2);
+/* Stage radices the transform planner gives a plan with the six transform lengths len[6]
+ * (the extension transforms 2 s Nx and 2 s Ny, the box transforms P1 and P2, the output
+ * transforms 2 Nx and 2 Ny; Section 5 and the node sums of EInter are evaluated by these
+ * FFTs).  radices: caller-owned host array [6][20], each length's stage radices in
+ * execution order, unused entries 0; nst: [6] stage counts, 0 for a length that has no
+ * factorisation into the supported radices.  Host only: no device is touched.  Errors:
+ * CAVITY_EINVAL (NULL argument, a length below 1 or above 2^20). */
+int cavity_debug_fft_plans(const int* len, int* radices, int* nst);
 
 #ifdef __cplusplus
 }

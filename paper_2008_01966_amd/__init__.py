@@ -94,7 +94,8 @@ EXPORTS = [
     "cavity_server_wait", "cavity_server_release", "cavity_server_now_ms",
     "cavity_server_destroy", "cavity_debug_columns",
     "cavity_debug_profiles", "cavity_debug_spectrum", "cavity_debug_tbc",
-    "cavity_debug_operator", "cavity_debug_rhs", "cavity_probe_kernel", "cavity_probe_read",
+    "cavity_debug_operator", "cavity_debug_rhs", "cavity_debug_fft_plans", "cavity_probe_kernel",
+    "cavity_probe_read",
 ]
 _NOT_INT = ("cavity_plan_destroy", "cavity_status_string", "cavity_last_error",
             "cavity_server_destroy", "cavity_server_now_ms")
@@ -141,6 +142,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cavity_debug_tbc.argtypes = [vp, i, P(C128), P(C128)]
     lib.cavity_debug_operator.argtypes = [vp, P(C128), P(C128)]
     lib.cavity_debug_rhs.argtypes = [vp, d, d, i, P(C128), P(C128)]
+    lib.cavity_debug_fft_plans.argtypes = [P(i), P(i), P(i)]
     lib.cavity_probe_kernel.argtypes = [i, i]
     lib.cavity_probe_read.argtypes = [P(i), P(d), P(d)]
     lib.cavity_plan_footprint.argtypes = [d, d, d, i, i, i, P(EpsStack), d, P(Opts),
@@ -389,6 +391,18 @@ class Plan:
         _check(self._lib.cavity_debug_rhs(self._h, float(theta), float(phi), int(pol), _cbuf(g1),
                                           _cbuf(g2)))
         return g1, g2
+
+
+def fft_plans(lengths):
+    """Stage radices the transform planner gives a plan whose six transform lengths are
+    `lengths` (2 s Nx, 2 s Ny, P1, P2, 2 Nx, 2 Ny): a list of six tuples (empty when a length
+    has no factorisation).  Host only (cavity_debug_fft_plans)."""
+    lib = load_library()
+    ln = (ctypes.c_int * 6)(*map(int, lengths))
+    rad = (ctypes.c_int * 120)()
+    nst = (ctypes.c_int * 6)()
+    _check(lib.cavity_debug_fft_plans(ln, rad, nst))
+    return [tuple(rad[20 * k + t] for t in range(nst[k])) for k in range(6)]
 
 
 def solve_group(plans, thetas, phis, pols, fields: bool = True):

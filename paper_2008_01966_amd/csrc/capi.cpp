@@ -2247,4 +2247,17 @@ int cavity_debug_rhs(cavity_plan p, double theta, double phi, int pol, cavity_c1
   return CAVITY_OK;
 }
 
+int cavity_debug_fft_plans(const int* len, int* radices, int* nst) {
+  if (!len || !radices || !nst) return fail(CAVITY_EINVAL, "NULL argument");
+  for (int i = 0; i < 6; ++i)
+    if (len[i] < 1 || len[i] > (1 << 20)) return fail(CAVITY_EINVAL, "transform length out of range");
+  const bool small_radices = small_radix_plans(len, 6);
+  for (int i = 0; i < 6; ++i) {
+    const cav::FftPlan pl = make_fft_plan(len[i], small_radices);
+    nst[i] = pl.nst;
+    for (int t = 0; t < 20; ++t) radices[20 * i + t] = t < pl.nst ? pl.radix[t] : 0;
+  }
+  return CAVITY_OK;
+}
+
 }  // extern "C"

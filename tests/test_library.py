@@ -194,3 +194,40 @@ def test_binding_validates_spectrum_and_thickness_arguments():
     with pytest.raises(ValueError):
         P.Plan(1.0, 1.0, 0.5, 16, 16, 8, stream=0, layer_depth=(0.5,))
     assert P.SPECTRA == {"exact": 0, "asymptotic": 1}
+
+
+def test_fft_planner_radix_choice():
+    """The transform planner's choice for the six lengths of a plan (2 s Nx, 2 s Ny, P1, P2,
+    2 Nx, 2 Ny), host only: radices up to 8 where they need no more stages; all six in radices
+    up to 8 when each needs at most one stage more and is at most 1000 points long; otherwise
+    each length on its fewest stages.  Every factorisation multiplies out to its length."""
+    small8 = [(8, 8, 8)] * 2 + [(5, 5, 5, 5)] * 2 + [(8, 8, 8)] * 2
+    assert P.fft_plans((512, 512, 625, 625, 512, 512)) == small8
+    # one stage more than 16.8 and 16.10 (2 wavelengths at 32 nodes per wavelength)
+    assert P.fft_plans((128, 128, 160, 160, 128, 128)) == \
+        [(8, 4, 4)] * 2 + [(8, 5, 4)] * 2 + [(8, 4, 4)] * 2
+    # one stage more than 12.8.8 and 12.10.8 (12 wavelengths)
+    assert P.fft_plans((768, 768, 960, 960, 768, 768)) == \
+        [(8, 6, 4, 4)] * 2 + [(8, 6, 5, 4)] * 2 + [(8, 6, 4, 4)] * 2
+    # above 1000 points no extra stage: 1024 and 1250 keep 16.8.8 and 10.5.5.5
+    assert P.fft_plans((1024, 1024, 1250, 1250, 1024, 1024)) == \
+        [(16, 8, 8)] * 2 + [(10, 5, 5, 5)] * 2 + [(16, 8, 8)] * 2
+    # one length beyond the bound keeps the others on their fewest stages too
+    assert P.fft_plans((768, 768, 2048, 2048, 960, 128)) == \
+        [(12, 8, 8)] * 2 + [(16, 16, 8)] * 2 + [(12, 10, 8), (16, 8)]
+    # the prime radix 11 (the M = N = 21 geometries of Section 7: 44 = 4 x 11)
+    assert P.fft_plans((44, 44, 100, 100, 44, 44)) == [(11, 4)] * 2 + [(10, 10)] * 2 + [(11, 4)] * 2
+    # no factorisation: a prime factor above 13
+    assert P.fft_plans((34, 34, 40, 40, 34, 34))[0] == ()
+    for n in (6, 30, 96, 250, 378, 486, 640, 729, 1000, 1452, 2000, 3125):
+        for plan in P.fft_plans((n,) * 6):
+            assert _product(plan) == n and max(plan) <= 16
+    with pytest.raises(P.CavityError):
+        P.fft_plans((0, 1, 2, 3, 4, 5))
+
+
+def _product(t):
+    out = 1
+    for r in t:
+        out *= r
+    return out
